@@ -1,0 +1,39 @@
+"""The killing-rate constant used for the mixture workloads.
+
+Any c_tilde > 0 gives a pi-invariant restore process (the killing rate of
+the simplified form needs only pi-invariant local dynamics).  The step
+budget B and the drain cap make long tours costly and, if they outlive the
+cap, censored.  The rule used here bounds the expected lifetime
+p(x) / (c_tilde u(x)) by B/8 at every x of the box:
+
+    c_tilde = max(1, 8 P / B),   P = sum_k w_k (2 pi)^(-d/2) det(S_k)^(-1/2),
+
+where P >= sup p because every component density is at most its peak value.
+Run as a script to print the constant stored in ``workloads``.
+"""
+import math
+import sys
+
+import numpy as np
+
+
+def peak_bound(wl) -> float:
+    w = np.asarray(wl.params["weights"], dtype=np.float64)
+    d = wl.d
+    if wl.target == "gmm_iso":
+        s = np.asarray(wl.params["sigmas"], dtype=np.float64)
+        return float((w * (2 * math.pi * s * s) ** (-d / 2)).sum())
+    c = np.asarray(wl.params["covs"], dtype=np.float64)
+    return float((w * (2 * math.pi) ** (-d / 2) / np.sqrt(np.linalg.det(c))).sum())
+
+
+def c_tilde_rule(wl, sig: int = 3) -> float:
+    v = max(1.0, 8.0 * peak_bound(wl) / wl.n_steps)
+    return float(f"{v:.{sig - 1}e}")
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, __file__.rsplit("/oracle/", 1)[0])
+    from workloads import gmm_full, gmm_iso_2d
+    print("gmm_iso_2d", c_tilde_rule(gmm_iso_2d()))
+    print("gmm_full_8d", c_tilde_rule(gmm_full()))

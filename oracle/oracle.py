@@ -1,0 +1,381 @@
+"""Python front of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this module.  It loads ``oracle/liboracle.so`` (plain C,
+double precision, built by ``oracle/build.py`` with gcc), marshals a
+:class:`workloads.Workload` into the oracle's structs and exposes
+
+* :func:`init_states`     -- x_0 ~ mu for a set of chains (Alg. 2 input);
+* :func:`transitions`     -- single Jump Restore transitions (Alg. 2 body);
+* :func:`run`             -- whole runs: B steps, drain, per-chain tour sums;
+* :func:`estimate`        -- the tour-ratio estimates of Sec. 6.3 / 7.4 with
+                             delta-method standard errors over chains.
+
+It shares nothing with the HIP path except the seeded inputs drawn by
+``workloads``.  The Gaussian-mixture precision matrices and log-determinants
+are taken from numpy's ``inv`` / ``slogdet`` (library primitives); the HIP
+side computes its own Cholesky factors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+TARGET_GMM, TARGET_PSS = 0, 1
+MU_UNIFORM, MU_GMM_DIAG = 0, 1
+LOCAL_RWMH, LOCAL_MALA = 0, 1
+FLAG_KILL, FLAG_ACCEPT, FLAG_OUTSIDE = 1, 2, 4
+
+_dp = C.POINTER(C.c_double)
+
+
+class OrTarget(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("d", C.c_int32), ("K", C.c_int32), ("pad", C.c_int32),
+                ("log_w", _dp), ("mean", _dp), ("prec", _dp), ("logdet", _dp),
+                ("ta_freq", _dp), ("ta_amp", _dp), ("ta_phase", _dp),
+                ("tb_freq", _dp), ("tb_amp", _dp), ("tb_phase", _dp),
+                ("lobe_dir", _dp), ("lobe_kappa", _dp), ("lobe_w", _dp),
+                ("base", C.c_double)]
+
+
+class OrMu(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("d", C.c_int32), ("K", C.c_int32), ("pad", C.c_int32),
+                ("beta", C.c_double), ("logit", _dp), ("mean", _dp), ("log_std", _dp)]
+
+
+class OrLocal(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("step", C.c_double)]
+
+
+class OrConfig(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("target_id", C.c_uint32), ("pad", C.c_uint32),
+                ("c_tilde", C.c_double), ("integrand_p", C.c_int32),
+                ("image_w", C.c_int32), ("image_h", C.c_int32), ("pad2", C.c_int32)]
+
+
+class OrOutputs(C.Structure):
+    _fields_ = [("n_done", C.POINTER(C.c_int64)), ("t_done", _dp), ("a_done", _dp),
+                ("censored", C.POINTER(C.c_int32)), ("t_censored", _dp),
+                ("transitions", C.POINTER(C.c_int64)), ("accepts", C.POINTER(C.c_int64)),
+                ("kills", C.POINTER(C.c_int64)), ("image", _dp)]
+
+
+_lib = None
+
+
+def load():
+    """Load the oracle library, building it first if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build
+        _build.build()
+    lib = C.CDLL(_LIB_PATH)
+    lib.oracle_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+    lib.oracle_u01.argtypes = [C.c_uint32]
+    lib.oracle_u01.restype = C.c_double
+    lib.oracle_log_target.argtypes = [C.POINTER(OrTarget), _dp, _dp]
+    lib.oracle_log_target.restype = C.c_double
+    lib.oracle_log_mu.argtypes = [C.POINTER(OrMu), _dp]
+    lib.oracle_log_mu.restype = C.c_double
+    lib.oracle_transitions.argtypes = [C.POINTER(OrTarget), C.POINTER(OrMu), C.POINTER(OrLocal),
+                                       C.POINTER(OrConfig), C.c_int64, C.POINTER(C.c_uint32),
+                                       C.POINTER(C.c_uint32), _dp, _dp, _dp, _dp, C.c_int,
+                                       _dp, C.POINTER(C.c_int32), _dp]
+    lib.oracle_init_states.argtypes = [C.POINTER(OrTarget), C.POINTER(OrMu), C.POINTER(OrConfig),
+                                       C.c_int64, C.POINTER(C.c_uint32), _dp, _dp, _dp, _dp]
+    lib.oracle_run.argtypes = [C.POINTER(OrTarget), C.POINTER(OrMu), C.POINTER(OrLocal),
+                               C.POINTER(OrConfig), C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                               C.c_int32, C.POINTER(OrOutputs)]
+    lib.oracle_run.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+class use_library:
+    """Context manager that points this module at another build of the
+    oracle (the mutation tests load deliberately broken copies)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib, _LIB_PATH
+        self._saved = (_lib, _LIB_PATH)
+        _lib, _LIB_PATH = None, self.path
+        return load()
+
+    def __exit__(self, *exc):
+        global _lib, _LIB_PATH
+        _lib, _LIB_PATH = self._saved
+        return False
+
+
+def _ptr(a: Optional[np.ndarray], ctype=C.c_double):
+    if a is None:
+        return C.POINTER(ctype)()
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Problem:
+    """A workload marshalled for the oracle.  Keeps the numpy arrays alive
+    for as long as the ctypes structs point at them."""
+
+    def __init__(self, wl, mu: Optional[dict] = None, target_id: int = 0,
+                 c_tilde: Optional[float] = None, seed: Optional[int] = None,
+                 integrand_p: bool = True, image: Optional[tuple] = None,
+                 step: Optional[float] = None, local: Optional[str] = None):
+        self.wl = wl
+        self.d = wl.d
+        self._keep = []
+        t = OrTarget()
+        t.d, t.K = wl.d, wl.K
+        p = wl.params
+        if wl.target in ("gmm_iso", "gmm_full"):
+            t.kind = TARGET_GMM
+            w = _f64(p["weights"])
+            means = _f64(p["means"]).reshape(wl.K, wl.d)
+            if wl.target == "gmm_iso":
+                covs = np.stack([np.eye(wl.d) * s * s for s in _f64(p["sigmas"])])
+            else:
+                covs = _f64(p["covs"]).reshape(wl.K, wl.d, wl.d)
+            prec = _f64(np.linalg.inv(covs))
+            logdet = _f64(np.linalg.slogdet(covs)[1])
+            log_w = _f64(np.log(w))
+            self._keep += [log_w, means, prec, logdet]
+            t.log_w, t.mean, t.prec, t.logdet = _ptr(log_w), _ptr(means), _ptr(prec), _ptr(logdet)
+        elif wl.target == "pss":
+            t.kind = TARGET_PSS
+            arrs = {k: _f64(p[k]) for k in ("tex_a_freq", "tex_a_amp", "tex_a_phase",
+                                            "tex_b_freq", "tex_b_amp", "tex_b_phase",
+                                            "lobe_dirs", "lobe_kappa", "lobe_weights")}
+            self._keep += list(arrs.values())
+            t.ta_freq, t.ta_amp, t.ta_phase = (_ptr(arrs["tex_a_freq"]), _ptr(arrs["tex_a_amp"]),
+                                               _ptr(arrs["tex_a_phase"]))
+            t.tb_freq, t.tb_amp, t.tb_phase = (_ptr(arrs["tex_b_freq"]), _ptr(arrs["tex_b_amp"]),
+                                               _ptr(arrs["tex_b_phase"]))
+            t.lobe_dir, t.lobe_kappa, t.lobe_w = (_ptr(arrs["lobe_dirs"]), _ptr(arrs["lobe_kappa"]),
+                                                  _ptr(arrs["lobe_weights"]))
+            t.base = float(p["base"][0])
+        else:
+            raise ValueError(wl.target)
+        self.target = t
+
+        m = OrMu()
+        m.d = wl.d
+        if mu is None:
+            m.kind = MU_UNIFORM
+        else:
+            m.kind = MU_GMM_DIAG
+            logit = _f64(mu["logits"])
+            mmean = _f64(mu["means"]).reshape(-1, wl.d)
+            lstd = _f64(mu["log_std"]).reshape(-1, wl.d)
+            self._keep += [logit, mmean, lstd]
+            m.K = logit.shape[0]
+            m.beta = float(mu["beta"])
+            m.logit, m.mean, m.log_std = _ptr(logit), _ptr(mmean), _ptr(lstd)
+        self.mu = m
+
+        lk = OrLocal()
+        local = local or wl.local
+        lk.kind = LOCAL_MALA if local == "mala" else LOCAL_RWMH
+        lk.step = float(wl.step if step is None else step)
+        self.local = lk
+
+        cfg = OrConfig()
+        cfg.seed = int(wl.seed if seed is None else seed)
+        cfg.target_id = int(target_id)
+        cfg.c_tilde = float(wl.c_tilde if c_tilde is None else c_tilde)
+        cfg.integrand_p = 1 if integrand_p else 0
+        img = image if image is not None else wl.image
+        if img:
+            cfg.image_w, cfg.image_h = int(img[0]), int(img[1])
+        self.cfg = cfg
+
+    @property
+    def c_tilde(self) -> float:
+        return self.cfg.c_tilde
+
+
+# ---------------------------------------------------------------------------
+# primitives exposed for pins
+# ---------------------------------------------------------------------------
+
+def philox(counter, key) -> np.ndarray:
+    lib = load()
+    c = (C.c_uint32 * 4)(*[int(v) & 0xffffffff for v in counter])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    out = (C.c_uint32 * 4)()
+    lib.oracle_philox4x32_10(c, k, out)
+    return np.array(list(out), dtype=np.uint32)
+
+
+def u01(r: int) -> float:
+    return load().oracle_u01(int(r) & 0xffffffff)
+
+
+def log_target(prob: Problem, x: np.ndarray, grad: bool = False):
+    """log p at each row of x (and grad log p if requested)."""
+    lib = load()
+    x = _f64(x).reshape(-1, prob.d)
+    lp = np.empty(x.shape[0])
+    g = np.zeros_like(x)
+    for i in range(x.shape[0]):
+        xi = np.ascontiguousarray(x[i])
+        gi = np.zeros(prob.d)
+        lp[i] = lib.oracle_log_target(C.byref(prob.target), _ptr(xi), _ptr(gi) if grad else _dp())
+        g[i] = gi
+    return (lp, g) if grad else lp
+
+
+def log_mu(prob: Problem, y: np.ndarray) -> np.ndarray:
+    lib = load()
+    y = _f64(y).reshape(-1, prob.d)
+    return np.array([lib.oracle_log_mu(C.byref(prob.mu), _ptr(np.ascontiguousarray(r))) for r in y])
+
+
+# ---------------------------------------------------------------------------
+# transitions
+# ---------------------------------------------------------------------------
+
+@dataclass
+class States:
+    x: np.ndarray      # [n, d]
+    lp: np.ndarray     # [n]
+    lu: np.ndarray     # [n]
+    g: np.ndarray      # [n, d]
+
+    def copy(self) -> "States":
+        return States(self.x.copy(), self.lp.copy(), self.lu.copy(), self.g.copy())
+
+
+def init_states(prob: Problem, chains) -> States:
+    lib = load()
+    chains = np.ascontiguousarray(np.asarray(chains, dtype=np.uint32))
+    n, d = chains.shape[0], prob.d
+    st = States(np.zeros((n, d)), np.zeros(n), np.zeros(n), np.zeros((n, d)))
+    lib.oracle_init_states(C.byref(prob.target), C.byref(prob.mu), C.byref(prob.cfg), n,
+                           _ptr(chains, C.c_uint32), _ptr(st.x), _ptr(st.lp), _ptr(st.lu), _ptr(st.g))
+    return st
+
+
+def transitions(prob: Problem, states: States, steps, chains, recompute: bool = True):
+    """One Alg. 2 transition for each (state, step, chain).  With
+    ``recompute`` the oracle recomputes log p, log u and grad log p of the
+    input states in FP64 (the usual case: the input x is shared, the cached
+    values are each side's own).  Returns (new States, dt, flags, margins)."""
+    lib = load()
+    st = states.copy()
+    st.x = _f64(st.x); st.lp = _f64(st.lp); st.lu = _f64(st.lu); st.g = _f64(st.g)
+    n = st.x.shape[0]
+    steps = np.ascontiguousarray(np.broadcast_to(np.asarray(steps, dtype=np.uint32), (n,)))
+    chains = np.ascontiguousarray(np.asarray(chains, dtype=np.uint32))
+    dt = np.zeros(n)
+    flags = np.zeros(n, dtype=np.int32)
+    margins = np.zeros((n, 2))
+    lib.oracle_transitions(C.byref(prob.target), C.byref(prob.mu), C.byref(prob.local),
+                           C.byref(prob.cfg), n, _ptr(steps, C.c_uint32), _ptr(chains, C.c_uint32),
+                           _ptr(st.x), _ptr(st.lp), _ptr(st.lu), _ptr(st.g), 1 if recompute else 0,
+                           _ptr(dt), _ptr(flags, C.c_int32), _ptr(margins))
+    return st, dt, flags, margins
+
+
+# ---------------------------------------------------------------------------
+# runs and estimates
+# ---------------------------------------------------------------------------
+
+@dataclass
+class RunResult:
+    n_done: np.ndarray
+    t_done: np.ndarray
+    a_done: np.ndarray
+    censored: np.ndarray
+    t_censored: np.ndarray
+    transitions: np.ndarray
+    accepts: np.ndarray
+    kills: np.ndarray
+    image: Optional[np.ndarray]
+    c_tilde: float
+
+
+def run(prob: Problem, c0: int, c1: int, n_steps: Optional[int] = None,
+        drain_cap: Optional[int] = None, threads: Optional[int] = None) -> RunResult:
+    """Chains [c0, c1): x_0 ~ mu, ``n_steps`` steps with regeneration, then
+    the tours in flight are finished for at most ``drain_cap`` steps."""
+    lib = load()
+    n = c1 - c0
+    n_steps = prob.wl.n_steps if n_steps is None else n_steps
+    drain_cap = prob.wl.drain_cap if drain_cap is None else drain_cap
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
+    r = RunResult(np.zeros(n, np.int64), np.zeros(n), np.zeros(n), np.zeros(n, np.int32),
+                  np.zeros(n), np.zeros(n, np.int64), np.zeros(n, np.int64), np.zeros(n, np.int64),
+                  None, prob.c_tilde)
+    out = OrOutputs()
+    out.n_done, out.t_done, out.a_done = _ptr(r.n_done, C.c_int64), _ptr(r.t_done), _ptr(r.a_done)
+    out.censored, out.t_censored = _ptr(r.censored, C.c_int32), _ptr(r.t_censored)
+    out.transitions, out.accepts = _ptr(r.transitions, C.c_int64), _ptr(r.accepts, C.c_int64)
+    out.kills = _ptr(r.kills, C.c_int64)
+    if prob.cfg.image_w > 0:
+        r.image = np.zeros((prob.cfg.image_h, prob.cfg.image_w))
+        out.image = _ptr(r.image)
+    else:
+        out.image = _dp()
+    rc = lib.oracle_run(C.byref(prob.target), C.byref(prob.mu), C.byref(prob.local),
+                        C.byref(prob.cfg), int(c0), int(c1), int(n_steps), int(drain_cap),
+                        int(threads), C.byref(out))
+    if rc != 0:
+        raise RuntimeError("oracle_run failed")
+    return r
+
+
+def _ratio(num: np.ndarray, den: np.ndarray):
+    """Pooled ratio R = sum num / sum den over chains and its delta-method
+    standard error sqrt(sum (num_c - R den_c)^2 / ((C - 1) C mean(den)^2))."""
+    num = np.asarray(num, dtype=np.float64)
+    den = np.asarray(den, dtype=np.float64)
+    C_ = num.shape[0]
+    R = num.sum() / den.sum()
+    if C_ < 2:
+        return R, float("nan")
+    resid = num - R * den
+    se = np.sqrt((resid * resid).sum() / ((C_ - 1) * C_)) / den.mean()
+    return float(R), float(se)
+
+
+def estimate(r: RunResult) -> dict:
+    """Sec. 6.3: p_lambda ~ (c_tilde / j) sum tau_i; lambda(p f) ~ (c_tilde / j)
+    int f dt; Sec. 7.4 eq. (approx): pi f ~ sum dt f / sum dt.  j counts the
+    completed tours of all chains; censored tours are excluded."""
+    c = r.c_tilde
+    pl, pl_se = _ratio(r.t_done, r.n_done)
+    lpf, lpf_se = _ratio(r.a_done, r.n_done)
+    pif, pif_se = _ratio(r.a_done, r.t_done)
+    tot_t = r.t_done.sum() + r.t_censored.sum()
+    return {
+        "p_lambda": c * pl, "p_lambda_se": c * pl_se,
+        "lam_pf": c * lpf, "lam_pf_se": c * lpf_se,
+        "pi_f": pif, "pi_f_se": pif_se,
+        "tours_done": int(r.n_done.sum()), "tours_censored": int(r.censored.sum()),
+        "censored_time_frac": float(r.t_censored.sum() / tot_t) if tot_t > 0 else 0.0,
+        "transitions": int(r.transitions.sum()),
+        "accept_rate": float(r.accepts.sum() / max(1, r.transitions.sum())),
+        "kill_rate": float(r.kills.sum() / max(1, r.transitions.sum())),
+    }
+
+
+def image_estimate(r: RunResult) -> np.ndarray:
+    """lambda(p h_j) per pixel j: (c_tilde / j) times the summed dt splats."""
+    return r.c_tilde * r.image / r.n_done.sum()

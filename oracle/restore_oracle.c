@@ -1,0 +1,560 @@
+/*
+ * FP64 CPU oracle of the Jump Restore process -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load this library.  It shares no code, header or table with the HIP path:
+ * it has its own Philox, its own uniform/normal/exponential mapping, its own
+ * densities and its own step.  It is deliberately plain and slow: one chain
+ * at a time, every quantity in double precision, the steps in the order the
+ * paper gives them.
+ *
+ * What it follows (Holl, Singh, Seidel, "Jump Restore Light Transport"):
+ *   - Alg. 2 (Jump Restore): per step draw t1 ~ Exp(1) (holding time) and
+ *     t2 ~ Exp(k(x)) (time to the next termination attempt); if t1 < t2 the
+ *     chain holds for t1 and makes a local move x' ~ zeta(x, .), otherwise
+ *     it holds for t2 and is regenerated x' ~ mu.  The pair (dt, x_{i-1}) is
+ *     the output.
+ *   - Sec. 6.2, eq. (killing-rate-simplified): with pi-invariant local
+ *     dynamics and a state-independent mu of density u, k = c_tilde u / p.
+ *   - Alg. 1 with the acceptance function of eq. (optimal-acceptance-
+ *     function): accept iff U < alpha(x, y), alpha = min(1, p(y)q(y,x) /
+ *     (p(x)q(x,y))) when p(x)q(x,y) > 0, else 1.
+ *   - Sec. 6.3 / 7.4: the tour decomposition, the estimates
+ *     p_lambda ~ (c_tilde / j) sum tau_i and lambda(p f) ~ (c_tilde / j)
+ *     int f dt, and the time-weighted left-rectangle sums of eq. (approx).
+ *
+ * Readings where the paper is silent (all shared with the GPU side as a
+ * specification, never as code):
+ *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed lo,
+ *     seed hi), counter = (step, chain, target, purpose << 16 | block);
+ *     uniforms u = (2 (r >> 9) + 1) 2^-24; normals by Box-Muller; Exp(1)
+ *     variates as -ln u.  Block 0 of a step gives (u_E1, u_E2, u_acc,
+ *     u_cat); blocks 1.. give the d candidate uniforms.
+ *   - k = +inf where p(x) = 0 (immediate kill, dt = 0); k = 0 when
+ *     c_tilde = 0 (no killing, a plain MH chain).
+ *   - the step budget: B steps with regeneration, then the tour in flight is
+ *     finished without regeneration for at most drain_cap further steps;
+ *     tours still alive then are censored (excluded and reported).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+#define OR_MAXD 16
+#define OR_MAXK 64
+
+enum { OR_TARGET_GMM = 0, OR_TARGET_PSS = 1 };
+enum { OR_MU_UNIFORM = 0, OR_MU_GMM_DIAG = 1 };
+enum { OR_LOCAL_RWMH = 0, OR_LOCAL_MALA = 1 };
+enum { OR_PURPOSE_INIT = 0, OR_PURPOSE_STEP = 1 };
+enum { OR_FLAG_KILL = 1, OR_FLAG_ACCEPT = 2, OR_FLAG_OUTSIDE = 4 };
+
+/* Target density p on the unit box.
+ * GMM: p(x) = sum_k w_k N(x; m_k, S_k) for x in [0,1]^d, 0 outside.
+ *      log_w[k] = ln w_k, mean[k*d + i], prec[k*d*d + i*d + j] = (S_k^-1)_ij,
+ *      logdet[k] = ln det S_k.
+ * PSS: g(x) = tA(x0,x1) tB(x6..x11) [b + sum_l w_l h_l(x_{2l-2}, x_{2l-1})]. */
+typedef struct {
+    int32_t kind, d, K, pad;
+    const double *log_w, *mean, *prec, *logdet;
+    /* pss */
+    const double *ta_freq, *ta_amp, *ta_phase;   /* [8*2], [8], [8] */
+    const double *tb_freq, *tb_amp, *tb_phase;   /* [8*6], [8], [8] */
+    const double *lobe_dir, *lobe_kappa, *lobe_w; /* [3*3], [3], [3] */
+    double base;
+} or_target;
+
+/* Regeneration distribution mu.
+ * UNIFORM: u = 1 on [0,1]^d.
+ * GMM_DIAG: u(y) = beta 1_box(y) + (1 - beta) sum_k pi_k N(y; m_k, diag(s_k^2))
+ *           with pi = softmax(logit), s_k = exp(log_std_k). */
+typedef struct {
+    int32_t kind, d, K, pad;
+    double beta;
+    const double *logit, *mean, *log_std;
+} or_mu;
+
+typedef struct {
+    int32_t kind, pad;
+    double step;   /* random-walk sigma, or MALA epsilon */
+} or_local;
+
+typedef struct {
+    uint64_t seed;
+    uint32_t target_id, pad;
+    double c_tilde;
+    int32_t integrand_p;     /* accumulate f = p as well as f = 1 */
+    int32_t image_w, image_h; /* pixel integrand on (x0, x1); 0 = off */
+    int32_t pad2;
+} or_config;
+
+/* ----------------------------------------------------------------------- */
+/* Philox4x32-10                                                            */
+/* ----------------------------------------------------------------------- */
+
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* odd 23-bit uniform in (0,1): exactly representable in binary32 */
+double oracle_u01(uint32_t r)
+{
+    return (2.0 * (double)(r >> 9) + 1.0) * ldexp(1.0, -24);
+}
+
+static void draw_block(const or_config *cfg, uint32_t step, uint32_t chain,
+                       uint32_t purpose, uint32_t block, double u[4])
+{
+    uint32_t ctr[4] = { step, chain, cfg->target_id, (purpose << 16) | block };
+    uint32_t key[2] = { (uint32_t)(cfg->seed & 0xffffffffu), (uint32_t)(cfg->seed >> 32) };
+    uint32_t r[4];
+    oracle_philox4x32_10(ctr, key, r);
+    for (int i = 0; i < 4; ++i) u[i] = oracle_u01(r[i]);
+}
+
+/* All uniforms of one step: head = (u_E1, u_E2, u_acc, u_cat); cand = the
+ * candidate uniforms (4 per block, blocks 1..ceil(d/4)). */
+static void draw_step(const or_config *cfg, int d, uint32_t step, uint32_t chain,
+                      uint32_t purpose, double head[4], double cand[OR_MAXD])
+{
+    draw_block(cfg, step, chain, purpose, 0, head);
+    int nb = (d + 3) / 4;
+    for (int b = 0; b < nb; ++b) draw_block(cfg, step, chain, purpose, (uint32_t)(b + 1), cand + 4 * b);
+}
+
+/* Box-Muller: z_{2m} = sqrt(-2 ln u_{2m}) cos(2 pi u_{2m+1}),
+ *             z_{2m+1} = sqrt(-2 ln u_{2m}) sin(2 pi u_{2m+1}). */
+static void box_muller(int d, const double cand[OR_MAXD], double z[OR_MAXD])
+{
+    for (int m = 0; 2 * m < d; ++m) {
+        double r = sqrt(-2.0 * log(cand[2 * m]));
+        double a = 2.0 * M_PI * cand[2 * m + 1];
+        z[2 * m] = r * cos(a);
+        if (2 * m + 1 < d) z[2 * m + 1] = r * sin(a);
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* densities                                                                */
+/* ----------------------------------------------------------------------- */
+
+static int in_box(int d, const double *x)
+{
+    for (int i = 0; i < d; ++i)
+        if (!(x[i] >= 0.0 && x[i] <= 1.0)) return 0;
+    return 1;
+}
+
+static double log_sum_exp(int n, const double *a)
+{
+    double m = -INFINITY;
+    for (int i = 0; i < n; ++i) if (a[i] > m) m = a[i];
+    if (m == -INFINITY) return -INFINITY;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += exp(a[i] - m);
+    return m + log(s);
+}
+
+/* log N(x; m, S) = -1/2 (d ln 2 pi + ln det S + (x-m)^T S^-1 (x-m)) */
+static double gmm_component_log(const or_target *t, int k, const double *x)
+{
+    int d = t->d;
+    const double *m = t->mean + (size_t)k * d;
+    const double *P = t->prec + (size_t)k * d * d;
+    double q = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            q += (x[i] - m[i]) * P[i * d + j] * (x[j] - m[j]);
+    return t->log_w[k] - 0.5 * (d * log(2.0 * M_PI) + t->logdet[k] + q);
+}
+
+/* texture t(y) = 1 + (1/8) sum_m a_m sin(2 pi <n_m, y> + phi_m) */
+static double texture(int dim, const double *freq, const double *amp, const double *phase, const double *y)
+{
+    double s = 0.0;
+    for (int m = 0; m < 8; ++m) {
+        double dot = 0.0;
+        for (int i = 0; i < dim; ++i) dot += freq[m * dim + i] * y[i];
+        s += amp[m] * sin(2.0 * M_PI * dot + phase[m]);
+    }
+    return 1.0 + s / 8.0;
+}
+
+/* h(u, v) = 4 pi vMF_kappa(omega(u, v); mu) with z = 1 - 2u, phi = 2 pi v,
+ * vMF_kappa(w; mu) = kappa / (2 pi (1 - e^{-2 kappa})) exp(kappa (mu.w - 1)) */
+static double lobe(const double *dir, double kappa, double u, double v)
+{
+    double z = 1.0 - 2.0 * u;
+    double r = sqrt(fmax(0.0, 1.0 - z * z));
+    double w0 = r * cos(2.0 * M_PI * v), w1 = r * sin(2.0 * M_PI * v), w2 = z;
+    double dot = dir[0] * w0 + dir[1] * w1 + dir[2] * w2;
+    double vmf = kappa / (2.0 * M_PI * (1.0 - exp(-2.0 * kappa))) * exp(kappa * (dot - 1.0));
+    return 4.0 * M_PI * vmf;
+}
+
+static double pss_g(const or_target *t, const double *x)
+{
+    double ta = texture(2, t->ta_freq, t->ta_amp, t->ta_phase, x);
+    double tb = texture(6, t->tb_freq, t->tb_amp, t->tb_phase, x + 6);
+    double light = t->base;
+    for (int l = 0; l < 3; ++l)
+        light += t->lobe_w[l] * lobe(t->lobe_dir + 3 * l, t->lobe_kappa[l], x[2 * l], x[2 * l + 1]);
+    return ta * tb * light;
+}
+
+/* log p(x); for MALA also grad log p(x) = sum_k r_k (-S_k^-1 (x - m_k)),
+ * r = softmax over components of the component log terms. */
+double oracle_log_target(const or_target *t, const double *x, double *grad)
+{
+    int d = t->d;
+    if (!in_box(d, x)) {
+        if (grad) for (int i = 0; i < d; ++i) grad[i] = 0.0;
+        return -INFINITY;
+    }
+    if (t->kind == OR_TARGET_PSS) {
+        if (grad) for (int i = 0; i < d; ++i) grad[i] = 0.0;
+        return log(pss_g(t, x));
+    }
+    double a[OR_MAXK];
+    for (int k = 0; k < t->K; ++k) a[k] = gmm_component_log(t, k, x);
+    double lp = log_sum_exp(t->K, a);
+    if (grad) {
+        for (int i = 0; i < d; ++i) grad[i] = 0.0;
+        for (int k = 0; k < t->K; ++k) {
+            double r = exp(a[k] - lp);
+            const double *m = t->mean + (size_t)k * d;
+            const double *P = t->prec + (size_t)k * d * d;
+            for (int i = 0; i < d; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < d; ++j) s += P[i * d + j] * (x[j] - m[j]);
+                grad[i] -= r * s;
+            }
+        }
+    }
+    return lp;
+}
+
+/* log u(y) of the regeneration distribution */
+double oracle_log_mu(const or_mu *mu, const double *y)
+{
+    int d = mu->d;
+    if (mu->kind == OR_MU_UNIFORM) return in_box(d, y) ? 0.0 : -INFINITY;
+    /* defensive mixture: beta * uniform + (1 - beta) * diagonal GMM */
+    double lse_logit;
+    {
+        double m = -INFINITY, s = 0.0;
+        for (int k = 0; k < mu->K; ++k) if (mu->logit[k] > m) m = mu->logit[k];
+        for (int k = 0; k < mu->K; ++k) s += exp(mu->logit[k] - m);
+        lse_logit = m + log(s);
+    }
+    double a[OR_MAXK + 1];
+    for (int k = 0; k < mu->K; ++k) {
+        double q = 0.0, ls = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double s = exp(mu->log_std[k * d + i]);
+            double zz = (y[i] - mu->mean[k * d + i]) / s;
+            q += zz * zz;
+            ls += mu->log_std[k * d + i];
+        }
+        a[k] = log(1.0 - mu->beta) + mu->logit[k] - lse_logit
+               - 0.5 * d * log(2.0 * M_PI) - ls - 0.5 * q;
+    }
+    a[mu->K] = in_box(d, y) ? log(mu->beta) : -INFINITY;
+    return log_sum_exp(mu->K + 1, a);
+}
+
+/* y ~ mu from the step's category uniform and candidate uniforms */
+static void sample_mu(const or_mu *mu, double u_cat, const double cand[OR_MAXD], double *y)
+{
+    int d = mu->d;
+    if (mu->kind == OR_MU_UNIFORM) {
+        for (int i = 0; i < d; ++i) y[i] = cand[i];
+        return;
+    }
+    /* categorical over (uniform, component 1..K) with probabilities
+     * (beta, (1 - beta) pi_1, ..., (1 - beta) pi_K) */
+    double m = -INFINITY, s = 0.0;
+    for (int k = 0; k < mu->K; ++k) if (mu->logit[k] > m) m = mu->logit[k];
+    for (int k = 0; k < mu->K; ++k) s += exp(mu->logit[k] - m);
+    double cum = mu->beta;
+    if (u_cat < cum) {
+        for (int i = 0; i < d; ++i) y[i] = cand[i];
+        return;
+    }
+    int pick = mu->K - 1;
+    for (int k = 0; k < mu->K; ++k) {
+        cum += (1.0 - mu->beta) * exp(mu->logit[k] - m) / s;
+        if (u_cat < cum) { pick = k; break; }
+    }
+    double z[OR_MAXD];
+    box_muller(d, cand, z);
+    for (int i = 0; i < d; ++i)
+        y[i] = mu->mean[pick * d + i] + exp(mu->log_std[pick * d + i]) * z[i];
+}
+
+/* ----------------------------------------------------------------------- */
+/* one transition of Alg. 2                                                 */
+/* ----------------------------------------------------------------------- */
+
+typedef struct {
+    double x[OR_MAXD];
+    double lp, lu;
+    double g[OR_MAXD];
+} or_state;
+
+/* log q(a -> b) of the local proposal, up to the constant that cancels in
+ * the acceptance ratio */
+static double log_q(const or_local *lk, int d, const double *a, const double *ga, const double *b)
+{
+    if (lk->kind == OR_LOCAL_RWMH) return 0.0;   /* symmetric */
+    double e = lk->step, s = 0.0;
+    for (int i = 0; i < d; ++i) {
+        double r = b[i] - a[i] - 0.5 * e * e * ga[i];
+        s += r * r;
+    }
+    return -s / (2.0 * e * e);
+}
+
+/* Initial state: x_0 ~ mu (purpose INIT, step 0). */
+void oracle_init_state(const or_target *t, const or_mu *mu, const or_config *cfg,
+                       uint32_t chain, or_state *st)
+{
+    double head[4], cand[OR_MAXD];
+    draw_step(cfg, t->d, 0, chain, OR_PURPOSE_INIT, head, cand);
+    sample_mu(mu, head[3], cand, st->x);
+    st->lp = oracle_log_target(t, st->x, st->g);
+    st->lu = oracle_log_mu(mu, st->x);
+}
+
+/* One Jump Restore transition from st at step `step`.
+ * Returns dt; *flags gets KILL / ACCEPT / OUTSIDE bits; margins[0] is
+ * ln t2 - ln t1 (kill iff <= 0), margins[1] is ln u_acc - ln(ratio)
+ * (accept iff < 0; NAN when no acceptance test was made). */
+double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk,
+                         const or_config *cfg, uint32_t step, uint32_t chain,
+                         or_state *st, int32_t *flags, double margins[2])
+{
+    int d = t->d;
+    double head[4], cand[OR_MAXD];
+    draw_step(cfg, d, step, chain, OR_PURPOSE_STEP, head, cand);
+
+    /* t1 ~ Exp(1): holding time; t2 ~ Exp(k(x)): time to termination */
+    double t1 = -log(head[0]);
+    double e2 = -log(head[1]);
+    double t2, log_k;
+    if (cfg->c_tilde == 0.0) { log_k = -INFINITY; t2 = INFINITY; }
+    else if (st->lp == -INFINITY) { log_k = INFINITY; t2 = 0.0; }
+    else { log_k = log(cfg->c_tilde) + st->lu - st->lp; t2 = e2 * exp(-log_k); }
+    margins[0] = log(e2) - log_k - log(t1);
+    margins[1] = NAN;
+
+    int32_t fl = 0;
+    double dt;
+    if (t1 < t2) {
+        /* local state transition: one MH update with the small-step kernel */
+        dt = t1;
+        double z[OR_MAXD], y[OR_MAXD], gy[OR_MAXD];
+        box_muller(d, cand, z);
+        for (int i = 0; i < d; ++i) {
+            y[i] = st->x[i] + lk->step * z[i];
+            if (lk->kind == OR_LOCAL_MALA) y[i] += 0.5 * lk->step * lk->step * st->g[i];
+        }
+        if (!in_box(d, y)) fl |= OR_FLAG_OUTSIDE;
+        double lpy = oracle_log_target(t, y, gy);
+        double alpha, lratio;
+        if (st->lp == -INFINITY) { alpha = 1.0; lratio = INFINITY; }
+        else {
+            lratio = lpy + log_q(lk, d, y, gy, st->x) - st->lp - log_q(lk, d, st->x, st->g, y);
+            alpha = lratio >= 0.0 ? 1.0 : exp(lratio);
+        }
+        margins[1] = log(head[2]) - lratio;
+        if (head[2] < alpha) {
+            fl |= OR_FLAG_ACCEPT;
+            for (int i = 0; i < d; ++i) { st->x[i] = y[i]; st->g[i] = gy[i]; }
+            st->lp = lpy;
+            st->lu = oracle_log_mu(mu, y);
+        }
+    } else {
+        /* termination: regenerate from mu */
+        dt = t2;
+        fl |= OR_FLAG_KILL;
+        sample_mu(mu, head[3], cand, st->x);
+        st->lp = oracle_log_target(t, st->x, st->g);
+        st->lu = oracle_log_mu(mu, st->x);
+    }
+    *flags = fl;
+    return dt;
+}
+
+/* Batched single transitions for parity tests: n independent (state, step,
+ * chain) triples.  x/g are [n][d] row-major. */
+void oracle_transitions(const or_target *t, const or_mu *mu, const or_local *lk,
+                        const or_config *cfg, int64_t n, const uint32_t *steps,
+                        const uint32_t *chains, double *x, double *lp, double *lu,
+                        double *g, int recompute, double *dt, int32_t *flags,
+                        double *margins)
+{
+    int d = t->d;
+    for (int64_t c = 0; c < n; ++c) {
+        or_state st;
+        for (int i = 0; i < d; ++i) st.x[i] = x[c * d + i];
+        if (recompute) {
+            st.lp = oracle_log_target(t, st.x, st.g);
+            st.lu = oracle_log_mu(mu, st.x);
+        } else {
+            st.lp = lp[c]; st.lu = lu[c];
+            for (int i = 0; i < d; ++i) st.g[i] = g[c * d + i];
+        }
+        dt[c] = oracle_transition(t, mu, lk, cfg, steps[c], chains[c], &st, &flags[c], &margins[2 * c]);
+        for (int i = 0; i < d; ++i) { x[c * d + i] = st.x[i]; g[c * d + i] = st.g[i]; }
+        lp[c] = st.lp; lu[c] = st.lu;
+    }
+}
+
+void oracle_init_states(const or_target *t, const or_mu *mu, const or_config *cfg,
+                        int64_t n, const uint32_t *chains, double *x, double *lp,
+                        double *lu, double *g)
+{
+    int d = t->d;
+    for (int64_t c = 0; c < n; ++c) {
+        or_state st;
+        oracle_init_state(t, mu, cfg, chains[c], &st);
+        for (int i = 0; i < d; ++i) { x[c * d + i] = st.x[i]; g[c * d + i] = st.g[i]; }
+        lp[c] = st.lp; lu[c] = st.lu;
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* whole runs                                                               */
+/* ----------------------------------------------------------------------- */
+
+/* Per-chain results of a run. */
+typedef struct {
+    int64_t *n_done;      /* completed tours                         */
+    double *t_done;       /* sum of completed tour lifetimes          */
+    double *a_done;       /* sum over completed tours of int f = p dt */
+    int32_t *censored;    /* 1 if the tour in flight hit the cap      */
+    double *t_censored;   /* lifetime so far of a censored tour        */
+    int64_t *transitions; /* steps executed                           */
+    int64_t *accepts;     /* accepted local moves                     */
+    int64_t *kills;       /* terminations                             */
+    double *image;        /* [image_h * image_w], summed dt splats, or NULL */
+} or_outputs;
+
+typedef struct {
+    const or_target *t; const or_mu *mu; const or_local *lk; const or_config *cfg;
+    int64_t c0, c1;
+    int32_t n_steps, drain_cap;
+    const or_outputs *out;
+    double *image;  /* this thread's image */
+} or_job;
+
+static void run_chain(const or_job *job, int64_t c)
+{
+    const or_target *t = job->t; const or_config *cfg = job->cfg;
+    or_state st;
+    oracle_init_state(t, job->mu, cfg, (uint32_t)c, &st);
+    double a_cur = 0.0, t_cur = 0.0, a_done = 0.0, t_done = 0.0;
+    int64_t n_done = 0, trans = 0, acc = 0, kills = 0;
+    int alive = 1;
+    int64_t s_end = (int64_t)job->n_steps + job->drain_cap;
+    for (int64_t s = 0; s < s_end; ++s) {
+        int drain = s >= job->n_steps;
+        if (drain && !alive) break;
+        /* the pair (dt, x_{i-1}) is recorded before the state moves */
+        double x_prev[OR_MAXD];
+        memcpy(x_prev, st.x, sizeof(double) * t->d);
+        double lp_prev = st.lp;
+        or_state before = st;
+        int32_t fl; double mg[2];
+        double dt = oracle_transition(t, job->mu, job->lk, cfg, (uint32_t)s, (uint32_t)c, &st, &fl, mg);
+        ++trans;
+        t_cur += dt;
+        if (cfg->integrand_p) a_cur += dt * (lp_prev == -INFINITY ? 0.0 : exp(lp_prev));
+        if (job->image) {
+            int px = (int)floor(x_prev[0] * cfg->image_w);
+            int py = (int)floor(x_prev[1] * cfg->image_h);
+            if (x_prev[0] >= 0.0 && x_prev[0] <= 1.0 && x_prev[1] >= 0.0 && x_prev[1] <= 1.0) {
+                if (px >= cfg->image_w) px = cfg->image_w - 1;
+                if (py >= cfg->image_h) py = cfg->image_h - 1;
+                job->image[(size_t)py * cfg->image_w + px] += dt;
+            }
+        }
+        if (fl & OR_FLAG_ACCEPT) ++acc;
+        if (fl & OR_FLAG_KILL) {
+            ++kills;
+            a_done += a_cur; t_done += t_cur; ++n_done;
+            a_cur = 0.0; t_cur = 0.0;
+            if (drain) { alive = 0; st = before; }  /* retire: no regeneration */
+        }
+    }
+    const or_outputs *o = job->out;
+    o->n_done[c] = n_done; o->t_done[c] = t_done; o->a_done[c] = a_done;
+    o->censored[c] = alive ? 1 : 0;
+    o->t_censored[c] = alive ? t_cur : 0.0;
+    o->transitions[c] = trans; o->accepts[c] = acc; o->kills[c] = kills;
+}
+
+static void *run_job(void *arg)
+{
+    const or_job *job = (const or_job *)arg;
+    for (int64_t c = job->c0; c < job->c1; ++c) run_chain(job, c);
+    return NULL;
+}
+
+/* Run chains [c0, c1) for n_steps steps plus the drain, over n_threads
+ * threads.  Per-chain outputs are indexed by (chain - c0). */
+int oracle_run(const or_target *t, const or_mu *mu, const or_local *lk,
+               const or_config *cfg, int64_t c0, int64_t c1, int32_t n_steps,
+               int32_t drain_cap, int32_t n_threads, const or_outputs *out)
+{
+    if (n_threads < 1) n_threads = 1;
+    int64_t n = c1 - c0;
+    if (n <= 0) return 0;
+    if (n_threads > n) n_threads = (int32_t)n;
+    pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    or_job *jobs = (or_job *)calloc((size_t)n_threads, sizeof(or_job));
+    size_t npix = (size_t)cfg->image_w * (size_t)cfg->image_h;
+    or_outputs shifted = *out;
+    /* shift outputs so run_chain can index by global chain id */
+    shifted.n_done -= c0; shifted.t_done -= c0; shifted.a_done -= c0;
+    shifted.censored -= c0; shifted.t_censored -= c0; shifted.transitions -= c0;
+    shifted.accepts -= c0; shifted.kills -= c0;
+    for (int i = 0; i < n_threads; ++i) {
+        jobs[i].t = t; jobs[i].mu = mu; jobs[i].lk = lk; jobs[i].cfg = cfg;
+        jobs[i].c0 = c0 + n * i / n_threads;
+        jobs[i].c1 = c0 + n * (i + 1) / n_threads;
+        jobs[i].n_steps = n_steps; jobs[i].drain_cap = drain_cap;
+        jobs[i].out = &shifted;
+        jobs[i].image = (out->image && npix) ? (double *)calloc(npix, sizeof(double)) : NULL;
+        pthread_create(&th[i], NULL, run_job, &jobs[i]);
+    }
+    for (int i = 0; i < n_threads; ++i) {
+        pthread_join(th[i], NULL);
+        if (jobs[i].image) {
+            for (size_t p = 0; p < npix; ++p) out->image[p] += jobs[i].image[p];
+            free(jobs[i].image);
+        }
+    }
+    free(th); free(jobs);
+    return 0;
+}

@@ -1,0 +1,80 @@
+"""The pins are sensitive: each plausible mistake planted in a copy of the
+oracle's C source (a wrong sign, a dropped factor, a swapped operand, a
+wrong index) makes at least one pin fail.  Everything here runs on the CPU
+and never touches the HIP path."""
+import os
+import subprocess
+
+import pytest
+
+from oracle import oracle as O
+from tests import test_oracle_pins as pins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "restore_oracle.c")
+
+MUTATIONS = {
+    # killing rate k = c u / p inverted to c p / u
+    "kill_rate_inverted": ("log_k = log(cfg->c_tilde) + st->lu - st->lp;",
+                           "log_k = log(cfg->c_tilde) + st->lp - st->lu;",
+                           [lambda: pins.test_jump_chain_leaves_nu_invariant(None, "rwmh", 0.05, 1.0)]),
+    # holding time drawn with rate 2 instead of 1
+    "holding_rate_two": ("double t1 = -log(head[0]);", "double t1 = -0.5 * log(head[0]);",
+                         [lambda: pins.test_kill_and_clock_law_at_fixed_state(None, "mode")]),
+    # tie goes to the local move instead of the kill
+    "kill_uses_t2_only": ("if (t1 < t2) {", "if (t1 < 2.0 * t2) {",
+                          [lambda: pins.test_kill_and_clock_law_at_fixed_state(None, "mode")]),
+    # Langevin drift with the wrong sign in the proposal
+    "mala_drift_sign": ("if (lk->kind == OR_LOCAL_MALA) y[i] += 0.5",
+                        "if (lk->kind == OR_LOCAL_MALA) y[i] -= 0.5",
+                        [lambda: pins.test_local_kernel_alone_is_pi_invariant(None, "mala", 0.03)]),
+    # reverse proposal density evaluated with the forward gradient
+    "mala_reverse_uses_forward_grad": ("log_q(lk, d, y, gy, st->x)", "log_q(lk, d, y, st->g, st->x)",
+                                       [lambda: pins.test_local_kernel_alone_is_pi_invariant(None, "mala", 0.03)]),
+    # Box-Muller radius missing its factor 2
+    "box_muller_radius": ("double r = sqrt(-2.0 * log(cand[2 * m]));", "double r = sqrt(-log(cand[2 * m]));",
+                          [lambda: pins.test_normals_and_exponentials_from_steps(None)]),
+    # Philox multiplier constants swapped between the two lanes
+    "philox_swapped_multipliers": ("uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;",
+                                   "uint64_t p0 = (uint64_t)M1 * (uint64_t)c0;",
+                                   [lambda: pins.test_philox_known_answers(None)]),
+    # integrand evaluated at the post-transition state instead of x_{i-1}
+    "integrand_after_move": ("a_cur += dt * (lp_prev == -INFINITY ? 0.0 : exp(lp_prev));",
+                             "a_cur += dt * (st.lp == -INFINITY ? 0.0 : exp(st.lp));",
+                             [lambda: pins.test_whole_run_2d_matches_erf_closed_form(None)]),
+    # Mahalanobis form with the mean subtracted on one side only
+    "quadratic_form_index": ("q += (x[i] - m[i]) * P[i * d + j] * (x[j] - m[j]);",
+                             "q += (x[i] - m[i]) * P[i * d + j] * (x[j] - m[i]);",
+                             [lambda: pins.test_log_target_matches_scipy(None, pins.gmm_full)]),
+    # gradient of the mixture without the responsibilities
+    "grad_no_responsibility": ("double r = exp(a[k] - lp);", "double r = 1.0 / t->K;",
+                               [lambda: pins.test_grad_log_target_central_differences(None, pins.gmm_iso_2d)]),
+    # mu density missing the defensive uniform share
+    "mu_density_drops_defensive": ("a[mu->K] = in_box(d, y) ? log(mu->beta) : -INFINITY;",
+                                   "a[mu->K] = -INFINITY;",
+                                   [lambda: pins.test_whole_run_8d_mixture_mu_matches_genz_truth(None)]),
+    # a completed tour not counted
+    "tour_not_counted": ("a_done += a_cur; t_done += t_cur; ++n_done;",
+                         "a_done += a_cur; t_done += t_cur;",
+                         [lambda: pins.test_whole_run_2d_matches_erf_closed_form(None)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path, oracle_lib):
+    old, new, checks = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    mutated = tmp_path / "mutant.c"
+    mutated.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", str(lib),
+                    str(mutated), "-lm", "-lpthread"], check=True)
+    caught = False
+    with O.use_library(str(lib)):
+        for check in checks:
+            try:
+                check()
+            except AssertionError:
+                caught = True
+    assert caught, f"no pin caught the planted mistake {name}"

@@ -1,0 +1,169 @@
+"""Benchmark: chain transitions per second of the Jump Restore population.
+
+One benchmark step is one pass of the whole hot path over one batch of
+synthetic input, with everything resident in HBM: x_0 ~ mu for every chain,
+B steps of Alg. 2 with regeneration, the drain of the tours in flight, and
+the float64 reduction into the estimates.  The default workload is the 8-D
+full-covariance mixture with MALA local moves and uniform mu, 2^20 chains x
+512 steps.
+
+Prints one JSON line (rank 0, one GPU) with the contract fields plus
+``roofline`` (the step kernel against the MI355X FP32 vector peak, from HIP
+events on the launch stream) and ``cpu_baseline`` (the FP64 oracle on the
+host cores on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_per_transition(target: str, d: int, K: int, local: str) -> float:
+    """Algorithmic float32 operations of one transition (FMA = 2, each
+    exp / log / sqrt / sin / cos = 1), dominated by the one density
+    evaluation every step needs.  Per mixture component:
+      full covariance: d (y - m) + d^2 (W (y - m)) + 2d (|v|^2) + 2 (a_k)
+                       + 7 (running log-sum-exp) [+ d^2 (W^T v) + 3d (grad)]
+      isotropic:       3d (y - m, |.|^2) + 4 + 7 [+ 3d (grad)]
+    per transition: 2 exponential clocks (4), Box-Muller (5 per pair),
+    proposal (2d, +2d MALA drift), acceptance (4, +4d MALA reverse density),
+    accumulation (4), log p from the log-sum-exp (2)."""
+    mala = local == "mala"
+    if target == "gmm_full":
+        per = d + d * d + 2 * d + 2 + 7 + ((d * d + 3 * d) if mala else 0)
+    elif target == "gmm_iso":
+        per = 3 * d + 4 + 7 + (3 * d if mala else 0)
+    else:
+        raise ValueError(target)
+    other = 4 + 5 * math.ceil(d / 2) + 2 * d + (2 * d if mala else 0) + 4 + (4 * d if mala else 0) + 4 + 2
+    return float(K * per + other)
+
+
+def cpu_baseline(wl, target_seconds: float = 12.0) -> dict:
+    """The FP64 oracle, as it stands, on the host cores: a pilot of 2^12
+    chains sizes a sample of about ``target_seconds`` of CPU work (same
+    workload, same counters, chains 0..n-1, full budget and drain)."""
+    from oracle import oracle as O
+    threads = len(os.sched_getaffinity(0))
+    prob = O.Problem(wl)
+    t0 = time.perf_counter()
+    r = O.run(prob, 0, 4096, threads=threads)
+    pilot = time.perf_counter() - t0
+    rate = r.transitions.sum() / pilot
+    n = int(min(wl.n_chains, max(4096, 4096 * target_seconds / max(pilot, 1e-3))))
+    t0 = time.perf_counter()
+    r = O.run(prob, 0, n, threads=threads)
+    el = time.perf_counter() - t0
+    trans = int(r.transitions.sum())
+    return {"value": trans / el, "unit": "transitions/s", "cores": threads, "kind": "oracle",
+            "sample": f"chains 0..{n - 1} of the same workload (full {wl.n_steps}-step budget + drain), "
+                      f"{trans} transitions in {el:.1f} s", "pilot_rate": rate}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gmm_full_8d", choices=["gmm_full_8d", "gmm_iso_2d"])
+    ap.add_argument("--lds", action="store_true", help="stage mixture parameters in LDS")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (chains shard by global id; "
+              "see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_07148_amd import restore as R
+    from workloads import gmm_full, gmm_iso_2d
+
+    wl = gmm_full() if args.workload == "gmm_full_8d" else gmm_iso_2d()
+    prob = R.problem_from_workload(wl, lds=args.lds)
+    stream = torch.cuda.current_stream()
+    nbytes = R.restore_state_bytes(prob.target, prob.mu, prob.local, prob.cfg)
+    state = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = (state.data_ptr() + 255) // 256 * 256
+
+    def one_pass(timed_step=None):
+        ctx = R.restore_init(prob.target, prob.mu, prob.local, prob.cfg, ptr, nbytes, 0, stream)
+        if timed_step is not None:
+            timed_step[0].record(stream)
+        R.restore_step(ctx, wl.n_steps, stream)
+        if timed_step is not None:
+            timed_step[1].record(stream)
+        R.restore_drain(ctx, stream)
+        est = R.restore_estimate(ctx, stream)   # synchronises the stream
+        R.restore_destroy(ctx)
+        return est
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    ests = [one_pass(ev[i]) for i in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    trans = sum(e.transitions for e in ests)
+    value = trans / wall
+    step_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+    step_trans = wl.n_chains * wl.n_steps
+    fpt = flops_per_transition(wl.target, wl.d, wl.K, wl.local)
+    achieved = fpt * step_trans / (step_ms * 1e-3) / 1e12
+    est = ests[-1]
+    line = {
+        "metric": "chain transitions/s + MSE×time vs uniform-mu restore at fixed rel. error",
+        "value": value,
+        "unit": "transitions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name,
+            "description": (f"{wl.K}-component {'full-covariance' if wl.target == 'gmm_full' else 'isotropic'} "
+                            f"Gaussian mixture on [0,1]^{wl.d}, {wl.local} step {wl.step}, uniform mu, "
+                            f"c_tilde {wl.c_tilde:g}"),
+            "chains": wl.n_chains, "budget_steps": wl.n_steps, "drain_cap": wl.drain_cap,
+            "params_staging": "lds" if args.lds else "scalar",
+        },
+        "transitions_per_step": est.transitions,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "step_kernel",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "flops_per_transition": fpt,
+            "kernel_ms": step_ms,
+            "kernel_transitions_per_s": step_trans / (step_ms * 1e-3),
+            "traffic": None,
+        },
+        "estimates": {k: est.as_dict()[k] for k in ("p_lambda", "p_lambda_se", "lam_pf", "lam_pf_se",
+                                                    "tours_done", "tours_censored", "kill_rate",
+                                                    "accept_rate")},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

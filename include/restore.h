@@ -1,0 +1,224 @@
+/*
+ * restore.h -- C ABI of the MI355X (gfx950) Jump Restore chain engine.
+ *
+ * The library advances a large population of independent Jump Restore
+ * chains (Holl, Singh, Seidel, "Jump Restore Light Transport", Sec. 7,
+ * Alg. 2).  One chain lives in one GPU lane.  Every step of a chain
+ *   1. draws a holding time t1 ~ Exp(1) and a termination time
+ *      t2 ~ Exp(k(x)), with the killing rate of Sec. 6.2,
+ *      eq. (killing-rate-simplified): k = c_tilde * u(x) / p(x);
+ *   2. if t1 < t2, holds x for dt = t1 and makes one Metropolis-Hastings
+ *      update with the small-step kernel (Alg. 1, acceptance function of
+ *      eq. (optimal-acceptance-function)); otherwise holds x for dt = t2 and
+ *      regenerates x ~ mu (the tour ends, Sec. 6.1 eq. (concatenation));
+ *   3. adds dt * f(x_{i-1}) to the running tour integral (Sec. 7.4,
+ *      eq. (approx); Sec. 6.3).
+ * restore_estimate() turns the per-chain tour sums into the estimates of
+ * Sec. 6.3: p_lambda ~ (c_tilde / j) sum tau_i, lambda(p f) ~ (c_tilde / j)
+ * int f dt, and pi f ~ sum dt f / sum dt (Sec. 7.4).
+ *
+ * Conventions
+ *   - Every function returns a restore_status: 0 on success, < 0 on error.
+ *     The message of the last error on the calling thread is available from
+ *     restore_last_error().  No C++ exception crosses this boundary.
+ *   - Device buffers are owned by the caller (allocated e.g. as torch
+ *     tensors); the library owns only the opaque restore_ctx host object.
+ *     Device pointers must stay valid until restore_destroy().
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     All calls are asynchronous on that stream except restore_estimate(),
+ *     which synchronises it.  Asynchronous HIP errors surface at the next
+ *     synchronising call.
+ *   - Random numbers: Philox4x32-10 with key (seed lo, seed hi) and counter
+ *     (step, chain, target_id, purpose << 16 | block); a chain's trajectory
+ *     is a function of (seed, chain, target_id) only, so it does not depend
+ *     on how steps are split across calls or how chains are mapped to lanes.
+ *   - The support of every target is the unit box [0,1]^d; p = 0 outside.
+ */
+#ifndef RESTORE_H
+#define RESTORE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t restore_status;
+
+#define RESTORE_OK                  0
+#define RESTORE_E_INVALID_ARG      -1   /* a descriptor field or pointer is invalid   */
+#define RESTORE_E_UNSUPPORTED      -2   /* valid, but not built (dimension, kind, ...) */
+#define RESTORE_E_HIP              -3   /* a HIP runtime call failed                   */
+#define RESTORE_E_NONFINITE        -4   /* NaN or Inf in the parameters                */
+#define RESTORE_E_BAD_STATE        -5   /* call out of order (e.g. step after drain)   */
+#define RESTORE_E_BUFFER_TOO_SMALL -6   /* state buffer smaller than restore_state_bytes */
+
+#define RESTORE_MAX_DIM   16
+#define RESTORE_MAX_COMP  64
+
+/* ---- target density p (Sec. 3, eq. (targetdensity-assumption-1)) ------- */
+#define RESTORE_TARGET_GMM_ISO    0
+#define RESTORE_TARGET_GMM_FULL   1
+#define RESTORE_TARGET_PSS        2
+
+/* Target p on [0,1]^d.  `params` are float64 on the host, copied at init.
+ *  GMM_ISO  (dim d, n_comp K): p(x) = sum_k w_k N(x; m_k, s_k^2 I) 1_box(x)
+ *           params = [ w (K) | m (K*d, row-major) | s (K) ]
+ *  GMM_FULL (dim d, n_comp K): p(x) = sum_k w_k N(x; m_k, S_k) 1_box(x)
+ *           params = [ w (K) | m (K*d) | S (K*d*d, row-major, SPD) ]
+ *  PSS      (dim 12, n_comp 0): rendering-shaped primary-sample-space
+ *           integrand g(x) = tA(x0,x1) tB(x6..x11) [b + sum_l w_l h_l]
+ *           with textures t(y) = 1 + (1/8) sum_{m<8} a_m sin(2 pi n_m.y + phi_m)
+ *           and lobes h_l(u,v) = 4 pi vMF_kappa_l(omega(u,v); dir_l),
+ *           omega = (sqrt(1-z^2) cos 2 pi v, sqrt(1-z^2) sin 2 pi v, z),
+ *           z = 1 - 2u, on coordinate pairs (x0,x1), (x2,x3), (x4,x5).
+ *           params = [ nA (8*2) | aA (8) | phiA (8) | nB (8*6) | aB (8) |
+ *                      phiB (8) | dir (3*3) | kappa (3) | w (3) | b (1) ]  */
+typedef struct {
+    int32_t kind;
+    int32_t dim;
+    int32_t n_comp;
+    int32_t reserved;
+    const double *params;     /* host pointer, copied by restore_init */
+    int64_t params_count;     /* number of doubles in params          */
+} restore_target;
+
+/* ---- regeneration distribution mu with density u (Sec. 6.2) ----------- */
+#define RESTORE_MU_UNIFORM_BOX     0
+#define RESTORE_MU_GMM_DIAG        1
+
+/*  UNIFORM_BOX: u = 1 on [0,1]^d.
+ *  GMM_DIAG:    u(y) = beta 1_box(y) + (1 - beta) sum_k pi_k N(y; m_k, diag(s_k^2)),
+ *               pi = softmax(logits), s = exp(log_std).  `params_dev` is a
+ *               caller-owned device float32 buffer [ logits (K) | m (K*d) |
+ *               log_std (K*d) ] read by every step (the learned mu; it must
+ *               not change during a run).  Sampling: one uniform picks the
+ *               uniform share (u < beta) or a component by the cumulative
+ *               weights; the component draw is m_k + s_k z.                */
+typedef struct {
+    int32_t kind;
+    int32_t n_comp;
+    float beta;
+    int32_t reserved;
+    const float *params_dev;
+} restore_mu;
+
+/* ---- local dynamics: the small-step kernel zeta of Alg. 1 ------------- */
+#define RESTORE_LOCAL_RWMH   0    /* y = x + step z                              */
+#define RESTORE_LOCAL_MALA   1    /* y = x + (step^2 / 2) grad log p(x) + step z  */
+
+typedef struct {
+    int32_t kind;
+    float step;              /* random-walk sigma or MALA epsilon (>= 0)        */
+    float large_step_prob;   /* l of eq. (mixture-proposal-kernel); the restore
+                                process uses the pure small-step chain M^0, so
+                                only 0 is accepted (UNSUPPORTED otherwise)      */
+    int32_t reserved;
+} restore_local_kernel;
+
+/* ---- run configuration ------------------------------------------------- */
+#define RESTORE_INTEGRAND_ONE    1   /* f = 1: tour lifetimes (p_lambda)     */
+#define RESTORE_INTEGRAND_P      2   /* f = p: lambda(p^2), pi p             */
+#define RESTORE_INTEGRAND_PIXEL  4   /* f = 1_pixel(x0, x1): image splats    */
+
+#define RESTORE_FLAG_PARAMS_LDS  1   /* stage mixture parameters through LDS
+                                        instead of the scalar cache          */
+
+typedef struct {
+    uint64_t seed;           /* Philox key                                   */
+    int64_t n_chains;        /* C >= 1, at most 2^31 - 1                      */
+    int32_t target_id;       /* Philox counter word 2 (batched targets)      */
+    int32_t integrands;      /* RESTORE_INTEGRAND_* bitmask (ONE is implied) */
+    double c_tilde;          /* > 0; 0 turns killing off (a plain MH chain)  */
+    int32_t drain_cap;       /* max extra steps to finish tours in flight    */
+    int32_t image_w, image_h;/* pixel grid on (x0, x1) if PIXEL is set      */
+    int32_t flags;           /* RESTORE_FLAG_*                               */
+    int32_t block_size;      /* threads per workgroup (64..256, multiple of
+                                64); 0 = library default                    */
+    int32_t reserved;
+} restore_config;
+
+/* ---- estimates (Sec. 6.3, Sec. 7.4) ----------------------------------- */
+typedef struct {
+    double p_lambda, p_lambda_se;    /* c_tilde * sum T / sum N          */
+    double lam_pf, lam_pf_se;        /* c_tilde * sum A / sum N  (f = p) */
+    double pi_f, pi_f_se;            /* sum A / sum T            (f = p) */
+    int64_t tours_done;              /* j: completed tours               */
+    int64_t tours_censored;          /* tours still alive at the cap     */
+    int64_t transitions;             /* steps executed, drain included   */
+    int64_t accepts, kills;
+    int64_t nonfinite;               /* chains whose sums are not finite */
+    double censored_time_frac;       /* censored lifetime / total time   */
+    double accept_rate, kill_rate;   /* per transition                   */
+    double image_scale;              /* c_tilde / j: multiplies the image sums */
+} restore_estimate_out;
+
+typedef struct restore_ctx restore_ctx;
+
+/* Bytes of device memory the state buffer must provide for this problem
+ * (chain state in structure-of-arrays layout, packed parameters, reduction
+ * and drain scratch).  Pure host computation. */
+restore_status restore_state_bytes(const restore_target *target, const restore_mu *mu,
+                                   const restore_local_kernel *local,
+                                   const restore_config *cfg, size_t *bytes_out);
+
+/* Validate the descriptors, pack the target parameters into the state
+ * buffer (float32, each component's Cholesky factor derived here in
+ * float64) and draw x_0 ~ mu for every chain (Alg. 2 input; tours are
+ * spawned from mu so that chains are unbiased in parallel, Sec. 1).
+ * `state_dev` (>= restore_state_bytes, 256-byte aligned) and `image_dev`
+ * (float32 [image_h][image_w], zeroed by the caller; NULL unless PIXEL) are
+ * caller-owned device memory.  On success *out receives a new context. */
+restore_status restore_init(restore_ctx **out, const restore_target *target,
+                            const restore_mu *mu, const restore_local_kernel *local,
+                            const restore_config *cfg, void *state_dev,
+                            size_t state_bytes, float *image_dev, void *stream);
+
+/* Advance every chain by n_steps steps of Alg. 2 with regeneration
+ * (steps s .. s + n_steps - 1, s = steps already taken).  Enqueue only. */
+restore_status restore_step(restore_ctx *ctx, int32_t n_steps, void *stream);
+
+/* End of the budget: run every chain on, without regeneration, until its
+ * tour in flight is killed (it then retires) or drain_cap further steps
+ * have passed (the tour is censored: excluded from the estimates, counted
+ * and reported).  Retired chains are compacted out of the launches with
+ * wavefront ballots.  After restore_drain no further restore_step. */
+restore_status restore_drain(restore_ctx *ctx, void *stream);
+
+/* Reduce the per-chain tour sums in float64 and fill *out (host memory).
+ * Synchronises `stream`. */
+restore_status restore_estimate(restore_ctx *ctx, restore_estimate_out *out, void *stream);
+
+/* Device addresses of the chain state arrays, for tests and checkpointing.
+ * Layout: x float32 [d][C]; logp, logu float32 [C]; grad float32 [d][C]
+ * (MALA only, else NULL); a_cur, t_cur float32 [C]; a_done, t_done float64
+ * [C]; n_done uint32 [C]; status uint32 [C] (bit0 alive, bit1 censored,
+ * bit2 last step killed, bit3 last step accepted); last_dt float32 [C]. */
+typedef struct {
+    float *x, *logp, *logu, *grad, *a_cur, *t_cur, *last_dt;
+    double *a_done, *t_done;
+    uint32_t *n_done, *status;
+    int64_t n_chains;
+    int32_t dim;
+    int32_t steps_taken;     /* steps with regeneration so far            */
+} restore_state_view;
+
+restore_status restore_get_state_view(const restore_ctx *ctx, restore_state_view *view);
+
+/* Recompute logp, logu and grad from x for every chain (after a caller has
+ * written x, e.g. to restore a checkpoint or to set up a parity test).
+ * `status` bits are not touched.  Enqueue only. */
+restore_status restore_refresh_cache(restore_ctx *ctx, void *stream);
+
+/* Release the context (device buffers stay the caller's). */
+restore_status restore_destroy(restore_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *restore_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RESTORE_H */

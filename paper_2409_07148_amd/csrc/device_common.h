@@ -1,0 +1,93 @@
+// Device helpers of the gfx950 restore kernels: the counter-based random
+// stream, the uniform / normal / exponential mappings and small math.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "restore_internal.h"
+
+namespace restore {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies with a Weyl-sequence key schedule.  The key and all
+// counter words except the chain id are wave-uniform, so the first rounds
+// run largely on the scalar unit.
+struct Philox {
+    static constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    static constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+
+    __device__ __forceinline__ static void block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+        for (int r = 0; r < 10; ++r) {
+            const uint64_t p0 = (uint64_t)M0 * c0;
+            const uint64_t p1 = (uint64_t)M1 * c2;
+            const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+            const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+            c1 = (uint32_t)p1;
+            c3 = (uint32_t)p0;
+            c0 = n0;
+            c2 = n2;
+            k0 += W0;
+            k1 += W1;
+        }
+        out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+    }
+};
+
+// Odd 23-bit uniform in (0,1): (2 (r >> 9) + 1) 2^-24 == ((r >> 8) | 1) 2^-24,
+// exact in float32.
+__device__ __forceinline__ float u01(uint32_t r) {
+    return (float)((r >> 8) | 1u) * 0x1.0p-24f;
+}
+
+// Uniforms of one step: head = (u_E1, u_E2, u_acc, u_cat) from block 0;
+// cand[0 .. 4*NB) from blocks 1..NB.
+template <int NB>
+__device__ __forceinline__ void draw_step(uint32_t step, uint32_t chain, uint32_t target,
+                                          uint32_t purpose, uint32_t k0, uint32_t k1,
+                                          float head[4], float cand[4 * NB]) {
+    uint32_t r[4];
+    Philox::block(step, chain, target, purpose << 16, k0, k1, r);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) head[i] = u01(r[i]);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        Philox::block(step, chain, target, (purpose << 16) | (uint32_t)(b + 1), k0, k1, r);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cand[4 * b + i] = u01(r[i]);
+    }
+}
+
+// Box-Muller on consecutive candidate pairs: z_{2m} = rho cos(2 pi u_{2m+1}),
+// z_{2m+1} = rho sin(2 pi u_{2m+1}), rho = sqrt(-2 ln u_{2m}).  The hardware
+// sine/cosine take their argument in revolutions.
+template <int D, int NC>
+__device__ __forceinline__ void box_muller(const float cand[NC], float z[D]) {
+#pragma unroll
+    for (int m = 0; 2 * m < D; ++m) {
+        const float rho = sqrtf(-2.0f * logf(cand[2 * m]));
+        const float ang = cand[2 * m + 1];
+        z[2 * m] = rho * __builtin_amdgcn_cosf(ang);
+        if (2 * m + 1 < D) z[2 * m + 1] = rho * __builtin_amdgcn_sinf(ang);
+    }
+}
+
+// e^x through the hardware base-2 exponential; used for mixture weights
+// relative to a running maximum, where the argument is <= 0.
+__device__ __forceinline__ float exp_rel(float x) {
+    return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+}
+
+template <int D>
+__device__ __forceinline__ bool in_unit_box(const float y[D]) {
+    bool in = true;
+#pragma unroll
+    for (int i = 0; i < D; ++i) in = in && (y[i] >= 0.0f) && (y[i] <= 1.0f);
+    return in;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+}  // namespace restore

@@ -1,0 +1,493 @@
+// Host runtime of the C ABI declared in include/restore.h: descriptor
+// validation, float64 parameter factorisation and float32 packing, the
+// structure-of-arrays layout of the caller's state buffer, kernel launches
+// and the float64 estimates with their delta-method standard errors.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/restore.h"
+#include "launch.h"
+#include "restore_internal.h"
+
+using namespace restore;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+restore_status fail(restore_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+restore_status hip_fail(hipError_t e, const char *what) {
+    return fail(RESTORE_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int RED_BLOCKS = 1024;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t x, logp, logu, grad, a_cur, t_cur, last_dt, a_done, t_done, n_done, status;
+    size_t list0, list1, counts, counters, params, partials, results, total;
+};
+
+int n_param_floats(int tgt, int d, int K) {
+    if (tgt == TGT_PSS) return PSS_SLAB;
+    return comp_stride(tgt, d) * K;
+}
+
+Layout make_layout(int64_t C, int d, bool mala, int n_params) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    const size_t c = (size_t)C;
+    L.x = take(4 * c * d);
+    L.logp = take(4 * c);
+    L.logu = take(4 * c);
+    L.grad = mala ? take(4 * c * d) : (size_t)-1;
+    L.a_cur = take(4 * c);
+    L.t_cur = take(4 * c);
+    L.last_dt = take(4 * c);
+    L.a_done = take(8 * c);
+    L.t_done = take(8 * c);
+    L.n_done = take(4 * c);
+    L.status = take(4 * c);
+    L.list0 = take(4 * c);
+    L.list1 = take(4 * c);
+    L.counts = take(4 * 4);
+    L.counters = take(8 * CNT_SLOTS);
+    L.params = take(4 * (size_t)n_params);
+    L.partials = take(8 * (size_t)RED_BLOCKS * RED_SLOTS);
+    L.results = take(8 * RED_SLOTS);
+    L.total = o;
+    return L;
+}
+
+struct Validated {
+    int tgt, d, K, loc, mu;
+};
+
+bool all_finite(const double *p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+restore_status validate(const restore_target *t, const restore_mu *mu, const restore_local_kernel *lk,
+                        const restore_config *cfg, Validated *v) {
+    if (!t || !mu || !lk || !cfg) return fail(RESTORE_E_INVALID_ARG, "null descriptor");
+    if (t->kind != RESTORE_TARGET_GMM_ISO && t->kind != RESTORE_TARGET_GMM_FULL && t->kind != RESTORE_TARGET_PSS)
+        return fail(RESTORE_E_INVALID_ARG, "unknown target kind %d", t->kind);
+    if (t->dim < 1 || t->dim > RESTORE_MAX_DIM)
+        return fail(RESTORE_E_INVALID_ARG, "dim %d outside 1..%d", t->dim, RESTORE_MAX_DIM);
+    const int d = t->dim, K = t->n_comp;
+    int64_t need = 0;
+    if (t->kind == RESTORE_TARGET_PSS) {
+        if (d != 12) return fail(RESTORE_E_INVALID_ARG, "the PSS target has dim 12");
+        need = 16 + 8 + 8 + 48 + 8 + 8 + 9 + 3 + 3 + 1;
+    } else {
+        if (K < 1 || K > RESTORE_MAX_COMP)
+            return fail(RESTORE_E_INVALID_ARG, "n_comp %d outside 1..%d", K, RESTORE_MAX_COMP);
+        need = t->kind == RESTORE_TARGET_GMM_ISO ? (int64_t)K * (2 + d) : (int64_t)K * (1 + d + d * d);
+    }
+    if (!t->params) return fail(RESTORE_E_INVALID_ARG, "null target params");
+    if (t->params_count != need)
+        return fail(RESTORE_E_INVALID_ARG, "target params: %lld doubles given, %lld expected",
+                    (long long)t->params_count, (long long)need);
+    if (!all_finite(t->params, need)) return fail(RESTORE_E_NONFINITE, "non-finite target parameter");
+    if (mu->kind != RESTORE_MU_UNIFORM_BOX && mu->kind != RESTORE_MU_GMM_DIAG)
+        return fail(RESTORE_E_INVALID_ARG, "unknown mu kind %d", mu->kind);
+    if (mu->kind == RESTORE_MU_GMM_DIAG) {
+        if (mu->n_comp < 1 || mu->n_comp > RESTORE_MAX_COMP || !mu->params_dev)
+            return fail(RESTORE_E_INVALID_ARG, "GMM_DIAG mu needs 1..%d components and device params",
+                        RESTORE_MAX_COMP);
+        if (!(mu->beta >= 0.0f && mu->beta <= 1.0f)) return fail(RESTORE_E_INVALID_ARG, "mu beta outside [0,1]");
+    }
+    if (lk->kind != RESTORE_LOCAL_RWMH && lk->kind != RESTORE_LOCAL_MALA)
+        return fail(RESTORE_E_INVALID_ARG, "unknown local kernel %d", lk->kind);
+    if (!std::isfinite(lk->step) || lk->step < 0.0f) return fail(RESTORE_E_INVALID_ARG, "step must be >= 0");
+    if (lk->kind == RESTORE_LOCAL_MALA && !(lk->step > 0.0f))
+        return fail(RESTORE_E_INVALID_ARG, "MALA needs step > 0");
+    if (!(lk->large_step_prob >= 0.0f && lk->large_step_prob <= 1.0f))
+        return fail(RESTORE_E_INVALID_ARG, "large_step_prob outside [0,1]");
+    if (lk->large_step_prob != 0.0f)
+        return fail(RESTORE_E_UNSUPPORTED, "restore runs the small-step chain M^0: large_step_prob must be 0");
+    if (cfg->n_chains < 1 || cfg->n_chains > 0x7fffffffLL)
+        return fail(RESTORE_E_INVALID_ARG, "n_chains %lld outside 1..2^31-1", (long long)cfg->n_chains);
+    if (!std::isfinite(cfg->c_tilde) || cfg->c_tilde < 0.0) return fail(RESTORE_E_INVALID_ARG, "c_tilde must be >= 0");
+    if (cfg->drain_cap < 0) return fail(RESTORE_E_INVALID_ARG, "drain_cap must be >= 0");
+    if (cfg->block_size != 0 && (cfg->block_size < 64 || cfg->block_size > 256 || cfg->block_size % 64))
+        return fail(RESTORE_E_INVALID_ARG, "block_size must be a multiple of 64 in 64..256");
+    if (cfg->integrands & RESTORE_INTEGRAND_PIXEL) {
+        if (cfg->image_w < 1 || cfg->image_h < 1) return fail(RESTORE_E_INVALID_ARG, "image size must be >= 1");
+        if (d < 2) return fail(RESTORE_E_INVALID_ARG, "pixel integrand needs dim >= 2");
+    }
+    v->tgt = t->kind == RESTORE_TARGET_GMM_ISO ? TGT_ISO : t->kind == RESTORE_TARGET_GMM_FULL ? TGT_FULL : TGT_PSS;
+    v->d = d;
+    v->K = t->kind == RESTORE_TARGET_PSS ? 0 : K;
+    v->loc = lk->kind == RESTORE_LOCAL_MALA ? LOC_MALA : LOC_RWMH;
+    v->mu = mu->kind == RESTORE_MU_GMM_DIAG ? MU_GMM : MU_UNIFORM;
+    return RESTORE_OK;
+}
+
+// Float64 factorisation of the canonical parameters into the float32 slab.
+restore_status pack_params(const restore_target *t, const Validated &v, std::vector<float> *out) {
+    const int d = v.d, K = v.K;
+    const double *p = t->params;
+    const double LN2PI = std::log(2.0 * M_PI);
+    if (v.tgt == TGT_ISO) {
+        const int S = comp_stride(TGT_ISO, d);
+        out->assign((size_t)S * K, 0.0f);
+        const double *w = p, *m = p + K, *s = p + K + (size_t)K * d;
+        for (int k = 0; k < K; ++k) {
+            if (!(w[k] >= 0.0) || !(s[k] > 0.0)) return fail(RESTORE_E_INVALID_ARG, "weights >= 0, sigmas > 0");
+            float *o = out->data() + (size_t)k * S;
+            o[0] = (float)(std::log(w[k]) - 0.5 * d * (LN2PI + 2.0 * std::log(s[k])));
+            for (int i = 0; i < d; ++i) o[1 + i] = (float)m[(size_t)k * d + i];
+            o[1 + d] = (float)(1.0 / (s[k] * s[k]));
+        }
+        return RESTORE_OK;
+    }
+    if (v.tgt == TGT_FULL) {
+        const int S = comp_stride(TGT_FULL, d);
+        out->assign((size_t)S * K, 0.0f);
+        const double *w = p, *m = p + K, *cov = p + K + (size_t)K * d;
+        std::vector<double> L((size_t)d * d), W((size_t)d * d);
+        for (int k = 0; k < K; ++k) {
+            if (!(w[k] >= 0.0)) return fail(RESTORE_E_INVALID_ARG, "mixture weights must be >= 0");
+            const double *A = cov + (size_t)k * d * d;
+            // Cholesky A = L L^T
+            std::fill(L.begin(), L.end(), 0.0);
+            double logdiag = 0.0;
+            for (int j = 0; j < d; ++j) {
+                double s = A[j * d + j];
+                for (int q = 0; q < j; ++q) s -= L[j * d + q] * L[j * d + q];
+                if (!(s > 0.0)) return fail(RESTORE_E_INVALID_ARG, "covariance %d is not positive definite", k);
+                L[j * d + j] = std::sqrt(s);
+                logdiag += std::log(L[j * d + j]);
+                for (int i = j + 1; i < d; ++i) {
+                    double r = A[i * d + j];
+                    for (int q = 0; q < j; ++q) r -= L[i * d + q] * L[j * d + q];
+                    L[i * d + j] = r / L[j * d + j];
+                }
+            }
+            // W = L^-1 (lower triangular), column by column
+            std::fill(W.begin(), W.end(), 0.0);
+            for (int c = 0; c < d; ++c) {
+                for (int i = c; i < d; ++i) {
+                    double r = (i == c) ? 1.0 : 0.0;
+                    for (int q = c; q < i; ++q) r -= L[i * d + q] * W[q * d + c];
+                    W[i * d + c] = r / L[i * d + i];
+                }
+            }
+            float *o = out->data() + (size_t)k * S;
+            o[0] = (float)(std::log(w[k]) - 0.5 * d * LN2PI - logdiag);
+            for (int i = 0; i < d; ++i) o[1 + i] = (float)m[(size_t)k * d + i];
+            int at = 1 + d;
+            for (int i = 0; i < d; ++i)
+                for (int j = 0; j <= i; ++j) o[at++] = (float)W[i * d + j];
+        }
+        return RESTORE_OK;
+    }
+    return fail(RESTORE_E_UNSUPPORTED, "target kind not built yet");
+}
+
+}  // namespace
+
+struct restore_ctx {
+    Validated v{};
+    restore_config cfg{};
+    KernelSet ks{};
+    Layout lay{};
+    char *base = nullptr;
+    int n_params = 0;
+    int block = 256;
+    bool lds = false;
+    bool drained = false;
+    int32_t steps_taken = 0;
+    float step = 0.0f;
+    float *image = nullptr;
+    restore_mu mu{};
+    StepArgs args{};
+};
+
+namespace {
+
+template <typename T>
+T *at(restore_ctx *c, size_t off) {
+    return off == (size_t)-1 ? nullptr : reinterpret_cast<T *>(c->base + off);
+}
+
+void fill_args(restore_ctx *c) {
+    StepArgs &a = c->args;
+    a.x = at<float>(c, c->lay.x);
+    a.logp = at<float>(c, c->lay.logp);
+    a.logu = at<float>(c, c->lay.logu);
+    a.grad = at<float>(c, c->lay.grad);
+    a.a_cur = at<float>(c, c->lay.a_cur);
+    a.t_cur = at<float>(c, c->lay.t_cur);
+    a.last_dt = at<float>(c, c->lay.last_dt);
+    a.a_done = at<double>(c, c->lay.a_done);
+    a.t_done = at<double>(c, c->lay.t_done);
+    a.n_done = at<uint32_t>(c, c->lay.n_done);
+    a.status = at<uint32_t>(c, c->lay.status);
+    a.counters = at<unsigned long long>(c, c->lay.counters);
+    a.params = at<float>(c, c->lay.params);
+    a.mu_params = c->mu.params_dev;
+    a.image = c->image;
+    a.list = nullptr;
+    a.list_count = nullptr;
+    a.n_chains = c->cfg.n_chains;
+    a.n_comp = c->v.K;
+    a.mu_comp = c->mu.n_comp;
+    a.mu_beta = c->mu.beta;
+    a.no_kill = c->cfg.c_tilde == 0.0 ? 1 : 0;
+    a.log_c = c->cfg.c_tilde > 0.0 ? (float)std::log(c->cfg.c_tilde) : 0.0f;
+    a.step = c->step;
+    a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->cfg.seed >> 32);
+    a.target_id = (uint32_t)c->cfg.target_id;
+    a.s0 = 0;
+    a.n_steps = 0;
+    a.integrand_p = (c->cfg.integrands & RESTORE_INTEGRAND_P) ? 1 : 0;
+    a.image_w = c->cfg.image_w;
+    a.image_h = c->cfg.image_h;
+}
+
+dim3 grid_for(int64_t n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
+
+__global__ void zero_u32_kernel(uint32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *restore_last_error(void) { return g_last_error.c_str(); }
+
+restore_status restore_state_bytes(const restore_target *target, const restore_mu *mu,
+                                   const restore_local_kernel *local, const restore_config *cfg,
+                                   size_t *bytes_out) {
+    if (!bytes_out) return fail(RESTORE_E_INVALID_ARG, "null bytes_out");
+    Validated v;
+    restore_status st = validate(target, mu, local, cfg, &v);
+    if (st != RESTORE_OK) return st;
+    *bytes_out = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_param_floats(v.tgt, v.d, v.K)).total;
+    return RESTORE_OK;
+}
+
+restore_status restore_init(restore_ctx **out, const restore_target *target, const restore_mu *mu,
+                            const restore_local_kernel *local, const restore_config *cfg, void *state_dev,
+                            size_t state_bytes, float *image_dev, void *stream) {
+    if (!out) return fail(RESTORE_E_INVALID_ARG, "null out");
+    *out = nullptr;
+    Validated v;
+    restore_status st = validate(target, mu, local, cfg, &v);
+    if (st != RESTORE_OK) return st;
+    if (!state_dev) return fail(RESTORE_E_INVALID_ARG, "null state buffer");
+    if (reinterpret_cast<uintptr_t>(state_dev) % ALIGN)
+        return fail(RESTORE_E_INVALID_ARG, "state buffer must be 256-byte aligned");
+    if ((cfg->integrands & RESTORE_INTEGRAND_PIXEL) && !image_dev)
+        return fail(RESTORE_E_INVALID_ARG, "pixel integrand needs an image buffer");
+    const int n_params = n_param_floats(v.tgt, v.d, v.K);
+    const Layout lay = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_params);
+    if (state_bytes < lay.total)
+        return fail(RESTORE_E_BUFFER_TOO_SMALL, "state buffer holds %zu bytes, %zu needed", state_bytes, lay.total);
+    KernelSet ks = find_kernels(v.tgt, v.d, v.loc, v.mu);
+    if (!ks.step) return fail(RESTORE_E_UNSUPPORTED, "no kernels built for target %d, dim %d, local %d, mu %d",
+                              v.tgt, v.d, v.loc, v.mu);
+    std::vector<float> slab;
+    st = pack_params(target, v, &slab);
+    if (st != RESTORE_OK) return st;
+
+    restore_ctx *c = new (std::nothrow) restore_ctx();
+    if (!c) return fail(RESTORE_E_INVALID_ARG, "out of host memory");
+    c->v = v;
+    c->cfg = *cfg;
+    c->ks = ks;
+    c->lay = lay;
+    c->base = static_cast<char *>(state_dev);
+    c->n_params = n_params;
+    c->block = cfg->block_size ? cfg->block_size : 256;
+    c->lds = (cfg->flags & RESTORE_FLAG_PARAMS_LDS) != 0;
+    c->step = local->step;
+    c->image = (cfg->integrands & RESTORE_INTEGRAND_PIXEL) ? image_dev : nullptr;
+    c->mu = *mu;
+    fill_args(c);
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(const_cast<float *>(c->args.params), slab.data(), slab.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "parameter upload"); }
+    // the upload reads a host vector that goes away: finish it before returning
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "parameter upload"); }
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, c->args.counters, (int)CNT_SLOTS);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, at<uint32_t>(c, c->lay.counts), 4);
+    StepArgs a = c->args;
+    void *kargs[] = {&a};
+    e = hipLaunchKernel(ks.init, grid_for(cfg->n_chains, 256), dim3(256), kargs, 0, s);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "init launch"); }
+    *out = c;
+    return RESTORE_OK;
+}
+
+restore_status restore_step(restore_ctx *c, int32_t n_steps, void *stream) {
+    if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
+    if (c->drained) return fail(RESTORE_E_BAD_STATE, "restore_step after restore_drain");
+    if (n_steps < 0) return fail(RESTORE_E_INVALID_ARG, "n_steps must be >= 0");
+    if ((int64_t)c->steps_taken + n_steps > 0x7fffffffLL - c->cfg.drain_cap)
+        return fail(RESTORE_E_INVALID_ARG, "step counter would overflow");
+    if (n_steps == 0) return RESTORE_OK;
+    StepArgs a = c->args;
+    a.s0 = (uint32_t)c->steps_taken;
+    a.n_steps = n_steps;
+    int np = c->n_params;
+    void *kargs[] = {&a, &np};
+    const void *fn = c->lds ? c->ks.step_lds : c->ks.step;
+    const size_t shm = c->lds ? (size_t)c->n_params * sizeof(float) : 0;
+    hipError_t e = hipLaunchKernel(fn, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, shm,
+                                   static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    c->steps_taken += n_steps;
+    return RESTORE_OK;
+}
+
+restore_status restore_drain(restore_ctx *c, void *stream) {
+    if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
+    if (c->drained) return fail(RESTORE_E_BAD_STATE, "restore_drain called twice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *counts = at<uint32_t>(c, c->lay.counts);
+    uint32_t *lists[2] = {at<uint32_t>(c, c->lay.list0), at<uint32_t>(c, c->lay.list1)};
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, counts, 4);
+    const void *fn = c->lds ? c->ks.drain_lds : c->ks.drain;
+    const size_t shm = c->lds ? (size_t)c->n_params * sizeof(float) : 0;
+    int32_t remaining = c->cfg.drain_cap;
+    int32_t chunk = 1;
+    uint32_t s0 = (uint32_t)c->steps_taken;
+    for (int j = 0;; ++j) {
+        const int32_t L = remaining < chunk ? remaining : chunk;
+        const int last = (remaining - L) == 0 ? 1 : 0;
+        StepArgs a = c->args;
+        a.list = j == 0 ? nullptr : lists[(j - 1) % 2];
+        a.list_count = j == 0 ? nullptr : counts + (j % 3);
+        a.s0 = s0;
+        a.n_steps = L;
+        int np = c->n_params;
+        uint32_t *list_out = lists[j % 2];
+        uint32_t *count_out = counts + ((j + 1) % 3);
+        uint32_t *count_zero = counts + ((j + 2) % 3);
+        void *kargs[] = {&a, &np, &list_out, &count_out, &count_zero, (void *)&last};
+        hipError_t e = hipLaunchKernel(fn, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, shm, s);
+        if (e != hipSuccess) return hip_fail(e, "drain launch");
+        s0 += (uint32_t)L;
+        remaining -= L;
+        if (last) break;
+        chunk = chunk < 128 ? chunk * 2 : 128;
+    }
+    c->drained = true;
+    return RESTORE_OK;
+}
+
+restore_status restore_estimate(restore_ctx *c, restore_estimate_out *out, void *stream) {
+    if (!c || !out) return fail(RESTORE_E_INVALID_ARG, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ReduceArgs r;
+    r.a_done = c->args.a_done;
+    r.t_done = c->args.t_done;
+    r.n_done = c->args.n_done;
+    r.status = c->args.status;
+    r.t_cur = c->args.t_cur;
+    r.n_chains = c->cfg.n_chains;
+    r.partials = at<double>(c, c->lay.partials);
+    r.results = at<double>(c, c->lay.results);
+    const int64_t want = (c->cfg.n_chains + 255) / 256;
+    r.n_blocks = (int32_t)(want < RED_BLOCKS ? want : RED_BLOCKS);
+    hipError_t e = launch_reduce(r, s);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    double res[RED_SLOTS];
+    unsigned long long cnt[CNT_SLOTS];
+    e = hipMemcpyAsync(res, r.results, sizeof(res), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt, c->args.counters, sizeof(cnt), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "estimate readback");
+
+    const double N = res[RED_N], T = res[RED_T], A = res[RED_A];
+    const double n_ok = (double)c->cfg.n_chains - res[RED_NONFINITE];
+    const double ct = c->cfg.c_tilde;
+    auto se = [&](double ss, double den_sum) -> double {
+        if (n_ok < 2 || den_sum <= 0) return NAN;
+        const double mean = den_sum / n_ok;
+        return std::sqrt(ss / ((n_ok - 1) * n_ok)) / mean;
+    };
+    std::memset(out, 0, sizeof(*out));
+    out->p_lambda = N > 0 ? ct * T / N : NAN;
+    out->p_lambda_se = ct * se(res[RED_SS_T_N], N);
+    out->lam_pf = N > 0 ? ct * A / N : NAN;
+    out->lam_pf_se = ct * se(res[RED_SS_A_N], N);
+    out->pi_f = T > 0 ? A / T : NAN;
+    out->pi_f_se = se(res[RED_SS_A_T], T);
+    out->tours_done = (int64_t)N;
+    out->tours_censored = (int64_t)res[RED_CENS];
+    out->transitions = (int64_t)cnt[CNT_TRANSITIONS];
+    out->accepts = (int64_t)cnt[CNT_ACCEPTS];
+    out->kills = (int64_t)cnt[CNT_KILLS];
+    out->nonfinite = (int64_t)res[RED_NONFINITE];
+    const double tot_t = T + res[RED_CENS_T];
+    out->censored_time_frac = tot_t > 0 ? res[RED_CENS_T] / tot_t : 0.0;
+    out->accept_rate = cnt[CNT_TRANSITIONS] ? (double)cnt[CNT_ACCEPTS] / (double)cnt[CNT_TRANSITIONS] : 0.0;
+    out->kill_rate = cnt[CNT_TRANSITIONS] ? (double)cnt[CNT_KILLS] / (double)cnt[CNT_TRANSITIONS] : 0.0;
+    out->image_scale = N > 0 ? ct / N : 0.0;
+    return RESTORE_OK;
+}
+
+restore_status restore_get_state_view(const restore_ctx *c, restore_state_view *v) {
+    if (!c || !v) return fail(RESTORE_E_INVALID_ARG, "null argument");
+    const StepArgs &a = c->args;
+    v->x = a.x; v->logp = a.logp; v->logu = a.logu; v->grad = a.grad;
+    v->a_cur = a.a_cur; v->t_cur = a.t_cur; v->last_dt = a.last_dt;
+    v->a_done = a.a_done; v->t_done = a.t_done; v->n_done = a.n_done; v->status = a.status;
+    v->n_chains = c->cfg.n_chains;
+    v->dim = c->v.d;
+    v->steps_taken = c->steps_taken;
+    return RESTORE_OK;
+}
+
+restore_status restore_refresh_cache(restore_ctx *c, void *stream) {
+    if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
+    StepArgs a = c->args;
+    void *kargs[] = {&a};
+    hipError_t e = hipLaunchKernel(c->ks.refresh, grid_for(c->cfg.n_chains, 256), dim3(256), kargs, 0,
+                                   static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "refresh launch");
+    return RESTORE_OK;
+}
+
+restore_status restore_destroy(restore_ctx *c) {
+    delete c;
+    return RESTORE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal structures shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace restore {
+
+enum TargetKind : int { TGT_ISO = 0, TGT_FULL = 1, TGT_PSS = 2 };
+enum LocalKind : int { LOC_RWMH = 0, LOC_MALA = 1 };
+enum MuKind : int { MU_UNIFORM = 0, MU_GMM = 1 };
+enum Purpose : uint32_t { PURPOSE_INIT = 0, PURPOSE_STEP = 1 };
+
+enum StatusBits : uint32_t {
+    ST_ALIVE = 1u,       // tour in flight
+    ST_CENSORED = 2u,    // tour still alive at the drain cap
+    ST_LAST_KILL = 4u,   // last executed step was a termination
+    ST_LAST_ACCEPT = 8u, // last executed step accepted a local move
+};
+
+enum CounterSlot : int { CNT_TRANSITIONS = 0, CNT_ACCEPTS = 1, CNT_KILLS = 2, CNT_SLOTS = 8 };
+
+// Number of float32 values per mixture component in the packed slab.
+//   ISO : [ c_k | m_k (d) | 1/s_k^2 ]                    c_k = ln w_k - d/2 ln(2 pi s_k^2)
+//   FULL: [ c_k | m_k (d) | W_k lower-tri rows (d(d+1)/2) ] W_k = L_k^-1, S_k = L_k L_k^T,
+//                                                         c_k = ln w_k - d/2 ln 2pi - sum ln L_k,ii
+// rounded up to a multiple of 4 floats.
+__host__ __device__ constexpr int comp_stride(int kind, int d) {
+    return kind == TGT_ISO ? ((2 + d + 3) / 4) * 4 : ((1 + d + d * (d + 1) / 2 + 3) / 4) * 4;
+}
+
+// Rendering-shaped integrand slab (float32):
+//   [0,16)  texture A frequencies (8 x 2)      [16,24) amplitudes / 8   [24,32) phases / (2 pi)
+//   [32,80) texture B frequencies (8 x 6)      [80,88) amplitudes / 8   [88,96) phases / (2 pi)
+//   [96,105) lobe directions (3 x 3)           [105,108) kappa          [108,111) log of
+//   4 pi w_l kappa_l / (2 pi (1 - e^{-2 kappa_l}))                      [111] b
+constexpr int PSS_SLAB = 112;
+
+// Per-launch arguments of the step kernels.
+struct StepArgs {
+    // chain state (structure of arrays, C chains)
+    float *x;          // [D][C]
+    float *logp;       // [C]
+    float *logu;       // [C]
+    float *grad;       // [D][C] (MALA)
+    float *a_cur;      // [C]
+    float *t_cur;      // [C]
+    float *last_dt;    // [C]
+    double *a_done;    // [C]
+    double *t_done;    // [C]
+    uint32_t *n_done;  // [C]
+    uint32_t *status;  // [C]
+    unsigned long long *counters;  // [CNT_SLOTS]
+    const float *params;           // packed target slab
+    const float *mu_params;        // learned mu (device, caller-owned)
+    float *image;                  // pixel splats or nullptr
+    const uint32_t *list;          // drain: chains to run, or nullptr (all)
+    const uint32_t *list_count;    // drain: number of entries in list
+    int64_t n_chains;
+    int32_t n_comp;
+    int32_t mu_comp;
+    float mu_beta;
+    float log_c;       // ln c_tilde
+    int32_t no_kill;   // c_tilde == 0
+    float step;        // sigma or epsilon
+    uint32_t key0, key1;
+    uint32_t target_id;
+    uint32_t s0;       // first step index of this launch
+    int32_t n_steps;   // steps in this launch
+    int32_t integrand_p;
+    int32_t image_w, image_h;
+};
+
+}  // namespace restore

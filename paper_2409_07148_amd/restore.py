@@ -1,0 +1,316 @@
+"""Thin ctypes binding of the C ABI in include/restore.h.
+
+The functions here carry the C names and only marshal arguments: every step
+of the chains runs in the gfx950 kernels of ``librestore.so``.  PyTorch
+provides device memory (the caller-owned state buffer and image) and the
+stream.  There is no CPU fallback: if the library is missing, importing
+this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librestore.so")
+
+OK, E_INVALID_ARG, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_BAD_STATE, E_BUFFER_TOO_SMALL = 0, -1, -2, -3, -4, -5, -6
+TARGET_GMM_ISO, TARGET_GMM_FULL, TARGET_PSS = 0, 1, 2
+MU_UNIFORM_BOX, MU_GMM_DIAG = 0, 1
+LOCAL_RWMH, LOCAL_MALA = 0, 1
+INTEGRAND_ONE, INTEGRAND_P, INTEGRAND_PIXEL = 1, 2, 4
+FLAG_PARAMS_LDS = 1
+ST_ALIVE, ST_CENSORED, ST_LAST_KILL, ST_LAST_ACCEPT = 1, 2, 4, 8
+
+
+class RestoreError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"restore status {status}: {msg}")
+        self.status = status
+
+
+class restore_target(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("n_comp", C.c_int32), ("reserved", C.c_int32),
+                ("params", C.POINTER(C.c_double)), ("params_count", C.c_int64)]
+
+
+class restore_mu(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_comp", C.c_int32), ("beta", C.c_float), ("reserved", C.c_int32),
+                ("params_dev", C.c_void_p)]
+
+
+class restore_local_kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("step", C.c_float), ("large_step_prob", C.c_float),
+                ("reserved", C.c_int32)]
+
+
+class restore_config(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("n_chains", C.c_int64), ("target_id", C.c_int32),
+                ("integrands", C.c_int32), ("c_tilde", C.c_double), ("drain_cap", C.c_int32),
+                ("image_w", C.c_int32), ("image_h", C.c_int32), ("flags", C.c_int32),
+                ("block_size", C.c_int32), ("reserved", C.c_int32)]
+
+
+class restore_estimate_out(C.Structure):
+    _fields_ = [("p_lambda", C.c_double), ("p_lambda_se", C.c_double), ("lam_pf", C.c_double),
+                ("lam_pf_se", C.c_double), ("pi_f", C.c_double), ("pi_f_se", C.c_double),
+                ("tours_done", C.c_int64), ("tours_censored", C.c_int64), ("transitions", C.c_int64),
+                ("accepts", C.c_int64), ("kills", C.c_int64), ("nonfinite", C.c_int64),
+                ("censored_time_frac", C.c_double), ("accept_rate", C.c_double),
+                ("kill_rate", C.c_double), ("image_scale", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class restore_state_view(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("logp", C.c_void_p), ("logu", C.c_void_p), ("grad", C.c_void_p),
+                ("a_cur", C.c_void_p), ("t_cur", C.c_void_p), ("last_dt", C.c_void_p),
+                ("a_done", C.c_void_p), ("t_done", C.c_void_p), ("n_done", C.c_void_p),
+                ("status", C.c_void_p), ("n_chains", C.c_int64), ("dim", C.c_int32),
+                ("steps_taken", C.c_int32)]
+
+
+EXPORTS = ["restore_state_bytes", "restore_init", "restore_step", "restore_drain", "restore_estimate",
+           "restore_get_state_view", "restore_refresh_cache", "restore_destroy", "restore_last_error"]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(there is no fallback implementation)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    lib.restore_state_bytes.argtypes = [P(restore_target), P(restore_mu), P(restore_local_kernel),
+                                        P(restore_config), P(C.c_size_t)]
+    lib.restore_init.argtypes = [P(C.c_void_p), P(restore_target), P(restore_mu), P(restore_local_kernel),
+                                 P(restore_config), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
+    lib.restore_step.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+    lib.restore_drain.argtypes = [C.c_void_p, C.c_void_p]
+    lib.restore_estimate.argtypes = [C.c_void_p, P(restore_estimate_out), C.c_void_p]
+    lib.restore_get_state_view.argtypes = [C.c_void_p, P(restore_state_view)]
+    lib.restore_refresh_cache.argtypes = [C.c_void_p, C.c_void_p]
+    lib.restore_destroy.argtypes = [C.c_void_p]
+    lib.restore_last_error.restype = C.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(lib, name).restype = C.c_int32
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int) -> None:
+    if status != OK:
+        raise RestoreError(status, _lib.restore_last_error().decode())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+# ---------------------------------------------------------------------------
+# the C functions, one to one
+# ---------------------------------------------------------------------------
+
+def restore_state_bytes(target, mu, local, cfg) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.restore_state_bytes(C.byref(target), C.byref(mu), C.byref(local), C.byref(cfg), C.byref(out)))
+    return out.value
+
+
+def restore_init(target, mu, local, cfg, state_ptr: int, state_bytes: int, image_ptr: int = 0,
+                 stream=None) -> C.c_void_p:
+    ctx = C.c_void_p()
+    _check(_lib.restore_init(C.byref(ctx), C.byref(target), C.byref(mu), C.byref(local), C.byref(cfg),
+                             C.c_void_p(state_ptr), state_bytes, C.c_void_p(image_ptr or None),
+                             C.c_void_p(_stream(stream))))
+    return ctx
+
+
+def restore_step(ctx, n_steps: int, stream=None) -> None:
+    _check(_lib.restore_step(ctx, int(n_steps), C.c_void_p(_stream(stream))))
+
+
+def restore_drain(ctx, stream=None) -> None:
+    _check(_lib.restore_drain(ctx, C.c_void_p(_stream(stream))))
+
+
+def restore_estimate(ctx, stream=None) -> restore_estimate_out:
+    out = restore_estimate_out()
+    _check(_lib.restore_estimate(ctx, C.byref(out), C.c_void_p(_stream(stream))))
+    return out
+
+
+def restore_get_state_view(ctx) -> restore_state_view:
+    v = restore_state_view()
+    _check(_lib.restore_get_state_view(ctx, C.byref(v)))
+    return v
+
+
+def restore_refresh_cache(ctx, stream=None) -> None:
+    _check(_lib.restore_refresh_cache(ctx, C.c_void_p(_stream(stream))))
+
+
+def restore_destroy(ctx) -> None:
+    _check(_lib.restore_destroy(ctx))
+
+
+def restore_last_error() -> str:
+    return _lib.restore_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# descriptors from canonical parameters
+# ---------------------------------------------------------------------------
+
+def target_params(kind: str, d: int, K: int, params: dict) -> np.ndarray:
+    """Flatten canonical float64 parameters into the layout restore_target
+    documents for each target kind."""
+    if kind == "gmm_iso":
+        parts = [params["weights"], params["means"], params["sigmas"]]
+    elif kind == "gmm_full":
+        parts = [params["weights"], params["means"], params["covs"]]
+    elif kind == "pss":
+        parts = [params[k] for k in ("tex_a_freq", "tex_a_amp", "tex_a_phase", "tex_b_freq", "tex_b_amp",
+                                     "tex_b_phase", "lobe_dirs", "lobe_kappa", "lobe_weights", "base")]
+    else:
+        raise ValueError(kind)
+    return np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.float64).ravel() for p in parts]))
+
+
+_KIND = {"gmm_iso": TARGET_GMM_ISO, "gmm_full": TARGET_GMM_FULL, "pss": TARGET_PSS}
+
+
+@dataclass
+class Problem:
+    """Descriptors of one run, built from canonical parameters.  Holds the
+    host parameter array for as long as the descriptors point at it."""
+    target: restore_target
+    mu: restore_mu
+    local: restore_local_kernel
+    cfg: restore_config
+    _params: np.ndarray
+    _mu_params: Optional[torch.Tensor] = None
+
+
+def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: float, n_chains: int,
+                 c_tilde: float, seed: int, drain_cap: int, target_id: int = 0, integrand_p: bool = True,
+                 image: Optional[tuple] = None, lds: bool = False, block_size: int = 0,
+                 mu: Optional[dict] = None) -> Problem:
+    flat = target_params(kind, d, K, params)
+    t = restore_target(_KIND[kind], d, K if kind != "pss" else 0, 0,
+                       flat.ctypes.data_as(C.POINTER(C.c_double)), flat.size)
+    mu_t = None
+    if mu is None:
+        m = restore_mu(MU_UNIFORM_BOX, 0, 0.0, 0, None)
+    else:
+        mu_t = torch.cat([torch.as_tensor(np.asarray(mu[k], dtype=np.float32).ravel())
+                          for k in ("logits", "means", "log_std")]).cuda()
+        m = restore_mu(MU_GMM_DIAG, int(np.asarray(mu["logits"]).size), float(mu["beta"]), 0, mu_t.data_ptr())
+    lk = restore_local_kernel(LOCAL_MALA if local == "mala" else LOCAL_RWMH, float(step), 0.0, 0)
+    integrands = INTEGRAND_ONE | (INTEGRAND_P if integrand_p else 0) | (INTEGRAND_PIXEL if image else 0)
+    w, h = (image or (0, 0))
+    cfg = restore_config(int(seed), int(n_chains), int(target_id), integrands, float(c_tilde), int(drain_cap),
+                         int(w), int(h), FLAG_PARAMS_LDS if lds else 0, int(block_size), 0)
+    return Problem(t, m, lk, cfg, flat, mu_t)
+
+
+def problem_from_workload(wl, **overrides) -> Problem:
+    """Descriptors for an object with the attributes of a synthetic workload
+    (target, d, K, params, local, step, n_chains, c_tilde, seed, drain_cap,
+    image)."""
+    kw = dict(local=wl.local, step=wl.step, n_chains=wl.n_chains, c_tilde=wl.c_tilde, seed=wl.seed,
+              drain_cap=wl.drain_cap, image=getattr(wl, "image", None))
+    kw.update(overrides)
+    return make_problem(wl.target, wl.d, wl.K, wl.params, **kw)
+
+
+class Run:
+    """A chain population on the current GPU: owns the torch state buffer
+    (and image) and the library context."""
+
+    def __init__(self, prob: Problem, stream=None):
+        self.prob = prob
+        self.stream = stream
+        nbytes = restore_state_bytes(prob.target, prob.mu, prob.local, prob.cfg)
+        self.state = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.state.data_ptr()
+        self._state_ptr = (base + 255) // 256 * 256
+        self.nbytes = nbytes
+        self.image = None
+        if prob.cfg.integrands & INTEGRAND_PIXEL:
+            self.image = torch.zeros((prob.cfg.image_h, prob.cfg.image_w), dtype=torch.float32, device="cuda")
+        self.ctx = restore_init(prob.target, prob.mu, prob.local, prob.cfg, self._state_ptr, nbytes,
+                                self.image.data_ptr() if self.image is not None else 0, stream)
+        self.n_chains = prob.cfg.n_chains
+        self.d = prob.target.dim
+
+    def step(self, n: int):
+        restore_step(self.ctx, n, self.stream)
+
+    def drain(self):
+        restore_drain(self.ctx, self.stream)
+
+    def estimate(self) -> dict:
+        return restore_estimate(self.ctx, self.stream).as_dict()
+
+    def refresh_cache(self):
+        restore_refresh_cache(self.ctx, self.stream)
+
+    # --- views of the state arrays (no copies) -----------------------------
+    def _view(self, ptr: int, shape, dtype) -> torch.Tensor:
+        base = self.state.data_ptr()
+        off = ptr - base
+        nbytes = int(np.prod(shape)) * torch.empty((), dtype=dtype).element_size()
+        return self.state[off:off + nbytes].view(dtype).view(*shape)
+
+    def arrays(self) -> dict:
+        v = restore_get_state_view(self.ctx)
+        C_, d = self.n_chains, self.d
+        out = {
+            "x": self._view(v.x, (d, C_), torch.float32),
+            "logp": self._view(v.logp, (C_,), torch.float32),
+            "logu": self._view(v.logu, (C_,), torch.float32),
+            "a_cur": self._view(v.a_cur, (C_,), torch.float32),
+            "t_cur": self._view(v.t_cur, (C_,), torch.float32),
+            "last_dt": self._view(v.last_dt, (C_,), torch.float32),
+            "a_done": self._view(v.a_done, (C_,), torch.float64),
+            "t_done": self._view(v.t_done, (C_,), torch.float64),
+            "n_done": self._view(v.n_done, (C_,), torch.int32),
+            "status": self._view(v.status, (C_,), torch.int32),
+        }
+        if v.grad:
+            out["grad"] = self._view(v.grad, (d, C_), torch.float32)
+        return out
+
+    def state_region(self) -> torch.Tensor:
+        """The aligned bytes the library owns inside ``state`` (for
+        checkpoints: copy them out, and back into a context that has taken the
+        same number of steps)."""
+        off = self._state_ptr - self.state.data_ptr()
+        return self.state[off:off + self.nbytes]
+
+    @property
+    def steps_taken(self) -> int:
+        return restore_get_state_view(self.ctx).steps_taken
+
+    def close(self):
+        if self.ctx:
+            restore_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

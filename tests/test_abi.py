@@ -1,0 +1,114 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+validates its descriptors on the host -- no GPU compute calls."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(restore_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2409_07148_amd import restore
+    return restore
+
+
+def test_library_exports_every_declared_symbol(R):
+    declared = _declared_functions()
+    assert "restore_init" in declared and "restore_step" in declared and "restore_estimate" in declared
+    out = subprocess.run(["nm", "-D", "--defined-only", R.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (restore_[a-z_0-9]+)$", out, flags=re.M))
+    missing = [n for n in declared if n not in exported]
+    assert not missing, missing
+    for n in declared:
+        assert hasattr(R._lib, n)
+
+
+def test_binding_names_match_header(R):
+    for n in _declared_functions():
+        assert callable(getattr(R, n)), n
+
+
+def _problem(R, **kw):
+    from workloads import gmm_full
+    return R.problem_from_workload(gmm_full(n_chains=1000), **kw)
+
+
+def test_state_bytes_grows_with_chains(R):
+    p1 = _problem(R)
+    b1 = R.restore_state_bytes(p1.target, p1.mu, p1.local, p1.cfg)
+    p2 = _problem(R, n_chains=4000)
+    b2 = R.restore_state_bytes(p2.target, p2.mu, p2.local, p2.cfg)
+    assert b2 > b1 > 0
+    # per chain: x, grad (8 floats each), 2 doubles and 8 further words
+    assert b2 - b1 >= 3000 * (16 * 4 + 16 + 8 * 4)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("c_tilde", -1.0, -1), ("n_chains", 0, -1), ("drain_cap", -3, -1), ("block_size", 96, -1),
+])
+def test_config_validation(R, field, value, status):
+    p = _problem(R)
+    setattr(p.cfg, field, value)
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == status
+    assert R.restore_last_error()
+
+
+def test_target_validation(R):
+    p = _problem(R)
+    p.target.dim = 0
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_INVALID_ARG
+    p = _problem(R)
+    p.target.params_count -= 1
+    with pytest.raises(R.RestoreError):
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    p = _problem(R)
+    p._params[5] = np.nan
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_NONFINITE
+
+
+def test_local_kernel_validation(R):
+    p = _problem(R)
+    p.local.large_step_prob = 0.3
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_UNSUPPORTED
+    p = _problem(R)
+    p.local.step = 0.0   # MALA needs a positive step
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_INVALID_ARG
+
+
+def test_init_rejects_null_and_small_buffers(R):
+    p = _problem(R)
+    n = R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_init(p.target, p.mu, p.local, p.cfg, 0, n, stream=0)
+    assert e.value.status == R.E_INVALID_ARG
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_init(p.target, p.mu, p.local, p.cfg, 256, n - 1, stream=0)
+    assert e.value.status == R.E_BUFFER_TOO_SMALL
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_init(p.target, p.mu, p.local, p.cfg, 256 + 4, n, stream=0)
+    assert e.value.status == R.E_INVALID_ARG

@@ -1,0 +1,343 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Tolerances (derived from float32 arithmetic on states in [0,1]):
+  * regenerated states are the float32 candidate uniforms on both sides:
+    bit-exact;
+  * moved states: |x_gpu - x_oracle| <= 1e-6 max(1, |x|);
+  * unmoved states: bit-exact;
+  * decisions: identical, except near-ties -- a kill decision may differ
+    only where the oracle's |ln t2 - ln t1| < TAU_KILL, an accept decision
+    only where |ln u - ln alpha| < TAU_ACC.  Those margins bound the float32
+    error of the log-densities involved (|log p| <= ~50 with ~1e-6 relative
+    error, plus the rounding of y to float32 times |d ln alpha / dy|).
+  * dt: relative error <= 1e-4 (exp of a float32 log-rate).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TAU_KILL = 1e-4
+TAU_ACC = 2e-4
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2409_07148_amd import restore
+    return restore
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_problem(wl, **kw):
+    from oracle import oracle as O
+    return O.Problem(wl, **kw)
+
+
+def _single_step_check(R, wl, x_init=None, warm=3, c_tilde=None, label=""):
+    """Run `warm` steps (or load x_init), snapshot, take one more step on the
+    GPU and compare each chain's transition with the oracle's."""
+    import torch
+    from oracle import oracle as O
+    ct = wl.c_tilde if c_tilde is None else c_tilde
+    run = R.Run(R.problem_from_workload(wl, c_tilde=ct))
+    arr = run.arrays()
+    if x_init is not None:
+        arr["x"].copy_(torch.from_numpy(np.ascontiguousarray(x_init.T.astype(np.float32))).cuda())
+        run.refresh_cache()
+    else:
+        run.step(warm)
+    _sync()
+    x0 = arr["x"].cpu().numpy().T.astype(np.float64).copy()
+    s = run.steps_taken
+    run.step(1)
+    _sync()
+    x1 = arr["x"].cpu().numpy().T.astype(np.float64)
+    status = arr["status"].cpu().numpy()
+    dt_g = arr["last_dt"].cpu().numpy().astype(np.float64)
+    lp_g = arr["logp"].cpu().numpy().astype(np.float64)
+    n = wl.n_chains
+    oprob = O.Problem(wl, c_tilde=ct)
+    st = O.States(x0, np.zeros(n), np.zeros(n), np.zeros_like(x0))
+    new, dt_o, flags, margins = O.transitions(oprob, st, s, np.arange(n), recompute=True)
+    kill_g = (status & R.ST_LAST_KILL) != 0
+    acc_g = (status & R.ST_LAST_ACCEPT) != 0
+    kill_o = (flags & O.FLAG_KILL) != 0
+    acc_o = (flags & O.FLAG_ACCEPT) != 0
+    kflip = kill_g != kill_o
+    aflip = (acc_g != acc_o) & ~kill_o & ~kill_g
+    _say(f"[{label}] n={n} kills={kill_o.sum()} accepts={acc_o.sum()} kill flips={kflip.sum()} "
+         f"(max |margin| {np.abs(margins[kflip, 0]).max() if kflip.any() else 0:.2e}) "
+         f"accept flips={aflip.sum()} (max |margin| {np.abs(margins[aflip, 1]).max() if aflip.any() else 0:.2e})")
+    assert np.all(np.abs(margins[kflip, 0]) < TAU_KILL), "kill decision differs outside the near-tie margin"
+    assert np.all(np.abs(margins[aflip, 1]) < TAU_ACC), "accept decision differs outside the near-tie margin"
+    same = ~kflip & ~aflip
+    regen = same & kill_o
+    moved = same & acc_o & ~kill_o
+    stay = same & ~kill_o & ~acc_o
+    assert np.array_equal(x1[regen], new.x[regen]), "regenerated states must be the exact uniforms"
+    assert np.array_equal(x1[stay], x0[stay]), "rejected moves must leave x bit-identical"
+    if moved.any():
+        err = np.abs(x1[moved] - new.x[moved]) / np.maximum(1.0, np.abs(new.x[moved]))
+        _say(f"[{label}] moved={moved.sum()} max state rel err {err.max():.2e}")
+        assert err.max() <= 1e-6
+    rel_dt = np.abs(dt_g[same] - dt_o[same]) / np.maximum(np.abs(dt_o[same]), 1e-30)
+    ok_dt = (dt_o[same] == 0) & (dt_g[same] == 0)
+    _say(f"[{label}] max dt rel err {np.where(ok_dt, 0, rel_dt).max():.2e}")
+    assert np.all(ok_dt | (rel_dt <= 1e-4))
+    fin = same & np.isfinite(new.lp)
+    lerr = np.abs(lp_g[fin] - new.lp[fin])
+    _say(f"[{label}] max |log p| err {lerr.max() if fin.any() else 0:.2e}")
+    assert np.all(lerr <= 1e-5 * np.maximum(1.0, np.abs(new.lp[fin])))
+    assert np.array_equal(np.isfinite(lp_g[same]), np.isfinite(new.lp[same]))
+    run.close()
+    return kill_o.sum(), acc_o.sum(), moved.sum()
+
+
+def _pi_draws(wl, n, seed):
+    """Exact draws of the truncated mixture (component, Gaussian, reject
+    outside the box) -- states in the modes, where local moves happen."""
+    rng = np.random.default_rng(seed)
+    w, m = wl.params["weights"], wl.params["means"]
+    if wl.target == "gmm_iso":
+        covs = [np.eye(wl.d) * s * s for s in wl.params["sigmas"]]
+    else:
+        covs = wl.params["covs"]
+    out = []
+    while sum(len(o) for o in out) < n:
+        k = rng.choice(wl.K, size=n, p=w)
+        x = np.stack([rng.multivariate_normal(m[j], covs[j]) for j in k])
+        out.append(x[np.all((x >= 0) & (x <= 1), axis=1)])
+    return np.concatenate(out)[:n]
+
+
+# ---------------------------------------------------------------------------
+# init and single transitions
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["gmm_iso_2d", "gmm_full_8d"])
+def test_init_matches_oracle(R, which):
+    from workloads import gmm_full, gmm_iso_2d
+    from oracle import oracle as O
+    wl = gmm_iso_2d(n_chains=5000) if which == "gmm_iso_2d" else gmm_full(n_chains=3001)
+    _say(f"[init {which}] start")
+    run = R.Run(R.problem_from_workload(wl))
+    _sync()
+    arr = run.arrays()
+    x = arr["x"].cpu().numpy().T.astype(np.float64)
+    st = O.init_states(O.Problem(wl), np.arange(wl.n_chains))
+    assert np.array_equal(x, st.x)
+    lp = arr["logp"].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(lp - st.lp) <= 1e-5 * np.maximum(1, np.abs(st.lp)))
+    assert np.all(arr["status"].cpu().numpy() == R.ST_ALIVE)
+    if "grad" in arr:
+        g = arr["grad"].cpu().numpy().T.astype(np.float64)
+        near = st.lp > np.quantile(st.lp, 0.5)
+        scale = np.maximum(1.0, np.abs(st.g[near]).max(axis=1, keepdims=True))
+        assert np.all(np.abs(g[near] - st.g[near]) <= 1e-4 * scale)
+    run.close()
+
+
+def test_single_transitions_2d_after_warmup(R):
+    from workloads import gmm_iso_2d
+    k, a, m = _single_step_check(R, gmm_iso_2d(n_chains=20000), warm=7, label="2d warm")
+    assert k > 1000 and a > 1000
+
+
+def test_single_transitions_2d_from_pi(R):
+    from workloads import gmm_iso_2d
+    wl = gmm_iso_2d(n_chains=20000)
+    k, a, m = _single_step_check(R, wl, x_init=_pi_draws(wl, wl.n_chains, 5), label="2d pi")
+    assert a > 5000
+
+
+@pytest.mark.parametrize("c_tilde", [3.34e7, 1e5])
+def test_single_transitions_8d_mala_from_pi(R, c_tilde):
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=8192)
+    k, a, m = _single_step_check(R, wl, x_init=_pi_draws(wl, wl.n_chains, 6), c_tilde=c_tilde,
+                                 label=f"8d pi c={c_tilde:g}")
+    assert a > 1000
+
+
+def test_single_transitions_8d_mala_after_warmup(R):
+    from workloads import gmm_full
+    _single_step_check(R, gmm_full(n_chains=8192), warm=4, label="8d warm")
+
+
+def test_single_transitions_full_cov_2d_rw(R):
+    from workloads import gmm_full
+    wl = gmm_full(d=2, K=4, n_chains=10000, problem_seed=77, local="rwmh", step=0.02, c_tilde=3.0)
+    _single_step_check(R, wl, x_init=_pi_draws(wl, wl.n_chains, 8), label="full2d rw")
+
+
+# ---------------------------------------------------------------------------
+# whole runs
+# ---------------------------------------------------------------------------
+
+def _gpu_run(R, wl, **kw):
+    run = R.Run(R.problem_from_workload(wl, **kw))
+    run.step(wl.n_steps)
+    run.drain()
+    est = run.estimate()
+    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done", "a_done", "status")}
+    run.close()
+    return est, arr
+
+
+def test_whole_run_2d_matches_oracle_and_truth(R):
+    from workloads import gmm_iso_2d
+    from oracle import oracle as O, truth
+    wl = gmm_iso_2d()
+    _say("[run 2d] gpu")
+    est, arr = _gpu_run(R, wl)
+    _say("[run 2d] oracle")
+    ores = O.run(O.Problem(wl), 0, wl.n_chains)
+    oest = O.estimate(ores)
+    tr = truth.truths(wl)
+    for key in ("p_lambda", "lam_pf", "pi_f"):
+        se = math.hypot(est[key + "_se"], oest[key + "_se"])
+        _say(f"[run 2d] {key}: gpu {est[key]:.6g} +- {est[key + '_se']:.2g}  oracle {oest[key]:.6g}  "
+             f"truth {tr[key]:.6g}  rel err {abs(est[key] / tr[key] - 1):.2e}")
+        assert abs(est[key] - oest[key]) < 3 * se
+        assert abs(est[key] - tr[key]) < 3 * est[key + "_se"]
+    assert est["tours_censored"] == 0 and oest["tours_censored"] == 0
+    assert est["transitions"] == est["transitions"]
+    same_n = np.mean(arr["n_done"].astype(np.int64) == ores.n_done)
+    _say(f"[run 2d] chains with identical tour counts: {same_n:.3f}; "
+         f"transitions gpu {est['transitions']} oracle {oest['transitions']}")
+    assert same_n > 0.5
+    assert abs(est["transitions"] - oest["transitions"]) < 0.01 * oest["transitions"]
+    assert np.all((arr["status"] & R.ST_ALIVE) == 0)
+
+
+def test_full_size_8d_sampled_chains_match_oracle(R):
+    """The 8-D workload at its full size (2^20 chains x 512 steps + drain),
+    in the configuration the benchmark times; 384 chains spread over the
+    population are rerun by the oracle from the same counters."""
+    from workloads import gmm_full
+    from oracle import oracle as O, truth
+    wl = gmm_full()
+    _say("[full 8d] gpu run 2^20 x 512")
+    est, arr = _gpu_run(R, wl)
+    _say(f"[full 8d] transitions {est['transitions']} tours {est['tours_done']} censored {est['tours_censored']}")
+    rng = np.random.default_rng(3)
+    ids = np.unique(np.concatenate([rng.integers(0, wl.n_chains, 380), [0, 1, wl.n_chains - 2, wl.n_chains - 1]]))
+    oprob = O.Problem(wl)
+    same = 0
+    for c in ids:
+        r = O.run(oprob, int(c), int(c) + 1, threads=1)
+        ok = (int(arr["n_done"][c]) == int(r.n_done[0]) and
+              abs(arr["t_done"][c] - r.t_done[0]) <= 1e-4 * max(1e-30, abs(r.t_done[0])) and
+              abs(arr["a_done"][c] - r.a_done[0]) <= 1e-3 * max(1e-30, abs(r.a_done[0])))
+        same += ok
+    _say(f"[full 8d] sampled chains identical to the oracle: {same}/{len(ids)}")
+    assert same >= len(ids) - 2
+    tr = truth.truths(wl)
+    for key in ("p_lambda", "lam_pf"):
+        _say(f"[full 8d] {key}: {est[key]:.6g} +- {est[key + '_se']:.2g}, truth {tr[key]:.6g}, "
+             f"rel err {abs(est[key] / tr[key] - 1):.3f}")
+
+
+# ---------------------------------------------------------------------------
+# determinism and edge cases
+# ---------------------------------------------------------------------------
+
+def _state_snapshot(run):
+    return {k: v.cpu().numpy().copy() for k, v in run.arrays().items()}
+
+
+def test_split_steps_block_size_and_lds_are_bit_identical(R):
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=3000)
+    ref = R.Run(R.problem_from_workload(wl))
+    ref.step(7)
+    a = _state_snapshot(ref)
+    for kw, split in [({}, (3, 4)), ({"block_size": 64}, (7,)), ({"lds": True}, (2, 5)),
+                      ({"block_size": 128, "lds": True}, (1, 1, 5))]:
+        run = R.Run(R.problem_from_workload(wl, **kw))
+        for n in split:
+            run.step(n)
+        b = _state_snapshot(run)
+        for key in a:
+            assert np.array_equal(a[key], b[key]), (kw, split, key)
+        run.close()
+    ref.close()
+
+
+def test_drain_lds_matches_scalar_params(R):
+    from workloads import gmm_iso_2d
+    wl = gmm_iso_2d(n_chains=2000, n_steps=50)
+    e1, a1 = _gpu_run(R, wl)
+    e2, a2 = _gpu_run(R, wl, lds=True)
+    for k in a1:
+        assert np.array_equal(a1[k], a2[k])
+    assert e1["p_lambda"] == e2["p_lambda"] and e1["transitions"] == e2["transitions"]
+
+
+@pytest.mark.parametrize("n_chains", [1, 63, 65, 1000])
+def test_ragged_chain_counts(R, n_chains):
+    from workloads import gmm_iso_2d
+    from oracle import oracle as O
+    wl = gmm_iso_2d(n_chains=n_chains, n_steps=40)
+    est, arr = _gpu_run(R, wl)
+    ores = O.run(O.Problem(wl), 0, n_chains, threads=1)
+    match = np.mean(arr["n_done"].astype(np.int64) == ores.n_done)
+    assert match >= 0.9
+    assert est["transitions"] >= n_chains * 40
+
+
+def test_zero_drain_cap_censors_every_tour_in_flight(R):
+    from workloads import gmm_iso_2d
+    wl = gmm_iso_2d(n_chains=512, n_steps=30)
+    est, arr = _gpu_run(R, wl, drain_cap=0)
+    assert est["tours_censored"] == 512
+    assert np.all((arr["status"] & R.ST_CENSORED) != 0)
+    assert est["transitions"] == 512 * 30
+
+
+def test_no_killing_is_a_plain_mh_chain(R):
+    from workloads import gmm_iso_2d
+    wl = gmm_iso_2d(n_chains=4096, n_steps=60)
+    run = R.Run(R.problem_from_workload(wl, c_tilde=0.0, drain_cap=0))
+    run.step(60)
+    run.drain()
+    est = run.estimate()
+    assert est["kills"] == 0 and est["accepts"] > 0
+    assert est["tours_censored"] == 4096
+    run.close()
+
+
+def test_state_checkpoint_resume(R):
+    """Copy the state bytes out and back into a context at the same step
+    count: the continuation is bit-identical."""
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=2048)
+    a = R.Run(R.problem_from_workload(wl))
+    a.step(5)
+    saved = a.state_region().clone()
+    a.step(5)
+    ref = _state_snapshot(a)
+    c = R.Run(R.problem_from_workload(wl))
+    c.step(5)
+    c.state_region().copy_(saved)
+    c.step(5)
+    got = _state_snapshot(c)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+    a.close()
+    c.close()

@@ -28,25 +28,33 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
 
 
-def flops_per_transition(target: str, d: int, K: int, local: str) -> float:
-    """Algorithmic float32 operations of one transition (FMA = 2, each
-    exp / log / sqrt / sin / cos = 1), dominated by the one density
-    evaluation every step needs.  Per mixture component:
-      full covariance: d (y - m) + d^2 (W (y - m)) + 2d (|v|^2) + 2 (a_k)
-                       + 7 (running log-sum-exp) [+ d^2 (W^T v) + 3d (grad)]
-      isotropic:       3d (y - m, |.|^2) + 4 + 7 [+ 3d (grad)]
-    per transition: 2 exponential clocks (4), Box-Muller (5 per pair),
-    proposal (2d, +2d MALA drift), acceptance (4, +4d MALA reverse density),
-    accumulation (4), log p from the log-sum-exp (2)."""
+def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: float) -> dict:
+    """Algorithmic float32 operations of one transition (FMA = 2 flops; each
+    exp / log / sqrt / sin / cos = 1), i.e. what the method must compute,
+    dominated by the one target-density evaluation every step needs.
+
+    Per mixture component, log p only (full covariance):
+        d (y - m) + d^2 (triangular W (y - m)) + 2d (|v|^2) + 2 (a_k) + 5 (log-sum-exp)
+    (isotropic: 3d + 7).  The gradient, needed only where a local MALA move
+    is made, adds d^2 + 2d per component (isotropic: 3d).
+    A terminated step (regeneration): clocks 6 + accumulation 4 + density.
+    A local step: clocks and accumulation 10, Box-Muller 5 per pair,
+    proposal 3d, MALA reverse proposal density 3d + 3, acceptance 3, the
+    density and gradient at the proposal, and -- once per tour -- the
+    gradient at the regenerated start.
+    Returns the per-transition count averaged with the measured kill rate."""
     mala = local == "mala"
     if target == "gmm_full":
-        per = d + d * d + 2 * d + 2 + 7 + ((d * d + 3 * d) if mala else 0)
+        lp, gr = d * d + 3 * d + 7, d * d + 2 * d
     elif target == "gmm_iso":
-        per = 3 * d + 4 + 7 + (3 * d if mala else 0)
+        lp, gr = 3 * d + 7, 3 * d
     else:
         raise ValueError(target)
-    other = 4 + 5 * math.ceil(d / 2) + 2 * d + (2 * d if mala else 0) + 4 + (4 * d if mala else 0) + 4 + 2
-    return float(K * per + other)
+    f_kill = K * lp + 2 + 10
+    f_local = (10 + 5 * math.ceil(d / 2) + 3 * d + 3 + K * lp + 2
+               + ((3 * d + 3 + K * gr + kill_rate * K * gr) if mala else 0))
+    return {"kill": float(f_kill), "local": float(f_local),
+            "mean": float(kill_rate * f_kill + (1.0 - kill_rate) * f_local)}
 
 
 def cpu_baseline(wl, target_seconds: float = 12.0) -> dict:
@@ -119,9 +127,9 @@ def main():
     value = trans / wall
     step_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
     step_trans = wl.n_chains * wl.n_steps
-    fpt = flops_per_transition(wl.target, wl.d, wl.K, wl.local)
-    achieved = fpt * step_trans / (step_ms * 1e-3) / 1e12
     est = ests[-1]
+    fpt = flops_per_transition(wl.target, wl.d, wl.K, wl.local, est.kill_rate)
+    achieved = fpt["mean"] * step_trans / (step_ms * 1e-3) / 1e12
     line = {
         "metric": "chain transitions/s + MSE×time vs uniform-mu restore at fixed rel. error",
         "value": value,

@@ -15,6 +15,7 @@ enum StatusBits : uint32_t {
     ST_CENSORED = 2u,    // tour still alive at the drain cap
     ST_LAST_KILL = 4u,   // last executed step was a termination
     ST_LAST_ACCEPT = 8u, // last executed step accepted a local move
+    ST_GRAD_VALID = 16u, // the cached grad log p(x) belongs to x (MALA)
 };
 
 enum CounterSlot : int { CNT_TRANSITIONS = 0, CNT_ACCEPTS = 1, CNT_KILLS = 2, CNT_SLOTS = 8 };

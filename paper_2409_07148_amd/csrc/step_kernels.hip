@@ -43,9 +43,8 @@ __device__ __forceinline__ float log_mu(const StepArgs &a, const float y[D]) {
 }
 
 template <int D, int MU, int NC>
-__device__ __forceinline__ void sample_mu(const StepArgs &a, float u_cat, const float cand[NC],
-                                          const float z[D], float y[D]) {
-    (void)a; (void)u_cat; (void)z;
+__device__ __forceinline__ void sample_mu(const StepArgs &a, float u_cat, const float cand[NC], float y[D]) {
+    (void)a; (void)u_cat;
 #pragma unroll
     for (int i = 0; i < D; ++i) y[i] = cand[i];
 }
@@ -140,25 +139,34 @@ __device__ __forceinline__ void step_once(const StepArgs &a, const float *__rest
         return;
     }
 
-    // candidate: mu sample if killed, small-step proposal otherwise
-    float z[D];
-    box_muller<D, 4 * NB>(cand, z);
-    float ymu[D], y[D];
-    sample_mu<D, MU, 4 * NB>(a, head[3], cand, z, ymu);
-    const float h = 0.5f * a.step * a.step;
+    // candidate: mu sample if killed, small-step proposal otherwise.  A
+    // regenerated chain gets its gradient only when it first survives a
+    // step, so waves whose lanes were all killed skip that work.
+    float y[D];
     float zz = 0.0f;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        float delta = a.step * z[i];
-        if (LOC == LOC_MALA) {
-            delta = fmaf(h, ch.g[i], delta);
-            zz = fmaf(z[i], z[i], zz);
+    const float h = 0.5f * a.step * a.step;
+    if (kill) {
+        sample_mu<D, MU, 4 * NB>(a, head[3], cand, y);
+    } else {
+        if (LOC == LOC_MALA && !(ch.status & ST_GRAD_VALID)) {
+            (void)log_target<D, TGT, true>(P, a.n_comp, ch.x, ch.g);
+            ch.status |= ST_GRAD_VALID;
         }
-        y[i] = kill ? ymu[i] : ch.x[i] + delta;
+        float z[D];
+        box_muller<D, 4 * NB>(cand, z);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            float delta = a.step * z[i];
+            if (LOC == LOC_MALA) {
+                delta = fmaf(h, ch.g[i], delta);
+                zz = fmaf(z[i], z[i], zz);
+            }
+            y[i] = ch.x[i] + delta;
+        }
     }
 
     float gy[D];
-    const float lpy = log_target<D, TGT, LOC == LOC_MALA>(P, a.n_comp, y, gy);
+    const float lpy = log_target<D, TGT, LOC == LOC_MALA>(P, a.n_comp, y, gy, !kill);
     const float luy = log_mu<D, MU>(a, y);
 
     accept = false;
@@ -185,8 +193,13 @@ __device__ __forceinline__ void step_once(const StepArgs &a, const float *__rest
 #pragma unroll
         for (int i = 0; i < D; ++i) ch.x[i] = y[i];
         if (LOC == LOC_MALA) {
+            if (accept) {
 #pragma unroll
-            for (int i = 0; i < D; ++i) ch.g[i] = gy[i];
+                for (int i = 0; i < D; ++i) ch.g[i] = gy[i];
+                ch.status |= ST_GRAD_VALID;
+            } else {
+                ch.status &= ~ST_GRAD_VALID;
+            }
         }
         ch.lp = lpy;
         ch.lu = luy;
@@ -290,17 +303,16 @@ __global__ __launch_bounds__(256) void init_kernel(StepArgs a) {
     constexpr int NB = NBlocks<D>::value;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n_chains) return;
-    float head[4], cand[4 * NB], z[D];
+    float head[4], cand[4 * NB];
     draw_step<NB>(0u, (uint32_t)c, a.target_id, PURPOSE_INIT, a.key0, a.key1, head, cand);
-    box_muller<D, 4 * NB>(cand, z);
     Chain<D, LOC> ch;
-    sample_mu<D, MU, 4 * NB>(a, head[3], cand, z, ch.x);
+    sample_mu<D, MU, 4 * NB>(a, head[3], cand, ch.x);
     ch.lp = log_target<D, TGT, LOC == LOC_MALA>(a.params, a.n_comp, ch.x, ch.g);
     ch.lu = log_mu<D, MU>(a, ch.x);
     ch.a_cur = ch.t_cur = 0.0f;
     ch.a_done = ch.t_done = 0.0;
     ch.n_done = 0u;
-    ch.status = ST_ALIVE;
+    ch.status = ST_ALIVE | (LOC == LOC_MALA ? ST_GRAD_VALID : 0u);
     ch.last_dt = 0.0f;
     store_chain(a, (uint32_t)c, ch);
 }
@@ -319,6 +331,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(StepArgs a) {
     if (LOC == LOC_MALA) {
 #pragma unroll
         for (int i = 0; i < D; ++i) a.grad[i * C + c] = g[i];
+        a.status[c] |= ST_GRAD_VALID;
     }
 }
 

@@ -20,7 +20,7 @@ struct GmmIso {
 
     template <bool GRAD>
     __device__ __forceinline__ static float eval(const float *__restrict__ P, int K, const float y[D],
-                                                 float g[D]) {
+                                                 float g[D], bool want) {
         float M = -INFINITY, S = 0.0f;
         float G[D];
 #pragma unroll
@@ -39,7 +39,7 @@ struct GmmIso {
             const float sc = exp_rel(M - Mn);
             const float w = exp_rel(ak - Mn);
             S = fmaf(S, sc, w);
-            if (GRAD) {
+            if (GRAD && want) {
                 const float wi = -w * ivar;
 #pragma unroll
                 for (int i = 0; i < D; ++i) G[i] = fmaf(G[i], sc, wi * dx[i]);
@@ -47,7 +47,7 @@ struct GmmIso {
             M = Mn;
         }
         const float lp = M + logf(S);
-        if (GRAD) {
+        if (GRAD && want) {
             const float inv = 1.0f / S;
 #pragma unroll
             for (int i = 0; i < D; ++i) g[i] = G[i] * inv;
@@ -66,7 +66,7 @@ struct GmmFull {
 
     template <bool GRAD>
     __device__ __forceinline__ static float eval(const float *__restrict__ P, int K, const float y[D],
-                                                 float g[D]) {
+                                                 float g[D], bool want) {
         float M = -INFINITY, S = 0.0f;
         float G[D];
 #pragma unroll
@@ -91,7 +91,7 @@ struct GmmFull {
             const float sc = exp_rel(M - Mn);
             const float w = exp_rel(ak - Mn);
             S = fmaf(S, sc, w);
-            if (GRAD) {
+            if (GRAD && want) {
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     float u = 0.0f;
@@ -103,7 +103,7 @@ struct GmmFull {
             M = Mn;
         }
         const float lp = M + logf(S);
-        if (GRAD) {
+        if (GRAD && want) {
             const float inv = 1.0f / S;
 #pragma unroll
             for (int i = 0; i < D; ++i) g[i] = G[i] * inv;
@@ -119,12 +119,15 @@ struct TargetOf<D, TGT_ISO> { using type = GmmIso<D>; };
 template <int D>
 struct TargetOf<D, TGT_FULL> { using type = GmmFull<D>; };
 
-// log p(y) (and its gradient) with p = 0 outside the unit box.
+// log p(y) with p = 0 outside the unit box; with GRAD, lanes that `want` it
+// also get grad log p(y) (the gradient work is skipped by waves where no
+// lane wants it).
 template <int D, int TGT, bool GRAD>
-__device__ __forceinline__ float log_target(const float *__restrict__ P, int K, const float y[D], float g[D]) {
-    const float lp = TargetOf<D, TGT>::type::template eval<GRAD>(P, K, y, g);
+__device__ __forceinline__ float log_target(const float *__restrict__ P, int K, const float y[D], float g[D],
+                                            bool want = true) {
+    const float lp = TargetOf<D, TGT>::type::template eval<GRAD>(P, K, y, g, want);
     const bool in = in_unit_box<D>(y);
-    if (GRAD) {
+    if (GRAD && want) {
 #pragma unroll
         for (int i = 0; i < D; ++i) g[i] = in ? g[i] : 0.0f;
     }

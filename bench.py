@@ -44,6 +44,16 @@ def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: flo
     gradient at the regenerated start.
     Returns the per-transition count averaged with the measured kill rate."""
     mala = local == "mala"
+    if target == "pss":
+        # rendering-shaped integrand: two textures of 8 sinusoids (dot product
+        # 2m, sine 1, FMA 2), three lobes (omega 8, difference 5, norm 5,
+        # exp and FMA 3), light sum 3, three logs and two adds 5; the pixel
+        # index of the splat 4.
+        dens = 8 * (2 * 2 + 3) + 8 * (2 * 6 + 3) + 3 * 21 + 3 + 5
+        f_kill = dens + 10 + 4
+        f_local = f_kill + 5 * math.ceil(d / 2) + 2 * d + 3
+        return {"kill": float(f_kill), "local": float(f_local),
+                "mean": float(kill_rate * f_kill + (1.0 - kill_rate) * f_local)}
     if target == "gmm_full":
         lp, gr = d * d + 3 * d + 7, d * d + 2 * d
     elif target == "gmm_iso":
@@ -55,6 +65,25 @@ def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: flo
                + ((3 * d + 3 + K * gr + kill_rate * K * gr) if mala else 0))
     return {"kill": float(f_kill), "local": float(f_local),
             "mean": float(kill_rate * f_kill + (1.0 - kill_rate) * f_local)}
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
+    size), or None when the kernel sources have changed since the counters
+    were taken or no summary exists for this workload."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2409_07148_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != rec.get("csrc_sha256"):
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(wl, target_seconds: float = 12.0) -> dict:
@@ -83,9 +112,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gmm_full_8d", choices=["gmm_full_8d", "gmm_iso_2d"])
+    ap.add_argument("--workload", default="gmm_full_8d", choices=["gmm_full_8d", "gmm_iso_2d", "pss_render_12d"])
     ap.add_argument("--lds", action="store_true", help="stage mixture parameters in LDS")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-image", action="store_true",
+                    help="diagnostic: run the rendering-shaped workload without its pixel integrand")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (chains shard by global id; "
@@ -94,17 +127,25 @@ def main():
 
     import torch
     from paper_2409_07148_amd import restore as R
-    from workloads import gmm_full, gmm_iso_2d
+    from workloads import gmm_full, gmm_iso_2d, pss_render
 
-    wl = gmm_full() if args.workload == "gmm_full_8d" else gmm_iso_2d()
+    wl = {"gmm_full_8d": gmm_full, "gmm_iso_2d": gmm_iso_2d, "pss_render_12d": pss_render}[args.workload]()
+    if args.no_image:
+        wl = wl.with_(image=None)
     prob = R.problem_from_workload(wl, lds=args.lds)
     stream = torch.cuda.current_stream()
     nbytes = R.restore_state_bytes(prob.target, prob.mu, prob.local, prob.cfg)
     state = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
     ptr = (state.data_ptr() + 255) // 256 * 256
+    image = None
+    if wl.image:
+        image = torch.zeros((wl.image[1], wl.image[0]), dtype=torch.float32, device="cuda")
 
     def one_pass(timed_step=None):
-        ctx = R.restore_init(prob.target, prob.mu, prob.local, prob.cfg, ptr, nbytes, 0, stream)
+        if image is not None:
+            image.zero_()
+        ctx = R.restore_init(prob.target, prob.mu, prob.local, prob.cfg, ptr, nbytes,
+                             image.data_ptr() if image is not None else 0, stream)
         if timed_step is not None:
             timed_step[0].record(stream)
         R.restore_step(ctx, wl.n_steps, stream)
@@ -147,7 +188,10 @@ def main():
             "workload": wl.name,
             "description": (f"{wl.K}-component {'full-covariance' if wl.target == 'gmm_full' else 'isotropic'} "
                             f"Gaussian mixture on [0,1]^{wl.d}, {wl.local} step {wl.step}, uniform mu, "
-                            f"c_tilde {wl.c_tilde:g}"),
+                            f"c_tilde {wl.c_tilde:g}") if wl.target != "pss" else
+                           (f"12-D primary-sample-space integrand (2 textures x 8 sinusoids, 3 vMF lobes "
+                            f"kappa 1e3) splatted to a {(wl.image or (0, 0))[0]}x{(wl.image or (0, 0))[1]} image, rwmh step {wl.step}, "
+                            f"uniform mu, c_tilde {wl.c_tilde:g}"),
             "chains": wl.n_chains, "budget_steps": wl.n_steps, "drain_cap": wl.drain_cap,
             "params_staging": "lds" if args.lds else "scalar",
         },
@@ -162,12 +206,18 @@ def main():
             "flops_per_transition": fpt,
             "kernel_ms": step_ms,
             "kernel_transitions_per_s": step_trans / (step_ms * 1e-3),
-            "traffic": None,
+            "traffic": measured_traffic(wl.name if not args.no_image else ""),
         },
         "estimates": {k: est.as_dict()[k] for k in ("p_lambda", "p_lambda_se", "lam_pf", "lam_pf_se",
                                                     "tours_done", "tours_censored", "kill_rate",
                                                     "accept_rate")},
     }
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

@@ -120,7 +120,8 @@ typedef struct {
 /* ---- run configuration ------------------------------------------------- */
 #define RESTORE_INTEGRAND_ONE    1   /* f = 1: tour lifetimes (p_lambda)     */
 #define RESTORE_INTEGRAND_P      2   /* f = p: lambda(p^2), pi p             */
-#define RESTORE_INTEGRAND_PIXEL  4   /* f = 1_pixel(x0, x1): image splats    */
+#define RESTORE_INTEGRAND_PIXEL  4   /* f = 1_pixel(x0, x1): image splats
+                                        (built for the PSS target)        */
 
 #define RESTORE_FLAG_PARAMS_LDS  1   /* stage mixture parameters through LDS
                                         instead of the scalar cache          */

@@ -18,6 +18,15 @@ import numpy as np
 
 
 def peak_bound(wl) -> float:
+    if wl.target == "pss":
+        # g <= max tA * max tB * (b + sum_l w_l max h_l), max t <= 1 + sum |a_m| / 8,
+        # max h = 4 pi kappa / (2 pi (1 - e^{-2 kappa}))
+        p = wl.params
+        ta = 1 + np.abs(p["tex_a_amp"]).sum() / 8
+        tb = 1 + np.abs(p["tex_b_amp"]).sum() / 8
+        k = np.asarray(p["lobe_kappa"], dtype=np.float64)
+        hmax = 2 * k / -np.expm1(-2 * k)
+        return float(ta * tb * (p["base"][0] + (np.asarray(p["lobe_weights"]) * hmax).sum()))
     w = np.asarray(wl.params["weights"], dtype=np.float64)
     d = wl.d
     if wl.target == "gmm_iso":
@@ -34,6 +43,7 @@ def c_tilde_rule(wl, sig: int = 3) -> float:
 
 if __name__ == "__main__":
     sys.path.insert(0, __file__.rsplit("/oracle/", 1)[0])
-    from workloads import gmm_full, gmm_iso_2d
+    from workloads import gmm_full, gmm_iso_2d, pss_render
     print("gmm_iso_2d", c_tilde_rule(gmm_iso_2d()))
     print("gmm_full_8d", c_tilde_rule(gmm_full()))
+    print("pss_render_12d", c_tilde_rule(pss_render()))

@@ -134,8 +134,10 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
     if (cfg->block_size != 0 && (cfg->block_size < 64 || cfg->block_size > 256 || cfg->block_size % 64))
         return fail(RESTORE_E_INVALID_ARG, "block_size must be a multiple of 64 in 64..256");
     if (cfg->integrands & RESTORE_INTEGRAND_PIXEL) {
-        if (cfg->image_w < 1 || cfg->image_h < 1) return fail(RESTORE_E_INVALID_ARG, "image size must be >= 1");
-        if (d < 2) return fail(RESTORE_E_INVALID_ARG, "pixel integrand needs dim >= 2");
+        if (cfg->image_w < 1 || cfg->image_h < 1 || (int64_t)cfg->image_w * cfg->image_h > (1LL << 28))
+            return fail(RESTORE_E_INVALID_ARG, "image size must be >= 1 and at most 2^28 pixels");
+        if (t->kind != RESTORE_TARGET_PSS)
+            return fail(RESTORE_E_UNSUPPORTED, "pixel splats are built for the rendering-shaped target");
     }
     v->tgt = t->kind == RESTORE_TARGET_GMM_ISO ? TGT_ISO : t->kind == RESTORE_TARGET_GMM_FULL ? TGT_FULL : TGT_PSS;
     v->d = d;
@@ -204,7 +206,41 @@ restore_status pack_params(const restore_target *t, const Validated &v, std::vec
         }
         return RESTORE_OK;
     }
-    return fail(RESTORE_E_UNSUPPORTED, "target kind not built yet");
+    // rendering-shaped integrand: see the slab layout in restore_internal.h
+    out->assign(PSS_SLAB, 0.0f);
+    float *o = out->data();
+    const double *nA = p, *aA = p + 16, *phA = p + 24, *nB = p + 32, *aB = p + 80, *phB = p + 88;
+    const double *dir = p + 96, *kap = p + 105, *wl = p + 108, b = p[111];
+    double sa = 0.0, sb = 0.0;
+    for (int m = 0; m < 8; ++m) { sa += std::fabs(aA[m]); sb += std::fabs(aB[m]); }
+    if (!(sa < 8.0 && sb < 8.0)) return fail(RESTORE_E_INVALID_ARG, "texture amplitudes must keep t > 0");
+    for (int i = 0; i < 16; ++i) {
+        if (nA[i] != std::floor(nA[i])) return fail(RESTORE_E_INVALID_ARG, "texture frequencies must be integers");
+        o[i] = (float)nA[i];
+    }
+    for (int i = 0; i < 48; ++i) {
+        if (nB[i] != std::floor(nB[i])) return fail(RESTORE_E_INVALID_ARG, "texture frequencies must be integers");
+        o[32 + i] = (float)nB[i];
+    }
+    auto frac = [](double x) { return x - std::floor(x); };
+    for (int m = 0; m < 8; ++m) {
+        o[16 + m] = (float)(aA[m] / 8.0);
+        o[24 + m] = (float)frac(phA[m] / (2.0 * M_PI));
+        o[80 + m] = (float)(aB[m] / 8.0);
+        o[88 + m] = (float)frac(phB[m] / (2.0 * M_PI));
+    }
+    for (int l = 0; l < 3; ++l) {
+        const double n2 = dir[3 * l] * dir[3 * l] + dir[3 * l + 1] * dir[3 * l + 1] + dir[3 * l + 2] * dir[3 * l + 2];
+        if (std::fabs(n2 - 1.0) > 1e-9) return fail(RESTORE_E_INVALID_ARG, "lobe directions must be unit vectors");
+        if (!(kap[l] > 0.0) || !(wl[l] >= 0.0)) return fail(RESTORE_E_INVALID_ARG, "kappa > 0 and w >= 0");
+        for (int i = 0; i < 3; ++i) o[96 + 3 * l + i] = (float)dir[3 * l + i];
+        o[105 + l] = (float)kap[l];
+        // ln(4 pi w kappa / (2 pi (1 - e^{-2 kappa}))) = ln(2 w kappa / (1 - e^{-2 kappa}))
+        o[108 + l] = wl[l] > 0.0 ? (float)std::log(2.0 * wl[l] * kap[l] / -std::expm1(-2.0 * kap[l])) : -INFINITY;
+    }
+    if (!(b >= 0.0)) return fail(RESTORE_E_INVALID_ARG, "base level b must be >= 0");
+    o[111] = (float)b;
+    return RESTORE_OK;
 }
 
 }  // namespace

@@ -15,6 +15,8 @@
 // wave do the same work whichever clock fired.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "restore_internal.h"
 #include "targets.h"
 #include "launch.h"
@@ -24,15 +26,24 @@ namespace restore {
 template <int D>
 struct NBlocks { static constexpr int value = (D + 3) / 4; };
 
-// Parameters of the target in LDS (broadcast reads) or straight from global
-// memory (wave-uniform addresses -> scalar loads).
+// Parameters of the target in LDS (broadcast reads) or read through the
+// constant address space (wave-uniform addresses -> scalar loads).
 template <bool LDS>
-__device__ __forceinline__ const float *stage_params(const float *__restrict__ params, int n_floats,
-                                                     float *smem) {
-    if (!LDS) return params;
-    for (int i = threadIdx.x; i < n_floats; i += blockDim.x) smem[i] = params[i];
-    __syncthreads();
-    return smem;
+struct ParamPtr { using type = const_fptr; };
+template <>
+struct ParamPtr<true> { using type = const float *; };
+
+template <bool LDS>
+__device__ __forceinline__ typename ParamPtr<LDS>::type stage_params(const float *params, int n_floats,
+                                                                    float *smem) {
+    if constexpr (LDS) {
+        for (int i = threadIdx.x; i < n_floats; i += blockDim.x) smem[i] = params[i];
+        __syncthreads();
+        return smem;
+    } else {
+        (void)n_floats; (void)smem;
+        return (const_fptr)params;
+    }
 }
 
 template <int D, int MU>
@@ -60,7 +71,15 @@ struct Chain {
     uint32_t n_done;
     uint32_t status;
     float last_dt;
+    // pixel splats of this lane not yet added to the image: consecutive
+    // steps in the same pixel (rejected moves) are combined in registers
+    int32_t splat_pix;
+    float splat_acc;
 };
+
+__device__ __forceinline__ void flush_splat(const StepArgs &a, int32_t pix, float acc) {
+    if (pix >= 0) atomicAdd(a.image + pix, acc);
+}
 
 template <int D, int LOC>
 __device__ __forceinline__ void load_chain(const StepArgs &a, uint32_t c, Chain<D, LOC> &ch) {
@@ -80,6 +99,8 @@ __device__ __forceinline__ void load_chain(const StepArgs &a, uint32_t c, Chain<
     ch.n_done = a.n_done[c];
     ch.status = a.status[c];
     ch.last_dt = a.last_dt[c];
+    ch.splat_pix = -1;
+    ch.splat_acc = 0.0f;
 }
 
 template <int D, int LOC>
@@ -104,10 +125,17 @@ __device__ __forceinline__ void store_chain(const StepArgs &a, uint32_t c, const
 
 // One transition of Alg. 2 for one lane.  Returns kill / accept through the
 // flags.  In the drain (RETIRE) a terminated chain is not regenerated.
-template <int D, int TGT, int LOC, int MU, bool RETIRE>
-__device__ __forceinline__ void step_once(const StepArgs &a, const float *__restrict__ P, uint32_t s,
+template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT>
+__device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                                           uint32_t chain, Chain<D, LOC> &ch, bool &kill, bool &accept) {
     constexpr int NB = NBlocks<D>::value;
+    if constexpr (std::is_same<PT, const_fptr>::value) {
+        // keep the scalar parameter loads inside the step: hoisted out of the
+        // step loop, a large slab overflows the SGPRs and spills to VGPR lanes
+        uint64_t pv = (uint64_t)P;
+        asm volatile("" : "+s"(pv));
+        P = (PT)pv;
+    }
     float head[4], cand[4 * NB];
     draw_step<NB>(s, chain, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
 
@@ -126,6 +154,22 @@ __device__ __forceinline__ void step_once(const StepArgs &a, const float *__rest
     // accumulate dt f(x_{i-1}) into the tour in flight
     ch.t_cur += dt;
     if (a.integrand_p) ch.a_cur = fmaf(dt, expf(ch.lp), ch.a_cur);
+    if (TGT == TGT_PSS && a.image) {
+        // f = 1_pixel(x0, x1) at the pre-transition state (p = 0 off the box)
+        const float u0 = ch.x[0], u1 = ch.x[1];
+        int32_t pix = -1;
+        if (u0 >= 0.0f && u0 <= 1.0f && u1 >= 0.0f && u1 <= 1.0f) {
+            const int px = min(max((int)(u0 * (float)a.image_w), 0), a.image_w - 1);
+            const int py = min(max((int)(u1 * (float)a.image_h), 0), a.image_h - 1);
+            pix = py * a.image_w + px;
+        }
+        if (pix != ch.splat_pix) {
+            flush_splat(a, ch.splat_pix, ch.splat_acc);
+            ch.splat_pix = pix;
+            ch.splat_acc = 0.0f;
+        }
+        ch.splat_acc += dt;
+    }
     ch.last_dt = dt;
     if (kill) {
         ch.a_done += (double)ch.a_cur;
@@ -221,7 +265,7 @@ __device__ __forceinline__ void add_counters(unsigned long long *counters, unsig
 template <int D, int TGT, int LOC, int MU, bool LDS>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_floats) {
     extern __shared__ float smem[];
-    const float *P = stage_params<LDS>(a.params, n_param_floats, smem);
+    const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n_chains) return;
     Chain<D, LOC> ch;
@@ -235,6 +279,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_float
     }
     ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT)) | (kill ? ST_LAST_KILL : 0u) |
                 (accept ? ST_LAST_ACCEPT : 0u);
+    if (TGT == TGT_PSS && a.image) flush_splat(a, ch.splat_pix, ch.splat_acc);
     store_chain(a, (uint32_t)c, ch);
     const unsigned long long lanes = __popcll(__ballot(1));
     add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill);
@@ -249,7 +294,7 @@ __global__ __launch_bounds__(256) void drain_kernel(StepArgs a, int n_param_floa
                                                      uint32_t *count_out, uint32_t *count_zero,
                                                      int last_chunk) {
     extern __shared__ float smem[];
-    const float *P = stage_params<LDS>(a.params, n_param_floats, smem);
+    const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
     if (blockIdx.x == 0 && threadIdx.x == 0) *count_zero = 0u;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n_in = a.list ? (int64_t)*a.list_count : a.n_chains;
@@ -280,6 +325,7 @@ __global__ __launch_bounds__(256) void drain_kernel(StepArgs a, int n_param_floa
                     (kill_last ? ST_LAST_KILL : 0u) | (acc_last ? ST_LAST_ACCEPT : 0u);
     }
     if (alive && last_chunk) ch.status |= ST_CENSORED;
+    if (TGT == TGT_PSS && a.image) flush_splat(a, ch.splat_pix, ch.splat_acc);
     store_chain(a, c, ch);
     add_counters(a.counters, n_t, n_acc, n_kill);
     if (!last_chunk) {
@@ -307,7 +353,7 @@ __global__ __launch_bounds__(256) void init_kernel(StepArgs a) {
     draw_step<NB>(0u, (uint32_t)c, a.target_id, PURPOSE_INIT, a.key0, a.key1, head, cand);
     Chain<D, LOC> ch;
     sample_mu<D, MU, 4 * NB>(a, head[3], cand, ch.x);
-    ch.lp = log_target<D, TGT, LOC == LOC_MALA>(a.params, a.n_comp, ch.x, ch.g);
+    ch.lp = log_target<D, TGT, LOC == LOC_MALA>((const_fptr)a.params, a.n_comp, ch.x, ch.g);
     ch.lu = log_mu<D, MU>(a, ch.x);
     ch.a_cur = ch.t_cur = 0.0f;
     ch.a_done = ch.t_done = 0.0;
@@ -326,7 +372,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(StepArgs a) {
     float x[D], g[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) x[i] = a.x[i * C + c];
-    a.logp[c] = log_target<D, TGT, LOC == LOC_MALA>(a.params, a.n_comp, x, g);
+    a.logp[c] = log_target<D, TGT, LOC == LOC_MALA>((const_fptr)a.params, a.n_comp, x, g);
     a.logu[c] = log_mu<D, MU>(a, x);
     if (LOC == LOC_MALA) {
 #pragma unroll
@@ -363,6 +409,10 @@ static KernelSet make_set() {
 
 KernelSet find_kernels(int tgt, int d, int loc, int mu) {
     if (mu != MU_UNIFORM) return KernelSet{};
+    if (tgt == TGT_PSS) {
+        if (d == 12 && loc == LOC_RWMH) return make_set<12, TGT_PSS, LOC_RWMH, MU_UNIFORM>();
+        return KernelSet{};
+    }
     if (tgt == TGT_ISO && loc == LOC_RWMH) {
         switch (d) { RESTORE_SETS_FOR(TGT_ISO, LOC_RWMH, MU_UNIFORM) default: break; }
     } else if (tgt == TGT_ISO && loc == LOC_MALA) {

@@ -12,21 +12,26 @@
 
 namespace restore {
 
+// Parameters read through the constant address space: wave-uniform loads
+// from it always become scalar (SMEM) loads feeding SGPR operands, even
+// when the kernel also writes global memory (image splats) that the
+// compiler cannot prove disjoint from the slab.
+typedef const __attribute__((address_space(4))) float *const_fptr;
+
 // Isotropic Gaussian mixture: a_k = c_k - (1/(2 s_k^2)) |y - m_k|^2,
 // grad log p = sum_k r_k (-(y - m_k) / s_k^2), r = softmax(a).
 template <int D>
 struct GmmIso {
     static constexpr int STRIDE = comp_stride(TGT_ISO, D);
 
-    template <bool GRAD>
-    __device__ __forceinline__ static float eval(const float *__restrict__ P, int K, const float y[D],
-                                                 float g[D], bool want) {
+    template <bool GRAD, class PT>
+    __device__ __forceinline__ static float eval(PT P, int K, const float y[D], float g[D], bool want) {
         float M = -INFINITY, S = 0.0f;
         float G[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) G[i] = 0.0f;
         for (int k = 0; k < K; ++k) {
-            const float *pk = P + k * STRIDE;
+            const auto pk = P + k * STRIDE;
             const float ivar = pk[1 + D];
             float dx[D], q = 0.0f;
 #pragma unroll
@@ -64,16 +69,15 @@ template <int D>
 struct GmmFull {
     static constexpr int STRIDE = comp_stride(TGT_FULL, D);
 
-    template <bool GRAD>
-    __device__ __forceinline__ static float eval(const float *__restrict__ P, int K, const float y[D],
-                                                 float g[D], bool want) {
+    template <bool GRAD, class PT>
+    __device__ __forceinline__ static float eval(PT P, int K, const float y[D], float g[D], bool want) {
         float M = -INFINITY, S = 0.0f;
         float G[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) G[i] = 0.0f;
         for (int k = 0; k < K; ++k) {
-            const float *pk = P + k * STRIDE;
-            const float *W = pk + 1 + D;
+            const auto pk = P + k * STRIDE;
+            const auto W = pk + 1 + D;
             float dx[D], v[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) dx[i] = y[i] - pk[1 + i];
@@ -112,19 +116,72 @@ struct GmmFull {
     }
 };
 
+// Rendering-shaped integrand on [0,1]^12 (slab layout in restore_internal.h):
+//   g(x) = tA(x0,x1) tB(x6..x11) [b + sum_l w_l h_l(x_{2l}, x_{2l+1})],
+//   t(y) = 1 + (1/8) sum_m a_m sin(2 pi (<n_m, y> + phi_m / 2 pi)),
+//   w_l h_l(u, v) = C_l exp(-kappa_l |omega(u,v) - dir_l|^2 / 2)  (= exp(kappa (dir.omega - 1))
+//   for unit vectors, without the cancellation of dir.omega - 1 near the lobe),
+//   omega = (2 sqrt(u (1 - u)) cos 2 pi v, 2 sqrt(u (1 - u)) sin 2 pi v, 1 - 2u).
+// Texture phases are reduced modulo one revolution term by term (the
+// frequencies are integers), so the hardware sine sees arguments in [0, 1).
+template <int D>
+struct Pss {
+    // one sinusoid per iteration (not unrolled): only that row's scalars are
+    // live, which keeps the slab from overflowing the SGPR file
+    template <int DIM, class PT>
+    __device__ __forceinline__ static float texture(PT freq, PT amp, PT phase, const float *y) {
+        float t = 1.0f;
+#pragma unroll 1
+        for (int m = 0; m < 8; ++m) {
+            float s = phase[m];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) s = __builtin_amdgcn_fractf(s + __builtin_amdgcn_fractf(freq[m * DIM + i] * y[i]));
+            t = fmaf(amp[m], __builtin_amdgcn_sinf(s), t);
+        }
+        return t;
+    }
+
+    template <bool GRAD, class PT>
+    __device__ __forceinline__ static float eval(PT P, int K, const float y[D], float g[D], bool want) {
+        static_assert(D == 12, "the rendering-shaped integrand lives on [0,1]^12");
+        (void)K; (void)g; (void)want;
+        const float ta = texture<2>(P + 0, P + 16, P + 24, y);
+        const float tb = texture<6>(P + 32, P + 80, P + 88, y + 6);
+        float light = P[111];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const float u = y[2 * l], v = y[2 * l + 1];
+            const float z = 1.0f - 2.0f * u;
+            const float r = 2.0f * sqrtf(fmaxf(u * (1.0f - u), 0.0f));
+            const auto dir = P + 96 + 3 * l;
+            // the lobe exponent amplifies direction errors by ~kappa |omega - dir|,
+            // so the azimuth uses the correctly rounded sin/cos of pi (2v)
+            float sv, cv;
+            sincospif(2.0f * v, &sv, &cv);
+            const float d0 = r * cv - dir[0];
+            const float d1 = r * sv - dir[1];
+            const float d2 = z - dir[2];
+            const float q = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+            light += expf(fmaf(-0.5f * P[105 + l], q, P[108 + l]));
+        }
+        return logf(ta) + logf(tb) + logf(light);
+    }
+};
+
 template <int D, int TGT>
 struct TargetOf;
 template <int D>
 struct TargetOf<D, TGT_ISO> { using type = GmmIso<D>; };
 template <int D>
 struct TargetOf<D, TGT_FULL> { using type = GmmFull<D>; };
+template <int D>
+struct TargetOf<D, TGT_PSS> { using type = Pss<D>; };
 
 // log p(y) with p = 0 outside the unit box; with GRAD, lanes that `want` it
 // also get grad log p(y) (the gradient work is skipped by waves where no
 // lane wants it).
-template <int D, int TGT, bool GRAD>
-__device__ __forceinline__ float log_target(const float *__restrict__ P, int K, const float y[D], float g[D],
-                                            bool want = true) {
+template <int D, int TGT, bool GRAD, class PT>
+__device__ __forceinline__ float log_target(PT P, int K, const float y[D], float g[D], bool want = true) {
     const float lp = TargetOf<D, TGT>::type::template eval<GRAD>(P, K, y, g, want);
     const bool in = in_unit_box<D>(y);
     if (GRAD && want) {

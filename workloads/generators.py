@@ -137,9 +137,15 @@ def gmm_full(d: int = 8, K: int = 16, n_chains: int = 1 << 20,
                     problem_seed)
 
 
+# c_tilde of the rendering-shaped workload by the same rule, with the bound
+# max tA * max tB * (b + sum_l w_l max h_l) of g.  Written by
+# oracle/choose_c_tilde.py.
+C_TILDE_PSS_12D = 155.0
+
+
 def pss_render(n_chains: int = 1 << 20, n_steps: int = 256,
                problem_seed: int = 1003, seed: int = 2003,
-               image=(512, 512), c_tilde: float = 1.0) -> Workload:
+               image=(512, 512), c_tilde: float = C_TILDE_PSS_12D) -> Workload:
     """12-D rendering-shaped integrand on [0,1]^12.
 
     g(x) = tA(x0,x1) * tB(x6..x11) * [b + sum_l w_l h_l(x_{2l-2}, x_{2l-1})]
@@ -178,7 +184,7 @@ def pss_render(n_chains: int = 1 << 20, n_steps: int = 256,
     }
     return Workload("pss_render_12d", "pss", 12, 0, params, "rwmh", 0.02,
                     n_chains, n_steps, 4 * n_steps, float(c_tilde), seed,
-                    problem_seed, image=tuple(image))
+                    problem_seed, image=tuple(image) if image else None)
 
 
 def batched_uneven(n_targets: int = 256, problem_seed: int = 1005,

@@ -215,6 +215,74 @@ restore_status restore_refresh_cache(restore_ctx *ctx, void *stream);
 /* Release the context (device buffers stay the caller's). */
 restore_status restore_destroy(restore_ctx *ctx);
 
+/* ---- batched targets ---------------------------------------------------
+ * Many independent targets (full-covariance mixtures of uneven dimension,
+ * component count and chain count; random-walk MH local moves; uniform mu)
+ * advanced together.  Each target is its own restore problem exactly as
+ * above (Alg. 2 with the killing rate of eq. (killing-rate-simplified));
+ * target i uses Philox target id cfgs[i].target_id, so its chains follow
+ * the same trajectories as a single-target run with that id.
+ * One pass = x_0 ~ mu, n_steps steps with regeneration, the drain of the
+ * tours in flight (cfgs[i].drain_cap) and the per-target reduction.  The
+ * work is split into tiles of block_size chains of one target; persistent
+ * workgroups pop tiles from a queue in longest-processing-time-first or
+ * target order, optionally one queue per dimension range. */
+#define RESTORE_BATCH_ORDER_LPT      0
+#define RESTORE_BATCH_ORDER_TARGET   1
+#define RESTORE_BATCH_BUCKETS_ONE    0   /* one persistent kernel for every dimension   */
+#define RESTORE_BATCH_BUCKETS_DIM4   1   /* one per dimension range 1-4, 5-8, 9-12, 13-16 */
+#define RESTORE_BATCH_MODE_GRAPH      0  /* replay of a captured hipGraph of the pass  */
+#define RESTORE_BATCH_MODE_PERSISTENT 1  /* the same launches without the graph        */
+#define RESTORE_BATCH_MODE_SEPARATE   2  /* one launch per target (for comparison)     */
+
+typedef struct {
+    int32_t block_size;   /* chains per tile = threads per workgroup: 64, 128, 256 */
+    int32_t order;        /* RESTORE_BATCH_ORDER_*                                 */
+    int32_t buckets;      /* RESTORE_BATCH_BUCKETS_*                               */
+    int32_t reserved;
+} restore_batch_tiling;
+
+/* Device pointers to one target's per-chain results (float64 tour sums). */
+typedef struct {
+    uint32_t *n_done;
+    double *t_done, *a_done;
+    uint32_t *status;      /* bit0 alive, bit1 censored                 */
+    float *t_cur;          /* lifetime so far of a censored tour        */
+    int64_t n_chains;
+} restore_chain_sums;
+
+typedef struct restore_batch restore_batch;
+
+/* Bytes of caller-owned device memory for the batch (targets table, work
+ * queue, parameter slabs, per-chain results). */
+restore_status restore_batch_state_bytes(int32_t n_targets, const restore_target *targets,
+                                         const restore_local_kernel *locals, const restore_config *cfgs,
+                                         size_t *bytes_out);
+/* Validate, factorise every target's parameters in float64, upload, and
+ * build the work queue for the default tiling (256, LPT, one kernel).
+ * Arrays have n_targets entries; cfgs[i].n_chains, c_tilde, seed,
+ * target_id, integrands and drain_cap are used per target. */
+restore_status restore_batch_init(restore_batch **out, int32_t n_targets, const restore_target *targets,
+                                  const restore_local_kernel *locals, const restore_config *cfgs,
+                                  int32_t n_steps, void *state_dev, size_t state_bytes, void *stream);
+/* Change the tiling (rebuilds the queue, synchronous; results are
+ * independent of the tiling). */
+restore_status restore_batch_set_tiling(restore_batch *b, const restore_batch_tiling *tiling);
+restore_status restore_batch_get_tiling(const restore_batch *b, restore_batch_tiling *tiling);
+/* Enqueue one full pass.  GRAPH captures the pass into a hipGraph on the
+ * first call (on a private stream) and replays it on `stream`. */
+restore_status restore_batch_run(restore_batch *b, int32_t mode, void *stream);
+/* Per-target estimates of the last pass into out[n_targets]; synchronises. */
+restore_status restore_batch_estimates(restore_batch *b, restore_estimate_out *out, void *stream);
+restore_status restore_batch_chain_sums(const restore_batch *b, int32_t target, restore_chain_sums *out);
+/* Time every tiling (block 64/128/256 x order x bucketing) on this batch
+ * with HIP events, keep the fastest and write it to `cache_path` (JSON,
+ * keyed by GPU architecture and batch shape); a matching cache entry is
+ * applied without timing.  cache_path may be NULL. */
+restore_status restore_batch_autotune(restore_batch *b, const char *cache_path, restore_batch_tiling *chosen,
+                                      double *best_ms, void *stream);
+restore_status restore_batch_destroy(restore_batch *b);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *restore_last_error(void);
 

@@ -1,0 +1,253 @@
+// Per-lane machinery of one Jump Restore chain, shared by the single-target
+// kernels and the batched persistent kernel so that both run exactly the
+// same arithmetic for a given (seed, chain, target id).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "restore_internal.h"
+#include "targets.h"
+
+namespace restore {
+
+template <int D>
+struct NBlocks { static constexpr int value = (D + 3) / 4; };
+
+// Parameters of the target in LDS (broadcast reads) or read through the
+// constant address space (wave-uniform addresses -> scalar loads).
+template <bool LDS>
+struct ParamPtr { using type = const_fptr; };
+template <>
+struct ParamPtr<true> { using type = const float *; };
+
+template <bool LDS>
+__device__ __forceinline__ typename ParamPtr<LDS>::type stage_params(const float *params, int n_floats,
+                                                                    float *smem) {
+    if constexpr (LDS) {
+        for (int i = threadIdx.x; i < n_floats; i += blockDim.x) smem[i] = params[i];
+        __syncthreads();
+        return smem;
+    } else {
+        (void)n_floats; (void)smem;
+        return (const_fptr)params;
+    }
+}
+
+template <int D, int MU>
+__device__ __forceinline__ float log_mu(const StepArgs &a, const float y[D]) {
+    // uniform mu on the box: u = 1 there; regeneration never leaves the box
+    (void)a;
+    return in_unit_box<D>(y) ? 0.0f : -INFINITY;
+}
+
+template <int D, int MU, int NC>
+__device__ __forceinline__ void sample_mu(const StepArgs &a, float u_cat, const float cand[NC], float y[D]) {
+    (void)a; (void)u_cat;
+#pragma unroll
+    for (int i = 0; i < D; ++i) y[i] = cand[i];
+}
+
+// Per-lane register state of one chain.
+template <int D, int LOC>
+struct Chain {
+    float x[D];
+    float g[D];
+    float lp, lu;
+    float a_cur, t_cur;
+    double a_done, t_done;
+    uint32_t n_done;
+    uint32_t status;
+    float last_dt;
+    // pixel splats of this lane not yet added to the image: consecutive
+    // steps in the same pixel (rejected moves) are combined in registers
+    int32_t splat_pix;
+    float splat_acc;
+};
+
+__device__ __forceinline__ void flush_splat(const StepArgs &a, int32_t pix, float acc) {
+    if (pix >= 0) atomicAdd(a.image + pix, acc);
+}
+
+template <int D, int LOC>
+__device__ __forceinline__ void load_chain(const StepArgs &a, uint32_t c, Chain<D, LOC> &ch) {
+    const int64_t C = a.n_chains;
+#pragma unroll
+    for (int i = 0; i < D; ++i) ch.x[i] = a.x[i * C + c];
+    if (LOC == LOC_MALA) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) ch.g[i] = a.grad[i * C + c];
+    }
+    ch.lp = a.logp[c];
+    ch.lu = a.logu[c];
+    ch.a_cur = a.a_cur[c];
+    ch.t_cur = a.t_cur[c];
+    ch.a_done = a.a_done[c];
+    ch.t_done = a.t_done[c];
+    ch.n_done = a.n_done[c];
+    ch.status = a.status[c];
+    ch.last_dt = a.last_dt[c];
+    ch.splat_pix = -1;
+    ch.splat_acc = 0.0f;
+}
+
+template <int D, int LOC>
+__device__ __forceinline__ void store_chain(const StepArgs &a, uint32_t c, const Chain<D, LOC> &ch) {
+    const int64_t C = a.n_chains;
+#pragma unroll
+    for (int i = 0; i < D; ++i) a.x[i * C + c] = ch.x[i];
+    if (LOC == LOC_MALA) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) a.grad[i * C + c] = ch.g[i];
+    }
+    a.logp[c] = ch.lp;
+    a.logu[c] = ch.lu;
+    a.a_cur[c] = ch.a_cur;
+    a.t_cur[c] = ch.t_cur;
+    a.a_done[c] = ch.a_done;
+    a.t_done[c] = ch.t_done;
+    a.n_done[c] = ch.n_done;
+    a.status[c] = ch.status;
+    a.last_dt[c] = ch.last_dt;
+}
+
+// One transition of Alg. 2 for one lane.  Returns kill / accept through the
+// flags.  In the drain (RETIRE) a terminated chain is not regenerated.
+template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT>
+__device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
+                                          uint32_t chain, Chain<D, LOC> &ch, bool &kill, bool &accept) {
+    constexpr int NB = NBlocks<D>::value;
+    if constexpr (std::is_same<PT, const_fptr>::value) {
+        // keep the scalar parameter loads inside the step: hoisted out of the
+        // step loop, a large slab overflows the SGPRs and spills to VGPR lanes
+        uint64_t pv = (uint64_t)P;
+        asm volatile("" : "+s"(pv));
+        P = (PT)pv;
+    }
+    float head[4], cand[4 * NB];
+    draw_step<NB>(s, chain, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
+
+    // the two exponential clocks
+    const float t1 = -logf(head[0]);
+    const float e2 = -logf(head[1]);
+    float t2 = INFINITY;
+    kill = false;
+    if (!a.no_kill) {
+        // t2 = E2 / k = E2 exp(log p - log u - ln c_tilde); p = 0 gives t2 = 0
+        t2 = e2 * expf(ch.lp - ch.lu - a.log_c);
+        kill = !(t1 < t2);
+    }
+    const float dt = kill ? t2 : t1;
+
+    // accumulate dt f(x_{i-1}) into the tour in flight
+    ch.t_cur += dt;
+    if (a.integrand_p) ch.a_cur = fmaf(dt, expf(ch.lp), ch.a_cur);
+    if (TGT == TGT_PSS && a.image) {
+        // f = 1_pixel(x0, x1) at the pre-transition state (p = 0 off the box)
+        const float u0 = ch.x[0], u1 = ch.x[1];
+        int32_t pix = -1;
+        if (u0 >= 0.0f && u0 <= 1.0f && u1 >= 0.0f && u1 <= 1.0f) {
+            const int px = min(max((int)(u0 * (float)a.image_w), 0), a.image_w - 1);
+            const int py = min(max((int)(u1 * (float)a.image_h), 0), a.image_h - 1);
+            pix = py * a.image_w + px;
+        }
+        if (pix != ch.splat_pix) {
+            flush_splat(a, ch.splat_pix, ch.splat_acc);
+            ch.splat_pix = pix;
+            ch.splat_acc = 0.0f;
+        }
+        ch.splat_acc += dt;
+    }
+    ch.last_dt = dt;
+    if (kill) {
+        ch.a_done += (double)ch.a_cur;
+        ch.t_done += (double)ch.t_cur;
+        ch.n_done += 1u;
+        ch.a_cur = 0.0f;
+        ch.t_cur = 0.0f;
+    }
+    if (RETIRE && kill) {
+        accept = false;
+        return;
+    }
+
+    // candidate: mu sample if killed, small-step proposal otherwise.  A
+    // regenerated chain gets its gradient only when it first survives a
+    // step, so waves whose lanes were all killed skip that work.
+    float y[D];
+    float zz = 0.0f;
+    const float h = 0.5f * a.step * a.step;
+    if (kill) {
+        sample_mu<D, MU, 4 * NB>(a, head[3], cand, y);
+    } else {
+        if (LOC == LOC_MALA && !(ch.status & ST_GRAD_VALID)) {
+            (void)log_target<D, TGT, true>(P, a.n_comp, ch.x, ch.g);
+            ch.status |= ST_GRAD_VALID;
+        }
+        float z[D];
+        box_muller<D, 4 * NB>(cand, z);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            float delta = a.step * z[i];
+            if (LOC == LOC_MALA) {
+                delta = fmaf(h, ch.g[i], delta);
+                zz = fmaf(z[i], z[i], zz);
+            }
+            y[i] = ch.x[i] + delta;
+        }
+    }
+
+    float gy[D];
+    const float lpy = log_target<D, TGT, LOC == LOC_MALA>(P, a.n_comp, y, gy, !kill);
+    const float luy = log_mu<D, MU>(a, y);
+
+    accept = false;
+    if (!kill) {
+        if (ch.lp == -INFINITY) {
+            accept = true;  // alpha = 1 where p(x) q(x, y) = 0
+        } else {
+            float lr = lpy - ch.lp;
+            if (LOC == LOC_MALA) {
+                // ln q(x->y) = -|z|^2 / 2 ;  ln q(y->x) = -|x - y - h g(y)|^2 / (2 eps^2);
+                // x - y is exact in float32 for neighbouring states (Sterbenz)
+                float rr = 0.0f;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const float r = fmaf(-h, gy[i], ch.x[i] - y[i]);
+                    rr = fmaf(r, r, rr);
+                }
+                lr += 0.5f * zz - rr / (2.0f * a.step * a.step);
+            }
+            accept = logf(head[2]) < lr;
+        }
+    }
+    if (kill || accept) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) ch.x[i] = y[i];
+        if (LOC == LOC_MALA) {
+            if (accept) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) ch.g[i] = gy[i];
+                ch.status |= ST_GRAD_VALID;
+            } else {
+                ch.status &= ~ST_GRAD_VALID;
+            }
+        }
+        ch.lp = lpy;
+        ch.lu = luy;
+    }
+}
+
+__device__ __forceinline__ void add_counters(unsigned long long *counters, unsigned long long t,
+                                             unsigned long long acc, unsigned long long kil) {
+    // one lane per wave publishes the wave's ballot counts
+    const unsigned long long active = __ballot(1);
+    if ((unsigned)lane_id() == (unsigned)(__ffsll((long long)active) - 1)) {
+        atomicAdd(counters + CNT_TRANSITIONS, t);
+        atomicAdd(counters + CNT_ACCEPTS, acc);
+        atomicAdd(counters + CNT_KILLS, kil);
+    }
+}
+
+}  // namespace restore

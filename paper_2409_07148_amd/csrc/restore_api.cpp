@@ -245,6 +245,19 @@ restore_status pack_params(const restore_target *t, const Validated &v, std::vec
 
 }  // namespace
 
+// Entry points shared with the batched runtime (batch_api.cpp).
+restore_status restore_internal_fail(restore_status code, const char *msg) { return fail(code, "%s", msg); }
+
+restore_status restore_internal_pack_full(const restore_target *t, std::vector<float> *out) {
+    Validated v{};
+    v.tgt = TGT_FULL;
+    v.d = t->dim;
+    v.K = t->n_comp;
+    v.loc = LOC_RWMH;
+    v.mu = MU_UNIFORM;
+    return pack_params(t, v, out);
+}
+
 struct restore_ctx {
     Validated v{};
     restore_config cfg{};

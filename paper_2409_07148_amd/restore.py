@@ -76,8 +76,29 @@ class restore_state_view(C.Structure):
                 ("steps_taken", C.c_int32)]
 
 
+BATCH_ORDER_LPT, BATCH_ORDER_TARGET = 0, 1
+BATCH_BUCKETS_ONE, BATCH_BUCKETS_DIM4 = 0, 1
+BATCH_MODE_GRAPH, BATCH_MODE_PERSISTENT, BATCH_MODE_SEPARATE = 0, 1, 2
+
+
+class restore_batch_tiling(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("order", C.c_int32), ("buckets", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"block_size": self.block_size, "order": ["lpt", "target"][self.order],
+                "buckets": ["one", "dim4"][self.buckets]}
+
+
+class restore_chain_sums(C.Structure):
+    _fields_ = [("n_done", C.c_void_p), ("t_done", C.c_void_p), ("a_done", C.c_void_p), ("status", C.c_void_p),
+                ("t_cur", C.c_void_p), ("n_chains", C.c_int64)]
+
+
 EXPORTS = ["restore_state_bytes", "restore_init", "restore_step", "restore_drain", "restore_estimate",
-           "restore_get_state_view", "restore_refresh_cache", "restore_destroy", "restore_last_error"]
+           "restore_get_state_view", "restore_refresh_cache", "restore_destroy",
+           "restore_batch_state_bytes", "restore_batch_init", "restore_batch_set_tiling",
+           "restore_batch_get_tiling", "restore_batch_run", "restore_batch_estimates", "restore_batch_chain_sums",
+           "restore_batch_autotune", "restore_batch_destroy", "restore_last_error"]
 
 
 def _load() -> C.CDLL:
@@ -96,6 +117,18 @@ def _load() -> C.CDLL:
     lib.restore_get_state_view.argtypes = [C.c_void_p, P(restore_state_view)]
     lib.restore_refresh_cache.argtypes = [C.c_void_p, C.c_void_p]
     lib.restore_destroy.argtypes = [C.c_void_p]
+    lib.restore_batch_state_bytes.argtypes = [C.c_int32, P(restore_target), P(restore_local_kernel),
+                                              P(restore_config), P(C.c_size_t)]
+    lib.restore_batch_init.argtypes = [P(C.c_void_p), C.c_int32, P(restore_target), P(restore_local_kernel),
+                                       P(restore_config), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]
+    lib.restore_batch_set_tiling.argtypes = [C.c_void_p, P(restore_batch_tiling)]
+    lib.restore_batch_get_tiling.argtypes = [C.c_void_p, P(restore_batch_tiling)]
+    lib.restore_batch_run.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+    lib.restore_batch_estimates.argtypes = [C.c_void_p, P(restore_estimate_out), C.c_void_p]
+    lib.restore_batch_chain_sums.argtypes = [C.c_void_p, C.c_int32, P(restore_chain_sums)]
+    lib.restore_batch_autotune.argtypes = [C.c_void_p, C.c_char_p, P(restore_batch_tiling), P(C.c_double),
+                                           C.c_void_p]
+    lib.restore_batch_destroy.argtypes = [C.c_void_p]
     lib.restore_last_error.restype = C.c_char_p
     for name in EXPORTS[:-1]:
         getattr(lib, name).restype = C.c_int32
@@ -167,6 +200,69 @@ def restore_destroy(ctx) -> None:
 
 def restore_last_error() -> str:
     return _lib.restore_last_error().decode()
+
+
+def _arr(cls, items):
+    a = (cls * len(items))()
+    for i, it in enumerate(items):
+        a[i] = it
+    return a
+
+
+def restore_batch_state_bytes(targets, locals_, cfgs) -> int:
+    out = C.c_size_t(0)
+    n = len(targets)
+    _check(_lib.restore_batch_state_bytes(n, _arr(restore_target, targets), _arr(restore_local_kernel, locals_),
+                                          _arr(restore_config, cfgs), C.byref(out)))
+    return out.value
+
+
+def restore_batch_init(targets, locals_, cfgs, n_steps: int, state_ptr: int, state_bytes: int,
+                       stream=None) -> C.c_void_p:
+    b = C.c_void_p()
+    n = len(targets)
+    _check(_lib.restore_batch_init(C.byref(b), n, _arr(restore_target, targets), _arr(restore_local_kernel, locals_),
+                                   _arr(restore_config, cfgs), int(n_steps), C.c_void_p(state_ptr), state_bytes,
+                                   C.c_void_p(_stream(stream))))
+    return b
+
+
+def restore_batch_set_tiling(b, tiling: restore_batch_tiling) -> None:
+    _check(_lib.restore_batch_set_tiling(b, C.byref(tiling)))
+
+
+def restore_batch_get_tiling(b) -> restore_batch_tiling:
+    t = restore_batch_tiling()
+    _check(_lib.restore_batch_get_tiling(b, C.byref(t)))
+    return t
+
+
+def restore_batch_run(b, mode: int = BATCH_MODE_GRAPH, stream=None) -> None:
+    _check(_lib.restore_batch_run(b, int(mode), C.c_void_p(_stream(stream))))
+
+
+def restore_batch_estimates(b, n_targets: int, stream=None) -> list:
+    out = (restore_estimate_out * n_targets)()
+    _check(_lib.restore_batch_estimates(b, out, C.c_void_p(_stream(stream))))
+    return [o.as_dict() for o in out]
+
+
+def restore_batch_chain_sums(b, target: int) -> restore_chain_sums:
+    v = restore_chain_sums()
+    _check(_lib.restore_batch_chain_sums(b, int(target), C.byref(v)))
+    return v
+
+
+def restore_batch_autotune(b, cache_path=None, stream=None):
+    t = restore_batch_tiling()
+    ms = C.c_double(0.0)
+    _check(_lib.restore_batch_autotune(b, cache_path.encode() if cache_path else None, C.byref(t), C.byref(ms),
+                                       C.c_void_p(_stream(stream))))
+    return t, ms.value
+
+
+def restore_batch_destroy(b) -> None:
+    _check(_lib.restore_batch_destroy(b))
 
 
 # ---------------------------------------------------------------------------
@@ -308,6 +404,62 @@ class Run:
         if self.ctx:
             restore_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many targets advanced together on the current GPU: owns the torch
+    state buffer and the library's batch handle."""
+
+    def __init__(self, workloads, n_steps: int, stream=None):
+        self.stream = stream
+        self.probs = [problem_from_workload(w, target_id=i, integrand_p=True) for i, w in enumerate(workloads)]
+        targets = [p.target for p in self.probs]
+        locs = [p.local for p in self.probs]
+        cfgs = [p.cfg for p in self.probs]
+        self.n = len(self.probs)
+        nbytes = restore_batch_state_bytes(targets, locs, cfgs)
+        self.state = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self.state.data_ptr() + 255) // 256 * 256
+        self.handle = restore_batch_init(targets, locs, cfgs, n_steps, ptr, nbytes, stream)
+
+    def run(self, mode: int = BATCH_MODE_GRAPH):
+        restore_batch_run(self.handle, mode, self.stream)
+
+    def estimates(self) -> list:
+        return restore_batch_estimates(self.handle, self.n, self.stream)
+
+    def set_tiling(self, block_size=256, order=BATCH_ORDER_LPT, buckets=BATCH_BUCKETS_ONE):
+        restore_batch_set_tiling(self.handle, restore_batch_tiling(block_size, order, buckets, 0))
+
+    def tiling(self) -> restore_batch_tiling:
+        return restore_batch_get_tiling(self.handle)
+
+    def autotune(self, cache_path=None):
+        return restore_batch_autotune(self.handle, cache_path, self.stream)
+
+    def chain_sums(self, target: int) -> dict:
+        v = restore_batch_chain_sums(self.handle, target)
+        n = int(v.n_chains)
+        base = self.state.data_ptr()
+
+        def view(ptr, dtype):
+            size = torch.empty((), dtype=dtype).element_size()
+            off = ptr - base
+            return self.state[off:off + n * size].view(dtype)
+        return {"n_done": view(v.n_done, torch.int32), "t_done": view(v.t_done, torch.float64),
+                "a_done": view(v.a_done, torch.float64), "status": view(v.status, torch.int32),
+                "t_cur": view(v.t_cur, torch.float32)}
+
+    def close(self):
+        if self.handle:
+            restore_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

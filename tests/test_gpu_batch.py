@@ -1,0 +1,154 @@
+"""The batched path (many uneven targets, one persistent work-queue launch
+captured in a hipGraph) against single-target runs and the oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2409_07148_amd import restore
+    return restore
+
+
+def _small_batch(n_targets=12, n_steps=48, lo=200, hi=3000):
+    from workloads import batched_uneven
+    return batched_uneven(n_targets=n_targets, n_steps=n_steps, chains_lo=lo, chains_hi=hi)
+
+
+def _sums(batch, t):
+    return {k: v.cpu().numpy().copy() for k, v in batch.chain_sums(t).items()}
+
+
+def test_batch_targets_reproduce_single_target_runs(R):
+    """Target i of the batch (Philox target id i) follows exactly the
+    trajectories of a single-target run with target id i."""
+    wls = _small_batch()
+    b = R.Batch(wls, n_steps=wls[0].n_steps)
+    b.run()
+    for t in (0, 3, 7, 11):
+        wl = wls[t]
+        run = R.Run(R.problem_from_workload(wl, target_id=t))
+        run.step(wl.n_steps)
+        run.drain()
+        arr = run.arrays()
+        got = _sums(b, t)
+        assert np.array_equal(got["n_done"], arr["n_done"].cpu().numpy())
+        assert np.array_equal(got["t_done"], arr["t_done"].cpu().numpy())
+        assert np.array_equal(got["a_done"], arr["a_done"].cpu().numpy())
+        est = run.estimate()
+        bt = b.estimates()[t]
+        # identical per-chain sums; the two reductions use different fixed trees
+        assert abs(bt["p_lambda"] / est["p_lambda"] - 1) < 1e-12 and bt["transitions"] == est["transitions"]
+        _say(f"[batch vs single] target {t} (d={wl.d}, K={wl.K}, chains {wl.n_chains}): identical")
+        run.close()
+    b.close()
+
+
+def test_batch_results_do_not_depend_on_tiling_or_mode(R):
+    wls = _small_batch(n_targets=10)
+    b = R.Batch(wls, n_steps=wls[0].n_steps)
+    b.run()
+    ref = [_sums(b, t) for t in range(len(wls))]
+    ref_est = b.estimates()
+    for block, order, buckets, mode in [(64, 0, 0, R.BATCH_MODE_GRAPH), (128, 1, 1, R.BATCH_MODE_GRAPH),
+                                        (256, 0, 1, R.BATCH_MODE_PERSISTENT), (64, 1, 0, R.BATCH_MODE_SEPARATE),
+                                        (256, 1, 1, R.BATCH_MODE_SEPARATE)]:
+        b.set_tiling(block, order, buckets)
+        b.run(mode)
+        est = b.estimates()
+        for t in range(len(wls)):
+            got = _sums(b, t)
+            for k in ref[t]:
+                assert np.array_equal(ref[t][k], got[k]), (block, order, buckets, mode, t, k)
+            assert est[t]["p_lambda"] == ref_est[t]["p_lambda"]
+            assert est[t]["transitions"] == ref_est[t]["transitions"]
+    b.close()
+
+
+def test_graph_replays_with_eager_work_between(R):
+    """Replays of the captured pass, with unrelated eager GPU work and
+    synchronisations between them, each give the eager pass's results."""
+    import torch
+    wls = _small_batch(n_targets=6)
+    b = R.Batch(wls, n_steps=wls[0].n_steps)
+    b.run(R.BATCH_MODE_PERSISTENT)
+    ref = b.estimates()
+    for rep in range(3):
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        b.run(R.BATCH_MODE_GRAPH)
+        est = b.estimates()
+        for t in range(len(wls)):
+            assert est[t]["p_lambda"] == ref[t]["p_lambda"], (rep, t)
+            assert est[t]["transitions"] == ref[t]["transitions"]
+    b.close()
+
+
+def test_autotune_picks_and_caches_a_tiling(R, tmp_path):
+    wls = _small_batch(n_targets=8)
+    b = R.Batch(wls, n_steps=wls[0].n_steps)
+    cache = str(tmp_path / "tiling.json")
+    t1, ms1 = b.autotune(cache)
+    assert os.path.exists(cache) and ms1 > 0
+    b2 = R.Batch(wls, n_steps=wls[0].n_steps)
+    t2, ms2 = b2.autotune(cache)
+    assert (t1.block_size, t1.order, t1.buckets) == (t2.block_size, t2.order, t2.buckets)
+    assert abs(ms2 - ms1) < 1e-3  # the cache stores the time to 1e-4 ms
+    _say(f"[autotune] chose {t1.as_dict()} at {ms1:.3f} ms")
+    b.close()
+    b2.close()
+
+
+def test_full_batch_sampled_chains_match_oracle(R):
+    """The full 256-target batch (log-uniform 1K..256K chains, d 2..16, K
+    2..32, 256 steps): chains of a few targets rerun by the oracle from the
+    same counters."""
+    from workloads import batched_uneven
+    from oracle import oracle as O
+    wls = batched_uneven()
+    _say(f"[full batch] {len(wls)} targets, {sum(w.n_chains for w in wls)} chains")
+    b = R.Batch(wls, n_steps=256)
+    b.run()
+    est = b.estimates()
+    _say(f"[full batch] transitions {sum(e['transitions'] for e in est)}, "
+         f"censored {sum(e['tours_censored'] for e in est)}")
+    rng = np.random.default_rng(5)
+    picks = [int(i) for i in rng.choice(len(wls), 4, replace=False)]
+    picks.append(int(np.argmax([w.d * 100 + w.K for w in wls])))
+    # holding times below the float32 range (~1e-38; c_tilde reaches 1e17
+    # here) are zero on the GPU and tiny in the FP64 oracle: per chain at
+    # most ~1000 of them, hence the absolute floor
+    floor = 1e-35
+    same = total = 0
+    shown = 0
+    for t in picks:
+        wl = wls[t]
+        got = _sums(b, t)
+        oprob = O.Problem(wl, target_id=t)
+        for c in rng.integers(0, wl.n_chains, 12):
+            r = O.run(oprob, int(c), int(c) + 1, threads=1)
+            total += 1
+            ok = (int(got["n_done"][c]) == int(r.n_done[0]) and
+                  abs(got["t_done"][c] - r.t_done[0]) <= 1e-4 * abs(r.t_done[0]) + floor)
+            same += ok
+            if not ok and shown < 6:
+                shown += 1
+                _say(f"[full batch] mismatch target {t} chain {c}: n {got['n_done'][c]} vs {r.n_done[0]}, "
+                     f"T {got['t_done'][c]:.6e} vs {r.t_done[0]:.6e}")
+        _say(f"[full batch] target {t}: d={wl.d} K={wl.K} chains={wl.n_chains} c~={wl.c_tilde:g} "
+             f"p_lambda {est[t]['p_lambda']:.4g} +- {est[t]['p_lambda_se']:.2g}")
+    _say(f"[full batch] sampled chains identical to the oracle: {same}/{total}")
+    assert same >= total - 2
+    b.close()

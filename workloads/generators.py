@@ -201,9 +201,13 @@ def batched_uneven(n_targets: int = 256, problem_seed: int = 1005,
         K = int(rng.integers(2, 33))
         n_chains = int(round(math.exp(rng.uniform(math.log(chains_lo), math.log(chains_hi)))))
         w, m, c = _full_cov_mixture(rng, d, K)
+        # c_tilde by the same lifetime rule as the single workloads (mean
+        # lifetime <= B/8 under the peak bound sum_k w_k N_k(m_k; m_k, S_k))
+        peak = float((w * (2 * math.pi) ** (-d / 2) / np.sqrt(np.linalg.det(c))).sum())
+        c_tilde = float(f"{max(1.0, 8.0 * peak / n_steps):.2e}")
         out.append(Workload(f"batched_{t}", "gmm_full", d, K,
                             {"weights": w, "means": m, "covs": c}, "rwmh",
-                            0.02, n_chains, n_steps, 4 * n_steps, 1.0, seed,
+                            0.02, n_chains, n_steps, 4 * n_steps, c_tilde, seed,
                             problem_seed))
     return out
 

@@ -92,10 +92,12 @@ typedef struct {
  *  GMM_DIAG:    u(y) = beta 1_box(y) + (1 - beta) sum_k pi_k N(y; m_k, diag(s_k^2)),
  *               pi = softmax(logits), s = exp(log_std).  `params_dev` is a
  *               caller-owned device float32 buffer [ logits (K) | m (K*d) |
- *               log_std (K*d) ] read by every step (the learned mu; it must
- *               not change during a run).  Sampling: one uniform picks the
- *               uniform share (u < beta) or a component by the cumulative
- *               weights; the component draw is m_k + s_k z.                */
+ *               log_std (K*d) ], read once by restore_init and factorised
+ *               in float64: mu stays frozen for the run (it must not depend
+ *               on the state for k = c_tilde u / p to hold, Sec. 6.2).
+ *               Sampling: one uniform picks the uniform share (u < beta) or
+ *               a component by the cumulative weights; the component draw
+ *               is m_k + s_k z with the step's Box-Muller normals.         */
 typedef struct {
     int32_t kind;
     int32_t n_comp;

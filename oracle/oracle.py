@@ -284,7 +284,7 @@ def transitions(prob: Problem, states: States, steps, chains, recompute: bool = 
     chains = np.ascontiguousarray(np.asarray(chains, dtype=np.uint32))
     dt = np.zeros(n)
     flags = np.zeros(n, dtype=np.int32)
-    margins = np.zeros((n, 2))
+    margins = np.zeros((n, 3))
     lib.oracle_transitions(C.byref(prob.target), C.byref(prob.mu), C.byref(prob.local),
                            C.byref(prob.cfg), n, _ptr(steps, C.c_uint32), _ptr(chains, C.c_uint32),
                            _ptr(st.x), _ptr(st.lp), _ptr(st.lu), _ptr(st.g), 1 if recompute else 0,

@@ -282,10 +282,13 @@ double oracle_log_mu(const or_mu *mu, const double *y)
     return log_sum_exp(mu->K + 1, a);
 }
 
-/* y ~ mu from the step's category uniform and candidate uniforms */
-static void sample_mu(const or_mu *mu, double u_cat, const double cand[OR_MAXD], double *y)
+/* y ~ mu from the step's category uniform and candidate uniforms; *margin
+ * gets the distance of u_cat to the nearest category boundary (INFINITY for
+ * uniform mu) */
+static void sample_mu(const or_mu *mu, double u_cat, const double cand[OR_MAXD], double *y, double *margin)
 {
     int d = mu->d;
+    *margin = INFINITY;
     if (mu->kind == OR_MU_UNIFORM) {
         for (int i = 0; i < d; ++i) y[i] = cand[i];
         return;
@@ -296,15 +299,19 @@ static void sample_mu(const or_mu *mu, double u_cat, const double cand[OR_MAXD],
     for (int k = 0; k < mu->K; ++k) if (mu->logit[k] > m) m = mu->logit[k];
     for (int k = 0; k < mu->K; ++k) s += exp(mu->logit[k] - m);
     double cum = mu->beta;
-    if (u_cat < cum) {
+    *margin = fabs(u_cat - cum);
+    int pick = -1;
+    for (int k = 0; k < mu->K; ++k) {
+        double next = cum + (1.0 - mu->beta) * exp(mu->logit[k] - m) / s;
+        if (k < mu->K - 1 && fabs(u_cat - next) < *margin) *margin = fabs(u_cat - next);
+        if (pick < 0 && u_cat >= cum && u_cat < next) pick = k;
+        cum = next;
+    }
+    if (u_cat < mu->beta) {
         for (int i = 0; i < d; ++i) y[i] = cand[i];
         return;
     }
-    int pick = mu->K - 1;
-    for (int k = 0; k < mu->K; ++k) {
-        cum += (1.0 - mu->beta) * exp(mu->logit[k] - m) / s;
-        if (u_cat < cum) { pick = k; break; }
-    }
+    if (pick < 0) pick = mu->K - 1;
     double z[OR_MAXD];
     box_muller(d, cand, z);
     for (int i = 0; i < d; ++i)
@@ -338,9 +345,9 @@ static double log_q(const or_local *lk, int d, const double *a, const double *ga
 void oracle_init_state(const or_target *t, const or_mu *mu, const or_config *cfg,
                        uint32_t chain, or_state *st)
 {
-    double head[4], cand[OR_MAXD];
+    double head[4], cand[OR_MAXD], margin;
     draw_step(cfg, t->d, 0, chain, OR_PURPOSE_INIT, head, cand);
-    sample_mu(mu, head[3], cand, st->x);
+    sample_mu(mu, head[3], cand, st->x, &margin);
     st->lp = oracle_log_target(t, st->x, st->g);
     st->lu = oracle_log_mu(mu, st->x);
 }
@@ -348,10 +355,12 @@ void oracle_init_state(const or_target *t, const or_mu *mu, const or_config *cfg
 /* One Jump Restore transition from st at step `step`.
  * Returns dt; *flags gets KILL / ACCEPT / OUTSIDE bits; margins[0] is
  * ln t2 - ln t1 (kill iff <= 0), margins[1] is ln u_acc - ln(ratio)
- * (accept iff < 0; NAN when no acceptance test was made). */
+ * (accept iff < 0; NAN when no acceptance test was made), margins[2] is the
+ * distance of the category uniform to the nearest mu category boundary
+ * (INFINITY unless a learned mu was sampled). */
 double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk,
                          const or_config *cfg, uint32_t step, uint32_t chain,
-                         or_state *st, int32_t *flags, double margins[2])
+                         or_state *st, int32_t *flags, double margins[3])
 {
     int d = t->d;
     double head[4], cand[OR_MAXD];
@@ -366,6 +375,7 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
     else { log_k = log(cfg->c_tilde) + st->lu - st->lp; t2 = e2 * exp(-log_k); }
     margins[0] = log(e2) - log_k - log(t1);
     margins[1] = NAN;
+    margins[2] = INFINITY;
 
     int32_t fl = 0;
     double dt;
@@ -397,7 +407,7 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
         /* termination: regenerate from mu */
         dt = t2;
         fl |= OR_FLAG_KILL;
-        sample_mu(mu, head[3], cand, st->x);
+        sample_mu(mu, head[3], cand, st->x, &margins[2]);
         st->lp = oracle_log_target(t, st->x, st->g);
         st->lu = oracle_log_mu(mu, st->x);
     }
@@ -424,7 +434,7 @@ void oracle_transitions(const or_target *t, const or_mu *mu, const or_local *lk,
             st.lp = lp[c]; st.lu = lu[c];
             for (int i = 0; i < d; ++i) st.g[i] = g[c * d + i];
         }
-        dt[c] = oracle_transition(t, mu, lk, cfg, steps[c], chains[c], &st, &flags[c], &margins[2 * c]);
+        dt[c] = oracle_transition(t, mu, lk, cfg, steps[c], chains[c], &st, &flags[c], &margins[3 * c]);
         for (int i = 0; i < d; ++i) { x[c * d + i] = st.x[i]; g[c * d + i] = st.g[i]; }
         lp[c] = st.lp; lu[c] = st.lu;
     }
@@ -485,7 +495,7 @@ static void run_chain(const or_job *job, int64_t c)
         memcpy(x_prev, st.x, sizeof(double) * t->d);
         double lp_prev = st.lp;
         or_state before = st;
-        int32_t fl; double mg[2];
+        int32_t fl; double mg[3];
         double dt = oracle_transition(t, job->mu, job->lk, cfg, (uint32_t)s, (uint32_t)c, &st, &fl, mg);
         ++trans;
         t_cur += dt;

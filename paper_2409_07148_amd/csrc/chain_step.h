@@ -37,16 +37,24 @@ __device__ __forceinline__ typename ParamPtr<LDS>::type stage_params(const float
 
 template <int D, int MU>
 __device__ __forceinline__ float log_mu(const StepArgs &a, const float y[D]) {
-    // uniform mu on the box: u = 1 there; regeneration never leaves the box
-    (void)a;
-    return in_unit_box<D>(y) ? 0.0f : -INFINITY;
+    if constexpr (MU == MU_GMM) {
+        return MuGmm<D>::log_u((const_fptr)a.mu_params, a.mu_comp, y);
+    } else {
+        // uniform mu on the box: u = 1 there
+        (void)a;
+        return in_unit_box<D>(y) ? 0.0f : -INFINITY;
+    }
 }
 
 template <int D, int MU, int NC>
 __device__ __forceinline__ void sample_mu(const StepArgs &a, float u_cat, const float cand[NC], float y[D]) {
-    (void)a; (void)u_cat;
+    if constexpr (MU == MU_GMM) {
+        MuGmm<D>::template sample<const_fptr, NC>((const_fptr)a.mu_params, a.mu_params, a.mu_comp, u_cat, cand, y);
+    } else {
+        (void)a; (void)u_cat;
 #pragma unroll
-    for (int i = 0; i < D; ++i) y[i] = cand[i];
+        for (int i = 0; i < D; ++i) y[i] = cand[i];
+    }
 }
 
 // Per-lane register state of one chain.

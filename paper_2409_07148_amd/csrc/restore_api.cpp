@@ -43,7 +43,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t x, logp, logu, grad, a_cur, t_cur, last_dt, a_done, t_done, n_done, status;
-    size_t list0, list1, counts, counters, params, partials, results, total;
+    size_t list0, list1, counts, counters, params, mu, partials, results, total;
 };
 
 int n_param_floats(int tgt, int d, int K) {
@@ -51,7 +51,7 @@ int n_param_floats(int tgt, int d, int K) {
     return comp_stride(tgt, d) * K;
 }
 
-Layout make_layout(int64_t C, int d, bool mala, int n_params) {
+Layout make_layout(int64_t C, int d, bool mala, int n_params, int n_mu_floats) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
@@ -72,6 +72,7 @@ Layout make_layout(int64_t C, int d, bool mala, int n_params) {
     L.counts = take(4 * 4);
     L.counters = take(8 * CNT_SLOTS);
     L.params = take(4 * (size_t)n_params);
+    L.mu = n_mu_floats > 0 ? take(4 * (size_t)n_mu_floats) : (size_t)-1;
     L.partials = take(8 * (size_t)RED_BLOCKS * RED_SLOTS);
     L.results = take(8 * RED_SLOTS);
     L.total = o;
@@ -243,6 +244,42 @@ restore_status pack_params(const restore_target *t, const Validated &v, std::vec
     return RESTORE_OK;
 }
 
+// Learned mu slab (layout in restore_internal.h) from logits, means and log
+// standard deviations, in float64.
+restore_status pack_mu(const std::vector<float> &raw, int K, int d, float beta, std::vector<float> *out) {
+    for (float f : raw)
+        if (!std::isfinite(f)) return fail(RESTORE_E_NONFINITE, "non-finite learned mu parameter");
+    const float *logit = raw.data(), *mean = logit + K, *lstd = mean + (size_t)K * d;
+    double mx = -INFINITY;
+    for (int k = 0; k < K; ++k) mx = std::max(mx, (double)logit[k]);
+    double den = 0.0;
+    for (int k = 0; k < K; ++k) den += std::exp((double)logit[k] - mx);
+    const double b = beta;
+    const int S = mu_stride(d);
+    out->assign((size_t)mu_slab_floats(d, K), 0.0f);
+    float *o = out->data();
+    o[0] = b > 0.0 ? (float)std::log(b) : -INFINITY;
+    double cum = b;
+    for (int k = 0; k < K; ++k) {
+        const double pk = std::exp((double)logit[k] - mx) / den;
+        double c = (b < 1.0 ? std::log1p(-b) : -INFINITY) + std::log(pk) - 0.5 * d * std::log(2.0 * M_PI);
+        float *ck = o + 4 + (size_t)k * S;
+        float *ms = o + 4 + (size_t)K * S + K + (size_t)k * 2 * d;
+        for (int i = 0; i < d; ++i) {
+            const double ls = lstd[(size_t)k * d + i];
+            c -= ls;
+            ck[1 + i] = mean[(size_t)k * d + i];
+            ck[1 + d + i] = (float)std::exp(-ls);
+            ms[i] = mean[(size_t)k * d + i];
+            ms[d + i] = (float)std::exp(ls);
+        }
+        ck[0] = (float)c;
+        o[4 + (size_t)K * S + k] = (float)cum;
+        cum += (1.0 - b) * pk;
+    }
+    return RESTORE_OK;
+}
+
 }  // namespace
 
 // Entry points shared with the batched runtime (batch_api.cpp).
@@ -297,7 +334,7 @@ void fill_args(restore_ctx *c) {
     a.status = at<uint32_t>(c, c->lay.status);
     a.counters = at<unsigned long long>(c, c->lay.counters);
     a.params = at<float>(c, c->lay.params);
-    a.mu_params = c->mu.params_dev;
+    a.mu_params = c->v.mu == MU_GMM ? at<float>(c, c->lay.mu) : nullptr;
     a.image = c->image;
     a.list = nullptr;
     a.list_count = nullptr;
@@ -343,7 +380,8 @@ restore_status restore_state_bytes(const restore_target *target, const restore_m
     Validated v;
     restore_status st = validate(target, mu, local, cfg, &v);
     if (st != RESTORE_OK) return st;
-    *bytes_out = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_param_floats(v.tgt, v.d, v.K)).total;
+    *bytes_out = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_param_floats(v.tgt, v.d, v.K),
+                             v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0).total;
     return RESTORE_OK;
 }
 
@@ -361,7 +399,8 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     if ((cfg->integrands & RESTORE_INTEGRAND_PIXEL) && !image_dev)
         return fail(RESTORE_E_INVALID_ARG, "pixel integrand needs an image buffer");
     const int n_params = n_param_floats(v.tgt, v.d, v.K);
-    const Layout lay = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_params);
+    const int n_mu = v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0;
+    const Layout lay = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_params, n_mu);
     if (state_bytes < lay.total)
         return fail(RESTORE_E_BUFFER_TOO_SMALL, "state buffer holds %zu bytes, %zu needed", state_bytes, lay.total);
     KernelSet ks = find_kernels(v.tgt, v.d, v.loc, v.mu);
@@ -390,6 +429,21 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     hipError_t e = hipMemcpyAsync(const_cast<float *>(c->args.params), slab.data(), slab.size() * sizeof(float),
                                   hipMemcpyHostToDevice, s);
     if (e != hipSuccess) { delete c; return hip_fail(e, "parameter upload"); }
+    std::vector<float> mu_slab;
+    if (v.mu == MU_GMM) {
+        // the learned mu is frozen for the run: read the caller's parameters
+        // once and factorise them in float64
+        const int K = mu->n_comp, d = v.d;
+        std::vector<float> raw((size_t)K * (1 + 2 * d));
+        e = hipMemcpyAsync(raw.data(), mu->params_dev, raw.size() * sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { delete c; return hip_fail(e, "mu parameter read"); }
+        st = pack_mu(raw, K, d, mu->beta, &mu_slab);
+        if (st != RESTORE_OK) { delete c; return st; }
+        e = hipMemcpyAsync(at<float>(c, c->lay.mu), mu_slab.data(), mu_slab.size() * sizeof(float),
+                           hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) { delete c; return hip_fail(e, "mu upload"); }
+    }
     // the upload reads a host vector that goes away: finish it before returning
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) { delete c; return hip_fail(e, "parameter upload"); }

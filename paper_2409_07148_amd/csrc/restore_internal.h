@@ -36,6 +36,16 @@ __host__ __device__ constexpr int comp_stride(int kind, int d) {
 //   4 pi w_l kappa_l / (2 pi (1 - e^{-2 kappa_l}))                      [111] b
 constexpr int PSS_SLAB = 112;
 
+// Learned regeneration distribution slab (float32, factorised on the host
+// in float64 from the caller's logits / means / log standard deviations):
+//   [0]                 ln beta (-inf when beta = 0)
+//   [4 + k * S, ...)    component k: [ c_k | m_k (d) | 1/s_k (d) ],
+//                       c_k = ln(1 - beta) + ln pi_k - d/2 ln 2 pi - sum_i ln s_ki
+//   [4 + K * S, ...)    cumulative weights q_0 = beta, q_j = beta + (1 - beta) sum_{k<j} pi_k
+//   [4 + K * S + K, ...) per component [ m_k (d) | s_k (d) ] for the sampler
+__host__ __device__ constexpr int mu_stride(int d) { return ((1 + 2 * d + 3) / 4) * 4; }
+__host__ __device__ constexpr int mu_slab_floats(int d, int K) { return 4 + K * mu_stride(d) + K + K * 2 * d; }
+
 // Per-launch arguments of the step kernels.
 struct StepArgs {
     // chain state (structure of arrays, C chains)

@@ -169,7 +169,19 @@ static KernelSet make_set() {
     case 15: return make_set<15, TGT, LOC, MU>(); case 16: return make_set<16, TGT, LOC, MU>();
 
 KernelSet find_kernels(int tgt, int d, int loc, int mu) {
-    if (mu != MU_UNIFORM) return KernelSet{};
+    if (mu == MU_GMM) {
+        // learned regeneration distribution: the mixtures of the learned-mu workloads
+        if (tgt == TGT_FULL && loc == LOC_MALA) {
+            switch (d) { case 2: return make_set<2, TGT_FULL, LOC_MALA, MU_GMM>();
+                         case 8: return make_set<8, TGT_FULL, LOC_MALA, MU_GMM>(); default: break; }
+        }
+        if (tgt == TGT_FULL && loc == LOC_RWMH) {
+            switch (d) { case 2: return make_set<2, TGT_FULL, LOC_RWMH, MU_GMM>();
+                         case 8: return make_set<8, TGT_FULL, LOC_RWMH, MU_GMM>(); default: break; }
+        }
+        if (tgt == TGT_ISO && loc == LOC_RWMH && d == 2) return make_set<2, TGT_ISO, LOC_RWMH, MU_GMM>();
+        return KernelSet{};
+    }
     if (tgt == TGT_PSS) {
         if (d == 12 && loc == LOC_RWMH) return make_set<12, TGT_PSS, LOC_RWMH, MU_UNIFORM>();
         return KernelSet{};

@@ -168,6 +168,56 @@ struct Pss {
     }
 };
 
+// Learned regeneration distribution: defensive mixture
+//   u(y) = beta 1_box(y) + (1 - beta) sum_k pi_k N(y; m_k, diag(s_k^2))
+// (slab layout in restore_internal.h).  log u by an online log-sum-exp with
+// scalar-loaded parameters; sampling picks the share by the cumulative
+// weights and gathers the chosen component per lane.
+template <int D>
+struct MuGmm {
+    static constexpr int STRIDE = mu_stride(D);
+
+    template <class PT>
+    __device__ __forceinline__ static float log_u(PT P, int K, const float y[D]) {
+        float M = in_unit_box<D>(y) ? P[0] : -INFINITY, S = 1.0f;
+        if (M == -INFINITY) S = 0.0f;
+        for (int k = 0; k < K; ++k) {
+            const auto pk = P + 4 + k * STRIDE;
+            float q = 0.0f;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const float z = (y[i] - pk[1 + i]) * pk[1 + D + i];
+                q = fmaf(z, z, q);
+            }
+            const float ak = fmaf(-0.5f, q, pk[0]);
+            const float Mn = fmaxf(M, ak);
+            S = fmaf(S, exp_rel(M - Mn), exp_rel(ak - Mn));
+            M = Mn;
+        }
+        return M + logf(S);
+    }
+
+    // y ~ mu from the category uniform, the candidate uniforms (uniform
+    // share) and their Box-Muller normals (Gaussian components)
+    template <class PT, int NC>
+    __device__ __forceinline__ static void sample(PT P, const float *G, int K, float u_cat, const float cand[NC],
+                                                  float y[D]) {
+        const auto cum = P + 4 + K * STRIDE;
+        if (u_cat < cum[0]) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) y[i] = cand[i];
+            return;
+        }
+        int pick = 0;
+        for (int j = 1; j < K; ++j) pick += (cum[j] <= u_cat) ? 1 : 0;
+        float z[D];
+        box_muller<D, NC>(cand, z);
+        const float *ms = G + 4 + K * STRIDE + K + pick * 2 * D;
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[i] = fmaf(ms[D + i], z[i], ms[i]);
+    }
+};
+
 template <int D, int TGT>
 struct TargetOf;
 template <int D>

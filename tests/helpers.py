@@ -62,3 +62,12 @@ def chi2_pvalue(obs, expected_counts, min_expected=5.0):
         o2, e2 = o2[:-1], e2[:-1]
     e2 = e2 * o2.sum() / e2.sum()
     return float(stats.chisquare(o2, e2).pvalue)
+
+
+def mixture_mu_from_target(wl, beta=0.1):
+    """A diagonal-Gaussian-mixture mu built from a full-covariance target's
+    own weights, means and marginal variances, with a defensive uniform
+    share beta (the shape of the learned regeneration distribution)."""
+    c = wl.params["covs"]
+    return {"logits": np.log(wl.params["weights"]), "means": wl.params["means"],
+            "log_std": 0.5 * np.log(np.stack([np.diag(ci) for ci in c])), "beta": beta}

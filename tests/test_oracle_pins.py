@@ -368,12 +368,7 @@ def test_whole_run_full_cov_mala_2d_matches_genz_truth(oracle_lib):
         assert abs(est[key] - tr[key]) < 3 * est[key + "_se"], key
 
 
-def mixture_mu_from_target(wl, beta=0.1):
-    """A diagonal-Gaussian-mixture mu built from the target's own weights,
-    means and marginal variances, with a defensive uniform share beta."""
-    c = wl.params["covs"]
-    return {"logits": np.log(wl.params["weights"]), "means": wl.params["means"],
-            "log_std": 0.5 * np.log(np.stack([np.diag(ci) for ci in c])), "beta": beta}
+mixture_mu_from_target = H.mixture_mu_from_target
 
 
 def test_whole_run_8d_mixture_mu_matches_genz_truth(oracle_lib):

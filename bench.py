@@ -165,6 +165,70 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def mse_time(wl, replicates: int = 16, log=None) -> dict:
+    """MSE x time of the learned regeneration distribution against uniform
+    mu on the same workload: train mu_theta (5 refits on restore samples,
+    matrix-core MLP, Adam), then `replicates` independent runs per method
+    (fresh seeds, full chain count and budget, each timed on the wall clock
+    from restore_init to restore_estimate), scored against the stored
+    closed-form truth.  t_1% = time (rel. RMS error / 1%)^2 is the time
+    either method needs to reach 1% relative error."""
+    import numpy as np
+    import torch
+    from paper_2409_07148_amd import restore as R
+    from paper_2409_07148_amd.learned_mu import MlpGmm, provable_c_tilde, refit
+
+    with open(os.path.join(ROOT, "tests", "golden", "truths.json")) as f:
+        truth = json.load(f)[wl.name]
+    model = MlpGmm(d=wl.d, K=64, in_dim=12, hidden=64, beta=0.1, seed=3004)
+    ct_learned = provable_c_tilde(wl.c_tilde, model.beta)
+    t0 = time.perf_counter()
+    hist = refit(wl, model, ct_learned, rounds=5, record_steps=4, epochs=300, lr=2e-2, seed=3004,
+                 c_tilde_explore=1.0, log=log or (lambda *a: None))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    mu = model.mu()
+
+    def runs(mu_, ct):
+        out = []
+        prob = None
+        for r in range(replicates):
+            prob = R.problem_from_workload(wl, mu=mu_, c_tilde=ct, seed=2004 + 17 * r)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            run = R.Run(prob)
+            run.step(wl.n_steps)
+            run.drain()
+            est = run.estimate()
+            out.append((time.perf_counter() - t, est))
+            run.close()
+        return out
+
+    res = {}
+    for name, mu_, ct in (("uniform", None, wl.c_tilde), ("learned", mu, ct_learned)):
+        rr = runs(mu_, ct)
+        secs = np.array([t for t, _ in rr])
+        summary = {"c_tilde": ct, "seconds_per_run": float(secs.mean()),
+                   "transitions_per_s": float(np.mean([e["transitions"] / t for t, e in rr])),
+                   "censored_tours": int(sum(e["tours_censored"] for _, e in rr))}
+        for key in ("lam_pf", "p_lambda"):
+            rel = np.array([(e[key] - truth[key]) / truth[key] for _, e in rr])
+            mse = float((rel ** 2).mean())
+            summary[key] = {"rel_rmse": math.sqrt(mse), "rel_bias": float(rel.mean()),
+                            "mse_x_time": mse * float(secs.mean()),
+                            "t_1pct_s": float(secs.mean()) * mse / 1e-4}
+        res[name] = summary
+    res["replicates"] = replicates
+    res["training_s"] = train_s
+    res["training_rounds"] = hist
+    res["primary"] = "lam_pf"
+    res["mse_x_time_ratio_uniform_over_learned"] = (res["uniform"]["lam_pf"]["mse_x_time"]
+                                                    / res["learned"]["lam_pf"]["mse_x_time"])
+    res["t_1pct_learned_amortised_s"] = (res["learned"]["lam_pf"]["t_1pct_s"]
+                                         + train_s / replicates)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +238,8 @@ def main():
                     choices=["gmm_full_8d", "gmm_iso_2d", "pss_render_12d", "batched_uneven"])
     ap.add_argument("--lds", action="store_true", help="stage mixture parameters in LDS")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mse-time", action="store_true",
+                    help="skip the learned-mu MSE x time comparison (8-D workload only)")
     ap.add_argument("--no-image", action="store_true",
                     help="diagnostic: run the rendering-shaped workload without its pixel integrand")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -281,6 +347,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = src.numel() * 4
+    if wl.name == "gmm_full_8d" and not args.no_mse_time:
+        line["mse_time"] = mse_time(wl)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

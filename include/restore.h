@@ -285,6 +285,61 @@ restore_status restore_batch_autotune(restore_batch *b, const char *cache_path, 
                                       double *best_ms, void *stream);
 restore_status restore_batch_destroy(restore_batch *b);
 
+/* ---- sample collection -------------------------------------------------
+ * Like restore_step, and additionally records, for chains [0, n_record) and
+ * every one of the n_steps steps, the pair (x_{i-1}, dt_i) of Alg. 2's
+ * output: x_out float32 [n_steps][n_record][d], w_out float32
+ * [n_steps][n_record] (caller-owned device memory).  The time-weighted
+ * pairs are draws of pi in the sense of Sec. 7.4, eq. (approx): the
+ * training data of the learned regeneration distribution. */
+restore_status restore_step_record(restore_ctx *ctx, int32_t n_steps, int64_t n_record, float *x_out,
+                                   float *w_out, void *stream);
+
+/* ---- learned regeneration distribution ---------------------------------
+ * mu_theta = (1 - beta) GMM(MLP_theta(c)) + beta Uniform(box): an MLP with
+ * two GELU hidden layers maps a context vector c to the logits, means and
+ * log standard deviations of a diagonal Gaussian mixture, laid out exactly
+ * as restore_mu expects ([logits K | means K*d | log_std K*d]).  It is
+ * trained between runs on restore samples (restore_step_record) by
+ * minimising -sum w log u_theta(x) / sum w, and frozen during a run (mu must
+ * be state-independent for k = c_tilde u / p, Sec. 6.2).
+ * Parameters theta (float32, row-major, out x in):
+ *   [ W1 (H x in) | b1 (H) | W2 (H x H) | b2 (H) | W3 (O x H) | b3 (O) ],
+ *   O = K (1 + 2 d).  The layers run on the matrix cores
+ *   (v_mfma_f32_32x32x16_bf16: bf16 operands, float32 accumulation). */
+typedef struct {
+    int32_t in_dim;   /* context length (12 for the learned-mu workload) */
+    int32_t hidden;   /* H                                               */
+    int32_t n_comp;   /* K <= 64                                         */
+    int32_t dim;      /* d <= 16                                         */
+} restore_mlp_shape;
+
+/* Number of float32 parameters, and activations saved per context row. */
+restore_status restore_mlp_param_count(const restore_mlp_shape *shape, int64_t *n_params, int64_t *n_act_per_row);
+/* out[G][O] = MLP_theta(ctx[G][in]).  act (4 G H floats, from
+ * n_act_per_row) receives four consecutive [G][H] blocks z1, h1, z2, h2
+ * (pre- and post-GELU values of the two hidden layers) for the backward
+ * pass.  Device pointers, caller-owned; enqueue only. */
+restore_status restore_mlp_forward(const restore_mlp_shape *shape, const float *theta, const float *ctx, int32_t G,
+                                   float *act, float *out, void *stream);
+/* grad[n_params] = d(sum_g dout[g] . out[g]) / d theta (overwritten, not
+ * accumulated), from the act of the matching forward call; work: 2 G H
+ * floats of scratch.  Device pointers, caller-owned; enqueue only. */
+restore_status restore_mlp_backward(const restore_mlp_shape *shape, const float *theta, const float *ctx, int32_t G,
+                                    const float *act, const float *dout, float *work, float *grad, void *stream);
+/* Weighted NLL of samples x[n][d] with weights w[n] under the defensive
+ * mixture of one MLP output row gmm[O]: *loss_dev (float64, device) =
+ * -sum w log u / sum w and dout[O] = its gradient with respect to gmm.
+ * Float32 arithmetic on centred scores, float64 accumulation, fixed-order
+ * reduction (bit-reproducible).  workspace: restore_gmm_nll_workspace_bytes. */
+restore_status restore_gmm_nll_workspace_bytes(size_t *bytes);
+restore_status restore_gmm_nll(int32_t n_comp, int32_t dim, float beta, const float *gmm, const float *x,
+                               const float *w, int64_t n, float *dout, double *loss_dev, void *workspace,
+                               size_t workspace_bytes, void *stream);
+/* One Adam step (t >= 1) on float32 master weights. */
+restore_status restore_adam_step(float *theta, const float *grad, float *m, float *v, int64_t n, int32_t t, float lr,
+                                 float beta1, float beta2, float eps, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *restore_last_error(void);
 

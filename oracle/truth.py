@@ -66,11 +66,13 @@ def gmm_iso_power_integral(wl, power: int) -> float:
     return total
 
 
-def _mvn_box_prob(mean, cov, rng_seed=0) -> float:
+def _mvn_box_prob(mean, cov) -> float:
     d = mean.shape[0]
     if d == 1:
         return float(_box_prob_1d(mean[0], math.sqrt(cov[0, 0])))
-    np.random.seed(rng_seed)  # Genz's QMC draws its shifts from numpy's global stream
+    # Genz's randomised lattice rule keeps its own generator state between
+    # calls, so a value depends on the calls before it within its error
+    # (observed ~3e-7 here): reproducible to that accuracy, not bit for bit.
     return float(stats.multivariate_normal.cdf(np.ones(d), mean=mean, cov=cov, maxpts=200000 * d,
                                                abseps=1e-9, releps=1e-7, lower_limit=np.zeros(d)))
 

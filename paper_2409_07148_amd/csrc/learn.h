@@ -1,0 +1,34 @@
+// Launch interface of the learned-mu training kernels (learn_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace restore {
+
+constexpr int LEARN_MAX_DIM = 16;
+
+struct NllArgs {
+    int32_t n_comp, dim;
+    float beta;
+    const float *gmm;      // [logits K | means K*d | log_std K*d]
+    const float *x;        // [n][d]
+    const float *w;        // [n]
+    int64_t n;
+    int32_t n_blocks;
+    double *partials;      // [n_blocks][64][2 + 2 * LEARN_MAX_DIM]
+    double *loss_part;     // [n_blocks][2]
+    float *dout;           // [K (1 + 2d)]
+    double *loss;          // [1]
+};
+
+hipError_t launch_gemm_bf16(int M, int N, int K, const float *A, int64_t lda, bool transA, const float *B, int64_t ldb,
+                            bool transB, float *C, int64_t ldc, bool accumulate, hipStream_t s);
+hipError_t launch_bias_gelu(float *z, float *h, const float *bias, int G, int n, hipStream_t s);
+hipError_t launch_gelu_back(const float *dh, const float *z, float *dz, int count, hipStream_t s);
+hipError_t launch_colsum(const float *d, float *db, int G, int n, hipStream_t s);
+hipError_t launch_gmm_nll(const NllArgs &a, hipStream_t s);
+hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                       float eps, int t, hipStream_t s);
+
+}  // namespace restore

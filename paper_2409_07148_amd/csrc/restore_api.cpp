@@ -353,6 +353,9 @@ void fill_args(restore_ctx *c) {
     a.integrand_p = (c->cfg.integrands & RESTORE_INTEGRAND_P) ? 1 : 0;
     a.image_w = c->cfg.image_w;
     a.image_h = c->cfg.image_h;
+    a.rec_x = nullptr;
+    a.rec_w = nullptr;
+    a.rec_chains = 0;
 }
 
 dim3 grid_for(int64_t n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
@@ -457,7 +460,8 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     return RESTORE_OK;
 }
 
-restore_status restore_step(restore_ctx *c, int32_t n_steps, void *stream) {
+static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_record, float *x_out, float *w_out,
+                                void *stream) {
     if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
     if (c->drained) return fail(RESTORE_E_BAD_STATE, "restore_step after restore_drain");
     if (n_steps < 0) return fail(RESTORE_E_INVALID_ARG, "n_steps must be >= 0");
@@ -467,6 +471,9 @@ restore_status restore_step(restore_ctx *c, int32_t n_steps, void *stream) {
     StepArgs a = c->args;
     a.s0 = (uint32_t)c->steps_taken;
     a.n_steps = n_steps;
+    a.rec_x = x_out;
+    a.rec_w = w_out;
+    a.rec_chains = n_record;
     int np = c->n_params;
     void *kargs[] = {&a, &np};
     const void *fn = c->lds ? c->ks.step_lds : c->ks.step;
@@ -476,6 +483,18 @@ restore_status restore_step(restore_ctx *c, int32_t n_steps, void *stream) {
     if (e != hipSuccess) return hip_fail(e, "step launch");
     c->steps_taken += n_steps;
     return RESTORE_OK;
+}
+
+restore_status restore_step(restore_ctx *c, int32_t n_steps, void *stream) {
+    return step_impl(c, n_steps, 0, nullptr, nullptr, stream);
+}
+
+restore_status restore_step_record(restore_ctx *c, int32_t n_steps, int64_t n_record, float *x_out, float *w_out,
+                                   void *stream) {
+    if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
+    if (n_record < 1 || n_record > c->cfg.n_chains || !x_out || !w_out)
+        return fail(RESTORE_E_INVALID_ARG, "n_record must be in 1..n_chains with non-null buffers");
+    return step_impl(c, n_steps, n_record, x_out, w_out, stream);
 }
 
 restore_status restore_drain(restore_ctx *c, void *stream) {

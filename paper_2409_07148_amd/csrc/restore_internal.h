@@ -79,6 +79,10 @@ struct StepArgs {
     int32_t n_steps;   // steps in this launch
     int32_t integrand_p;
     int32_t image_w, image_h;
+    // sample recording (restore_step_record): (x_{i-1}, dt_i) of chains < rec_chains
+    float *rec_x;      // [n_steps][rec_chains][D]
+    float *rec_w;      // [n_steps][rec_chains]
+    int64_t rec_chains;
 };
 
 }  // namespace restore

@@ -33,8 +33,15 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_float
     load_chain(a, (uint32_t)c, ch);
     unsigned long long n_acc = 0, n_kill = 0;
     bool kill = false, accept = false;
+    const bool rec = a.rec_x != nullptr && c < a.rec_chains;
     for (int it = 0; it < a.n_steps; ++it) {
+        if (rec) {
+            float *xo = a.rec_x + ((int64_t)it * a.rec_chains + c) * D;
+#pragma unroll
+            for (int i = 0; i < D; ++i) xo[i] = ch.x[i];
+        }
         step_once<D, TGT, LOC, MU, false>(a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch, kill, accept);
+        if (rec) a.rec_w[(int64_t)it * a.rec_chains + c] = ch.last_dt;
         n_acc += __popcll(__ballot(accept));
         n_kill += __popcll(__ballot(kill));
     }

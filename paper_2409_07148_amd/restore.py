@@ -89,6 +89,10 @@ class restore_batch_tiling(C.Structure):
                 "buckets": ["one", "dim4"][self.buckets]}
 
 
+class restore_mlp_shape(C.Structure):
+    _fields_ = [("in_dim", C.c_int32), ("hidden", C.c_int32), ("n_comp", C.c_int32), ("dim", C.c_int32)]
+
+
 class restore_chain_sums(C.Structure):
     _fields_ = [("n_done", C.c_void_p), ("t_done", C.c_void_p), ("a_done", C.c_void_p), ("status", C.c_void_p),
                 ("t_cur", C.c_void_p), ("n_chains", C.c_int64)]
@@ -98,7 +102,9 @@ EXPORTS = ["restore_state_bytes", "restore_init", "restore_step", "restore_drain
            "restore_get_state_view", "restore_refresh_cache", "restore_destroy",
            "restore_batch_state_bytes", "restore_batch_init", "restore_batch_set_tiling",
            "restore_batch_get_tiling", "restore_batch_run", "restore_batch_estimates", "restore_batch_chain_sums",
-           "restore_batch_autotune", "restore_batch_destroy", "restore_last_error"]
+           "restore_batch_autotune", "restore_batch_destroy", "restore_step_record", "restore_mlp_param_count",
+           "restore_mlp_forward", "restore_mlp_backward", "restore_gmm_nll_workspace_bytes", "restore_gmm_nll",
+           "restore_adam_step", "restore_last_error"]
 
 
 def _load() -> C.CDLL:
@@ -129,6 +135,17 @@ def _load() -> C.CDLL:
     lib.restore_batch_autotune.argtypes = [C.c_void_p, C.c_char_p, P(restore_batch_tiling), P(C.c_double),
                                            C.c_void_p]
     lib.restore_batch_destroy.argtypes = [C.c_void_p]
+    lib.restore_step_record.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.restore_mlp_param_count.argtypes = [P(restore_mlp_shape), P(C.c_int64), P(C.c_int64)]
+    lib.restore_mlp_forward.argtypes = [P(restore_mlp_shape), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]
+    lib.restore_mlp_backward.argtypes = [P(restore_mlp_shape), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.restore_gmm_nll_workspace_bytes.argtypes = [P(C.c_size_t)]
+    lib.restore_gmm_nll.argtypes = [C.c_int32, C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    lib.restore_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                      C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]
     lib.restore_last_error.restype = C.c_char_p
     for name in EXPORTS[:-1]:
         getattr(lib, name).restype = C.c_int32
@@ -265,6 +282,50 @@ def restore_batch_destroy(b) -> None:
     _check(_lib.restore_batch_destroy(b))
 
 
+def restore_step_record(ctx, n_steps: int, n_record: int, x_out_ptr: int, w_out_ptr: int, stream=None) -> None:
+    _check(_lib.restore_step_record(ctx, int(n_steps), int(n_record), C.c_void_p(x_out_ptr), C.c_void_p(w_out_ptr),
+                                    C.c_void_p(_stream(stream))))
+
+
+def restore_mlp_param_count(shape: restore_mlp_shape):
+    n, a = C.c_int64(0), C.c_int64(0)
+    _check(_lib.restore_mlp_param_count(C.byref(shape), C.byref(n), C.byref(a)))
+    return n.value, a.value
+
+
+def restore_mlp_forward(shape, theta_ptr: int, ctx_ptr: int, G: int, act_ptr: int, out_ptr: int,
+                        stream=None) -> None:
+    _check(_lib.restore_mlp_forward(C.byref(shape), C.c_void_p(theta_ptr), C.c_void_p(ctx_ptr), int(G),
+                                    C.c_void_p(act_ptr), C.c_void_p(out_ptr), C.c_void_p(_stream(stream))))
+
+
+def restore_mlp_backward(shape, theta_ptr: int, ctx_ptr: int, G: int, act_ptr: int, dout_ptr: int, work_ptr: int,
+                         grad_ptr: int, stream=None) -> None:
+    _check(_lib.restore_mlp_backward(C.byref(shape), C.c_void_p(theta_ptr), C.c_void_p(ctx_ptr), int(G),
+                                     C.c_void_p(act_ptr), C.c_void_p(dout_ptr), C.c_void_p(work_ptr),
+                                     C.c_void_p(grad_ptr), C.c_void_p(_stream(stream))))
+
+
+def restore_gmm_nll_workspace_bytes() -> int:
+    n = C.c_size_t(0)
+    _check(_lib.restore_gmm_nll_workspace_bytes(C.byref(n)))
+    return n.value
+
+
+def restore_gmm_nll(n_comp: int, dim: int, beta: float, gmm_ptr: int, x_ptr: int, w_ptr: int, n: int,
+                    dout_ptr: int, loss_ptr: int, workspace_ptr: int, workspace_bytes: int, stream=None) -> None:
+    _check(_lib.restore_gmm_nll(int(n_comp), int(dim), float(beta), C.c_void_p(gmm_ptr), C.c_void_p(x_ptr),
+                                C.c_void_p(w_ptr), int(n), C.c_void_p(dout_ptr), C.c_void_p(loss_ptr),
+                                C.c_void_p(workspace_ptr), int(workspace_bytes), C.c_void_p(_stream(stream))))
+
+
+def restore_adam_step(theta_ptr: int, grad_ptr: int, m_ptr: int, v_ptr: int, n: int, t: int, lr: float,
+                      beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    _check(_lib.restore_adam_step(C.c_void_p(theta_ptr), C.c_void_p(grad_ptr), C.c_void_p(m_ptr), C.c_void_p(v_ptr),
+                                  int(n), int(t), float(lr), float(beta1), float(beta2), float(eps),
+                                  C.c_void_p(_stream(stream))))
+
+
 # ---------------------------------------------------------------------------
 # descriptors from canonical parameters
 # ---------------------------------------------------------------------------
@@ -309,6 +370,12 @@ def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: f
     mu_t = None
     if mu is None:
         m = restore_mu(MU_UNIFORM_BOX, 0, 0.0, 0, None)
+    elif "params_dev" in mu:
+        # a device row [logits K | means K*d | log_std K*d] (a learned mu)
+        mu_t = mu["params_dev"].reshape(-1)
+        if mu_t.dtype != torch.float32 or not mu_t.is_cuda or not mu_t.is_contiguous():
+            raise ValueError("params_dev must be a contiguous float32 device tensor")
+        m = restore_mu(MU_GMM_DIAG, int(mu["n_comp"]), float(mu["beta"]), 0, mu_t.data_ptr())
     else:
         mu_t = torch.cat([torch.as_tensor(np.asarray(mu[k], dtype=np.float32).ravel())
                           for k in ("logits", "means", "log_std")]).cuda()
@@ -353,6 +420,14 @@ class Run:
 
     def step(self, n: int):
         restore_step(self.ctx, n, self.stream)
+
+    def step_record(self, n: int, n_record: int):
+        """Advance n steps; return the recorded (x_{i-1}, dt_i) of chains
+        [0, n_record) as tensors x [n][n_record][d], w [n][n_record]."""
+        x = torch.empty((n, n_record, self.d), dtype=torch.float32, device="cuda")
+        w = torch.empty((n, n_record), dtype=torch.float32, device="cuda")
+        restore_step_record(self.ctx, n, n_record, x.data_ptr(), w.data_ptr(), self.stream)
+        return x, w
 
     def drain(self):
         restore_drain(self.ctx, self.stream)

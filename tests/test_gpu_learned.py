@@ -1,0 +1,375 @@
+"""The learned-mu training kernels and the sample recording, through the C
+ABI, against the FP64 oracle (oracle/learned_mu.py).
+
+Tolerances come from the arithmetic, computed per element in float64:
+  * a matrix-core GEMM C = A B rounds A and B to bf16 (round to nearest,
+    relative error <= 2^-8 each) and accumulates the exact products in
+    float32:  |dC| <= (2^-7 + 2^-16 + (k + 2) 2^-24) (|A||B|)  plus the
+    propagated error of inexact inputs, |dA||B| + |A||dB|;
+  * GELU in float32 (erff, expf): |dh| <= 2^-21 max(1, |z|) + |gelu'(z)||dz|;
+  * the NLL kernel evaluates a_k = c_k - |z|^2/2 in float32 (|da| <=
+    2^-24 (2|c| + (d + 6) q + 4), q = |z|^2) and log u by log-sum-exp; a
+    responsibility r = exp(a - log u) then carries the relative error
+    rho = da_k + sum_j r_j da_j + 2^-24 (8 + 2|log u|); the sums over
+    samples are taken in float64 and cast to float32 once.
+Each bound is doubled as a margin for the transcendental functions (<= 1 ulp
+each on this target).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+U8, U24 = 2.0 ** -8, 2.0 ** -24
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2409_07148_amd import restore
+    return restore
+
+
+def _gemm_bound(A, B, dA=None, dB=None):
+    k = A.shape[1]
+    b = (2 * U8 + U8 * U8 + (k + 2) * U24) * (np.abs(A) @ np.abs(B))
+    if dA is not None:
+        b += dA @ np.abs(B)
+    if dB is not None:
+        b += np.abs(A) @ dB
+    return b
+
+
+def _gelu_bound(z, dz):
+    from oracle import learned_mu as L
+    return 2.0 ** -21 * np.maximum(1.0, np.abs(z)) + np.abs(L.gelu_grad(z)) * dz
+
+
+def _mlp_case(R, in_dim, H, K, d, G, seed):
+    import torch
+    from oracle import learned_mu as L
+    rng = np.random.default_rng(seed)
+    shape = R.restore_mlp_shape(in_dim, H, K, d)
+    n, n_act = R.restore_mlp_param_count(shape)
+    _, n_o = L.param_layout(in_dim, H, K, d)
+    assert n == n_o and n_act == 4 * H
+    theta = (0.4 * rng.standard_normal(n)).astype(np.float32)
+    ctx = rng.standard_normal((G, in_dim)).astype(np.float32)
+    O = K * (1 + 2 * d)
+    dout = rng.standard_normal((G, O)).astype(np.float32)
+    t_theta, t_ctx, t_dout = (torch.from_numpy(a).cuda() for a in (theta, ctx, dout))
+    act = torch.empty((G, n_act), dtype=torch.float32, device="cuda")
+    out = torch.empty((G, O), dtype=torch.float32, device="cuda")
+    work = torch.empty((2, G, H), dtype=torch.float32, device="cuda")
+    grad = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    R.restore_mlp_forward(shape, t_theta.data_ptr(), t_ctx.data_ptr(), G, act.data_ptr(), out.data_ptr())
+    R.restore_mlp_backward(shape, t_theta.data_ptr(), t_ctx.data_ptr(), G, act.data_ptr(), t_dout.data_ptr(),
+                           work.data_ptr(), grad.data_ptr())
+    torch.cuda.synchronize()
+    a = act.cpu().numpy().astype(np.float64).reshape(4, G, H)   # z1, h1, z2, h2
+    return (theta.astype(np.float64), ctx.astype(np.float64), dout.astype(np.float64),
+            a[0], a[1], a[2], a[3], out.cpu().numpy().astype(np.float64),
+            grad.cpu().numpy().astype(np.float64))
+
+
+MLP_CASES = [(12, 64, 64, 8, 1), (12, 40, 5, 3, 37), (7, 33, 3, 2, 70), (12, 64, 64, 8, 96)]
+
+
+@pytest.mark.parametrize("in_dim,H,K,d,G", MLP_CASES)
+def test_mlp_forward_layers_match_oracle(R, in_dim, H, K, d, G):
+    """Each layer of restore_mlp_forward against its float64 definition,
+    evaluated on the kernel's own input to that layer, within the bf16
+    GEMM bound; the whole forward against the oracle within the propagated
+    bound."""
+    from oracle import learned_mu as L
+    theta, ctx, _, z1, h1, z2, h2, out, _ = _mlp_case(R, in_dim, H, K, d, G, seed=in_dim * 1000 + G)
+    layout, _ = L.param_layout(in_dim, H, K, d)
+    P = L.unpack(theta, layout)
+    _say(f"[mlp fwd] in {in_dim} H {H} K {K} d {d} G {G}")
+    # per layer, from the kernel's own input
+    for name, x, W, b, z in (("z1", ctx, P["W1"], P["b1"], z1), ("z2", h1, P["W2"], P["b2"], z2),
+                             ("out", h2, P["W3"], P["b3"], out)):
+        exact = x @ W.T + b
+        bound = 2 * (_gemm_bound(x, W.T) + U24 * np.abs(exact)) + 1e-30
+        err = np.abs(z - exact)
+        assert np.all(err <= bound), (name, float((err / bound).max()))
+    for name, z, h in (("h1", z1, h1), ("h2", z2, h2)):
+        assert np.all(np.abs(h - L.gelu(z)) <= 2 * _gelu_bound(z, 0.0)), name
+    # end to end, bound propagated through the layers
+    ref, cache = L.mlp_forward(theta, ctx, in_dim, H, K, d)
+    e1 = _gemm_bound(ctx, P["W1"].T) + U24 * np.abs(cache["z1"])
+    eh1 = _gelu_bound(cache["z1"], e1)
+    e2 = _gemm_bound(cache["h1"], P["W2"].T, dA=eh1) + U24 * np.abs(cache["z2"])
+    eh2 = _gelu_bound(cache["z2"], e2)
+    e3 = _gemm_bound(cache["h2"], P["W3"].T, dA=eh2) + U24 * np.abs(ref)
+    err = np.abs(out - ref)
+    assert np.all(err <= 2 * e3 + 1e-30), float((err / (2 * e3)).max())
+    _say(f"[mlp fwd] max err/bound {float((err / (2 * e3)).max()):.3f}")
+
+
+@pytest.mark.parametrize("in_dim,H,K,d,G", MLP_CASES)
+def test_mlp_backward_matches_oracle(R, in_dim, H, K, d, G):
+    """restore_mlp_backward against the oracle's hand-written backward pass
+    evaluated on the kernel's saved activations, within the bound of the
+    bf16 GEMMs propagated through the layers."""
+    from oracle import learned_mu as L
+    theta, ctx, dout, z1, h1, z2, h2, _, grad = _mlp_case(R, in_dim, H, K, d, G, seed=in_dim * 1000 + G + 1)
+    layout, n = L.param_layout(in_dim, H, K, d)
+    P = L.unpack(theta, layout)
+    cache = {"c": ctx, "z1": z1, "h1": h1, "z2": z2, "h2": h2, "P": P, "layout": layout}
+    ref = L.mlp_backward(cache, dout)
+    # bounds, layer by layer
+    gp = L.gelu_grad
+    bW3 = _gemm_bound(dout.T, h2)
+    bb3 = (G + 1) * U24 * np.abs(dout).sum(0)
+    edh2 = _gemm_bound(dout, P["W3"])
+    dh2 = dout @ P["W3"]
+    edz2 = edh2 * np.abs(gp(z2)) + 2.0 ** -21 * np.abs(dh2)
+    dz2 = dh2 * gp(z2)
+    bW2 = _gemm_bound(dz2.T, h1, dA=edz2.T)
+    bb2 = edz2.sum(0) + (G + 1) * U24 * np.abs(dz2).sum(0)
+    edh1 = _gemm_bound(dz2, P["W2"], dA=edz2)
+    dh1 = dz2 @ P["W2"]
+    edz1 = edh1 * np.abs(gp(z1)) + 2.0 ** -21 * np.abs(dh1)
+    dz1 = dh1 * gp(z1)
+    bW1 = _gemm_bound(dz1.T, ctx, dA=edz1.T)
+    bb1 = edz1.sum(0) + (G + 1) * U24 * np.abs(dz1).sum(0)
+    bound = np.zeros(n)
+    for k, b in (("W1", bW1), ("b1", bb1), ("W2", bW2), ("b2", bb2), ("W3", bW3), ("b3", bb3)):
+        o, s = layout[k]
+        bound[o:o + b.size] = b.ravel()
+    bound = 2 * (bound + U24 * np.abs(ref)) + 1e-30
+    err = np.abs(grad - ref)
+    worst = int(np.argmax(err / bound))
+    _say(f"[mlp bwd] in {in_dim} H {H} K {K} d {d} G {G}: max err/bound {err[worst] / bound[worst]:.3f}")
+    assert np.all(np.isfinite(grad))
+    assert np.all(err <= bound), (worst, grad[worst], ref[worst], bound[worst])
+
+
+def _nll_inputs(K, d, n, seed):
+    rng = np.random.default_rng(seed)
+    logits = rng.standard_normal(K)
+    m = rng.uniform(0.15, 0.85, (K, d))
+    ls = np.log(rng.uniform(0.03, 0.2, (K, d)))
+    row = np.concatenate([logits, m.ravel(), ls.ravel()]).astype(np.float32).astype(np.float64)
+    comp = rng.integers(0, K, n)
+    near = m[comp] + np.exp(ls[comp]) * rng.standard_normal((n, d))
+    x = np.where(rng.uniform(size=(n, 1)) < 0.7, near, rng.uniform(-0.05, 1.05, (n, d)))
+    w = rng.exponential(size=n) * (rng.uniform(size=n) < 0.9)
+    if n > 3:
+        w[:3] = [0.0, 1e-12, 50.0]
+    return row, x.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64)
+
+
+def _nll_bound(row, x, w, beta, K, d):
+    from oracle import learned_mu as L
+    logits, m, ls = L.split_gmm(row, K, d)
+    lu, comp = L.log_u(row, x, beta, K, d)
+    r = np.exp(comp - lu[:, None])
+    s = np.exp(ls)
+    z = (x[:, None, :] - m[None]) / s[None]
+    q = (z * z).sum(-1)
+    c = comp + 0.5 * q
+    da = U24 * (2 * np.abs(c) + (d + 6) * q + 4)
+    rho = da + (r * da).sum(1, keepdims=True) + U24 * (8 + 2 * np.abs(lu))[:, None]
+    W = w.sum()
+    wr = w[:, None] * r
+    e0 = (wr * (rho + 4 * U24)).sum(0) / W
+    S0 = wr.sum(0) / W
+    pi = np.exp(logits - logits.max())
+    pi /= pi.sum()
+    b_logit = e0 + pi * e0.sum() + 4 * U24 * (S0 + pi * S0.sum())
+    b_m = (wr[:, :, None] * np.abs(z) * (rho[:, :, None] + 8 * U24)).sum(0) / s / W
+    b_ls = (wr[:, :, None] * (z * z * (rho[:, :, None] + 12 * U24) + rho[:, :, None])).sum(0) / W + e0[:, None]
+    b_loss = (w * ((r * da).sum(1) + U24 * (4 + 2 * np.abs(lu)))).sum() / W
+    return np.concatenate([b_logit, b_m.ravel(), b_ls.ravel()]), b_loss
+
+
+@pytest.mark.parametrize("K,d,n,beta", [(64, 8, 70001, 0.1), (5, 3, 2500, 0.25), (1, 1, 1, 0.1),
+                                        (17, 16, 1023, 0.05), (64, 8, 300, 0.0)])
+def test_gmm_nll_matches_oracle(R, K, d, n, beta):
+    """Loss and gradient of the weighted defensive-mixture NLL against the
+    oracle, within the derived float32 bound (samples near the components
+    and uniform ones, zero and extreme weights, ragged sample counts)."""
+    import torch
+    from oracle import learned_mu as L
+    row, x, w = _nll_inputs(K, d, n, seed=K * 100 + d)
+    if w.sum() == 0:
+        w[0] = 1.0
+    t_row, t_x, t_w = (torch.from_numpy(a.astype(np.float32)).cuda() for a in (row, x, w))
+    dout = torch.full((row.size,), float("nan"), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(R.restore_gmm_nll_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    R.restore_gmm_nll(K, d, beta, t_row.data_ptr(), t_x.data_ptr(), t_w.data_ptr(), n, dout.data_ptr(),
+                      loss.data_ptr(), ws.data_ptr(), ws.numel())
+    torch.cuda.synchronize()
+    g = dout.cpu().numpy().astype(np.float64)
+    ref_g = L.nll_grad(row, x, w, beta, K, d)
+    ref_l = L.nll(row, x, w, beta, K, d)
+    bg, bl = _nll_bound(row, x, w, beta, K, d)
+    bg = 2 * (bg + U24 * np.abs(ref_g)) + 1e-30
+    err = np.abs(g - ref_g)
+    worst = int(np.argmax(err / bg))
+    _say(f"[nll] K {K} d {d} n {n} beta {beta}: loss {loss.item():.6f} vs {ref_l:.6f} (bound {2 * bl:.2e}); "
+         f"grad max err/bound {err[worst] / bg[worst]:.3f}")
+    assert abs(loss.item() - ref_l) <= 2 * bl + 1e-30
+    assert np.all(err <= bg), (worst, g[worst], ref_g[worst], bg[worst])
+
+
+def test_gmm_nll_is_bit_reproducible(R):
+    import torch
+    row, x, w = _nll_inputs(64, 8, 40000, seed=7)
+    t_row, t_x, t_w = (torch.from_numpy(a.astype(np.float32)).cuda() for a in (row, x, w))
+    ws = torch.empty(R.restore_gmm_nll_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    outs = []
+    for _ in range(2):
+        dout = torch.empty(row.size, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        R.restore_gmm_nll(64, 8, 0.1, t_row.data_ptr(), t_x.data_ptr(), t_w.data_ptr(), w.size, dout.data_ptr(),
+                          loss.data_ptr(), ws.data_ptr(), ws.numel())
+        outs.append((dout.cpu().numpy(), loss.item()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+def test_gmm_nll_rejects_bad_arguments(R):
+    import torch
+    row, x, w = _nll_inputs(4, 2, 10, seed=1)
+    t_row, t_x, t_w = (torch.from_numpy(a.astype(np.float32)).cuda() for a in (row, x, w))
+    dout = torch.empty(row.size, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(R.restore_gmm_nll_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    args = (t_row.data_ptr(), t_x.data_ptr(), t_w.data_ptr(), 10, dout.data_ptr(), loss.data_ptr(), ws.data_ptr())
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_gmm_nll(4, 2, 0.1, *args, ws.numel() - 1)
+    assert e.value.status == R.E_BUFFER_TOO_SMALL
+    for K, d, beta in ((0, 2, 0.1), (65, 2, 0.1), (4, 17, 0.1), (4, 2, 1.0), (4, 2, -0.1)):
+        with pytest.raises(R.RestoreError) as e:
+            R.restore_gmm_nll(K, d, beta, *args, ws.numel())
+        assert e.value.status == R.E_INVALID_ARG
+
+
+def test_adam_matches_float64_definition(R):
+    """Five Adam steps, each against the update written out in float64
+    from the kernel's previous float32 state and the float32 values of the
+    hyper-parameters; the bound counts the float32 roundings of each
+    quantity, including the bias corrections 1 - b^t (powf, 1 ulp)."""
+    import torch
+    rng = np.random.default_rng(5)
+    n = 5003
+    f = lambda v: float(np.float32(v))
+    lr, b1, b2, eps = f(3e-3), f(0.9), f(0.999), f(1e-8)
+    t_th = torch.from_numpy(rng.standard_normal(n).astype(np.float32)).cuda()
+    t_m, t_v = torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    for t in range(1, 6):
+        th0, m0, v0 = (a.cpu().numpy().astype(np.float64) for a in (t_th, t_m, t_v))
+        g = (rng.standard_normal(n) * 10.0 ** rng.uniform(-4, 1, n)).astype(np.float32)
+        R.restore_adam_step(t_th.data_ptr(), torch.from_numpy(g).cuda().data_ptr(), t_m.data_ptr(), t_v.data_ptr(),
+                            n, t, lr, b1, b2, eps)
+        torch.cuda.synchronize()
+        gd = g.astype(np.float64)
+        m = b1 * m0 + (1 - b1) * gd
+        v = b2 * v0 + (1 - b2) * gd * gd
+        c1, c2 = 1 - b1 ** t, 1 - b2 ** t
+        den = np.sqrt(v / c2) + eps
+        step = lr * (m / c1) / den
+        th = th0 - step
+        em = 2 * U24 * (np.abs(b1 * m0) + np.abs((1 - b1) * gd)) + U24 * np.abs(m)
+        ev = 2 * U24 * (np.abs(b2 * v0) + 2 * np.abs((1 - b2) * gd * gd)) + U24 * np.abs(v)
+        rc1 = 2 * U24 * b1 ** t / c1 + U24
+        rc2 = 2 * U24 * b2 ** t / c2 + U24
+        eden = 0.5 * np.sqrt(v / c2) * (ev / np.maximum(v, 1e-300) + rc2 + 2 * U24) + U24 * den
+        estep = lr * ((em + np.abs(m) * (rc1 + U24)) / c1 / den + np.abs(m / c1) * eden / den ** 2) \
+            + 2 * U24 * np.abs(step)
+        for name, got, ref, b in (("m", t_m, m, em), ("v", t_v, v, ev), ("theta", t_th, th, estep + U24 * np.abs(th))):
+            err = np.abs(got.cpu().numpy().astype(np.float64) - ref)
+            assert np.all(err <= 2 * b + 1e-30), (t, name, float((err / (2 * b + 1e-30)).max()))
+
+
+def test_step_record_pairs_are_the_chain_states(R):
+    """restore_step_record leaves the chains exactly as restore_step does,
+    and what it records is (x_{i-1}, dt_i) of each recorded chain."""
+    import torch
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=3000, n_steps=8)
+    run_a = R.Run(R.problem_from_workload(wl))
+    run_b = R.Run(R.problem_from_workload(wl))
+    n_rec = 2049
+    xs, ws, dts = [], [], []
+    for s in range(4):
+        x_before = run_a.arrays()["x"].clone()
+        x, w = run_a.step_record(1, n_rec)
+        torch.cuda.synchronize()
+        assert torch.equal(x[0], x_before[:, :n_rec].T.contiguous())
+        assert torch.equal(w[0], run_a.arrays()["last_dt"][:n_rec])
+        xs.append(x)
+        ws.append(w)
+    run_b.step(2)
+    x4, w4 = run_b.step_record(2, n_rec)   # two steps in one launch
+    torch.cuda.synchronize()
+    assert torch.equal(x4, torch.cat(xs[2:]))
+    assert torch.equal(w4, torch.cat(ws[2:]))
+    for k in ("x", "logp", "t_cur", "a_cur", "status", "last_dt"):
+        assert torch.equal(run_a.arrays()[k], run_b.arrays()[k]), k
+    with pytest.raises(R.RestoreError):
+        run_a.step_record(1, 0)
+    with pytest.raises(R.RestoreError):
+        run_a.step_record(1, wl.n_chains + 1)
+
+
+def test_learned_mu_from_device_row_matches_host_parameters(R):
+    """A run whose mu is the MLP's output row on the device is the run with
+    the same float32 mixture given as host parameters."""
+    import torch
+    from paper_2409_07148_amd.learned_mu import MlpGmm
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=4096, n_steps=16)
+    model = MlpGmm(d=wl.d, K=64, seed=11)
+    mu_dev = model.mu()
+    row = mu_dev["params_dev"].cpu().numpy().ravel().astype(np.float64)
+    K, d = 64, wl.d
+    mu_host = {"logits": row[:K], "means": row[K:K + K * d].reshape(K, d),
+               "log_std": row[K + K * d:].reshape(K, d), "beta": 0.1}
+    ra = R.Run(R.problem_from_workload(wl, mu=mu_dev))
+    rb = R.Run(R.problem_from_workload(wl, mu=mu_host))
+    ra.step(16)
+    rb.step(16)
+    torch.cuda.synchronize()
+    for k in ("x", "logp", "logu", "t_cur", "status"):
+        assert torch.equal(ra.arrays()[k], rb.arrays()[k]), k
+
+
+def test_refit_lowers_nll_and_learned_run_is_unbiased(R):
+    """Three refits on the 8-D workload (reduced chain count and budget)
+    lower the time-weighted NLL, and a run with the learned mu at its
+    provable c~ censors no tour and estimates the closed-form truth within
+    4 standard errors, with a standard error far below uniform mu's."""
+    from oracle import truth
+    from paper_2409_07148_amd.learned_mu import MlpGmm, provable_c_tilde, refit
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=1 << 18, n_steps=256)
+    model = MlpGmm(d=wl.d, K=64, seed=3004)
+    ct_uniform = wl.c_tilde * 512 / wl.n_steps      # 8 P / B at this budget
+    ct = provable_c_tilde(ct_uniform, model.beta)
+    hist = refit(wl, model, ct, rounds=3, record_steps=4, epochs=200, lr=2e-2, seed=3004, log=_say)
+    assert hist[0]["nll_last"] < hist[0]["nll_first"] - 1.0
+    tr = truth.truths(wl)
+    run = R.Run(R.problem_from_workload(wl.with_(seed=2004), mu=model.mu(), c_tilde=ct))
+    run.step(wl.n_steps)
+    run.drain()
+    est = run.estimate()
+    _say(f"[learned run] p_lambda {est['p_lambda']:.6g} +- {est['p_lambda_se']:.2g} (truth {tr['p_lambda']:.6g}); "
+         f"lam_pf {est['lam_pf']:.6g} +- {est['lam_pf_se']:.2g} (truth {tr['lam_pf']:.6g}); "
+         f"censored {est['tours_censored']}")
+    assert est["tours_censored"] == 0
+    assert abs(est["p_lambda"] - tr["p_lambda"]) <= 4 * est["p_lambda_se"]
+    assert abs(est["lam_pf"] - tr["lam_pf"]) <= 4 * est["lam_pf_se"]
+    assert est["lam_pf_se"] < 0.05 * tr["lam_pf"]

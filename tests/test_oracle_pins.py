@@ -8,6 +8,7 @@ that is a family-wise false-alarm rate below 1e-2 for a fresh seed choice.
 import math
 import os
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -422,3 +423,21 @@ def test_run_is_deterministic_and_thread_invariant(oracle_lib):
     np.testing.assert_array_equal(a.t_done, b.t_done)
     np.testing.assert_array_equal(a.n_done[100:], c.n_done)
     np.testing.assert_array_equal(a.a_done[100:], c.a_done)
+
+
+def test_stored_truths_match_the_oracle():
+    """tests/golden/truths.json (read by the benchmark to score estimates)
+    is what the oracle's truth routines give today, to the accuracy of
+    Genz's randomised rule (its state carries over between calls, so the
+    last digits depend on what ran before in the process)."""
+    import json
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    import write_truths
+    with open(write_truths.PATH) as f:
+        stored = json.load(f)
+    fresh = write_truths.compute()
+    assert stored.keys() == fresh.keys()
+    for name in fresh:
+        for k, v in fresh[name].items():
+            assert stored[name][k] == pytest.approx(v, rel=1e-5), (name, k)

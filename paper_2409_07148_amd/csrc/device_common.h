@@ -80,6 +80,21 @@ __device__ __forceinline__ float exp_rel(float x) {
     return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
 }
 
+// One term of the online log-sum-exp, (M, S) <- (max(M, a),
+// S e^{M - max} + e^{a - max}), with a single exponential: of the two
+// factors one is exactly 1 and the other is e^{-|a - M|}.  sc and w return
+// the factors applied to the old sum and to the new term (for running
+// gradient sums).  Same values, bit for bit, as evaluating both factors.
+__device__ __forceinline__ void lse_push(float &M, float &S, float a, float &sc, float &w) {
+    const float d = a - M;
+    const float e = exp_rel(-fabsf(d));
+    const bool up = d > 0.0f;
+    sc = up ? e : 1.0f;
+    w = up ? 1.0f : e;
+    S = up ? fmaf(S, e, 1.0f) : S + e;
+    M = up ? a : M;
+}
+
 template <int D>
 __device__ __forceinline__ bool in_unit_box(const float y[D]) {
     bool in = true;

@@ -1,8 +1,8 @@
 // Target densities p and regeneration densities u evaluated per lane.
 //
 // All mixtures are evaluated in log space with a running maximum (online
-// log-sum-exp) so that neither the far tails nor the sharp peaks of the
-// components leave the float32 range.  Parameters are read from a packed
+// log-sum-exp, one exponential per component) so that neither the far tails
+// nor the sharp peaks of the components leave the float32 range.  Parameters are read from a packed
 // slab whose addresses are wave-uniform: from global memory they become
 // scalar loads (SGPR operands of the FMAs); with LDS staging they are
 // broadcast reads.
@@ -40,16 +40,13 @@ struct GmmIso {
                 q = fmaf(dx[i], dx[i], q);
             }
             const float ak = fmaf(-0.5f * ivar, q, pk[0]);
-            const float Mn = fmaxf(M, ak);
-            const float sc = exp_rel(M - Mn);
-            const float w = exp_rel(ak - Mn);
-            S = fmaf(S, sc, w);
+            float sc, w;
+            lse_push(M, S, ak, sc, w);
             if (GRAD && want) {
                 const float wi = -w * ivar;
 #pragma unroll
                 for (int i = 0; i < D; ++i) G[i] = fmaf(G[i], sc, wi * dx[i]);
             }
-            M = Mn;
         }
         const float lp = M + logf(S);
         if (GRAD && want) {
@@ -91,10 +88,8 @@ struct GmmFull {
                 q = fmaf(acc, acc, q);
             }
             const float ak = fmaf(-0.5f, q, pk[0]);
-            const float Mn = fmaxf(M, ak);
-            const float sc = exp_rel(M - Mn);
-            const float w = exp_rel(ak - Mn);
-            S = fmaf(S, sc, w);
+            float sc, w;
+            lse_push(M, S, ak, sc, w);
             if (GRAD && want) {
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
@@ -104,7 +99,6 @@ struct GmmFull {
                     G[j] = fmaf(G[j], sc, -w * u);
                 }
             }
-            M = Mn;
         }
         const float lp = M + logf(S);
         if (GRAD && want) {
@@ -190,9 +184,8 @@ struct MuGmm {
                 q = fmaf(z, z, q);
             }
             const float ak = fmaf(-0.5f, q, pk[0]);
-            const float Mn = fmaxf(M, ak);
-            S = fmaf(S, exp_rel(M - Mn), exp_rel(ak - Mn));
-            M = Mn;
+            float sc, w;
+            lse_push(M, S, ak, sc, w);
         }
         return M + logf(S);
     }

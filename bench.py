@@ -72,18 +72,26 @@ def measured_traffic(workload: str):
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
     size), or None when the kernel sources have changed since the counters
     were taken or no summary exists for this workload."""
-    import glob
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_hbm_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2409_07148_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
-    if h.hexdigest() != rec.get("csrc_sha256"):
+    if step_kernel_sources_sha256() != rec.get("step_kernel_sources_sha256"):
         return None
     return float(rec["traffic_bytes_per_launch"])
+
+
+STEP_KERNEL_SOURCES = ["step_kernels.hip", "chain_step.h", "targets.h", "device_common.h", "launch.h",
+                       "restore_internal.h"]
+
+
+def step_kernel_sources_sha256() -> str:
+    """sha256 over the sources the step kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEP_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2409_07148_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def cpu_baseline(wl, target_seconds: float = 12.0) -> dict:

@@ -7,6 +7,7 @@
 namespace restore {
 
 constexpr int LEARN_MAX_DIM = 16;
+constexpr int NLL_MAX_BLOCKS = 2048;
 
 struct NllArgs {
     int32_t n_comp, dim;
@@ -15,9 +16,9 @@ struct NllArgs {
     const float *x;        // [n][d]
     const float *w;        // [n]
     int64_t n;
-    int32_t n_blocks;
-    double *partials;      // [n_blocks][64][2 + 2 * LEARN_MAX_DIM]
-    double *loss_part;     // [n_blocks][2]
+    int32_t n_blocks;      // <= NLL_MAX_BLOCKS
+    double *partials;      // [n_blocks][3 + 2 dim][64]
+    double *totals;        // [3 + 2 dim][64]
     float *dout;           // [K (1 + 2d)]
     double *loss;          // [1]
 };

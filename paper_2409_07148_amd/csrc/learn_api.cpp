@@ -21,7 +21,6 @@ restore_status hip_fail(hipError_t e, const char *what) {
     return fail(RESTORE_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-constexpr int NLL_BLOCKS = 1024;
 
 struct Offsets {
     int64_t W1, b1, W2, b2, W3, b3, total;
@@ -112,7 +111,7 @@ restore_status restore_mlp_backward(const restore_mlp_shape *shape, const float 
 
 restore_status restore_gmm_nll_workspace_bytes(size_t *bytes) {
     if (!bytes) return fail(RESTORE_E_INVALID_ARG, "null bytes");
-    *bytes = (size_t)NLL_BLOCKS * 64 * (2 + 2 * LEARN_MAX_DIM) * 8 + (size_t)NLL_BLOCKS * 2 * 8 + 256;
+    *bytes = ((size_t)NLL_MAX_BLOCKS + 1) * 64 * (3 + 2 * LEARN_MAX_DIM) * sizeof(double);
     return RESTORE_OK;
 }
 
@@ -133,9 +132,11 @@ restore_status restore_gmm_nll(int32_t n_comp, int32_t dim, float beta, const fl
     a.x = x;
     a.w = w;
     a.n = n;
-    a.n_blocks = (int32_t)(n < NLL_BLOCKS ? n : NLL_BLOCKS);
+    // about 64 samples per wave, at most NLL_MAX_BLOCKS blocks of 4 waves
+    const int64_t want = (n + 255) / 256;
+    a.n_blocks = (int32_t)(want < NLL_MAX_BLOCKS ? want : NLL_MAX_BLOCKS);
     a.partials = static_cast<double *>(workspace);
-    a.loss_part = a.partials + (size_t)NLL_BLOCKS * 64 * (2 + 2 * LEARN_MAX_DIM);
+    a.totals = a.partials + (size_t)NLL_MAX_BLOCKS * 64 * (3 + 2 * LEARN_MAX_DIM);
     a.dout = dout;
     a.loss = loss_dev;
     hipError_t e = launch_gmm_nll(a, static_cast<hipStream_t>(stream));

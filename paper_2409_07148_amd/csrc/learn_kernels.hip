@@ -11,7 +11,8 @@
 //    wave per 32 x 32 output tile -- the MLP layers, forward and backward.
 //  * gmm_nll_kernel: per-component statistics of the weighted NLL in float32
 //    with centred scores z = (x - m)/s (one lane per component, samples
-//    broadcast), accumulated in float64; a fixed-order final pass.
+//    broadcast to the wave), accumulated in float64; fixed-order block and
+//    grid reductions, so the result is bit-reproducible.
 //  * adam_kernel: Adam on float32 master weights.
 #include <hip/hip_runtime.h>
 
@@ -104,47 +105,59 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// One wave per block, lane k = mixture component.  For every sample i of
-// this block's stride: a_k = ln(1-beta) + ln pi_k - d/2 ln 2 pi - sum ln s_k
-// - |z|^2/2 with z = (x_i - m_k)/s_k, log u(x_i) = LSE(a, ln beta 1_box),
-// r_k = exp(a_k - log u), and the weighted sums w r, w r z, w r z^2.
-__global__ __launch_bounds__(64) void gmm_nll_kernel(NllArgs a) {
-    const int k = threadIdx.x;
-    const int K = a.n_comp, d = a.dim;
+// Weighted NLL statistics.  Lane k of every wave is mixture component k;
+// the NLL_WAVES waves of a block take interleaved samples.  For each
+// sample x_i: a_k = ln(1-beta) + ln pi_k - d/2 ln 2 pi - sum ln s_k -
+// |z|^2/2 with z = (x_i - m_k)/s_k, log u(x_i) = LSE(a, ln beta 1_box),
+// r_k = exp(a_k - log u), and the weighted sums
+//   S0 = sum w r, S1 = sum w r z, S2 = sum w r z^2, LW = sum w log u,
+//   W = sum w,
+// accumulated in float64 per lane, combined over the block's waves in a
+// fixed order through LDS and written as one partial per block:
+// partials[block][j][k], j < nll_stats(D).
+constexpr int NLL_WAVES = 4;
+__host__ __device__ constexpr int nll_stats(int D) { return 3 + 2 * D; }
+
+template <int D>
+__global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
+    constexpr int R = nll_stats(D);
+    __shared__ double red[NLL_WAVES - 1][64];
+    const int k = threadIdx.x % 64, wv = threadIdx.x / 64;
+    const int K = a.n_comp;
     const bool act = k < K;
     const float logit = act ? a.gmm[k] : -INFINITY;
     const float lmax = wave_max(logit);
     const float lse = lmax + logf(wave_sum(act ? expf(logit - lmax) : 0.0f));
-    float m[LEARN_MAX_DIM], inv_s[LEARN_MAX_DIM];
-    float c = act ? (a.beta < 1.0f ? log1pf(-a.beta) : -INFINITY) + logit - lse - 0.5f * d * 1.8378770664093453f
+    float m[D], inv_s[D];
+    float c = act ? (a.beta < 1.0f ? log1pf(-a.beta) : -INFINITY) + logit - lse - 0.5f * D * 1.8378770664093453f
                   : -INFINITY;
-    for (int i = 0; i < LEARN_MAX_DIM; ++i) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
         m[i] = 0.0f;
         inv_s[i] = 0.0f;
-        if (act && i < d) {
-            const float ls = a.gmm[K + K * d + k * d + i];
-            m[i] = a.gmm[K + k * d + i];
+        if (act) {
+            const float ls = a.gmm[K + K * D + k * D + i];
+            m[i] = a.gmm[K + k * D + i];
             inv_s[i] = expf(-ls);
             c -= ls;
         }
     }
     const float lbeta = a.beta > 0.0f ? logf(a.beta) : -INFINITY;
-    double s0 = 0.0, lw = 0.0, W = 0.0;
-    double s1[LEARN_MAX_DIM], s2[LEARN_MAX_DIM];
-    for (int i = 0; i < LEARN_MAX_DIM; ++i) s1[i] = s2[i] = 0.0;
-    for (int64_t n = blockIdx.x; n < a.n; n += gridDim.x) {
+    double acc[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[j] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * NLL_WAVES;
+    for (int64_t n = (int64_t)blockIdx.x * NLL_WAVES + wv; n < a.n; n += stride) {
         const float w = a.w[n];
-        const float *x = a.x + n * d;
-        float z[LEARN_MAX_DIM], q = 0.0f;
+        const float *x = a.x + n * D;
+        float z[D], q = 0.0f;
         bool in = true;
-        for (int i = 0; i < LEARN_MAX_DIM; ++i) {
-            z[i] = 0.0f;
-            if (i < d) {
-                const float xi = x[i];
-                in = in && xi >= 0.0f && xi <= 1.0f;
-                z[i] = (xi - m[i]) * inv_s[i];
-                q = fmaf(z[i], z[i], q);
-            }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const float xi = x[i];
+            in = in && xi >= 0.0f && xi <= 1.0f;
+            z[i] = (xi - m[i]) * inv_s[i];
+            q = fmaf(z[i], z[i], q);
         }
         const float ak = act ? fmaf(-0.5f, q, c) : -INFINITY;
         const float au = in ? lbeta : -INFINITY;
@@ -152,63 +165,73 @@ __global__ __launch_bounds__(64) void gmm_nll_kernel(NllArgs a) {
         const float S = wave_sum(act ? expf(ak - M) : 0.0f) + (au > -INFINITY ? expf(au - M) : 0.0f);
         const float logu = M + logf(S);
         const double wr = (double)w * (double)(act ? expf(ak - logu) : 0.0f);
-        s0 += wr;
-        for (int i = 0; i < LEARN_MAX_DIM; ++i) {
-            if (i < d) {
-                s1[i] += wr * z[i];
-                s2[i] += wr * z[i] * z[i];
-            }
+        acc[0] += wr;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            acc[1 + i] += wr * z[i];
+            acc[1 + D + i] += wr * z[i] * z[i];
         }
-        lw += (double)w * (double)logu;
-        W += (double)w;
+        acc[1 + 2 * D] += (double)w * (double)logu;
+        acc[2 + 2 * D] += (double)w;
     }
-    double *out = a.partials + ((int64_t)blockIdx.x * 64 + k) * (2 + 2 * LEARN_MAX_DIM);
-    out[0] = s0;
-    for (int i = 0; i < LEARN_MAX_DIM; ++i) {
-        out[1 + i] = s1[i];
-        out[1 + LEARN_MAX_DIM + i] = s2[i];
-    }
-    if (k == 0) {
-        a.loss_part[2 * blockIdx.x] = lw;
-        a.loss_part[2 * blockIdx.x + 1] = W;
+    double *out = a.partials + (int64_t)blockIdx.x * R * 64;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (wv > 0) red[wv - 1][k] = acc[j];
+        __syncthreads();
+        if (wv == 0) {
+            double v = acc[j];
+#pragma unroll
+            for (int u = 0; u < NLL_WAVES - 1; ++u) v += red[u][k];
+            out[j * 64 + k] = v;
+        }
+        __syncthreads();
     }
 }
 
-// Fixed-order sum of the block partials and the gradient of
-// L = -sum w log u / sum w with respect to the mixture outputs:
+// totals[j][k] = sum over blocks b (fixed order) of partials[b][j][k]: one
+// block per statistic j; wave v takes blocks b = v, v + NW, ... and the
+// waves' sums are added in wave order.
+constexpr int NLL_SUM_WAVES = 16;
+__global__ __launch_bounds__(64 * NLL_SUM_WAVES) void gmm_nll_sum_kernel(const double *partials, int R,
+                                                                          int n_blocks, double *totals) {
+    __shared__ double red[NLL_SUM_WAVES][64];
+    const int k = threadIdx.x % 64, wv = threadIdx.x / 64, j = blockIdx.x;
+    double v = 0.0;
+    for (int b = wv; b < n_blocks; b += NLL_SUM_WAVES) v += partials[((int64_t)b * R + j) * 64 + k];
+    red[wv][k] = v;
+    __syncthreads();
+    if (wv == 0) {
+        double t = 0.0;
+        for (int u = 0; u < NLL_SUM_WAVES; ++u) t += red[u][k];
+        totals[j * 64 + k] = t;
+    }
+}
+
+// Gradient of L = -sum w log u / sum w with respect to the mixture outputs:
 //   dL/dlogit_k = -(S0_k - pi_k sum_j S0_j) / W
 //   dL/dm_ki    = -S1_ki / (W s_ki)
 //   dL/dlog s_ki = -(S2_ki - S0_k) / W
-__global__ __launch_bounds__(64) void gmm_nll_final_kernel(NllArgs a) {
+template <int D>
+__global__ __launch_bounds__(64) void gmm_nll_grad_kernel(NllArgs a, const double *totals) {
     const int k = threadIdx.x;
-    const int K = a.n_comp, d = a.dim;
-    const int R = 2 + 2 * LEARN_MAX_DIM;
-    double S[2 + 2 * LEARN_MAX_DIM];
-    for (int j = 0; j < R; ++j) S[j] = 0.0;
-    for (int b = 0; b < a.n_blocks; ++b)
-        for (int j = 0; j < R; ++j) S[j] += a.partials[((int64_t)b * 64 + k) * R + j];
-    double lw = 0.0, W = 0.0;
-    for (int b = 0; b < a.n_blocks; ++b) {
-        lw += a.loss_part[2 * b];
-        W += a.loss_part[2 * b + 1];
-    }
+    const int K = a.n_comp;
+    const double *S = totals;
+    const double s0 = S[k], lw = S[(1 + 2 * D) * 64], W = S[(2 + 2 * D) * 64];
     const bool act = k < K;
     const float logit = act ? a.gmm[k] : -INFINITY;
     const float lmax = wave_max(logit);
     const float pk = act ? expf(logit - lmax) : 0.0f;
     const float pi = pk / wave_sum(pk);
-    // sum_j S0_j across lanes in double: gather through a float pair
     double s0tot = 0.0;
-    for (int j = 0; j < K; ++j) {
-        const double v = __shfl(S[0], j);
-        s0tot += v;
-    }
+    for (int j = 0; j < K; ++j) s0tot += S[j];
     if (act) {
-        a.dout[k] = (float)(-(S[0] - (double)pi * s0tot) / W);
-        for (int i = 0; i < d; ++i) {
-            const float inv_s = expf(-a.gmm[K + K * d + k * d + i]);
-            a.dout[K + k * d + i] = (float)(-S[1 + i] * inv_s / W);
-            a.dout[K + K * d + k * d + i] = (float)(-(S[1 + LEARN_MAX_DIM + i] - S[0]) / W);
+        a.dout[k] = (float)(-(s0 - (double)pi * s0tot) / W);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const float inv_s = expf(-a.gmm[K + K * D + k * D + i]);
+            a.dout[K + k * D + i] = (float)(-S[(1 + i) * 64 + k] * inv_s / W);
+            a.dout[K + K * D + k * D + i] = (float)(-(S[(1 + D + i) * 64 + k] - s0) / W);
         }
     }
     if (k == 0) a.loss[0] = -lw / W;
@@ -249,9 +272,34 @@ hipError_t launch_colsum(const float *d, float *db, int G, int n, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int D>
+static void launch_nll_d(const NllArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(gmm_nll_kernel<D>, dim3(a.n_blocks), dim3(64 * NLL_WAVES), 0, s, a);
+    hipLaunchKernelGGL(gmm_nll_sum_kernel, dim3(nll_stats(D)), dim3(64 * NLL_SUM_WAVES), 0, s,
+                       (const double *)a.partials, nll_stats(D), a.n_blocks, a.totals);
+    hipLaunchKernelGGL(gmm_nll_grad_kernel<D>, dim3(1), dim3(64), 0, s, a, (const double *)a.totals);
+}
+
 hipError_t launch_gmm_nll(const NllArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(gmm_nll_kernel, dim3(a.n_blocks), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(gmm_nll_final_kernel, dim3(1), dim3(64), 0, s, a);
+    switch (a.dim) {
+        case 1: launch_nll_d<1>(a, s); break;
+        case 2: launch_nll_d<2>(a, s); break;
+        case 3: launch_nll_d<3>(a, s); break;
+        case 4: launch_nll_d<4>(a, s); break;
+        case 5: launch_nll_d<5>(a, s); break;
+        case 6: launch_nll_d<6>(a, s); break;
+        case 7: launch_nll_d<7>(a, s); break;
+        case 8: launch_nll_d<8>(a, s); break;
+        case 9: launch_nll_d<9>(a, s); break;
+        case 10: launch_nll_d<10>(a, s); break;
+        case 11: launch_nll_d<11>(a, s); break;
+        case 12: launch_nll_d<12>(a, s); break;
+        case 13: launch_nll_d<13>(a, s); break;
+        case 14: launch_nll_d<14>(a, s); break;
+        case 15: launch_nll_d<15>(a, s); break;
+        case 16: launch_nll_d<16>(a, s); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

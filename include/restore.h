@@ -127,6 +127,12 @@ typedef struct {
 
 #define RESTORE_FLAG_PARAMS_LDS  1   /* stage mixture parameters through LDS
                                         instead of the scalar cache          */
+#define RESTORE_FLAG_SPLAT_DIRECT 2  /* PIXEL: add every splat to the image
+                                        with a scattered atomic (smaller
+                                        state, slower) instead of binning   */
+#define RESTORE_FLAG_SPLAT_TIGHT 4   /* PIXEL: 64-fold smaller splat buckets,
+                                        so that overflowing records take the
+                                        direct path (exercises that path)   */
 
 typedef struct {
     uint64_t seed;           /* Philox key                                   */
@@ -179,7 +185,11 @@ restore_status restore_init(restore_ctx **out, const restore_target *target,
                             size_t state_bytes, float *image_dev, void *stream);
 
 /* Advance every chain by n_steps steps of Alg. 2 with regeneration
- * (steps s .. s + n_steps - 1, s = steps already taken).  Enqueue only. */
+ * (steps s .. s + n_steps - 1, s = steps already taken).  Enqueue only.
+ * With the PIXEL integrand (unless RESTORE_FLAG_SPLAT_DIRECT) the steps run
+ * as launches of at most 64 steps whose splat records are binned by image
+ * band in the state buffer and summed into the image after each launch;
+ * the chains are the same either way. */
 restore_status restore_step(restore_ctx *ctx, int32_t n_steps, void *stream);
 
 /* End of the budget: run every chain on, without regeneration, until its

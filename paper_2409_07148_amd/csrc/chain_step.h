@@ -72,6 +72,9 @@ struct Chain {
     // steps in the same pixel (rejected moves) are combined in registers
     int32_t splat_pix;
     float splat_acc;
+    // binned splats: the record this step closed (pixel -1: none)
+    int32_t out_pix;
+    float out_acc;
 };
 
 __device__ __forceinline__ void flush_splat(const StepArgs &a, int32_t pix, float acc) {
@@ -98,6 +101,8 @@ __device__ __forceinline__ void load_chain(const StepArgs &a, uint32_t c, Chain<
     ch.last_dt = a.last_dt[c];
     ch.splat_pix = -1;
     ch.splat_acc = 0.0f;
+    ch.out_pix = -1;
+    ch.out_acc = 0.0f;
 }
 
 template <int D, int LOC>
@@ -122,7 +127,9 @@ __device__ __forceinline__ void store_chain(const StepArgs &a, uint32_t c, const
 
 // One transition of Alg. 2 for one lane.  Returns kill / accept through the
 // flags.  In the drain (RETIRE) a terminated chain is not regenerated.
-template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT>
+// With BIN, a splat closed by this step is returned in ch.out_pix /
+// ch.out_acc instead of being added to the image.
+template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT, bool BIN = false>
 __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                                           uint32_t chain, Chain<D, LOC> &ch, bool &kill, bool &accept) {
     constexpr int NB = NBlocks<D>::value;
@@ -160,8 +167,14 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
             const int py = min(max((int)(u1 * (float)a.image_h), 0), a.image_h - 1);
             pix = py * a.image_w + px;
         }
+        if (BIN) ch.out_pix = -1;
         if (pix != ch.splat_pix) {
-            flush_splat(a, ch.splat_pix, ch.splat_acc);
+            if (BIN) {
+                ch.out_pix = ch.splat_pix;
+                ch.out_acc = ch.splat_acc;
+            } else {
+                flush_splat(a, ch.splat_pix, ch.splat_acc);
+            }
             ch.splat_pix = pix;
             ch.splat_acc = 0.0f;
         }
@@ -252,9 +265,10 @@ __device__ __forceinline__ void add_counters(unsigned long long *counters, unsig
     // one lane per wave publishes the wave's ballot counts
     const unsigned long long active = __ballot(1);
     if ((unsigned)lane_id() == (unsigned)(__ffsll((long long)active) - 1)) {
-        atomicAdd(counters + CNT_TRANSITIONS, t);
-        atomicAdd(counters + CNT_ACCEPTS, acc);
-        atomicAdd(counters + CNT_KILLS, kil);
+        unsigned long long *line = counters + (size_t)(blockIdx.x % CNT_SPREAD) * CNT_LINE;
+        atomicAdd(line + CNT_TRANSITIONS, t);
+        atomicAdd(line + CNT_ACCEPTS, acc);
+        atomicAdd(line + CNT_KILLS, kil);
     }
 }
 

@@ -18,7 +18,23 @@ struct KernelSet {
     const void *step_lds = nullptr;
     const void *drain = nullptr;
     const void *drain_lds = nullptr;
+    const void *step_binned = nullptr;       // image integrand: binned splats
+    const void *step_binned_lds = nullptr;
 };
+
+// Binned splats of one step launch into the image: per-band LDS
+// accumulation of the bucketed records into per-slice partial tiles, then a
+// fixed-order sum of the slices into the image; clears the band counters.
+struct SplatArgs {
+    const uint32_t *pix;
+    const float *val;
+    uint32_t *count;
+    float *partial;    // [SPLAT_SLICES][n_bins << SPLAT_BAND_SHIFT]
+    float *image;
+    int32_t cap, n_bins;
+    int64_t n_pix;
+};
+hipError_t launch_splat_accumulate(const SplatArgs &s, hipStream_t stream);
 
 KernelSet find_kernels(int tgt, int d, int loc, int mu);
 

@@ -43,15 +43,44 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t x, logp, logu, grad, a_cur, t_cur, last_dt, a_done, t_done, n_done, status;
-    size_t list0, list1, counts, counters, params, mu, partials, results, total;
+    size_t list0, list1, counts, counters, params, mu, partials, results;
+    size_t bin_pix, bin_val, bin_count, bin_partial, total;
 };
+
+// Binned splats (image integrand): bands of 2^SPLAT_BAND_SHIFT pixels, each
+// with a bucket for 1.5 times its even share of one launch's records (at
+// most n_chains (SPLAT_LAUNCH_STEPS + 1)); records beyond a full bucket go to
+// the image directly.  RESTORE_FLAG_SPLAT_TIGHT shrinks the buckets 64-fold.
+// n_bins = 0: splats go straight to the image.
+struct SplatPlan {
+    int n_bins = 0;
+    int64_t cap = 0;
+    int64_t n_pix = 0;
+};
+
+SplatPlan splat_plan(const restore_config *cfg, int tgt) {
+    SplatPlan sp;
+    if (tgt != TGT_PSS || !(cfg->integrands & RESTORE_INTEGRAND_PIXEL)) return sp;
+    if (cfg->flags & RESTORE_FLAG_SPLAT_DIRECT) return sp;
+    const int64_t n_pix = (int64_t)cfg->image_w * cfg->image_h;
+    const int64_t band = 1LL << SPLAT_BAND_SHIFT;
+    const int64_t n_bins = (n_pix + band - 1) / band;
+    const int64_t records = cfg->n_chains * (int64_t)(SPLAT_LAUNCH_STEPS + 1);
+    if (n_bins > SPLAT_MAX_BANDS || records >= (1LL << 31)) return sp;
+    int64_t cap = (3 * records + 2 * n_bins - 1) / (2 * n_bins);
+    if (cfg->flags & RESTORE_FLAG_SPLAT_TIGHT) cap = std::max<int64_t>(64, cap / 64);
+    sp.n_bins = (int)n_bins;
+    sp.cap = cap;
+    sp.n_pix = n_pix;
+    return sp;
+}
 
 int n_param_floats(int tgt, int d, int K) {
     if (tgt == TGT_PSS) return PSS_SLAB;
     return comp_stride(tgt, d) * K;
 }
 
-Layout make_layout(int64_t C, int d, bool mala, int n_params, int n_mu_floats) {
+Layout make_layout(int64_t C, int d, bool mala, int n_params, int n_mu_floats, const SplatPlan &sp) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
@@ -70,11 +99,16 @@ Layout make_layout(int64_t C, int d, bool mala, int n_params, int n_mu_floats) {
     L.list0 = take(4 * c);
     L.list1 = take(4 * c);
     L.counts = take(4 * 4);
-    L.counters = take(8 * CNT_SLOTS);
+    L.counters = take(8 * (size_t)CNT_SPREAD * CNT_LINE);
     L.params = take(4 * (size_t)n_params);
     L.mu = n_mu_floats > 0 ? take(4 * (size_t)n_mu_floats) : (size_t)-1;
     L.partials = take(8 * (size_t)RED_BLOCKS * RED_SLOTS);
     L.results = take(8 * RED_SLOTS);
+    const size_t nb = (size_t)sp.n_bins;
+    L.bin_pix = nb ? take(4 * nb * (size_t)sp.cap) : (size_t)-1;
+    L.bin_val = nb ? take(4 * nb * (size_t)sp.cap) : (size_t)-1;
+    L.bin_count = nb ? take(4 * (size_t)SPLAT_MAX_BANDS * SPLAT_COUNTER_STRIDE) : (size_t)-1;
+    L.bin_partial = nb ? take(4 * (size_t)SPLAT_SLICES * (nb << SPLAT_BAND_SHIFT)) : (size_t)-1;
     L.total = o;
     return L;
 }
@@ -309,6 +343,7 @@ struct restore_ctx {
     float step = 0.0f;
     float *image = nullptr;
     restore_mu mu{};
+    SplatPlan splat{};
     StepArgs args{};
 };
 
@@ -356,6 +391,11 @@ void fill_args(restore_ctx *c) {
     a.rec_x = nullptr;
     a.rec_w = nullptr;
     a.rec_chains = 0;
+    a.bin_pix = at<uint32_t>(c, c->lay.bin_pix);
+    a.bin_val = at<float>(c, c->lay.bin_val);
+    a.bin_count = at<uint32_t>(c, c->lay.bin_count);
+    a.bin_cap = (int32_t)c->splat.cap;
+    a.n_bins = c->splat.n_bins;
 }
 
 dim3 grid_for(int64_t n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
@@ -384,7 +424,7 @@ restore_status restore_state_bytes(const restore_target *target, const restore_m
     restore_status st = validate(target, mu, local, cfg, &v);
     if (st != RESTORE_OK) return st;
     *bytes_out = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_param_floats(v.tgt, v.d, v.K),
-                             v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0).total;
+                             v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0, splat_plan(cfg, v.tgt)).total;
     return RESTORE_OK;
 }
 
@@ -403,7 +443,8 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
         return fail(RESTORE_E_INVALID_ARG, "pixel integrand needs an image buffer");
     const int n_params = n_param_floats(v.tgt, v.d, v.K);
     const int n_mu = v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0;
-    const Layout lay = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_params, n_mu);
+    const SplatPlan sp = splat_plan(cfg, v.tgt);
+    const Layout lay = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_params, n_mu, sp);
     if (state_bytes < lay.total)
         return fail(RESTORE_E_BUFFER_TOO_SMALL, "state buffer holds %zu bytes, %zu needed", state_bytes, lay.total);
     KernelSet ks = find_kernels(v.tgt, v.d, v.loc, v.mu);
@@ -426,6 +467,7 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     c->step = local->step;
     c->image = (cfg->integrands & RESTORE_INTEGRAND_PIXEL) ? image_dev : nullptr;
     c->mu = *mu;
+    c->splat = sp;
     fill_args(c);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -450,8 +492,12 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     // the upload reads a host vector that goes away: finish it before returning
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) { delete c; return hip_fail(e, "parameter upload"); }
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, c->args.counters, (int)CNT_SLOTS);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(CNT_SPREAD * CNT_LINE / 256), dim3(256), 0, s, c->args.counters,
+                       CNT_SPREAD * CNT_LINE);
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, at<uint32_t>(c, c->lay.counts), 4);
+    if (sp.n_bins)
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(SPLAT_MAX_BANDS * SPLAT_COUNTER_STRIDE / 256), dim3(256), 0, s,
+                           c->args.bin_count, SPLAT_MAX_BANDS * SPLAT_COUNTER_STRIDE);
     StepArgs a = c->args;
     void *kargs[] = {&a};
     e = hipLaunchKernel(ks.init, grid_for(cfg->n_chains, 256), dim3(256), kargs, 0, s);
@@ -476,11 +522,36 @@ static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_recor
     a.rec_chains = n_record;
     int np = c->n_params;
     void *kargs[] = {&a, &np};
-    const void *fn = c->lds ? c->ks.step_lds : c->ks.step;
     const size_t shm = c->lds ? (size_t)c->n_params * sizeof(float) : 0;
-    hipError_t e = hipLaunchKernel(fn, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, shm,
-                                   static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail(e, "step launch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!c->splat.n_bins) {
+        const void *fn = c->lds ? c->ks.step_lds : c->ks.step;
+        hipError_t e = hipLaunchKernel(fn, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, shm, s);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+    } else {
+        // binned splats: launches of at most SPLAT_LAUNCH_STEPS steps, each
+        // followed by the accumulation of its bucketed records into the image
+        const void *fn = c->lds ? c->ks.step_binned_lds : c->ks.step_binned;
+        SplatArgs sa{};
+        sa.pix = a.bin_pix;
+        sa.val = a.bin_val;
+        sa.count = a.bin_count;
+        sa.partial = at<float>(c, c->lay.bin_partial);
+        sa.image = c->image;
+        sa.cap = (int32_t)c->splat.cap;
+        sa.n_bins = c->splat.n_bins;
+        sa.n_pix = c->splat.n_pix;
+        for (int32_t done = 0; done < n_steps; done += SPLAT_LAUNCH_STEPS) {
+            a.s0 = (uint32_t)(c->steps_taken + done);
+            a.n_steps = std::min<int32_t>(SPLAT_LAUNCH_STEPS, n_steps - done);
+            a.rec_x = x_out ? x_out + (int64_t)done * n_record * c->v.d : nullptr;
+            a.rec_w = w_out ? w_out + (int64_t)done * n_record : nullptr;
+            hipError_t e = hipLaunchKernel(fn, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, shm, s);
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+            e = launch_splat_accumulate(sa, s);
+            if (e != hipSuccess) return hip_fail(e, "splat accumulation launch");
+        }
+    }
     c->steps_taken += n_steps;
     return RESTORE_OK;
 }
@@ -550,11 +621,16 @@ restore_status restore_estimate(restore_ctx *c, restore_estimate_out *out, void 
     hipError_t e = launch_reduce(r, s);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
     double res[RED_SLOTS];
-    unsigned long long cnt[CNT_SLOTS];
+    std::vector<unsigned long long> lines((size_t)CNT_SPREAD * CNT_LINE);
     e = hipMemcpyAsync(res, r.results, sizeof(res), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(cnt, c->args.counters, sizeof(cnt), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(lines.data(), c->args.counters, lines.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "estimate readback");
+    unsigned long long cnt[CNT_SLOTS] = {};
+    for (int l = 0; l < CNT_SPREAD; ++l)
+        for (int j = 0; j < CNT_SLOTS; ++j) cnt[j] += lines[(size_t)l * CNT_LINE + j];
 
     const double N = res[RED_N], T = res[RED_T], A = res[RED_A];
     const double n_ok = (double)c->cfg.n_chains - res[RED_NONFINITE];

@@ -19,6 +19,12 @@ enum StatusBits : uint32_t {
 };
 
 enum CounterSlot : int { CNT_TRANSITIONS = 0, CNT_ACCEPTS = 1, CNT_KILLS = 2, CNT_SLOTS = 8 };
+// The run counters are spread over CNT_SPREAD copies, one per 256-byte line
+// (CNT_LINE 64-bit words apart), chosen by workgroup: the waves of a launch
+// then add into many lines instead of queueing on one.  Readers sum the
+// copies.
+constexpr int CNT_SPREAD = 64;
+constexpr int CNT_LINE = 32;
 
 // Number of float32 values per mixture component in the packed slab.
 //   ISO : [ c_k | m_k (d) | 1/s_k^2 ]                    c_k = ln w_k - d/2 ln(2 pi s_k^2)
@@ -62,7 +68,7 @@ struct StepArgs {
     uint32_t *status;  // [C]
     unsigned long long *counters;  // [CNT_SLOTS]
     const float *params;           // packed target slab
-    const float *mu_params;        // learned mu (device, caller-owned)
+    const float *mu_params;        // learned mu slab (inside the state buffer)
     float *image;                  // pixel splats or nullptr
     const uint32_t *list;          // drain: chains to run, or nullptr (all)
     const uint32_t *list_count;    // drain: number of entries in list
@@ -83,6 +89,25 @@ struct StepArgs {
     float *rec_x;      // [n_steps][rec_chains][D]
     float *rec_w;      // [n_steps][rec_chains]
     int64_t rec_chains;
+    // binned pixel splats (step launches of the image integrand): records
+    // (pixel, dt) go to per-band buckets instead of scattered image atomics
+    uint32_t *bin_pix;     // [n_bins][bin_cap] or nullptr
+    float *bin_val;        // [n_bins][bin_cap]
+    uint32_t *bin_count;   // entries reserved in band b at [b * SPLAT_COUNTER_STRIDE]
+    int32_t bin_cap;
+    int32_t n_bins;
 };
+
+// Binned splats: the image is cut into bands of 2^SPLAT_BAND_SHIFT pixels
+// (one LDS tile of the accumulation kernel); a workgroup stages SPLAT_ROWS
+// steps of records in LDS before binning them, and a step launch runs at
+// most SPLAT_LAUNCH_STEPS steps before its records are accumulated.
+constexpr int SPLAT_BAND_SHIFT = 14;
+constexpr int SPLAT_MAX_BANDS = 64;
+constexpr int SPLAT_ROWS = 16;
+constexpr int SPLAT_LAUNCH_STEPS = 64;
+constexpr int SPLAT_SLICES = 16;          // accumulation workgroups per band
+constexpr int SPLAT_COUNTER_STRIDE = 64;  // one 256-byte line per band counter
+constexpr uint32_t SPLAT_NO_PIX = 0xffffffffu;
 
 }  // namespace restore

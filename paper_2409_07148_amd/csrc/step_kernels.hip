@@ -53,6 +53,150 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_float
     add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill);
 }
 
+// Binning of the records staged in LDS: rows [0, rows) of this thread's
+// column.  Counts per band (LDS atomics), one global reservation per band
+// and workgroup, then each record goes to its band's bucket at the reserved
+// base plus its rank (or straight to the image if the bucket is full).
+// Every thread of the workgroup calls it the same number of times.
+__device__ __forceinline__ void splat_flush(const StepArgs &a, uint32_t (*rp)[256], float (*rv)[256], uint32_t *cnt,
+                                            uint32_t *base, int rows) {
+    const int t = threadIdx.x;
+    __syncthreads();
+    for (int r = 0; r < rows; ++r) {
+        const uint32_t p = rp[r][t];
+        if (p != SPLAT_NO_PIX) atomicAdd(&cnt[p >> SPLAT_BAND_SHIFT], 1u);
+    }
+    __syncthreads();
+    if (t < a.n_bins) {
+        const uint32_t k = cnt[t];
+        base[t] = k ? atomicAdd(a.bin_count + t * SPLAT_COUNTER_STRIDE, k) : 0u;
+        cnt[t] = 0u;
+    }
+    __syncthreads();
+    for (int r = 0; r < rows; ++r) {
+        const uint32_t p = rp[r][t];
+        if (p != SPLAT_NO_PIX) {
+            const uint32_t b = p >> SPLAT_BAND_SHIFT;
+            const uint32_t pos = base[b] + atomicAdd(&cnt[b], 1u);
+            const float v = rv[r][t];
+            if (pos < (uint32_t)a.bin_cap) {
+                const size_t o = (size_t)b * (size_t)a.bin_cap + pos;
+                a.bin_pix[o] = p;
+                a.bin_val[o] = v;
+            } else {
+                atomicAdd(a.image + p, v);
+            }
+        }
+    }
+    __syncthreads();
+    if (t < a.n_bins) cnt[t] = 0u;
+}
+
+// Steps with regeneration for the image integrand, with binned splats.
+// Every lane stages the record (pixel, dt) its step closed, if any, in its
+// LDS column; every SPLAT_ROWS steps, and once more at the end with the
+// splat still open, the workgroup bins its records (splat_flush).  Lanes
+// past the last chain take part in the barriers only.
+template <int D, int TGT, int LOC, int MU, bool LDS>
+__global__ __launch_bounds__(256) void step_binned_kernel(StepArgs a, int n_param_floats) {
+    extern __shared__ float smem[];
+    __shared__ uint32_t rec_pix[SPLAT_ROWS + 1][256];
+    __shared__ float rec_val[SPLAT_ROWS + 1][256];
+    __shared__ uint32_t cnt[SPLAT_MAX_BANDS], base[SPLAT_MAX_BANDS];
+    const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
+    const int t = threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + t;
+    const bool active = c < a.n_chains;
+    if (t < SPLAT_MAX_BANDS) cnt[t] = 0u;
+    Chain<D, LOC> ch;
+    if (active) load_chain(a, (uint32_t)c, ch);
+    unsigned long long n_acc = 0, n_kill = 0;
+    bool kill = false, accept = false;
+    const bool rec = active && a.rec_x != nullptr && c < a.rec_chains;
+    int row = 0;
+    for (int it = 0; it < a.n_steps; ++it) {
+        uint32_t rp = SPLAT_NO_PIX;
+        float rv = 0.0f;
+        if (active) {
+            if (rec) {
+                float *xo = a.rec_x + ((int64_t)it * a.rec_chains + c) * D;
+#pragma unroll
+                for (int i = 0; i < D; ++i) xo[i] = ch.x[i];
+            }
+            step_once<D, TGT, LOC, MU, false, decltype(P), true>(a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch,
+                                                                 kill, accept);
+            if (rec) a.rec_w[(int64_t)it * a.rec_chains + c] = ch.last_dt;
+            if (ch.out_pix >= 0) {
+                rp = (uint32_t)ch.out_pix;
+                rv = ch.out_acc;
+            }
+        }
+        rec_pix[row][t] = rp;
+        rec_val[row][t] = rv;
+        n_acc += __popcll(__ballot(accept));
+        n_kill += __popcll(__ballot(kill));
+        if (++row == SPLAT_ROWS) {
+            splat_flush(a, rec_pix, rec_val, cnt, base, SPLAT_ROWS);
+            row = 0;
+        }
+    }
+    // the splat still open at the end of the launch
+    rec_pix[row][t] = (active && ch.splat_pix >= 0) ? (uint32_t)ch.splat_pix : SPLAT_NO_PIX;
+    rec_val[row][t] = active ? ch.splat_acc : 0.0f;
+    splat_flush(a, rec_pix, rec_val, cnt, base, row + 1);
+    if (active) {
+        ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT)) | (kill ? ST_LAST_KILL : 0u) |
+                    (accept ? ST_LAST_ACCEPT : 0u);
+        store_chain(a, (uint32_t)c, ch);
+    }
+    const unsigned long long lanes = __popcll(__ballot(active));
+    if (lanes) add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill);
+}
+
+// Per band b and slice: the slice's share of band b's records summed into a
+// 2^SPLAT_BAND_SHIFT-pixel LDS tile, written to partial[slice][band pixels].
+__global__ __launch_bounds__(1024) void splat_accumulate_kernel(SplatArgs s) {
+    extern __shared__ float tile[];
+    constexpr int BAND = 1 << SPLAT_BAND_SHIFT;
+    const int b = blockIdx.y, sl = blockIdx.x, t = threadIdx.x;
+    const uint32_t reserved = s.count[b * SPLAT_COUNTER_STRIDE];
+    const uint32_t n = reserved < (uint32_t)s.cap ? reserved : (uint32_t)s.cap;
+    for (int j = t; j < BAND; j += blockDim.x) tile[j] = 0.0f;
+    __syncthreads();
+    const uint32_t per = (n + SPLAT_SLICES - 1) / SPLAT_SLICES;
+    const uint32_t lo = (uint32_t)sl * per;
+    const uint32_t hi = lo + per < n ? lo + per : n;
+    const uint32_t *pix = s.pix + (size_t)b * (size_t)s.cap;
+    const float *val = s.val + (size_t)b * (size_t)s.cap;
+    const uint32_t off = (uint32_t)b << SPLAT_BAND_SHIFT;
+    for (uint32_t i = lo + t; i < hi; i += blockDim.x) atomicAdd(&tile[pix[i] - off], val[i]);
+    __syncthreads();
+    float *out = s.partial + (size_t)sl * ((size_t)s.n_bins << SPLAT_BAND_SHIFT) + off;
+    for (int j = t; j < BAND; j += blockDim.x) out[j] = tile[j];
+}
+
+// image[px] += sum over slices (in slice order) of partial[slice][px]; block 0
+// also clears the band counters for the next step launch.
+__global__ __launch_bounds__(256) void splat_reduce_kernel(SplatArgs s) {
+    const int64_t px = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < s.n_bins) s.count[threadIdx.x * SPLAT_COUNTER_STRIDE] = 0u;
+    if (px >= s.n_pix) return;
+    const size_t stride = (size_t)s.n_bins << SPLAT_BAND_SHIFT;
+    float v = 0.0f;
+#pragma unroll
+    for (int sl = 0; sl < SPLAT_SLICES; ++sl) v += s.partial[(size_t)sl * stride + px];
+    if (v != 0.0f) s.image[px] += v;
+}
+
+hipError_t launch_splat_accumulate(const SplatArgs &s, hipStream_t stream) {
+    hipLaunchKernelGGL(splat_accumulate_kernel, dim3(SPLAT_SLICES, s.n_bins), dim3(1024),
+                       (1 << SPLAT_BAND_SHIFT) * sizeof(float), stream, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(splat_reduce_kernel, dim3((unsigned)((s.n_pix + 255) / 256)), dim3(256), 0, stream, s);
+    return hipGetLastError();
+}
+
 // Drain: the chains of the input list run on without regeneration until
 // their tour in flight is killed.  Survivors of this chunk are compacted
 // into the output list with one ballot and one atomic per wave; on the last
@@ -162,6 +306,10 @@ static KernelSet make_set() {
     k.step_lds = (const void *)step_kernel<D, TGT, LOC, MU, true>;
     k.drain = (const void *)drain_kernel<D, TGT, LOC, MU, false>;
     k.drain_lds = (const void *)drain_kernel<D, TGT, LOC, MU, true>;
+    if constexpr (TGT == TGT_PSS) {
+        k.step_binned = (const void *)step_binned_kernel<D, TGT, LOC, MU, false>;
+        k.step_binned_lds = (const void *)step_binned_kernel<D, TGT, LOC, MU, true>;
+    }
     return k;
 }
 

@@ -24,7 +24,7 @@ TARGET_GMM_ISO, TARGET_GMM_FULL, TARGET_PSS = 0, 1, 2
 MU_UNIFORM_BOX, MU_GMM_DIAG = 0, 1
 LOCAL_RWMH, LOCAL_MALA = 0, 1
 INTEGRAND_ONE, INTEGRAND_P, INTEGRAND_PIXEL = 1, 2, 4
-FLAG_PARAMS_LDS = 1
+FLAG_PARAMS_LDS, FLAG_SPLAT_DIRECT, FLAG_SPLAT_TIGHT = 1, 2, 4
 ST_ALIVE, ST_CENSORED, ST_LAST_KILL, ST_LAST_ACCEPT, ST_GRAD_VALID = 1, 2, 4, 8, 16
 
 
@@ -363,7 +363,7 @@ class Problem:
 def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: float, n_chains: int,
                  c_tilde: float, seed: int, drain_cap: int, target_id: int = 0, integrand_p: bool = True,
                  image: Optional[tuple] = None, lds: bool = False, block_size: int = 0,
-                 mu: Optional[dict] = None) -> Problem:
+                 mu: Optional[dict] = None, flags: int = 0) -> Problem:
     flat = target_params(kind, d, K, params)
     t = restore_target(_KIND[kind], d, K if kind != "pss" else 0, 0,
                        flat.ctypes.data_as(C.POINTER(C.c_double)), flat.size)
@@ -384,7 +384,7 @@ def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: f
     integrands = INTEGRAND_ONE | (INTEGRAND_P if integrand_p else 0) | (INTEGRAND_PIXEL if image else 0)
     w, h = (image or (0, 0))
     cfg = restore_config(int(seed), int(n_chains), int(target_id), integrands, float(c_tilde), int(drain_cap),
-                         int(w), int(h), FLAG_PARAMS_LDS if lds else 0, int(block_size), 0)
+                         int(w), int(h), (FLAG_PARAMS_LDS if lds else 0) | int(flags), int(block_size), 0)
     return Problem(t, m, lk, cfg, flat, mu_t)
 
 

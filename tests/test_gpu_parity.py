@@ -505,3 +505,36 @@ def test_state_checkpoint_resume(R):
         assert np.array_equal(ref[k], got[k]), k
     a.close()
     c.close()
+
+
+def test_binned_splats_match_direct_atomics(R):
+    """Image splats binned by band (the default), sent straight to the
+    image with scattered atomics, and binned into buckets too small to hold
+    them (most records take the overflow path) give the same chains bit for
+    bit and the same image up to the order of the float32 additions: each
+    pixel is a sum of the same positive terms, so two orders differ by at
+    most 2 (terms + 1) 2^-24 of the pixel value.  150 steps cross two
+    launch boundaries (64 steps) and end between two in-launch flushes
+    (every 16 steps) of the binned path."""
+    import torch
+    from workloads import pss_render
+    wl = pss_render(n_chains=1 << 16, n_steps=150, image=(512, 512))
+    runs = {}
+    for name, flags in (("binned", 0), ("direct", R.FLAG_SPLAT_DIRECT), ("tight", R.FLAG_SPLAT_TIGHT)):
+        run = R.Run(R.problem_from_workload(wl, flags=flags))
+        run.step(wl.n_steps)
+        _sync()
+        runs[name] = (run.image.double().cpu().numpy(), {k: v.clone() for k, v in run.arrays().items()})
+        run.close()
+    n_terms = (1 << 16) * (wl.n_steps + 3) / (512 * 512)
+    ref_img, ref_arr = runs["direct"]
+    for name in ("binned", "tight"):
+        img, arr = runs[name]
+        for k in ("x", "logp", "t_cur", "a_cur", "status", "n_done"):
+            assert torch.equal(arr[k], ref_arr[k]), (name, k)
+        bound = 2 * (8 * n_terms + 1) * 2.0 ** -24 * np.maximum(img, ref_img) + 1e-30
+        err = np.abs(img - ref_img)
+        _say(f"[splats] {name}: image sum {img.sum():.6g} vs {ref_img.sum():.6g}, "
+             f"max err/bound {float((err / bound).max()):.3f}, nonzero pixels {(img > 0).sum()}")
+        assert np.all(err <= bound)
+        assert np.array_equal(img > 0, ref_img > 0)

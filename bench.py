@@ -110,9 +110,13 @@ def cpu_baseline(wl, target_seconds: float = 12.0) -> dict:
     r = O.run(prob, 0, n, threads=threads)
     el = time.perf_counter() - t0
     trans = int(r.transitions.sum())
+    t0 = time.perf_counter()
+    r1 = O.run(prob, 0, 1024, threads=1)
+    one_core = r1.transitions.sum() / (time.perf_counter() - t0)
     return {"value": trans / el, "unit": "transitions/s", "cores": threads, "kind": "oracle",
             "sample": f"chains 0..{n - 1} of the same workload (full {wl.n_steps}-step budget + drain), "
-                      f"{trans} transitions in {el:.1f} s", "pilot_rate": rate}
+                      f"{trans} transitions in {el:.1f} s", "pilot_rate": rate,
+            "one_core_rate": float(one_core), "one_core_sample": "chains 0..1023, one thread"}
 
 
 def bench_batched(args):
@@ -177,10 +181,13 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
     """MSE x time of the learned regeneration distribution against uniform
     mu on the same workload: train mu_theta (5 refits on restore samples,
     matrix-core MLP, Adam), then `replicates` independent runs per method
-    (fresh seeds, full chain count and budget, each timed on the wall clock
-    from restore_init to restore_estimate), scored against the stored
-    closed-form truth.  t_1% = time (rel. RMS error / 1%)^2 is the time
-    either method needs to reach 1% relative error."""
+    and c~ (fresh seeds, full chain count and budget, each timed on the wall
+    clock from restore_init to restore_estimate), scored against the stored
+    closed-form truth.  t_1% = time (rel. RMS error / 1%)^2 is the time a
+    method needs to reach 1% relative error.  Each method is run at its
+    provable c~ (every mean lifetime <= B/8) and over a sweep of smaller
+    values; the comparison is reported at the provable c~ and at each
+    method's best c~ of the sweep."""
     import numpy as np
     import torch
     from paper_2409_07148_amd import restore as R
@@ -199,7 +206,6 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
 
     def runs(mu_, ct):
         out = []
-        prob = None
         for r in range(replicates):
             prob = R.problem_from_workload(wl, mu=mu_, c_tilde=ct, seed=2004 + 17 * r)
             torch.cuda.synchronize()
@@ -212,28 +218,32 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
             run.close()
         return out
 
-    res = {}
-    for name, mu_, ct in (("uniform", None, wl.c_tilde), ("learned", mu, ct_learned)):
-        rr = runs(mu_, ct)
+    def summary(rr, ct):
         secs = np.array([t for t, _ in rr])
-        summary = {"c_tilde": ct, "seconds_per_run": float(secs.mean()),
-                   "transitions_per_s": float(np.mean([e["transitions"] / t for t, e in rr])),
-                   "censored_tours": int(sum(e["tours_censored"] for _, e in rr))}
+        out = {"c_tilde": ct, "seconds_per_run": float(secs.mean()),
+               "transitions_per_s": float(np.mean([e["transitions"] / t for t, e in rr])),
+               "censored_tours": int(sum(e["tours_censored"] for _, e in rr)),
+               "kill_rate": float(np.mean([e["kill_rate"] for _, e in rr]))}
         for key in ("lam_pf", "p_lambda"):
             rel = np.array([(e[key] - truth[key]) / truth[key] for _, e in rr])
             mse = float((rel ** 2).mean())
-            summary[key] = {"rel_rmse": math.sqrt(mse), "rel_bias": float(rel.mean()),
-                            "mse_x_time": mse * float(secs.mean()),
-                            "t_1pct_s": float(secs.mean()) * mse / 1e-4}
-        res[name] = summary
-    res["replicates"] = replicates
-    res["training_s"] = train_s
-    res["training_rounds"] = hist
-    res["primary"] = "lam_pf"
+            out[key] = {"rel_rmse": math.sqrt(mse), "rel_bias": float(rel.mean()),
+                        "mse_x_time": mse * float(secs.mean()), "t_1pct_s": float(secs.mean()) * mse / 1e-4}
+        return out
+
+    sweeps = {"uniform": (None, [wl.c_tilde * 10.0 ** -k for k in range(7)]),
+              "learned": (mu, [ct_learned * 10.0 ** -k for k in (0, 2, 4, 6, 8, 9, 10)])}
+    res = {"replicates": replicates, "primary": "lam_pf", "training_s": train_s, "training_rounds": hist,
+           "sweep": {}}
+    for name, (mu_, cts) in sweeps.items():
+        res["sweep"][name] = [summary(runs(mu_, ct), ct) for ct in cts]
+        res[name] = res["sweep"][name][0]            # the provable c~
+        res[name + "_best"] = min(res["sweep"][name], key=lambda r: r["lam_pf"]["mse_x_time"])
     res["mse_x_time_ratio_uniform_over_learned"] = (res["uniform"]["lam_pf"]["mse_x_time"]
                                                     / res["learned"]["lam_pf"]["mse_x_time"])
-    res["t_1pct_learned_amortised_s"] = (res["learned"]["lam_pf"]["t_1pct_s"]
-                                         + train_s / replicates)
+    res["mse_x_time_ratio_at_best_c_tilde"] = (res["uniform_best"]["lam_pf"]["mse_x_time"]
+                                               / res["learned_best"]["lam_pf"]["mse_x_time"])
+    res["t_1pct_learned_amortised_s"] = (res["learned"]["lam_pf"]["t_1pct_s"] + train_s / replicates)
     return res
 
 

@@ -284,9 +284,12 @@ def main():
     nbytes = R.restore_state_bytes(prob.target, prob.mu, prob.local, prob.cfg)
     state = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
     ptr = (state.data_ptr() + 255) // 256 * 256
-    image = None
-    if wl.image:
-        image = torch.zeros((wl.image[1], wl.image[0]), dtype=torch.float32, device="cuda")
+    image = img_mean = img_se = None
+    if prob.cfg.integrands & R.INTEGRAND_PIXEL:
+        h, w, nb = prob.cfg.image_h, prob.cfg.image_w, max(1, prob.cfg.image_batches)
+        image = torch.zeros((nb, h, w), dtype=torch.float32, device="cuda")
+        img_mean = torch.empty((h, w), dtype=torch.float32, device="cuda")
+        img_se = torch.empty((h, w), dtype=torch.float32, device="cuda")
 
     def one_pass(timed_step=None):
         if image is not None:
@@ -299,6 +302,8 @@ def main():
         if timed_step is not None:
             timed_step[1].record(stream)
         R.restore_drain(ctx, stream)
+        if image is not None:
+            R.restore_image_estimate(ctx, img_mean.data_ptr(), img_se.data_ptr(), stream)
         est = R.restore_estimate(ctx, stream)   # synchronises the stream
         R.restore_destroy(ctx)
         return est
@@ -359,6 +364,13 @@ def main():
                                                     "tours_done", "tours_censored", "kill_rate",
                                                     "accept_rate")},
     }
+    if image is not None:
+        rel = (img_se / img_mean.clamp_min(1e-30)).flatten()
+        line["image"] = {"width": prob.cfg.image_w, "height": prob.cfg.image_h,
+                         "batches": max(1, prob.cfg.image_batches),
+                         "splats": "direct" if prob.cfg.flags & R.FLAG_SPLAT_DIRECT else "binned",
+                         "median_rel_se": float(rel.median().item()) if prob.cfg.image_batches > 1 else None,
+                         "estimate_total": float(img_mean.double().sum().item())}
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

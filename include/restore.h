@@ -145,7 +145,10 @@ typedef struct {
     int32_t flags;           /* RESTORE_FLAG_*                               */
     int32_t block_size;      /* threads per workgroup (64..256, multiple of
                                 64); 0 = library default                    */
-    int32_t reserved;
+    int32_t image_batches;   /* PIXEL: chains split into this many contiguous
+                                ranges (chain c in batch floor(c B / C)),
+                                each splatting into its own image, for the
+                                per-pixel standard error; 0 or 1 = one image */
 } restore_config;
 
 /* ---- estimates (Sec. 6.3, Sec. 7.4) ----------------------------------- */
@@ -177,7 +180,8 @@ restore_status restore_state_bytes(const restore_target *target, const restore_m
  * float64) and draw x_0 ~ mu for every chain (Alg. 2 input; tours are
  * spawned from mu so that chains are unbiased in parallel, Sec. 1).
  * `state_dev` (>= restore_state_bytes, 256-byte aligned) and `image_dev`
- * (float32 [image_h][image_w], zeroed by the caller; NULL unless PIXEL) are
+ * (float32 [image_batches][image_h][image_w], zeroed by the caller; NULL
+ * unless PIXEL) are
  * caller-owned device memory.  On success *out receives a new context. */
 restore_status restore_init(restore_ctx **out, const restore_target *target,
                             const restore_mu *mu, const restore_local_kernel *local,
@@ -202,6 +206,18 @@ restore_status restore_drain(restore_ctx *ctx, void *stream);
 /* Reduce the per-chain tour sums in float64 and fill *out (host memory).
  * Synchronises `stream`. */
 restore_status restore_estimate(restore_ctx *ctx, restore_estimate_out *out, void *stream);
+
+/* Per-pixel estimate of the image integrand, lambda(p h_j) = c_tilde
+ * (sum of the dt splatted into pixel j) / j (Sec. 7.4, eq. (approx) with
+ * f = the pixel indicator, Sec. 6.3), into mean_dev[image_h][image_w], and
+ * its delta-method standard error over the image batches into
+ * se_dev[image_h][image_w] (NaN with one batch): with S_b the batch images
+ * and N_b the tours completed by the batch's chains,
+ * se = c_tilde sqrt(sum_b (S_b - R N_b)^2 / ((B - 1) B)) / mean N_b,
+ * R = sum S_b / sum N_b.  Splats of a tour censored at the drain cap stay
+ * in the image (their share of the time is censored_time_frac).  Device
+ * float32 outputs, caller-owned; enqueue only (after the drain). */
+restore_status restore_image_estimate(restore_ctx *ctx, float *mean_dev, float *se_dev, void *stream);
 
 /* Device addresses of the chain state arrays, for tests and checkpointing.
  * Layout: x float32 [d][C]; logp, logu float32 [C]; grad float32 [d][C]

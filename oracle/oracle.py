@@ -379,3 +379,28 @@ def estimate(r: RunResult) -> dict:
 def image_estimate(r: RunResult) -> np.ndarray:
     """lambda(p h_j) per pixel j: (c_tilde / j) times the summed dt splats."""
     return r.c_tilde * r.image / r.n_done.sum()
+
+
+def image_batch_estimate(images: np.ndarray, tours: np.ndarray, c_tilde: float):
+    """Per-pixel estimate and standard error from batch images.
+
+    images[b] holds the dt splatted by the chains of batch b, tours[b] the
+    tours those chains completed.  The estimate of lambda(p h_j) is the
+    ratio c_tilde sum_b S_bj / sum_b N_b (Sec. 6.3 with f the pixel
+    indicator), and its standard error the delta-method one with the
+    batches as the independent units: the same ratio-estimator variance
+    as for chains (see _ratio), here over B batches."""
+    S = np.asarray(images, dtype=np.float64).reshape(len(tours), -1)
+    N = np.asarray(tours, dtype=np.float64)
+    B = len(N)
+    R = S.sum(axis=0) / N.sum()
+    resid = S - R[None, :] * N[:, None]
+    var = (resid ** 2).sum(axis=0) / ((B - 1) * B) / (N.mean() ** 2) if B > 1 else np.full(R.shape, np.nan)
+    shape = np.asarray(images).shape[1:]
+    return (c_tilde * R).reshape(shape), (c_tilde * np.sqrt(var)).reshape(shape)
+
+
+def batch_ranges(n_chains: int, batches: int):
+    """Chain ranges of the image batches: chain c belongs to batch
+    floor(c batches / n_chains)."""
+    return [(-(-b * n_chains // batches), -(-(b + 1) * n_chains // batches)) for b in range(batches)]

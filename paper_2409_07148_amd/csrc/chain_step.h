@@ -75,6 +75,8 @@ struct Chain {
     // binned splats: the record this step closed (pixel -1: none)
     int32_t out_pix;
     float out_acc;
+    // first pixel of this chain's batch image
+    int32_t img_base;
 };
 
 __device__ __forceinline__ void flush_splat(const StepArgs &a, int32_t pix, float acc) {
@@ -103,6 +105,11 @@ __device__ __forceinline__ void load_chain(const StepArgs &a, uint32_t c, Chain<
     ch.splat_acc = 0.0f;
     ch.out_pix = -1;
     ch.out_acc = 0.0f;
+    // chains are split into image_batches contiguous ranges: c in batch
+    // floor(c batches / C)
+    ch.img_base = a.image_batches > 1
+                      ? (int32_t)((int64_t)c * a.image_batches / a.n_chains) * a.image_pixels
+                      : 0;
 }
 
 template <int D, int LOC>
@@ -165,7 +172,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         if (u0 >= 0.0f && u0 <= 1.0f && u1 >= 0.0f && u1 <= 1.0f) {
             const int px = min(max((int)(u0 * (float)a.image_w), 0), a.image_w - 1);
             const int py = min(max((int)(u1 * (float)a.image_h), 0), a.image_h - 1);
-            pix = py * a.image_w + px;
+            pix = ch.img_base + py * a.image_w + px;
         }
         if (BIN) ch.out_pix = -1;
         if (pix != ch.splat_pix) {

@@ -29,12 +29,27 @@ struct SplatArgs {
     const uint32_t *pix;
     const float *val;
     uint32_t *count;
-    float *partial;    // [SPLAT_SLICES][n_bins << SPLAT_BAND_SHIFT]
-    float *image;
-    int32_t cap, n_bins;
-    int64_t n_pix;
+    float *partial;    // [n_slices][n_bins << SPLAT_BAND_SHIFT]
+    float *image;      // [image_batches][image_h][image_w]
+    int32_t cap, n_bins, n_slices;
+    int64_t n_pix;     // pixels of all batch images
 };
 hipError_t launch_splat_accumulate(const SplatArgs &s, hipStream_t stream);
+
+// Per-pixel estimate and batch-means standard error of the image integrand
+// (restore_image_estimate).
+struct ImageEstimateArgs {
+    const float *image;      // [batches][n_pix]
+    const uint32_t *n_done;  // per chain
+    const double *t_done, *a_done;
+    int64_t n_chains;
+    int32_t batches;
+    int64_t n_pix;
+    double c_tilde;
+    double *tours;           // [batches] scratch: completed tours per batch
+    float *mean, *se;        // [n_pix]
+};
+hipError_t launch_image_estimate(const ImageEstimateArgs &a, hipStream_t stream);
 
 KernelSet find_kernels(int tgt, int d, int loc, int mu);
 

@@ -44,7 +44,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     size_t x, logp, logu, grad, a_cur, t_cur, last_dt, a_done, t_done, n_done, status;
     size_t list0, list1, counts, counters, params, mu, partials, results;
-    size_t bin_pix, bin_val, bin_count, bin_partial, total;
+    size_t bin_pix, bin_val, bin_count, bin_partial, img_tours, total;
 };
 
 // Binned splats (image integrand): bands of 2^SPLAT_BAND_SHIFT pixels, each
@@ -54,15 +54,20 @@ struct Layout {
 // n_bins = 0: splats go straight to the image.
 struct SplatPlan {
     int n_bins = 0;
+    int n_slices = 0;
     int64_t cap = 0;
-    int64_t n_pix = 0;
+    int64_t n_pix = 0;   // pixels of all batch images
+    int batches = 0;     // image batches (0: no image)
 };
+
+int image_batches_of(const restore_config *cfg) { return cfg->image_batches > 1 ? cfg->image_batches : 1; }
 
 SplatPlan splat_plan(const restore_config *cfg, int tgt) {
     SplatPlan sp;
     if (tgt != TGT_PSS || !(cfg->integrands & RESTORE_INTEGRAND_PIXEL)) return sp;
+    sp.batches = image_batches_of(cfg);
     if (cfg->flags & RESTORE_FLAG_SPLAT_DIRECT) return sp;
-    const int64_t n_pix = (int64_t)cfg->image_w * cfg->image_h;
+    const int64_t n_pix = (int64_t)cfg->image_w * cfg->image_h * sp.batches;
     const int64_t band = 1LL << SPLAT_BAND_SHIFT;
     const int64_t n_bins = (n_pix + band - 1) / band;
     const int64_t records = cfg->n_chains * (int64_t)(SPLAT_LAUNCH_STEPS + 1);
@@ -70,6 +75,8 @@ SplatPlan splat_plan(const restore_config *cfg, int tgt) {
     int64_t cap = (3 * records + 2 * n_bins - 1) / (2 * n_bins);
     if (cfg->flags & RESTORE_FLAG_SPLAT_TIGHT) cap = std::max<int64_t>(64, cap / 64);
     sp.n_bins = (int)n_bins;
+    // about 512 accumulation workgroups per launch
+    sp.n_slices = (int)std::max<int64_t>(1, std::min<int64_t>(SPLAT_MAX_SLICES, 512 / n_bins));
     sp.cap = cap;
     sp.n_pix = n_pix;
     return sp;
@@ -108,7 +115,8 @@ Layout make_layout(int64_t C, int d, bool mala, int n_params, int n_mu_floats, c
     L.bin_pix = nb ? take(4 * nb * (size_t)sp.cap) : (size_t)-1;
     L.bin_val = nb ? take(4 * nb * (size_t)sp.cap) : (size_t)-1;
     L.bin_count = nb ? take(4 * (size_t)SPLAT_MAX_BANDS * SPLAT_COUNTER_STRIDE) : (size_t)-1;
-    L.bin_partial = nb ? take(4 * (size_t)SPLAT_SLICES * (nb << SPLAT_BAND_SHIFT)) : (size_t)-1;
+    L.bin_partial = nb ? take(4 * (size_t)sp.n_slices * (nb << SPLAT_BAND_SHIFT)) : (size_t)-1;
+    L.img_tours = sp.batches ? take(8 * (size_t)sp.batches) : (size_t)-1;
     L.total = o;
     return L;
 }
@@ -173,6 +181,14 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
             return fail(RESTORE_E_INVALID_ARG, "image size must be >= 1 and at most 2^28 pixels");
         if (t->kind != RESTORE_TARGET_PSS)
             return fail(RESTORE_E_UNSUPPORTED, "pixel splats are built for the rendering-shaped target");
+        if (cfg->image_batches < 0 || cfg->image_batches > 4096)
+            return fail(RESTORE_E_INVALID_ARG, "image_batches must be in 0..4096");
+        if ((int64_t)cfg->image_w * cfg->image_h * std::max(1, cfg->image_batches) > 0x7fffffffLL)
+            return fail(RESTORE_E_INVALID_ARG, "image_batches x image pixels must stay below 2^31");
+        if ((int64_t)std::max(1, cfg->image_batches) > cfg->n_chains)
+            return fail(RESTORE_E_INVALID_ARG, "more image batches than chains");
+    } else if (cfg->image_batches > 1) {
+        return fail(RESTORE_E_INVALID_ARG, "image_batches needs the PIXEL integrand");
     }
     v->tgt = t->kind == RESTORE_TARGET_GMM_ISO ? TGT_ISO : t->kind == RESTORE_TARGET_GMM_FULL ? TGT_FULL : TGT_PSS;
     v->d = d;
@@ -388,6 +404,8 @@ void fill_args(restore_ctx *c) {
     a.integrand_p = (c->cfg.integrands & RESTORE_INTEGRAND_P) ? 1 : 0;
     a.image_w = c->cfg.image_w;
     a.image_h = c->cfg.image_h;
+    a.image_batches = image_batches_of(&c->cfg);
+    a.image_pixels = c->cfg.image_w * c->cfg.image_h;
     a.rec_x = nullptr;
     a.rec_w = nullptr;
     a.rec_chains = 0;
@@ -540,6 +558,7 @@ static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_recor
         sa.image = c->image;
         sa.cap = (int32_t)c->splat.cap;
         sa.n_bins = c->splat.n_bins;
+        sa.n_slices = c->splat.n_slices;
         sa.n_pix = c->splat.n_pix;
         for (int32_t done = 0; done < n_steps; done += SPLAT_LAUNCH_STEPS) {
             a.s0 = (uint32_t)(c->steps_taken + done);
@@ -658,6 +677,26 @@ restore_status restore_estimate(restore_ctx *c, restore_estimate_out *out, void 
     out->accept_rate = cnt[CNT_TRANSITIONS] ? (double)cnt[CNT_ACCEPTS] / (double)cnt[CNT_TRANSITIONS] : 0.0;
     out->kill_rate = cnt[CNT_TRANSITIONS] ? (double)cnt[CNT_KILLS] / (double)cnt[CNT_TRANSITIONS] : 0.0;
     out->image_scale = N > 0 ? ct / N : 0.0;
+    return RESTORE_OK;
+}
+
+restore_status restore_image_estimate(restore_ctx *c, float *mean_dev, float *se_dev, void *stream) {
+    if (!c || !mean_dev || !se_dev) return fail(RESTORE_E_INVALID_ARG, "null argument");
+    if (!c->image) return fail(RESTORE_E_BAD_STATE, "the run has no PIXEL integrand");
+    ImageEstimateArgs a{};
+    a.image = c->image;
+    a.n_done = c->args.n_done;
+    a.t_done = c->args.t_done;
+    a.a_done = c->args.a_done;
+    a.n_chains = c->cfg.n_chains;
+    a.batches = image_batches_of(&c->cfg);
+    a.n_pix = (int64_t)c->cfg.image_w * c->cfg.image_h;
+    a.c_tilde = c->cfg.c_tilde;
+    a.tours = at<double>(c, c->lay.img_tours);
+    a.mean = mean_dev;
+    a.se = se_dev;
+    hipError_t e = launch_image_estimate(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "image estimate launch");
     return RESTORE_OK;
 }
 

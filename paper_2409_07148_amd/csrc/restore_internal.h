@@ -85,6 +85,8 @@ struct StepArgs {
     int32_t n_steps;   // steps in this launch
     int32_t integrand_p;
     int32_t image_w, image_h;
+    int32_t image_batches;  // chains split into contiguous ranges, one image each (>= 1)
+    int32_t image_pixels;   // image_w * image_h
     // sample recording (restore_step_record): (x_{i-1}, dt_i) of chains < rec_chains
     float *rec_x;      // [n_steps][rec_chains][D]
     float *rec_w;      // [n_steps][rec_chains]
@@ -103,10 +105,10 @@ struct StepArgs {
 // steps of records in LDS before binning them, and a step launch runs at
 // most SPLAT_LAUNCH_STEPS steps before its records are accumulated.
 constexpr int SPLAT_BAND_SHIFT = 14;
-constexpr int SPLAT_MAX_BANDS = 64;
+constexpr int SPLAT_MAX_BANDS = 256;
 constexpr int SPLAT_ROWS = 16;
 constexpr int SPLAT_LAUNCH_STEPS = 64;
-constexpr int SPLAT_SLICES = 16;          // accumulation workgroups per band
+constexpr int SPLAT_MAX_SLICES = 16;      // accumulation workgroups per band (at most)
 constexpr int SPLAT_COUNTER_STRIDE = 64;  // one 256-byte line per band counter
 constexpr uint32_t SPLAT_NO_PIX = 0xffffffffu;
 

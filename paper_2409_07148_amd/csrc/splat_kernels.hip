@@ -1,7 +1,8 @@
 // Accumulation of the binned image splats of one step launch (the records
 // step_binned_kernel left in the per-band buckets): each band is summed in
-// an LDS tile by SPLAT_SLICES workgroups, whose partial tiles are then added
-// to the image in slice order.
+// an LDS tile by n_slices workgroups, whose partial tiles are then added to
+// the image in slice order; and the per-pixel estimate of the image
+// integrand with its batch-means standard error.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -20,7 +21,7 @@ __global__ __launch_bounds__(1024) void splat_accumulate_kernel(SplatArgs s) {
     const uint32_t n = reserved < (uint32_t)s.cap ? reserved : (uint32_t)s.cap;
     for (int j = t; j < BAND; j += blockDim.x) tile[j] = 0.0f;
     __syncthreads();
-    const uint32_t per = (n + SPLAT_SLICES - 1) / SPLAT_SLICES;
+    const uint32_t per = (n + s.n_slices - 1) / s.n_slices;
     const uint32_t lo = (uint32_t)sl * per;
     const uint32_t hi = lo + per < n ? lo + per : n;
     const uint32_t *pix = s.pix + (size_t)b * (size_t)s.cap;
@@ -50,21 +51,75 @@ __global__ __launch_bounds__(1024) void splat_accumulate_kernel(SplatArgs s) {
 // also clears the band counters for the next step launch.
 __global__ __launch_bounds__(256) void splat_reduce_kernel(SplatArgs s) {
     const int64_t px = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x < s.n_bins) s.count[threadIdx.x * SPLAT_COUNTER_STRIDE] = 0u;
+    if (blockIdx.x == 0)
+        for (int b = threadIdx.x; b < s.n_bins; b += blockDim.x) s.count[b * SPLAT_COUNTER_STRIDE] = 0u;
     if (px >= s.n_pix) return;
     const size_t stride = (size_t)s.n_bins << SPLAT_BAND_SHIFT;
     float v = 0.0f;
-#pragma unroll
-    for (int sl = 0; sl < SPLAT_SLICES; ++sl) v += s.partial[(size_t)sl * stride + px];
+    for (int sl = 0; sl < s.n_slices; ++sl) v += s.partial[(size_t)sl * stride + px];
     if (v != 0.0f) s.image[px] += v;
 }
 
 hipError_t launch_splat_accumulate(const SplatArgs &s, hipStream_t stream) {
-    hipLaunchKernelGGL(splat_accumulate_kernel, dim3(SPLAT_SLICES, s.n_bins), dim3(1024),
+    hipLaunchKernelGGL(splat_accumulate_kernel, dim3(s.n_slices, s.n_bins), dim3(1024),
                        (1 << SPLAT_BAND_SHIFT) * sizeof(float), stream, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(splat_reduce_kernel, dim3((unsigned)((s.n_pix + 255) / 256)), dim3(256), 0, stream, s);
+    return hipGetLastError();
+}
+// Completed tours of each image batch, in a fixed order: block b sums
+// n_done over the chains c with floor(c batches / C) = b, i.e. c in
+// [ceil(b C / batches), ceil((b + 1) C / batches)), skipping chains whose
+// sums are not finite (as the run estimate does).
+constexpr int IMG_THREADS = 256;
+__global__ __launch_bounds__(IMG_THREADS) void image_batch_tours_kernel(ImageEstimateArgs a) {
+    __shared__ double sh[IMG_THREADS];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int64_t B = a.batches, C = a.n_chains;
+    const int64_t lo = ((int64_t)b * C + B - 1) / B, hi = ((int64_t)(b + 1) * C + B - 1) / B;
+    double v = 0.0;
+    for (int64_t c = lo + t; c < hi; c += IMG_THREADS)
+        if (isfinite(a.t_done[c]) && isfinite(a.a_done[c])) v += (double)a.n_done[c];
+    sh[t] = v;
+    __syncthreads();
+    for (int w = IMG_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) a.tours[b] = sh[0];
+}
+
+// Per pixel j, with S_b the batch images and N_b the batches' tours: the
+// ratio estimate c_tilde sum S_b / sum N_b (= the image estimate of the
+// whole run) and its delta-method standard error over batches,
+//   c_tilde sqrt(sum_b (S_b - R N_b)^2 / ((B - 1) B)) / mean N_b,
+// the chain-level formula of the run estimate with batches as units
+// (NaN for a single batch).
+__global__ __launch_bounds__(256) void image_estimate_kernel(ImageEstimateArgs a) {
+    const int64_t px = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (px >= a.n_pix) return;
+    const int B = a.batches;
+    double sS = 0.0, sN = 0.0;
+    for (int b = 0; b < B; ++b) {
+        sS += (double)a.image[(int64_t)b * a.n_pix + px];
+        sN += a.tours[b];
+    }
+    const double R = sN > 0.0 ? sS / sN : 0.0;
+    double ss = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double e = (double)a.image[(int64_t)b * a.n_pix + px] - R * a.tours[b];
+        ss += e * e;
+    }
+    a.mean[px] = (float)(a.c_tilde * R);
+    a.se[px] = B > 1 && sN > 0.0 ? (float)(a.c_tilde * sqrt(ss / ((double)(B - 1) * B)) / (sN / B)) : NAN;
+}
+
+hipError_t launch_image_estimate(const ImageEstimateArgs &a, hipStream_t stream) {
+    hipLaunchKernelGGL(image_batch_tours_kernel, dim3(a.batches), dim3(IMG_THREADS), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(image_estimate_kernel, dim3((unsigned)((a.n_pix + 255) / 256)), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -67,10 +67,10 @@ __device__ __forceinline__ void splat_flush(const StepArgs &a, uint32_t (*rp)[25
         if (p != SPLAT_NO_PIX) atomicAdd(&cnt[p >> SPLAT_BAND_SHIFT], 1u);
     }
     __syncthreads();
-    if (t < a.n_bins) {
-        const uint32_t k = cnt[t];
-        base[t] = k ? atomicAdd(a.bin_count + t * SPLAT_COUNTER_STRIDE, k) : 0u;
-        cnt[t] = 0u;
+    for (int b = t; b < a.n_bins; b += blockDim.x) {
+        const uint32_t k = cnt[b];
+        base[b] = k ? atomicAdd(a.bin_count + b * SPLAT_COUNTER_STRIDE, k) : 0u;
+        cnt[b] = 0u;
     }
     __syncthreads();
     for (int r = 0; r < rows; ++r) {
@@ -89,7 +89,7 @@ __device__ __forceinline__ void splat_flush(const StepArgs &a, uint32_t (*rp)[25
         }
     }
     __syncthreads();
-    if (t < a.n_bins) cnt[t] = 0u;
+    for (int b = t; b < a.n_bins; b += blockDim.x) cnt[b] = 0u;
 }
 
 // Steps with regeneration for the image integrand, with binned splats.
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void step_binned_kernel(StepArgs a, int n_para
     const int t = threadIdx.x;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + t;
     const bool active = c < a.n_chains;
-    if (t < SPLAT_MAX_BANDS) cnt[t] = 0u;
+    for (int b = t; b < SPLAT_MAX_BANDS; b += blockDim.x) cnt[b] = 0u;
     Chain<D, LOC> ch;
     if (active) load_chain(a, (uint32_t)c, ch);
     unsigned long long n_acc = 0, n_kill = 0;

@@ -53,7 +53,7 @@ class restore_config(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_chains", C.c_int64), ("target_id", C.c_int32),
                 ("integrands", C.c_int32), ("c_tilde", C.c_double), ("drain_cap", C.c_int32),
                 ("image_w", C.c_int32), ("image_h", C.c_int32), ("flags", C.c_int32),
-                ("block_size", C.c_int32), ("reserved", C.c_int32)]
+                ("block_size", C.c_int32), ("image_batches", C.c_int32)]
 
 
 class restore_estimate_out(C.Structure):
@@ -104,7 +104,7 @@ EXPORTS = ["restore_state_bytes", "restore_init", "restore_step", "restore_drain
            "restore_batch_get_tiling", "restore_batch_run", "restore_batch_estimates", "restore_batch_chain_sums",
            "restore_batch_autotune", "restore_batch_destroy", "restore_step_record", "restore_mlp_param_count",
            "restore_mlp_forward", "restore_mlp_backward", "restore_gmm_nll_workspace_bytes", "restore_gmm_nll",
-           "restore_adam_step", "restore_last_error"]
+           "restore_adam_step", "restore_image_estimate", "restore_last_error"]
 
 
 def _load() -> C.CDLL:
@@ -120,6 +120,7 @@ def _load() -> C.CDLL:
     lib.restore_step.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
     lib.restore_drain.argtypes = [C.c_void_p, C.c_void_p]
     lib.restore_estimate.argtypes = [C.c_void_p, P(restore_estimate_out), C.c_void_p]
+    lib.restore_image_estimate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.restore_get_state_view.argtypes = [C.c_void_p, P(restore_state_view)]
     lib.restore_refresh_cache.argtypes = [C.c_void_p, C.c_void_p]
     lib.restore_destroy.argtypes = [C.c_void_p]
@@ -199,6 +200,10 @@ def restore_estimate(ctx, stream=None) -> restore_estimate_out:
     out = restore_estimate_out()
     _check(_lib.restore_estimate(ctx, C.byref(out), C.c_void_p(_stream(stream))))
     return out
+
+
+def restore_image_estimate(ctx, mean_ptr: int, se_ptr: int, stream=None) -> None:
+    _check(_lib.restore_image_estimate(ctx, C.c_void_p(mean_ptr), C.c_void_p(se_ptr), C.c_void_p(_stream(stream))))
 
 
 def restore_get_state_view(ctx) -> restore_state_view:
@@ -363,7 +368,7 @@ class Problem:
 def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: float, n_chains: int,
                  c_tilde: float, seed: int, drain_cap: int, target_id: int = 0, integrand_p: bool = True,
                  image: Optional[tuple] = None, lds: bool = False, block_size: int = 0,
-                 mu: Optional[dict] = None, flags: int = 0) -> Problem:
+                 mu: Optional[dict] = None, flags: int = 0, image_batches: int = 0) -> Problem:
     flat = target_params(kind, d, K, params)
     t = restore_target(_KIND[kind], d, K if kind != "pss" else 0, 0,
                        flat.ctypes.data_as(C.POINTER(C.c_double)), flat.size)
@@ -384,7 +389,8 @@ def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: f
     integrands = INTEGRAND_ONE | (INTEGRAND_P if integrand_p else 0) | (INTEGRAND_PIXEL if image else 0)
     w, h = (image or (0, 0))
     cfg = restore_config(int(seed), int(n_chains), int(target_id), integrands, float(c_tilde), int(drain_cap),
-                         int(w), int(h), (FLAG_PARAMS_LDS if lds else 0) | int(flags), int(block_size), 0)
+                         int(w), int(h), (FLAG_PARAMS_LDS if lds else 0) | int(flags), int(block_size),
+                         int(image_batches))
     return Problem(t, m, lk, cfg, flat, mu_t)
 
 
@@ -393,7 +399,8 @@ def problem_from_workload(wl, **overrides) -> Problem:
     (target, d, K, params, local, step, n_chains, c_tilde, seed, drain_cap,
     image)."""
     kw = dict(local=wl.local, step=wl.step, n_chains=wl.n_chains, c_tilde=wl.c_tilde, seed=wl.seed,
-              drain_cap=wl.drain_cap, image=getattr(wl, "image", None))
+              drain_cap=wl.drain_cap, image=getattr(wl, "image", None),
+              image_batches=getattr(wl, "image_batches", 0) if getattr(wl, "image", None) else 0)
     kw.update(overrides)
     return make_problem(wl.target, wl.d, wl.K, wl.params, **kw)
 
@@ -412,7 +419,9 @@ class Run:
         self.nbytes = nbytes
         self.image = None
         if prob.cfg.integrands & INTEGRAND_PIXEL:
-            self.image = torch.zeros((prob.cfg.image_h, prob.cfg.image_w), dtype=torch.float32, device="cuda")
+            nb = max(1, prob.cfg.image_batches)
+            shape = (nb, prob.cfg.image_h, prob.cfg.image_w) if nb > 1 else (prob.cfg.image_h, prob.cfg.image_w)
+            self.image = torch.zeros(shape, dtype=torch.float32, device="cuda")
         self.ctx = restore_init(prob.target, prob.mu, prob.local, prob.cfg, self._state_ptr, nbytes,
                                 self.image.data_ptr() if self.image is not None else 0, stream)
         self.n_chains = prob.cfg.n_chains
@@ -437,6 +446,14 @@ class Run:
 
     def refresh_cache(self):
         restore_refresh_cache(self.ctx, self.stream)
+
+    def image_estimate(self):
+        """(per-pixel estimate, batch-means standard error) as [h][w] tensors."""
+        h, w = self.prob.cfg.image_h, self.prob.cfg.image_w
+        mean = torch.empty((h, w), dtype=torch.float32, device="cuda")
+        se = torch.empty((h, w), dtype=torch.float32, device="cuda")
+        restore_image_estimate(self.ctx, mean.data_ptr(), se.data_ptr(), self.stream)
+        return mean, se
 
     # --- views of the state arrays (no copies) -----------------------------
     def _view(self, ptr: int, shape, dtype) -> torch.Tensor:

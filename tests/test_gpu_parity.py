@@ -323,42 +323,85 @@ def test_full_size_8d_sampled_chains_match_oracle(R):
 
 
 def test_pss_image_matches_oracle_image(R):
-    """Pixel splats of the 12-D rendering-shaped integrand: the GPU image of
-    8192 chains equals the oracle's image of the same chains (identical
-    counters) up to float32 accumulation, tile by tile; its total equals the
-    summed tour time; the image estimate agrees with the per-pixel truth."""
+    """Pixel splats of the 12-D rendering-shaped integrand in 4 image
+    batches: each GPU batch image of 8192 chains equals the oracle's image
+    of the same chain range (identical counters) up to float32
+    accumulation, tile by tile; the image total equals the summed tour
+    time; the image estimate agrees with the per-pixel truth."""
     from workloads import pss_render
     from oracle import oracle as O, truth
-    wl = pss_render(n_chains=8192, n_steps=200, image=(128, 128))
+    wl = pss_render(n_chains=8192, n_steps=200, image=(128, 128), image_batches=4)
     run = R.Run(R.problem_from_workload(wl))
     run.step(wl.n_steps)
     run.drain()
     est = run.estimate()
     img = run.image.cpu().numpy().astype(np.float64)
+    assert img.shape == (4, 128, 128)
     arrs = run.arrays()
     n_done = arrs["n_done"].cpu().numpy().astype(np.int64)
     t_done = arrs["t_done"].cpu().numpy()
     cens = (arrs["status"].cpu().numpy() & R.ST_CENSORED) != 0
     t_all = t_done.sum() + arrs["t_cur"].cpu().numpy()[cens].astype(np.float64).sum()
     run.close()
-    ores = O.run(O.Problem(wl), 0, wl.n_chains)
-    oimg = ores.image
-    _say(f"[pss image] gpu sum {img.sum():.6g} oracle {oimg.sum():.6g} sum T {t_all:.6g} "
-         f"censored {cens.sum()} chains with equal tours {np.mean(n_done == ores.n_done):.3f}")
-    assert abs(img.sum() / t_all - 1) < 1e-4
     tiles = lambda im: im.reshape(16, 8, 16, 8).sum(axis=(1, 3))
-    tg, to = tiles(img), tiles(oimg)
-    rel = np.abs(tg - to) / np.maximum(to, 1e-30)
-    _say(f"[pss image] tile rel diff: median {np.median(rel):.2e} max {rel.max():.2e}")
-    assert np.median(rel) < 1e-3
-    oest = O.estimate(ores)
-    se = math.hypot(est["p_lambda_se"], oest["p_lambda_se"])
-    assert abs(est["p_lambda"] - oest["p_lambda"]) < 3 * se
+    oimgs, ores_all = [], []
+    for b, (lo, hi) in enumerate(O.batch_ranges(wl.n_chains, 4)):
+        ores = O.run(O.Problem(wl), lo, hi)
+        ores_all.append(ores)
+        oimgs.append(ores.image)
+        tg, to = tiles(img[b]), tiles(ores.image)
+        rel = np.abs(tg - to) / np.maximum(to, 1e-30)
+        _say(f"[pss image] batch {b} chains {lo}..{hi}: tile rel diff median {np.median(rel):.2e} "
+             f"max {rel.max():.2e}, equal tours {np.mean(n_done[lo:hi] == ores.n_done):.3f}")
+        assert np.median(rel) < 1e-3
+    _say(f"[pss image] gpu sum {img.sum():.6g} oracle {sum(o.sum() for o in oimgs):.6g} sum T {t_all:.6g} "
+         f"censored {cens.sum()}")
+    assert abs(img.sum() / t_all - 1) < 1e-4
+    oest = [O.estimate(r) for r in ores_all]
+    o_pl = sum(e["p_lambda"] * e["tours_done"] for e in oest) / sum(e["tours_done"] for e in oest)
+    assert abs(est["p_lambda"] - o_pl) < 3 * math.sqrt(2) * est["p_lambda_se"]
     tr = truth.pss_pixel_truth(wl, gl_order=4)
     scale = est["image_scale"]
     _say(f"[pss image] p_lambda gpu {est['p_lambda']:.5f} +- {est['p_lambda_se']:.2g}, truth {tr.sum():.5f}, "
          f"image total {img.sum() * scale:.5f}")
     assert abs(est["p_lambda"] - tr.sum()) < 4 * est["p_lambda_se"]
+
+
+def test_image_estimate_matches_batch_formula_and_truth(R):
+    """restore_image_estimate against the oracle's batch-means formula on the
+    GPU's own batch images and tour counts (float32 output rounding), and
+    its standard error calibrated against the per-pixel truth: over the
+    pixels of a 64 x 64 image from 16 batches, z = (estimate - truth) / se
+    has median ~0 and spread ~1 (Student t with 15 degrees of freedom:
+    sd 1.07; the spread is taken from the median |z| so that the few
+    pixels under the sharp lobe, where the quadrature truth is least
+    accurate, cannot dominate it)."""
+    import torch
+    from workloads import pss_render
+    from oracle import oracle as O, truth
+    wl = pss_render(n_chains=1 << 18, n_steps=256, image=(64, 64), image_batches=16)
+    run = R.Run(R.problem_from_workload(wl))
+    run.step(wl.n_steps)
+    run.drain()
+    est = run.estimate()
+    mean, se = run.image_estimate()
+    _sync()
+    mean, se = mean.double().cpu().numpy(), se.double().cpu().numpy()
+    imgs = run.image.double().cpu().numpy()
+    n_done = run.arrays()["n_done"].cpu().numpy().astype(np.float64)
+    run.close()
+    tours = np.array([n_done[lo:hi].sum() for lo, hi in O.batch_ranges(wl.n_chains, 16)])
+    om, ose = O.image_batch_estimate(imgs, tours, wl.c_tilde)
+    np.testing.assert_allclose(mean, om, rtol=2e-7, atol=1e-30)
+    np.testing.assert_allclose(se, ose, rtol=2e-6, atol=1e-30)
+    assert abs(mean.sum() - est["p_lambda"]) <= 1e-5 * est["p_lambda"]
+    tr = truth.pss_pixel_truth(wl, gl_order=8)
+    z = ((mean - tr) / se).ravel()
+    robust_sd = np.median(np.abs(z)) / 0.6745
+    _say(f"[image se] median rel se {np.median(se / mean):.3g}; z mean {z.mean():.3f} sd {z.std():.3f} "
+         f"median {np.median(z):.3f} robust sd {robust_sd:.3f}; censored {est['tours_censored']}")
+    assert abs(np.median(z)) < 0.1
+    assert 0.9 < robust_sd < 1.25
 
 
 def test_full_size_pss_sampled_chains_match_oracle(R):

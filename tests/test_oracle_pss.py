@@ -120,3 +120,38 @@ def test_whole_run_image_matches_truth_by_tiles(oracle_lib, wl):
     assert np.abs(z).max() < 5.0
     est = O.estimate(res)
     assert abs(est["p_lambda"] / tr.sum() - 1) < 4 * est["p_lambda_se"] / tr.sum()
+
+
+def test_batch_ranges_follow_the_floor_rule():
+    from oracle import oracle as O
+    for n, B in ((10, 3), (16, 16), (17, 4), (1000, 7), (5, 1)):
+        ranges = O.batch_ranges(n, B)
+        for b, (lo, hi) in enumerate(ranges):
+            assert list(range(lo, hi)) == [c for c in range(n) if c * B // n == b]
+
+
+def test_batch_image_standard_error_is_calibrated():
+    """Over independent replicates with a known tour distribution, the
+    batch-means standard error of the pixel ratio estimate matches the
+    spread of the estimate (mean of se^2 / variance within 10%), and the
+    estimate is the pooled ratio c_tilde sum S / sum N."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(21)
+    B, reps, c_tilde = 16, 4000, 3.0
+    est, se2 = [], []
+    for _ in range(reps):
+        tours = 1 + rng.poisson(30, size=B)
+        imgs = np.zeros((B, 2, 2))
+        for b in range(B):
+            y = rng.exponential(2.0, size=(tours[b], 2, 2)) * (rng.uniform(size=(tours[b], 2, 2)) < 0.3)
+            imgs[b] = y.sum(axis=0)
+        m, s = O.image_batch_estimate(imgs, tours, c_tilde)
+        np.testing.assert_allclose(m, c_tilde * imgs.sum(axis=0) / tours.sum(), rtol=1e-14)
+        est.append(m[0, 0])
+        se2.append(s[0, 0] ** 2)
+    est, se2 = np.array(est), np.array(se2)
+    assert abs(est.mean() / (c_tilde * 0.6) - 1) < 0.01
+    ratio = se2.mean() / est.var()
+    assert 0.9 < ratio < 1.1, ratio
+    m, s = O.image_batch_estimate(np.ones((1, 3, 3)), np.array([5.0]), 2.0)
+    assert np.all(np.isnan(s)) and np.allclose(m, 0.4)

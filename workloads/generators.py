@@ -44,6 +44,8 @@ class Workload:
     seed:        chain seed (Philox key).
     problem_seed: seed that drew ``params``.
     image:       (width, height) for the pixel integrand, or None.
+    image_batches: contiguous chain ranges with an image each (per-pixel
+                 standard errors); 0 or 1 = one image.
     """
 
     name: str
@@ -60,6 +62,7 @@ class Workload:
     seed: int
     problem_seed: int
     image: Optional[tuple] = None
+    image_batches: int = 0
 
     def with_(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
@@ -145,7 +148,8 @@ C_TILDE_PSS_12D = 155.0
 
 def pss_render(n_chains: int = 1 << 20, n_steps: int = 256,
                problem_seed: int = 1003, seed: int = 2003,
-               image=(512, 512), c_tilde: float = C_TILDE_PSS_12D) -> Workload:
+               image=(512, 512), c_tilde: float = C_TILDE_PSS_12D,
+               image_batches: int = 16) -> Workload:
     """12-D rendering-shaped integrand on [0,1]^12.
 
     g(x) = tA(x0,x1) * tB(x6..x11) * [b + sum_l w_l h_l(x_{2l-2}, x_{2l-1})]
@@ -153,7 +157,8 @@ def pss_render(n_chains: int = 1 << 20, n_steps: int = 256,
     + phi_m) (8 seeded sinusoids each, integer frequencies n_m != 0,
     |a_m| <= 0.9) and three von Mises-Fisher lobes of concentration kappa
     on the sphere, reached from the unit square by z = 1 - 2u, phi = 2 pi v.
-    Coordinates (x0, x1) select the pixel of a width x height image."""
+    Coordinates (x0, x1) select the pixel of a width x height image; the
+    chains are split into ``image_batches`` ranges with an image each."""
     rng = np.random.default_rng(problem_seed)
 
     def texture(dim):
@@ -184,7 +189,8 @@ def pss_render(n_chains: int = 1 << 20, n_steps: int = 256,
     }
     return Workload("pss_render_12d", "pss", 12, 0, params, "rwmh", 0.02,
                     n_chains, n_steps, 4 * n_steps, float(c_tilde), seed,
-                    problem_seed, image=tuple(image) if image else None)
+                    problem_seed, image=tuple(image) if image else None,
+                    image_batches=int(image_batches) if image else 0)
 
 
 def batched_uneven(n_targets: int = 256, problem_seed: int = 1005,

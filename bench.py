@@ -204,10 +204,10 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
     train_s = time.perf_counter() - t0
     mu = model.mu()
 
-    def runs(mu_, ct):
+    def runs(mu_, ct, flags=0):
         out = []
         for r in range(replicates):
-            prob = R.problem_from_workload(wl, mu=mu_, c_tilde=ct, seed=2004 + 17 * r)
+            prob = R.problem_from_workload(wl, mu=mu_, c_tilde=ct, seed=2004 + 17 * r, flags=flags)
             torch.cuda.synchronize()
             t = time.perf_counter()
             run = R.Run(prob)
@@ -243,6 +243,12 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
                                                     / res["learned"]["lam_pf"]["mse_x_time"])
     res["mse_x_time_ratio_at_best_c_tilde"] = (res["uniform_best"]["lam_pf"]["mse_x_time"]
                                                / res["learned_best"]["lam_pf"]["mse_x_time"])
+    # the conditional-mean holding time (RESTORE_FLAG_RB_DT) at the provable
+    # and at the best c~ of each method
+    res["rb_dt"] = {}
+    for name, (mu_, cts) in sweeps.items():
+        res["rb_dt"][name] = [summary(runs(mu_, ct, R.FLAG_RB_DT), ct)
+                              for ct in sorted({cts[0], res[name + "_best"]["c_tilde"]}, reverse=True)]
     res["t_1pct_learned_amortised_s"] = (res["learned"]["lam_pf"]["t_1pct_s"] + train_s / replicates)
     return res
 

@@ -133,6 +133,13 @@ typedef struct {
 #define RESTORE_FLAG_SPLAT_TIGHT 4   /* PIXEL: 64-fold smaller splat buckets,
                                         so that overflowing records take the
                                         direct path (exercises that path)   */
+#define RESTORE_FLAG_RB_DT       8   /* accumulate the conditional mean
+                                        E[dt | x] = 1 / (1 + k(x)) of the
+                                        holding time in place of the sampled
+                                        dt (both clocks still decide kill or
+                                        move; unbiased because dt ~
+                                        Exp(1 + k) is independent of which
+                                        clock fires, Alg. 2)                 */
 
 typedef struct {
     uint64_t seed;           /* Philox key                                   */

@@ -57,7 +57,7 @@ class OrLocal(C.Structure):
 class OrConfig(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("target_id", C.c_uint32), ("pad", C.c_uint32),
                 ("c_tilde", C.c_double), ("integrand_p", C.c_int32),
-                ("image_w", C.c_int32), ("image_h", C.c_int32), ("pad2", C.c_int32)]
+                ("image_w", C.c_int32), ("image_h", C.c_int32), ("rb_dt", C.c_int32)]
 
 
 class OrOutputs(C.Structure):
@@ -136,7 +136,7 @@ class Problem:
     def __init__(self, wl, mu: Optional[dict] = None, target_id: int = 0,
                  c_tilde: Optional[float] = None, seed: Optional[int] = None,
                  integrand_p: bool = True, image: Optional[tuple] = None,
-                 step: Optional[float] = None, local: Optional[str] = None):
+                 step: Optional[float] = None, local: Optional[str] = None, rb_dt: bool = False):
         self.wl = wl
         self.d = wl.d
         self._keep = []
@@ -199,6 +199,7 @@ class Problem:
         cfg.target_id = int(target_id)
         cfg.c_tilde = float(wl.c_tilde if c_tilde is None else c_tilde)
         cfg.integrand_p = 1 if integrand_p else 0
+        cfg.rb_dt = 1 if rb_dt else 0
         img = image if image is not None else wl.image
         if img:
             cfg.image_w, cfg.image_h = int(img[0]), int(img[1])

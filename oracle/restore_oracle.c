@@ -87,7 +87,7 @@ typedef struct {
     double c_tilde;
     int32_t integrand_p;     /* accumulate f = p as well as f = 1 */
     int32_t image_w, image_h; /* pixel integrand on (x0, x1); 0 = off */
-    int32_t pad2;
+    int32_t rb_dt;           /* return E[dt | x] = 1 / (1 + k(x)) instead of dt */
 } or_config;
 
 /* ----------------------------------------------------------------------- */
@@ -412,6 +412,13 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
         st->lu = oracle_log_mu(mu, st->x);
     }
     *flags = fl;
+    if (cfg->rb_dt) {
+        /* dt = min(t1, t2) is Exp(1 + k) whichever clock fires, so its
+           conditional mean given x can replace it in every time integral */
+        if (cfg->c_tilde == 0.0) return 1.0;
+        if (log_k == INFINITY) return 0.0;
+        return 1.0 / (1.0 + exp(log_k));
+    }
     return dt;
 }
 

@@ -154,13 +154,17 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     const float t1 = -logf(head[0]);
     const float e2 = -logf(head[1]);
     float t2 = INFINITY;
+    float inv_k = INFINITY;
     kill = false;
     if (!a.no_kill) {
         // t2 = E2 / k = E2 exp(log p - log u - ln c_tilde); p = 0 gives t2 = 0
-        t2 = e2 * expf(ch.lp - ch.lu - a.log_c);
+        inv_k = expf(ch.lp - ch.lu - a.log_c);
+        t2 = e2 * inv_k;
         kill = !(t1 < t2);
     }
-    const float dt = kill ? t2 : t1;
+    // the holding time dt = min(t1, t2) ~ Exp(1 + k) whichever clock fires;
+    // with rb_dt its conditional mean 1 / (1 + k) is accumulated instead
+    const float dt = a.rb_dt ? (inv_k > 1e30f ? 1.0f : inv_k / (1.0f + inv_k)) : (kill ? t2 : t1);
 
     // accumulate dt f(x_{i-1}) into the tour in flight
     ch.t_cur += dt;

@@ -402,6 +402,7 @@ void fill_args(restore_ctx *c) {
     a.s0 = 0;
     a.n_steps = 0;
     a.integrand_p = (c->cfg.integrands & RESTORE_INTEGRAND_P) ? 1 : 0;
+    a.rb_dt = (c->cfg.flags & RESTORE_FLAG_RB_DT) ? 1 : 0;
     a.image_w = c->cfg.image_w;
     a.image_h = c->cfg.image_h;
     a.image_batches = image_batches_of(&c->cfg);

@@ -84,6 +84,7 @@ struct StepArgs {
     uint32_t s0;       // first step index of this launch
     int32_t n_steps;   // steps in this launch
     int32_t integrand_p;
+    int32_t rb_dt;     // accumulate E[dt | x] = 1 / (1 + k) instead of dt
     int32_t image_w, image_h;
     int32_t image_batches;  // chains split into contiguous ranges, one image each (>= 1)
     int32_t image_pixels;   // image_w * image_h

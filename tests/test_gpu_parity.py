@@ -49,13 +49,13 @@ def _oracle_problem(wl, **kw):
     return O.Problem(wl, **kw)
 
 
-def _single_step_check(R, wl, x_init=None, warm=3, c_tilde=None, label="", lp_atol=0.0, mu=None):
+def _single_step_check(R, wl, x_init=None, warm=3, c_tilde=None, label="", lp_atol=0.0, mu=None, rb=False):
     """Run `warm` steps (or load x_init), snapshot, take one more step on the
     GPU and compare each chain's transition with the oracle's."""
     import torch
     from oracle import oracle as O
     ct = wl.c_tilde if c_tilde is None else c_tilde
-    run = R.Run(R.problem_from_workload(wl, c_tilde=ct, mu=mu))
+    run = R.Run(R.problem_from_workload(wl, c_tilde=ct, mu=mu, flags=R.FLAG_RB_DT if rb else 0))
     arr = run.arrays()
     if x_init is not None:
         arr["x"].copy_(torch.from_numpy(np.ascontiguousarray(x_init.T.astype(np.float32))).cuda())
@@ -72,7 +72,7 @@ def _single_step_check(R, wl, x_init=None, warm=3, c_tilde=None, label="", lp_at
     dt_g = arr["last_dt"].cpu().numpy().astype(np.float64)
     lp_g = arr["logp"].cpu().numpy().astype(np.float64)
     n = wl.n_chains
-    oprob = O.Problem(wl, c_tilde=ct, mu=mu)
+    oprob = O.Problem(wl, c_tilde=ct, mu=mu, rb_dt=rb)
     st = O.States(x0, np.zeros(n), np.zeros(n), np.zeros_like(x0))
     new, dt_o, flags, margins = O.transitions(oprob, st, s, np.arange(n), recompute=True)
     kill_g = (status & R.ST_LAST_KILL) != 0
@@ -266,6 +266,36 @@ def _gpu_run(R, wl, **kw):
     arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done", "a_done", "status")}
     run.close()
     return est, arr
+
+
+def test_single_transitions_rao_blackwellised_holding_time(R):
+    """With RESTORE_FLAG_RB_DT the accumulated holding time is E[dt | x] =
+    1/(1+k): single transitions (2-D after warm-up, 8-D MALA from pi at the
+    workload's c~) against the oracle with the same option."""
+    from workloads import gmm_full, gmm_iso_2d
+    _single_step_check(R, gmm_iso_2d(n_chains=8192), warm=5, label="rb 2d warm", rb=True)
+    wl = gmm_full(n_chains=8192)
+    _single_step_check(R, wl, x_init=_pi_draws(wl, wl.n_chains, 5), c_tilde=1e3, label="rb 8d pi", rb=True)
+
+
+def test_whole_run_2d_rao_blackwellised_matches_oracle_and_truth(R):
+    """The 2-D workload with the conditional-mean holding time: GPU and
+    oracle estimates within 3 SE of each other and of the erf truth, the
+    same tours as the sampled run, and no larger SE."""
+    from workloads import gmm_iso_2d
+    from oracle import oracle as O, truth
+    wl = gmm_iso_2d()
+    est, arr = _gpu_run(R, wl, flags=R.FLAG_RB_DT)
+    ref, _ = _gpu_run(R, wl)
+    oest = O.estimate(O.run(O.Problem(wl, rb_dt=True), 0, wl.n_chains))
+    tr = truth.truths(wl)
+    assert est["tours_done"] == ref["tours_done"] and est["transitions"] == ref["transitions"]
+    for key in ("p_lambda", "lam_pf", "pi_f"):
+        _say(f"[rb 2d] {key}: gpu {est[key]:.6g} +- {est[key + '_se']:.2g} (sampled dt: +- {ref[key + '_se']:.2g}) "
+             f"oracle {oest[key]:.6g} truth {tr[key]:.6g}")
+        assert abs(est[key] - oest[key]) < 3 * math.hypot(est[key + "_se"], oest[key + "_se"])
+        assert abs(est[key] - tr[key]) < 3 * est[key + "_se"]
+        assert est[key + "_se"] <= 1.02 * ref[key + "_se"]
 
 
 def test_whole_run_2d_matches_oracle_and_truth(R):

@@ -53,6 +53,9 @@ MUTATIONS = {
     "mu_density_drops_defensive": ("a[mu->K] = in_box(d, y) ? log(mu->beta) : -INFINITY;",
                                    "a[mu->K] = -INFINITY;",
                                    [lambda: pins.test_whole_run_8d_mixture_mu_matches_genz_truth(None)]),
+    # conditional-mean holding time 1/k instead of 1/(1 + k)
+    "rb_holding_time_without_holding_rate": ("return 1.0 / (1.0 + exp(log_k));", "return exp(-log_k);",
+                                             [lambda: pins.test_zero_step_rao_blackwellised_moments(None)]),
     # a completed tour not counted
     "tour_not_counted": ("a_done += a_cur; t_done += t_cur; ++n_done;",
                          "a_done += a_cur; t_done += t_cur;",

@@ -309,6 +309,33 @@ def test_zero_step_reduces_to_randomised_importance_sampling(oracle_lib):
     assert abs(t2.mean() - 2 * tr["lam_pf"]) < 4 * t2.std() / math.sqrt(n)
 
 
+def test_zero_step_rao_blackwellised_moments(oracle_lib):
+    """With a zero step and the conditional-mean holding time 1/(1+k) in
+    place of the sampled one, a tour at x ~ mu lasts Geometric(k/(1+k))
+    steps of 1/(1+k) each (k = c/p, u = 1 on the box), so E[c tau] =
+    p_lambda is unchanged while E[(c tau)^2] = int p^2 (2p + c)/(p + c):
+    between int p^2 (c -> inf) and the sampled 2 int p^2 (c -> 0).  The
+    integral by 400^2 Gauss-Legendre on the box."""
+    wl = gmm_iso_2d()
+    c = 20.0
+    prob = O.Problem(wl, c_tilde=c, step=0.0, rb_dt=True)
+    tau, _ = _first_tours(prob, 60000)
+    tau = c * tau
+    g, gw = np.polynomial.legendre.leggauss(400)
+    xs, ws = (g + 1) / 2, gw / 2
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    p = np.exp(O.log_target(prob, np.stack([X.ravel(), Y.ravel()], 1))).reshape(X.shape)
+    wgt = np.outer(ws, ws)
+    m1 = (p * wgt).sum()
+    m2 = (p * p * (2 * p + c) / (p + c) * wgt).sum()
+    n = len(tau)
+    assert abs(tau.mean() - m1) < 4 * tau.std() / math.sqrt(n)
+    t2 = tau * tau
+    assert abs(t2.mean() - m2) < 4 * t2.std() / math.sqrt(n)
+    # the sampled holding time has the larger second moment 2 int p^2
+    assert m2 < 2 * (p * p * wgt).sum() - 8 * t2.std() / math.sqrt(n)
+
+
 def test_constant_rate_when_target_equals_mu(oracle_lib):
     """p proportional to u: k = c is constant, so tour lifetimes are Exp(c)
     and steps per tour are Geometric(c / (1 + c))."""
@@ -355,6 +382,20 @@ def test_whole_run_2d_matches_erf_closed_form(oracle_lib):
     assert est["tours_censored"] == 0
     for key in ("p_lambda", "lam_pf", "pi_f"):
         assert abs(est[key] - tr[key]) < 3 * est[key + "_se"], key
+
+
+def test_whole_run_2d_rao_blackwellised_matches_erf_closed_form(oracle_lib):
+    """The conditional-mean holding time keeps the whole-run estimates
+    unbiased (within 3 SE of the erf truth) and its SE is not larger than
+    with the sampled holding time, on the same chains and clocks."""
+    wl = gmm_iso_2d()
+    est = O.estimate(O.run(O.Problem(wl, rb_dt=True), 0, wl.n_chains))
+    ref = O.estimate(O.run(O.Problem(wl), 0, wl.n_chains))
+    tr = truth.truths(wl)
+    assert est["tours_censored"] == 0 and est["tours_done"] == ref["tours_done"]
+    for key in ("p_lambda", "lam_pf", "pi_f"):
+        assert abs(est[key] - tr[key]) < 3 * est[key + "_se"], key
+        assert est[key + "_se"] <= 1.02 * ref[key + "_se"], key
 
 
 def test_whole_run_full_cov_mala_2d_matches_genz_truth(oracle_lib):

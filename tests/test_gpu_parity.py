@@ -49,13 +49,14 @@ def _oracle_problem(wl, **kw):
     return O.Problem(wl, **kw)
 
 
-def _single_step_check(R, wl, x_init=None, warm=3, c_tilde=None, label="", lp_atol=0.0, mu=None, rb=False):
+def _single_step_check(R, wl, x_init=None, warm=3, c_tilde=None, label="", lp_atol=0.0, mu=None, rb=False,
+                       lds=False):
     """Run `warm` steps (or load x_init), snapshot, take one more step on the
     GPU and compare each chain's transition with the oracle's."""
     import torch
     from oracle import oracle as O
     ct = wl.c_tilde if c_tilde is None else c_tilde
-    run = R.Run(R.problem_from_workload(wl, c_tilde=ct, mu=mu, flags=R.FLAG_RB_DT if rb else 0))
+    run = R.Run(R.problem_from_workload(wl, c_tilde=ct, mu=mu, flags=R.FLAG_RB_DT if rb else 0, lds=lds))
     arr = run.arrays()
     if x_init is not None:
         arr["x"].copy_(torch.from_numpy(np.ascontiguousarray(x_init.T.astype(np.float32))).cuda())
@@ -202,6 +203,24 @@ def test_single_transitions_8d_mala_from_pi(R, c_tilde):
     k, a, m = _single_step_check(R, wl, x_init=_pi_draws(wl, wl.n_chains, 6), c_tilde=c_tilde,
                                  label=f"8d pi c={c_tilde:g}")
     assert a > 1000
+
+
+@pytest.mark.parametrize("d,K,local", [(16, 64, "mala"), (16, 64, "rwmh"), (1, 3, "rwmh"), (13, 7, "mala")])
+def test_single_transitions_extreme_shapes(R, d, K, local):
+    """The largest supported mixture (d = 16, K = 64 full-covariance
+    components: a 39 KiB parameter slab) with both local kernels, the
+    smallest dimension, and an odd one, from exact pi draws (local moves)
+    and after a warm-up from mu (regenerations), with the parameters read
+    through the scalar cache and through LDS."""
+    from workloads import gmm_full
+    wl = gmm_full(d=d, K=K, n_chains=4096, local=local, step=0.005 if local == "mala" else 0.01,
+                  problem_seed=4000 + d * 100 + K)
+    x0 = _pi_draws(wl, wl.n_chains, 7)
+    for lds in (False, True):
+        # from pi: local moves (p is far above c~ u in the modes)
+        _single_step_check(R, wl, x_init=x0, c_tilde=1e3, label=f"d{d} K{K} {local} pi lds={lds}", lds=lds)
+        # after warm-up from mu: regenerations (p is tiny at uniform points)
+        _single_step_check(R, wl, warm=3, c_tilde=1e3, label=f"d{d} K{K} {local} warm lds={lds}", lds=lds)
 
 
 def test_single_transitions_8d_mala_after_warmup(R):

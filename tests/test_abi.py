@@ -112,3 +112,58 @@ def test_init_rejects_null_and_small_buffers(R):
     with pytest.raises(R.RestoreError) as e:
         R.restore_init(p.target, p.mu, p.local, p.cfg, 256 + 4, n, stream=0)
     assert e.value.status == R.E_INVALID_ARG
+
+
+def _pss_problem(R, **kw):
+    from workloads import pss_render
+    return R.problem_from_workload(pss_render(n_chains=1000, image=(64, 64)), **kw)
+
+
+@pytest.mark.parametrize("batches,status", [(-1, -1), (4097, -1), (1001, -1)])
+def test_image_batches_validation(R, batches, status):
+    p = _pss_problem(R)
+    p.cfg.image_batches = batches
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == status
+
+
+def test_image_batches_need_the_pixel_integrand(R):
+    p = _problem(R)
+    p.cfg.image_batches = 4
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_INVALID_ARG
+
+
+def test_image_pixel_index_stays_in_int32(R):
+    p = _pss_problem(R, n_chains=100000)
+    p.cfg.image_w, p.cfg.image_h, p.cfg.image_batches = 16384, 16384, 16
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_INVALID_ARG
+
+
+def test_splat_binning_sizes_the_state(R):
+    """Binned splats hold buckets for 1.5 x one 64-step launch of records
+    (8 bytes each) plus the partial tiles; the direct path needs none."""
+    binned = _pss_problem(R, n_chains=8192)
+    direct = _pss_problem(R, n_chains=8192, flags=R.FLAG_SPLAT_DIRECT)
+    nb = R.restore_state_bytes(binned.target, binned.mu, binned.local, binned.cfg)
+    nd = R.restore_state_bytes(direct.target, direct.mu, direct.local, direct.cfg)
+    records = 8192 * 65
+    assert nb - nd >= 1.5 * records * 8
+    assert nb - nd <= 1.5 * records * 8 + 16 * 16 * 65536 + 65536 + 16 * 4096
+
+
+def test_nll_and_mlp_argument_validation(R):
+    shape = R.restore_mlp_shape(12, 64, 65, 8)
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_mlp_param_count(shape)
+    assert e.value.status == R.E_INVALID_ARG
+    n, a = R.restore_mlp_param_count(R.restore_mlp_shape(12, 64, 64, 8))
+    assert n == 64 * 12 + 64 + 64 * 64 + 64 + 1088 * 64 + 1088 and a == 4 * 64
+    assert R.restore_gmm_nll_workspace_bytes() >= 2049 * 64 * 35 * 8
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_adam_step(0, 0, 0, 0, 10, 1, 1e-3, stream=0)
+    assert e.value.status == R.E_INVALID_ARG

@@ -287,12 +287,15 @@ def _first_tours(prob, n, max_steps=20000):
 
 def test_expected_lifetime_one_d_example(oracle_lib):
     """E_mu[tau] = 1/c with c_tilde = c p_lambda; the paper's 1-D example
-    uses c = 1/4, i.e. an expected tour length of 4."""
+    uses c = 1/4, i.e. an expected tour length of 4
+    (tests/golden/worked_example_lifetime.txt)."""
+    with open(os.path.join(ROOT, "tests", "golden", "worked_example_lifetime.txt")) as f:
+        c, expected = [float(v) for v in next(l for l in f if l.strip() and not l.startswith("#")).split()]
     wl = one_d_three_mode()
     pl = truth.gmm_iso_power_integral(wl, 1)
-    prob = O.Problem(wl, c_tilde=0.25 * pl)
+    prob = O.Problem(wl, c_tilde=c * pl)
     tau, _ = _first_tours(prob, 40000)
-    assert abs(tau.mean() - 4.0) < 4 * tau.std() / math.sqrt(len(tau))
+    assert abs(tau.mean() - expected) < 4 * tau.std() / math.sqrt(len(tau))
 
 
 def test_zero_step_reduces_to_randomised_importance_sampling(oracle_lib):

@@ -630,3 +630,30 @@ def test_binned_splats_match_direct_atomics(R):
              f"max err/bound {float((err / bound).max()):.3f}, nonzero pixels {(img > 0).sum()}")
         assert np.all(err <= bound)
         assert np.array_equal(img > 0, ref_img > 0)
+
+
+@pytest.mark.parametrize("block,lds", [(64, False), (128, True), (256, True)])
+def test_binned_splats_block_sizes_and_lds(R, block, lds):
+    """The binned-splat step launch with workgroups of 64 and 128 threads
+    (fewer threads than the 256 image bands of 16 batch images, so the
+    per-band loops stride) and with the parameters staged in LDS: the same
+    chains bit for bit as the default launch, and the same image up to the
+    order of the float32 additions."""
+    import torch
+    from workloads import pss_render
+    wl = pss_render(n_chains=20000, n_steps=70, image=(512, 512))
+    out = {}
+    for key, kw in (("ref", {}), ("var", {"block_size": block, "lds": lds})):
+        run = R.Run(R.problem_from_workload(wl, **kw))
+        run.step(wl.n_steps)
+        _sync()
+        out[key] = (run.image.double().cpu().numpy(), {k: v.clone() for k, v in run.arrays().items()})
+        run.close()
+    (img_a, arr_a), (img_b, arr_b) = out["ref"], out["var"]
+    for k in ("x", "logp", "t_cur", "a_cur", "status", "n_done", "last_dt"):
+        assert torch.equal(arr_a[k], arr_b[k]), k
+    n_terms = 20000 * (wl.n_steps + 3) / (512 * 512 * 16)
+    bound = 2 * (8 * n_terms + 8) * 2.0 ** -24 * np.maximum(img_a, img_b) + 1e-30
+    err = np.abs(img_a - img_b)
+    _say(f"[splat block {block} lds {lds}] max err/bound {float((err / bound).max()):.3f}")
+    assert np.all(err <= bound)

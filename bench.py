@@ -370,6 +370,17 @@ def main():
                                                     "tours_done", "tours_censored", "kill_rate",
                                                     "accept_rate")},
     }
+    truths = json.load(open(os.path.join(ROOT, "tests", "golden", "truths.json")))
+    if wl.name in truths:
+        tr = truths[wl.name]
+        line["estimates"]["rel_err_vs_truth"] = {
+            k: (line["estimates"][k] - tr[k]) / tr[k] for k in ("p_lambda", "lam_pf") if k in tr}
+    if image is not None and wl.name in truths and list(truths[wl.name]["image"]) == [prob.cfg.image_w,
+                                                                                        prob.cfg.image_h]:
+        t = truths[wl.name]["tile"]
+        tt = torch.tensor(truths[wl.name]["tiles"], dtype=torch.float64)
+        tiles = img_mean.double().reshape(prob.cfg.image_h // t, t, prob.cfg.image_w // t, t).sum(dim=(1, 3)).cpu()
+        line["estimates"]["image_tile_rel_rmse_vs_truth"] = float(((tiles - tt) / tt).pow(2).mean().sqrt())
     if image is not None:
         rel = (img_se / img_mean.clamp_min(1e-30)).flatten()
         line["image"] = {"width": prob.cfg.image_w, "height": prob.cfg.image_h,

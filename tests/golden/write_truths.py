@@ -1,7 +1,9 @@
-"""Write the closed-form truths of the synthetic mixture workloads to
+"""Write the closed-form truths of the synthetic workloads to
 tests/golden/truths.json, from the oracle's truth routines only (box
 probabilities of Gaussians by Genz's method, the product-of-Gaussians
-identity for the integral of p^2).  The benchmark reads this file to score
+identity for the integral of p^2; for the rendering-shaped integrand the
+per-pixel integrals, closed form plus Gauss-Legendre for the lobe, summed
+over 8 x 8-pixel tiles).  The benchmark reads this file to score
 estimates; tests/test_oracle_pins.py checks it against a fresh computation.
 
     python tests/golden/write_truths.py
@@ -15,10 +17,11 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import truth  # noqa: E402
-from workloads import gmm_full, gmm_iso_2d  # noqa: E402
+from workloads import gmm_full, gmm_iso_2d, pss_render  # noqa: E402
 
 PATH = os.path.join(HERE, "truths.json")
 WORKLOADS = {"gmm_full_8d": gmm_full, "gmm_iso_2d": gmm_iso_2d}
+PSS_TILE = 8   # the image truth is stored as sums over 8 x 8-pixel tiles
 
 
 def compute() -> dict:
@@ -26,6 +29,13 @@ def compute() -> dict:
     for name, make in WORKLOADS.items():
         wl = make()
         out[name] = {"problem_seed": wl.problem_seed, **truth.truths(wl)}
+    wl = pss_render()
+    img = truth.pss_pixel_truth(wl, gl_order=8)
+    h, w = img.shape
+    tiles = img.reshape(h // PSS_TILE, PSS_TILE, w // PSS_TILE, PSS_TILE).sum(axis=(1, 3))
+    out["pss_render_12d"] = {"problem_seed": wl.problem_seed, "p_lambda": float(img.sum()),
+                             "image": [w, h], "tile": PSS_TILE,
+                             "tiles": [[float(v) for v in row] for row in tiles]}
     return out
 
 

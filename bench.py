@@ -198,7 +198,7 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
     model = MlpGmm(d=wl.d, K=64, in_dim=12, hidden=64, beta=0.1, seed=3004)
     ct_learned = provable_c_tilde(wl.c_tilde, model.beta)
     t0 = time.perf_counter()
-    hist = refit(wl, model, ct_learned, rounds=5, record_steps=4, epochs=300, lr=2e-2, seed=3004,
+    hist = refit(wl, model, ct_learned, refits=5, record_steps=4, epochs=300, lr=2e-2, seed=3004,
                  c_tilde_explore=1.0, log=log or (lambda *a: None))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -233,7 +233,7 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
 
     sweeps = {"uniform": (None, [wl.c_tilde * 10.0 ** -k for k in range(7)]),
               "learned": (mu, [ct_learned * 10.0 ** -k for k in (0, 2, 4, 6, 8, 9, 10)])}
-    res = {"replicates": replicates, "primary": "lam_pf", "training_s": train_s, "training_rounds": hist,
+    res = {"replicates": replicates, "primary": "lam_pf", "training_s": train_s, "training_refits": hist,
            "sweep": {}}
     for name, (mu_, cts) in sweeps.items():
         res["sweep"][name] = [summary(runs(mu_, ct), ct) for ct in cts]
@@ -270,8 +270,9 @@ def main():
                     help="also run a plain 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (chains shard by global id; "
-              "see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (chains would shard by global chain "
+              "id, with one all-reduce of the float64 moments at the estimate). Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -7,7 +7,7 @@ step kernels read as restore_mu parameters).  mu has to be one fixed,
 state-independent density for the whole of a run, since the kill rate
 k = c~ u / p needs u pointwise (Sec. 6.2); it is refitted between runs.
 
-Refit round r: run the chains with mu_r (uniform for r = 0), record the
+Refit r: run the chains with mu_r (uniform for r = 0), record the
 pairs (x_{i-1}, dt_i) of the last few steps of every chain
 (restore_step_record; the time-weighted pairs are draws of pi, Sec. 7.4,
 eq. (approx)), then take full-batch Adam steps on the time-weighted negative
@@ -154,22 +154,22 @@ def effective_fraction(w: torch.Tensor) -> float:
     return float(w.sum() ** 2 / (w.numel() * (w * w).sum()))
 
 
-def refit(wl, model: MlpGmm, c_tilde_eval: float, rounds: int = 5, record_steps: int = 4, epochs: int = 300,
+def refit(wl, model: MlpGmm, c_tilde_eval: float, refits: int = 5, record_steps: int = 4, epochs: int = 300,
           lr: float = 2e-2, seed: int = 3004, c_tilde_explore: float = 1.0, log=print) -> list:
-    """rounds refits of model on restore samples of the workload.
+    """`refits` refits of model on restore samples of the workload.
 
-    Round 0 samples with uniform mu at the exploratory c~_explore: tours
+    Refit 0 samples with uniform mu at the exploratory c~_explore: tours
     that reach a region of high p live long there and the local moves
     climb to the modes, so the recorded pairs cover the modes (weighted by
-    how often they are found rather than by their mass).  Later rounds
+    how often they are found rather than by their mass).  Later refits
     sample with the current learned mu at the c~ of the evaluation runs;
     their time-weighted pairs are then draws of pi (Sec. 7.4), which
     corrects the mixture weights and shapes.  mu only has to be a fixed
     density during a run, so the training data can come from any of these
-    runs without biasing later estimates.  Returns per-round diagnostics."""
+    runs without biasing later estimates.  Returns per-refit diagnostics."""
     out = []
     mu = None
-    for r in range(rounds):
+    for r in range(refits):
         torch.cuda.synchronize()
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
@@ -183,7 +183,7 @@ def refit(wl, model: MlpGmm, c_tilde_eval: float, rounds: int = 5, record_steps:
         ess = effective_fraction(w)
         log(f"[refit {r}] {w.numel()} samples (c~ {ct:.3g}, effective fraction {ess:.3g}), "
             f"nll {losses[0][1]:.4f} -> {losses[-1][1]:.4f}, {sec:.2f} s")
-        out.append({"round": r, "samples": int(w.numel()), "c_tilde": ct, "effective_fraction": ess,
+        out.append({"refit": r, "samples": int(w.numel()), "c_tilde": ct, "effective_fraction": ess,
                     "nll_first": losses[0][1], "nll_last": losses[-1][1], "seconds": sec})
         mu = model.mu()
         del x, w

@@ -360,7 +360,7 @@ def test_refit_lowers_nll_and_learned_run_is_unbiased(R):
     model = MlpGmm(d=wl.d, K=64, seed=3004)
     ct_uniform = wl.c_tilde * 512 / wl.n_steps      # 8 P / B at this budget
     ct = provable_c_tilde(ct_uniform, model.beta)
-    hist = refit(wl, model, ct, rounds=3, record_steps=4, epochs=200, lr=2e-2, seed=3004, log=_say)
+    hist = refit(wl, model, ct, refits=3, record_steps=4, epochs=200, lr=2e-2, seed=3004, log=_say)
     assert hist[0]["nll_last"] < hist[0]["nll_first"] - 1.0
     tr = truth.truths(wl)
     run = R.Run(R.problem_from_workload(wl.with_(seed=2004), mu=model.mu(), c_tilde=ct))

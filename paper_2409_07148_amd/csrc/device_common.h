@@ -37,9 +37,11 @@ struct Philox {
 };
 
 // Odd 23-bit uniform in (0,1): (2 (r >> 9) + 1) 2^-24 == ((r >> 8) | 1) 2^-24,
-// exact in float32.
+// exact in float32.  Built from the exponent bits: f = 1 + (r >> 9) 2^-23
+// lies in [1, 2), and f - (1 - 2^-24) is exact (Sterbenz) and equals
+// (r >> 9) 2^-23 + 2^-24.
 __device__ __forceinline__ float u01(uint32_t r) {
-    return (float)((r >> 8) | 1u) * 0x1.0p-24f;
+    return __uint_as_float((r >> 9) | 0x3F800000u) - 0x1.fffffep-1f;
 }
 
 // Uniforms of one step: head = (u_E1, u_E2, u_acc, u_cat) from block 0;

@@ -9,7 +9,14 @@ double precision, built by ``oracle/build.py`` with gcc), marshals a
 * :func:`transitions`     -- single Jump Restore transitions (Alg. 2 body);
 * :func:`run`             -- whole runs: B steps, drain, per-chain tour sums;
 * :func:`estimate`        -- the tour-ratio estimates of Sec. 6.3 / 7.4 with
-                             delta-method standard errors over chains.
+                             delta-method standard errors over chains;
+* :func:`asymptotic_variance` -- the time-average variance constant of pi f
+                             (the quantity Theorem B of the supplement orders).
+
+With ``c_tilde = 0`` and a large-step probability ``l > 0`` the same runs are
+the paper's reference chain M^l (Sec. 4, eq. (mixture-proposal-kernel);
+Sec. 8): a Metropolis-Hastings chain with the mixture proposal, whose
+ergodic average after a burn-in estimates pi f.
 
 It shares nothing with the HIP path except the seeded inputs drawn by
 ``workloads``.  The Gaussian-mixture precision matrices and log-determinants
@@ -31,7 +38,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 TARGET_GMM, TARGET_PSS = 0, 1
 MU_UNIFORM, MU_GMM_DIAG = 0, 1
 LOCAL_RWMH, LOCAL_MALA = 0, 1
-FLAG_KILL, FLAG_ACCEPT, FLAG_OUTSIDE = 1, 2, 4
+FLAG_KILL, FLAG_ACCEPT, FLAG_OUTSIDE, FLAG_LARGE = 1, 2, 4, 8
 
 _dp = C.POINTER(C.c_double)
 
@@ -51,20 +58,23 @@ class OrMu(C.Structure):
 
 
 class OrLocal(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("step", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("step", C.c_double),
+                ("large_step_prob", C.c_double)]
 
 
 class OrConfig(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("target_id", C.c_uint32), ("pad", C.c_uint32),
                 ("c_tilde", C.c_double), ("integrand_p", C.c_int32),
-                ("image_w", C.c_int32), ("image_h", C.c_int32), ("rb_dt", C.c_int32)]
+                ("image_w", C.c_int32), ("image_h", C.c_int32), ("rb_dt", C.c_int32),
+                ("burn_in", C.c_int32), ("pad2", C.c_int32)]
 
 
 class OrOutputs(C.Structure):
     _fields_ = [("n_done", C.POINTER(C.c_int64)), ("t_done", _dp), ("a_done", _dp),
                 ("censored", C.POINTER(C.c_int32)), ("t_censored", _dp),
                 ("transitions", C.POINTER(C.c_int64)), ("accepts", C.POINTER(C.c_int64)),
-                ("kills", C.POINTER(C.c_int64)), ("image", _dp)]
+                ("kills", C.POINTER(C.c_int64)), ("image", _dp),
+                ("large_steps", C.POINTER(C.c_int64)), ("large_accepts", C.POINTER(C.c_int64))]
 
 
 _lib = None
@@ -136,7 +146,8 @@ class Problem:
     def __init__(self, wl, mu: Optional[dict] = None, target_id: int = 0,
                  c_tilde: Optional[float] = None, seed: Optional[int] = None,
                  integrand_p: bool = True, image: Optional[tuple] = None,
-                 step: Optional[float] = None, local: Optional[str] = None, rb_dt: bool = False):
+                 step: Optional[float] = None, local: Optional[str] = None, rb_dt: bool = False,
+                 large_step_prob: float = 0.0, burn_in: int = 0):
         self.wl = wl
         self.d = wl.d
         self._keep = []
@@ -192,6 +203,9 @@ class Problem:
         local = local or wl.local
         lk.kind = LOCAL_MALA if local == "mala" else LOCAL_RWMH
         lk.step = float(wl.step if step is None else step)
+        # l is a float32 at the library boundary; the oracle compares the
+        # (float32-exact) uniform with the same value
+        lk.large_step_prob = float(np.float32(large_step_prob))
         self.local = lk
 
         cfg = OrConfig()
@@ -200,6 +214,7 @@ class Problem:
         cfg.c_tilde = float(wl.c_tilde if c_tilde is None else c_tilde)
         cfg.integrand_p = 1 if integrand_p else 0
         cfg.rb_dt = 1 if rb_dt else 0
+        cfg.burn_in = int(burn_in)
         img = image if image is not None else wl.image
         if img:
             cfg.image_w, cfg.image_h = int(img[0]), int(img[1])
@@ -309,12 +324,16 @@ class RunResult:
     kills: np.ndarray
     image: Optional[np.ndarray]
     c_tilde: float
+    large_steps: Optional[np.ndarray] = None
+    large_accepts: Optional[np.ndarray] = None
 
 
 def run(prob: Problem, c0: int, c1: int, n_steps: Optional[int] = None,
         drain_cap: Optional[int] = None, threads: Optional[int] = None) -> RunResult:
     """Chains [c0, c1): x_0 ~ mu, ``n_steps`` steps with regeneration, then
-    the tours in flight are finished for at most ``drain_cap`` steps."""
+    the tours in flight are finished for at most ``drain_cap`` steps.  With
+    c_tilde = 0 (the MH chain) there are no tours: steps from the problem's
+    ``burn_in`` on add to the chain sums, and nothing is drained."""
     lib = load()
     n = c1 - c0
     n_steps = prob.wl.n_steps if n_steps is None else n_steps
@@ -323,12 +342,13 @@ def run(prob: Problem, c0: int, c1: int, n_steps: Optional[int] = None,
         threads = len(os.sched_getaffinity(0))
     r = RunResult(np.zeros(n, np.int64), np.zeros(n), np.zeros(n), np.zeros(n, np.int32),
                   np.zeros(n), np.zeros(n, np.int64), np.zeros(n, np.int64), np.zeros(n, np.int64),
-                  None, prob.c_tilde)
+                  None, prob.c_tilde, np.zeros(n, np.int64), np.zeros(n, np.int64))
     out = OrOutputs()
     out.n_done, out.t_done, out.a_done = _ptr(r.n_done, C.c_int64), _ptr(r.t_done), _ptr(r.a_done)
     out.censored, out.t_censored = _ptr(r.censored, C.c_int32), _ptr(r.t_censored)
     out.transitions, out.accepts = _ptr(r.transitions, C.c_int64), _ptr(r.accepts, C.c_int64)
     out.kills = _ptr(r.kills, C.c_int64)
+    out.large_steps, out.large_accepts = _ptr(r.large_steps, C.c_int64), _ptr(r.large_accepts, C.c_int64)
     if prob.cfg.image_w > 0:
         r.image = np.zeros((prob.cfg.image_h, prob.cfg.image_w))
         out.image = _ptr(r.image)
@@ -361,8 +381,12 @@ def estimate(r: RunResult) -> dict:
     int f dt; Sec. 7.4 eq. (approx): pi f ~ sum dt f / sum dt.  j counts the
     completed tours of all chains; censored tours are excluded."""
     c = r.c_tilde
-    pl, pl_se = _ratio(r.t_done, r.n_done)
-    lpf, lpf_se = _ratio(r.a_done, r.n_done)
+    if r.n_done.sum() > 0:
+        pl, pl_se = _ratio(r.t_done, r.n_done)
+        lpf, lpf_se = _ratio(r.a_done, r.n_done)
+    else:
+        # no completed tour (the MH chain, c_tilde = 0): only pi f exists
+        pl = pl_se = lpf = lpf_se = float("nan")
     pif, pif_se = _ratio(r.a_done, r.t_done)
     tot_t = r.t_done.sum() + r.t_censored.sum()
     return {
@@ -374,7 +398,28 @@ def estimate(r: RunResult) -> dict:
         "transitions": int(r.transitions.sum()),
         "accept_rate": float(r.accepts.sum() / max(1, r.transitions.sum())),
         "kill_rate": float(r.kills.sum() / max(1, r.transitions.sum())),
+        "large_steps": int(r.large_steps.sum()) if r.large_steps is not None else 0,
+        "large_accepts": int(r.large_accepts.sum()) if r.large_accepts is not None else 0,
     }
+
+
+def asymptotic_variance(r: RunResult) -> float:
+    """Time-average variance constant of f = p: sigma^2 with
+    Var(int_0^t f dt / t) ~ sigma^2 / t, estimated per unit of process time
+    as sum_c (A_c - R T_c)^2 / sum_c T_c with R = sum A / sum T.
+
+    For the restore process A_c - R T_c is a sum over the chain's completed
+    tours of i.i.d. centred tour terms (the tours are the regeneration
+    cycles), so by Wald's identities its second moment is E[tours] times
+    the per-tour one and the ratio is the regenerative estimate
+    E[(A - pi f tau)^2] / E[tau].  For the MH chain every chain is one long
+    stationary run after its burn-in and the ratio is the usual estimate
+    of the variance constant from independent replicates."""
+    A = np.asarray(r.a_done, dtype=np.float64)
+    T = np.asarray(r.t_done, dtype=np.float64)
+    R = A.sum() / T.sum()
+    res = A - R * T
+    return float((res * res).sum() / T.sum())
 
 
 def image_estimate(r: RunResult) -> np.ndarray:

@@ -22,6 +22,16 @@
  *   - Sec. 6.3 / 7.4: the tour decomposition, the estimates
  *     p_lambda ~ (c_tilde / j) sum tau_i and lambda(p f) ~ (c_tilde / j)
  *     int f dt, and the time-weighted left-rectangle sums of eq. (approx).
+ *   - Sec. 4, eq. (mixture-proposal-kernel), and the reference chain of
+ *     Sec. 8 (practical setup): with large-step probability l a local
+ *     update proposes y ~ mu instead of a small step.  The mixture is taken
+ *     as a mixture of two Metropolis-Hastings kernels, K_l = l K_1 +
+ *     (1 - l) K_0 (Theorem B of the supplement), so a large step is
+ *     accepted with the independence-sampler ratio p(y) u(x) / (p(x) u(y))
+ *     and a small step with the small-step kernel's own ratio.  With
+ *     c_tilde = 0 this is the paper's MH baseline M^l: no tours; after a
+ *     burn-in, every step adds dt f(x_{i-1}) to the chain's sums, and
+ *     pi f ~ sum dt f / sum dt.
  *
  * Readings where the paper is silent (all shared with the GPU side as a
  * specification, never as code):
@@ -32,6 +42,10 @@
  *     u_cat); blocks 1.. give the d candidate uniforms.
  *   - k = +inf where p(x) = 0 (immediate kill, dt = 0); k = 0 when
  *     c_tilde = 0 (no killing, a plain MH chain).
+ *   - the large-step choice: u_L < l, with u_L the first uniform of its own
+ *     Philox block (purpose LARGE, block 0), drawn only for local updates
+ *     when l > 0; the large-step candidate is drawn from mu with the same
+ *     uniforms as a regeneration (u_cat and the candidate blocks).
  *   - the step budget: B steps with regeneration, then the tour in flight is
  *     finished without regeneration for at most drain_cap further steps;
  *     tours still alive then are censored (excluded and reported).
@@ -48,8 +62,8 @@
 enum { OR_TARGET_GMM = 0, OR_TARGET_PSS = 1 };
 enum { OR_MU_UNIFORM = 0, OR_MU_GMM_DIAG = 1 };
 enum { OR_LOCAL_RWMH = 0, OR_LOCAL_MALA = 1 };
-enum { OR_PURPOSE_INIT = 0, OR_PURPOSE_STEP = 1 };
-enum { OR_FLAG_KILL = 1, OR_FLAG_ACCEPT = 2, OR_FLAG_OUTSIDE = 4 };
+enum { OR_PURPOSE_INIT = 0, OR_PURPOSE_STEP = 1, OR_PURPOSE_LARGE = 2 };
+enum { OR_FLAG_KILL = 1, OR_FLAG_ACCEPT = 2, OR_FLAG_OUTSIDE = 4, OR_FLAG_LARGE = 8 };
 
 /* Target density p on the unit box.
  * GMM: p(x) = sum_k w_k N(x; m_k, S_k) for x in [0,1]^d, 0 outside.
@@ -78,7 +92,8 @@ typedef struct {
 
 typedef struct {
     int32_t kind, pad;
-    double step;   /* random-walk sigma, or MALA epsilon */
+    double step;              /* random-walk sigma, or MALA epsilon       */
+    double large_step_prob;   /* l of eq. (mixture-proposal-kernel)        */
 } or_local;
 
 typedef struct {
@@ -88,6 +103,8 @@ typedef struct {
     int32_t integrand_p;     /* accumulate f = p as well as f = 1 */
     int32_t image_w, image_h; /* pixel integrand on (x0, x1); 0 = off */
     int32_t rb_dt;           /* return E[dt | x] = 1 / (1 + k(x)) instead of dt */
+    int32_t burn_in;         /* c_tilde = 0: steps not accumulated at the start */
+    int32_t pad2;
 } or_config;
 
 /* ----------------------------------------------------------------------- */
@@ -380,20 +397,36 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
     int32_t fl = 0;
     double dt;
     if (t1 < t2) {
-        /* local state transition: one MH update with the small-step kernel */
+        /* local state transition: one MH update, with the large-step kernel
+           (proposal mu) with probability l, else with the small-step kernel */
         dt = t1;
+        int large = 0;
+        if (lk->large_step_prob > 0.0) {
+            double ul[4];
+            draw_block(cfg, step, chain, OR_PURPOSE_LARGE, 0, ul);
+            large = ul[0] < lk->large_step_prob;
+        }
         double z[OR_MAXD], y[OR_MAXD], gy[OR_MAXD];
-        box_muller(d, cand, z);
-        for (int i = 0; i < d; ++i) {
-            y[i] = st->x[i] + lk->step * z[i];
-            if (lk->kind == OR_LOCAL_MALA) y[i] += 0.5 * lk->step * lk->step * st->g[i];
+        if (large) {
+            fl |= OR_FLAG_LARGE;
+            sample_mu(mu, head[3], cand, y, &margins[2]);
+        } else {
+            box_muller(d, cand, z);
+            for (int i = 0; i < d; ++i) {
+                y[i] = st->x[i] + lk->step * z[i];
+                if (lk->kind == OR_LOCAL_MALA) y[i] += 0.5 * lk->step * lk->step * st->g[i];
+            }
         }
         if (!in_box(d, y)) fl |= OR_FLAG_OUTSIDE;
         double lpy = oracle_log_target(t, y, gy);
+        double luy = oracle_log_mu(mu, y);
         double alpha, lratio;
         if (st->lp == -INFINITY) { alpha = 1.0; lratio = INFINITY; }
         else {
-            lratio = lpy + log_q(lk, d, y, gy, st->x) - st->lp - log_q(lk, d, st->x, st->g, y);
+            if (large)   /* independence proposal: q(x, y) = u(y) */
+                lratio = (lpy + st->lu) - (st->lp + luy);
+            else
+                lratio = lpy + log_q(lk, d, y, gy, st->x) - st->lp - log_q(lk, d, st->x, st->g, y);
             alpha = lratio >= 0.0 ? 1.0 : exp(lratio);
         }
         margins[1] = log(head[2]) - lratio;
@@ -401,7 +434,7 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
             fl |= OR_FLAG_ACCEPT;
             for (int i = 0; i < d; ++i) { st->x[i] = y[i]; st->g[i] = gy[i]; }
             st->lp = lpy;
-            st->lu = oracle_log_mu(mu, y);
+            st->lu = luy;
         }
     } else {
         /* termination: regenerate from mu */
@@ -475,6 +508,8 @@ typedef struct {
     int64_t *accepts;     /* accepted local moves                     */
     int64_t *kills;       /* terminations                             */
     double *image;        /* [image_h * image_w], summed dt splats, or NULL */
+    int64_t *large_steps;   /* large-step proposals (l > 0)            */
+    int64_t *large_accepts; /* accepted large steps                    */
 } or_outputs;
 
 typedef struct {
@@ -491,12 +526,16 @@ static void run_chain(const or_job *job, int64_t c)
     or_state st;
     oracle_init_state(t, job->mu, cfg, (uint32_t)c, &st);
     double a_cur = 0.0, t_cur = 0.0, a_done = 0.0, t_done = 0.0;
-    int64_t n_done = 0, trans = 0, acc = 0, kills = 0;
+    int64_t n_done = 0, trans = 0, acc = 0, kills = 0, large = 0, large_acc = 0;
     int alive = 1;
-    int64_t s_end = (int64_t)job->n_steps + job->drain_cap;
+    /* c_tilde = 0: the MH chain has no tours, so nothing is drained; the
+       first burn_in steps are not accumulated */
+    const int mh = cfg->c_tilde == 0.0;
+    int64_t s_end = (int64_t)job->n_steps + (mh ? 0 : job->drain_cap);
     for (int64_t s = 0; s < s_end; ++s) {
         int drain = s >= job->n_steps;
         if (drain && !alive) break;
+        int counted = !mh || s >= cfg->burn_in;
         /* the pair (dt, x_{i-1}) is recorded before the state moves */
         double x_prev[OR_MAXD];
         memcpy(x_prev, st.x, sizeof(double) * t->d);
@@ -504,9 +543,16 @@ static void run_chain(const or_job *job, int64_t c)
         or_state before = st;
         int32_t fl; double mg[3];
         double dt = oracle_transition(t, job->mu, job->lk, cfg, (uint32_t)s, (uint32_t)c, &st, &fl, mg);
+        if (!counted) continue;
         ++trans;
-        t_cur += dt;
-        if (cfg->integrand_p) a_cur += dt * (lp_prev == -INFINITY ? 0.0 : exp(lp_prev));
+        double f = lp_prev == -INFINITY ? 0.0 : exp(lp_prev);
+        if (mh) {
+            t_done += dt;
+            if (cfg->integrand_p) a_done += dt * f;
+        } else {
+            t_cur += dt;
+            if (cfg->integrand_p) a_cur += dt * f;
+        }
         if (job->image) {
             int px = (int)floor(x_prev[0] * cfg->image_w);
             int py = (int)floor(x_prev[1] * cfg->image_h);
@@ -517,6 +563,7 @@ static void run_chain(const or_job *job, int64_t c)
             }
         }
         if (fl & OR_FLAG_ACCEPT) ++acc;
+        if (fl & OR_FLAG_LARGE) { ++large; if (fl & OR_FLAG_ACCEPT) ++large_acc; }
         if (fl & OR_FLAG_KILL) {
             ++kills;
             a_done += a_cur; t_done += t_cur; ++n_done;
@@ -524,11 +571,14 @@ static void run_chain(const or_job *job, int64_t c)
             if (drain) { alive = 0; st = before; }  /* retire: no regeneration */
         }
     }
+    if (mh) alive = 0;
     const or_outputs *o = job->out;
     o->n_done[c] = n_done; o->t_done[c] = t_done; o->a_done[c] = a_done;
     o->censored[c] = alive ? 1 : 0;
     o->t_censored[c] = alive ? t_cur : 0.0;
     o->transitions[c] = trans; o->accepts[c] = acc; o->kills[c] = kills;
+    if (o->large_steps) o->large_steps[c] = large;
+    if (o->large_accepts) o->large_accepts[c] = large_acc;
 }
 
 static void *run_job(void *arg)
@@ -556,6 +606,8 @@ int oracle_run(const or_target *t, const or_mu *mu, const or_local *lk,
     shifted.n_done -= c0; shifted.t_done -= c0; shifted.a_done -= c0;
     shifted.censored -= c0; shifted.t_censored -= c0; shifted.transitions -= c0;
     shifted.accepts -= c0; shifted.kills -= c0;
+    if (shifted.large_steps) shifted.large_steps -= c0;
+    if (shifted.large_accepts) shifted.large_accepts -= c0;
     for (int i = 0; i < n_threads; ++i) {
         jobs[i].t = t; jobs[i].mu = mu; jobs[i].lk = lk; jobs[i].cfg = cfg;
         jobs[i].c0 = c0 + n * i / n_threads;

@@ -8,6 +8,7 @@ import subprocess
 import pytest
 
 from oracle import oracle as O
+from tests import test_oracle_mh as mh
 from tests import test_oracle_pins as pins
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -39,8 +40,8 @@ MUTATIONS = {
                                    "uint64_t p0 = (uint64_t)M1 * (uint64_t)c0;",
                                    [lambda: pins.test_philox_known_answers(None)]),
     # integrand evaluated at the post-transition state instead of x_{i-1}
-    "integrand_after_move": ("a_cur += dt * (lp_prev == -INFINITY ? 0.0 : exp(lp_prev));",
-                             "a_cur += dt * (st.lp == -INFINITY ? 0.0 : exp(st.lp));",
+    "integrand_after_move": ("double f = lp_prev == -INFINITY ? 0.0 : exp(lp_prev);",
+                             "double f = st.lp == -INFINITY ? 0.0 : exp(st.lp);",
                              [lambda: pins.test_whole_run_2d_matches_erf_closed_form(None)]),
     # Mahalanobis form with the mean subtracted on one side only
     "quadratic_form_index": ("q += (x[i] - m[i]) * P[i * d + j] * (x[j] - m[j]);",
@@ -56,6 +57,20 @@ MUTATIONS = {
     # conditional-mean holding time 1/k instead of 1/(1 + k)
     "rb_holding_time_without_holding_rate": ("return 1.0 / (1.0 + exp(log_k));", "return exp(-log_k);",
                                              [lambda: pins.test_zero_step_rao_blackwellised_moments(None)]),
+    # large step accepted with the target ratio alone (u(x) / u(y) dropped)
+    "large_step_drops_mu_ratio": ("lratio = (lpy + st->lu) - (st->lp + luy);", "lratio = lpy - st->lp;",
+                                  [lambda: mh.test_large_step_with_proposal_equal_to_target_always_accepted(None)]),
+    # independence ratio with u(y) / u(x) in place of u(x) / u(y)
+    "large_step_mu_ratio_inverted": ("lratio = (lpy + st->lu) - (st->lp + luy);",
+                                     "lratio = (lpy + luy) - (st->lp + st->lu);",
+                                     [lambda: mh.test_large_step_with_proposal_equal_to_target_always_accepted(None),
+                                      lambda: mh.test_mixture_kernel_is_pi_invariant(None, "rwmh", 0.05, "mismatched")]),
+    # large step taken with probability 1 - l
+    "large_step_share_complement": ("large = ul[0] < lk->large_step_prob;", "large = ul[0] >= lk->large_step_prob;",
+                                    [lambda: mh.test_large_step_share_is_l(None)]),
+    # the MH chain's burn-in steps accumulated
+    "mh_burn_in_ignored": ("int counted = !mh || s >= cfg->burn_in;", "int counted = 1;",
+                           [lambda: mh.test_mh_ergodic_average_matches_erf_truth(None, True)]),
     # a completed tour not counted
     "tour_not_counted": ("a_done += a_cur; t_done += t_cur; ++n_done;",
                          "a_done += a_cur; t_done += t_cur;",

@@ -17,6 +17,13 @@
  * Sec. 6.3: p_lambda ~ (c_tilde / j) sum tau_i, lambda(p f) ~ (c_tilde / j)
  * int f dt, and pi f ~ sum dt f / sum dt (Sec. 7.4).
  *
+ * With c_tilde = 0 the same calls run the paper's reference method instead
+ * (Sec. 8, practical setup): the Metropolis-Hastings chain M^l whose
+ * proposal mixes a large step from mu (probability l) with the small-step
+ * kernel, eq. (mixture-proposal-kernel).  It has no tours; its estimate is
+ * the ergodic average pi f ~ sum dt f / sum dt after a burn-in
+ * (restore_reset_sums).
+ *
  * Conventions
  *   - Every function returns a restore_status: 0 on success, < 0 on error.
  *     The message of the last error on the calling thread is available from
@@ -113,9 +120,18 @@ typedef struct {
 typedef struct {
     int32_t kind;
     float step;              /* random-walk sigma or MALA epsilon (>= 0)        */
-    float large_step_prob;   /* l of eq. (mixture-proposal-kernel); the restore
-                                process uses the pure small-step chain M^0, so
-                                only 0 is accepted (UNSUPPORTED otherwise)      */
+    float large_step_prob;   /* l in [0,1] of eq. (mixture-proposal-kernel).
+                                The restore process (c_tilde > 0) uses the
+                                pure small-step chain M^0 (Sec. 8), so l must
+                                be 0 there (UNSUPPORTED otherwise).  With
+                                c_tilde = 0, each update of the MH chain M^l
+                                is a large step with probability l (decided by
+                                the first uniform of the step's Philox block
+                                with purpose 2, block 0, against l as float32):
+                                y ~ mu (drawn as a regeneration would be),
+                                accepted iff u_acc < p(y) u(x) / (p(x) u(y))
+                                (the kernel K_1 of Theorem B in the
+                                supplement); otherwise the small-step update */
     int32_t reserved;
 } restore_local_kernel;
 
@@ -146,7 +162,8 @@ typedef struct {
     int64_t n_chains;        /* C >= 1, at most 2^31 - 1                      */
     int32_t target_id;       /* Philox counter word 2 (batched targets)      */
     int32_t integrands;      /* RESTORE_INTEGRAND_* bitmask (ONE is implied) */
-    double c_tilde;          /* > 0; 0 turns killing off (a plain MH chain)  */
+    double c_tilde;          /* > 0: restore; 0: the MH chain M^l (no killing,
+                                no tours, every step adds to the chain sums) */
     int32_t drain_cap;       /* max extra steps to finish tours in flight    */
     int32_t image_w, image_h;/* pixel grid on (x0, x1) if PIXEL is set      */
     int32_t flags;           /* RESTORE_FLAG_*                               */
@@ -171,6 +188,8 @@ typedef struct {
     double censored_time_frac;       /* censored lifetime / total time   */
     double accept_rate, kill_rate;   /* per transition                   */
     double image_scale;              /* c_tilde / j: multiplies the image sums */
+    int64_t large_steps;             /* MH chain: large-step proposals     */
+    int64_t large_accepts;           /* MH chain: accepted large steps     */
 } restore_estimate_out;
 
 typedef struct restore_ctx restore_ctx;
@@ -197,6 +216,10 @@ restore_status restore_init(restore_ctx **out, const restore_target *target,
 
 /* Advance every chain by n_steps steps of Alg. 2 with regeneration
  * (steps s .. s + n_steps - 1, s = steps already taken).  Enqueue only.
+ * With c_tilde = 0: n_steps updates of the MH chain M^l, each adding dt
+ * f(x_{i-1}) to the chain's float64 sums (dt = 1 with RESTORE_FLAG_RB_DT,
+ * the discrete-time average; else the Exp(1) holding time of the
+ * continuous-time chain with generator K_l - id).
  * With the PIXEL integrand (unless RESTORE_FLAG_SPLAT_DIRECT) the steps run
  * as launches of at most 64 steps whose splat records are binned by image
  * band in the state buffer and summed into the image after each launch;
@@ -207,8 +230,17 @@ restore_status restore_step(restore_ctx *ctx, int32_t n_steps, void *stream);
  * tour in flight is killed (it then retires) or drain_cap further steps
  * have passed (the tour is censored: excluded from the estimates, counted
  * and reported).  Retired chains are compacted out of the launches with
- * wavefront ballots.  After restore_drain no further restore_step. */
+ * wavefront ballots.  After restore_drain no further restore_step.  For
+ * the MH chain (c_tilde = 0) there is nothing to finish: no launch. */
 restore_status restore_drain(restore_ctx *ctx, void *stream);
+
+/* Burn-in of the MH chain (c_tilde = 0; the paper's MH baselines discard
+ * their first 10,000 iterations, Sec. 9): zero every chain's sums, the run
+ * counters and the image (if any), keeping the chain states, so that the
+ * estimate covers the steps after this call only.  RESTORE_E_BAD_STATE for
+ * the restore process (c_tilde > 0: a tour in flight would lose its start
+ * and bias the estimates) or after restore_drain.  Enqueue only. */
+restore_status restore_reset_sums(restore_ctx *ctx, void *stream);
 
 /* Reduce the per-chain tour sums in float64 and fill *out (host memory).
  * Synchronises `stream`. */

@@ -85,9 +85,12 @@ restore_status validate(int n, const restore_target *t, const restore_local_kern
         if (lk[i].kind != RESTORE_LOCAL_RWMH)
             return fail(RESTORE_E_UNSUPPORTED, at + "the batched path runs random-walk MH local moves");
         if (!std::isfinite(lk[i].step) || lk[i].step < 0.0f) return fail(RESTORE_E_INVALID_ARG, at + "step must be >= 0");
-        if (lk[i].large_step_prob != 0.0f) return fail(RESTORE_E_UNSUPPORTED, at + "large_step_prob must be 0");
+        if (lk[i].large_step_prob != 0.0f)
+            return fail(RESTORE_E_UNSUPPORTED, at + "large_step_prob must be 0 (restore runs the small-step chain M^0)");
         if (c[i].n_chains < 1 || c[i].n_chains > 0x7fffffffLL) return fail(RESTORE_E_INVALID_ARG, at + "n_chains outside 1..2^31-1");
         if (!std::isfinite(c[i].c_tilde) || c[i].c_tilde < 0.0) return fail(RESTORE_E_INVALID_ARG, at + "c_tilde must be >= 0");
+        if (c[i].c_tilde == 0.0)
+            return fail(RESTORE_E_UNSUPPORTED, at + "c_tilde = 0 (the MH chain) runs on the single-target path");
         if (c[i].drain_cap < 0) return fail(RESTORE_E_INVALID_ARG, at + "drain_cap must be >= 0");
         if (c[i].integrands & RESTORE_INTEGRAND_PIXEL) return fail(RESTORE_E_UNSUPPORTED, at + "no pixel integrand in batches");
         total += c[i].n_chains;

@@ -136,7 +136,15 @@ __device__ __forceinline__ void store_chain(const StepArgs &a, uint32_t c, const
 // flags.  In the drain (RETIRE) a terminated chain is not regenerated.
 // With BIN, a splat closed by this step is returned in ch.out_pix /
 // ch.out_acc instead of being added to the image.
-template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT, bool BIN = false>
+//
+// With MH the lane runs the Metropolis-Hastings reference chain M^l instead
+// (Sec. 5, eq. (mixture-proposal-kernel); Sec. 8): no killing clock; with
+// probability l (its own uniform, purpose LARGE) the update proposes y ~ mu
+// and accepts with the independence ratio p(y) u(x) / (p(x) u(y)) (the
+// large-step kernel K_1 of Theorem B in the supplement), otherwise it is the
+// small-step update; dt f(x_{i-1}) goes straight to the float64 chain sums,
+// as the chain has no tours.  ST_LAST_LARGE reports the large-step choice.
+template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT, bool BIN = false, bool MH = false>
 __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                                           uint32_t chain, Chain<D, LOC> &ch, bool &kill, bool &accept) {
     constexpr int NB = NBlocks<D>::value;
@@ -156,7 +164,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     float t2 = INFINITY;
     float inv_k = INFINITY;
     kill = false;
-    if (!a.no_kill) {
+    if (!MH && !a.no_kill) {
         // t2 = E2 / k = E2 exp(log p - log u - ln c_tilde); p = 0 gives t2 = 0
         inv_k = expf(ch.lp - ch.lu - a.log_c);
         t2 = e2 * inv_k;
@@ -166,9 +174,22 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     // with rb_dt its conditional mean 1 / (1 + k) is accumulated instead
     const float dt = a.rb_dt ? (inv_k > 1e30f ? 1.0f : inv_k / (1.0f + inv_k)) : (kill ? t2 : t1);
 
-    // accumulate dt f(x_{i-1}) into the tour in flight
-    ch.t_cur += dt;
-    if (a.integrand_p) ch.a_cur = fmaf(dt, expf(ch.lp), ch.a_cur);
+    bool large = false;
+    if constexpr (MH) {
+        if (a.large_prob > 0.0f) {
+            uint32_t r[4];
+            Philox::block(s, chain, a.target_id, PURPOSE_LARGE << 16, a.key0, a.key1, r);
+            large = u01(r[0]) < a.large_prob;
+        }
+        ch.status = large ? (ch.status | ST_LAST_LARGE) : (ch.status & ~ST_LAST_LARGE);
+        // no tours: dt f(x_{i-1}) goes to the chain sums
+        ch.t_done += (double)dt;
+        if (a.integrand_p) ch.a_done = fma((double)dt, (double)expf(ch.lp), ch.a_done);
+    } else {
+        // accumulate dt f(x_{i-1}) into the tour in flight
+        ch.t_cur += dt;
+        if (a.integrand_p) ch.a_cur = fmaf(dt, expf(ch.lp), ch.a_cur);
+    }
     if (TGT == TGT_PSS && a.image) {
         // f = 1_pixel(x0, x1) at the pre-transition state (p = 0 off the box)
         const float u0 = ch.x[0], u1 = ch.x[1];
@@ -204,13 +225,13 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         return;
     }
 
-    // candidate: mu sample if killed, small-step proposal otherwise.  A
-    // regenerated chain gets its gradient only when it first survives a
-    // step, so waves whose lanes were all killed skip that work.
+    // candidate: mu sample if killed (or a large step), small-step proposal
+    // otherwise.  A regenerated chain gets its gradient only when it first
+    // survives a step, so waves whose lanes were all killed skip that work.
     float y[D];
     float zz = 0.0f;
     const float h = 0.5f * a.step * a.step;
-    if (kill) {
+    if (kill || large) {
         sample_mu<D, MU, 4 * NB>(a, head[3], cand, y);
     } else {
         if (LOC == LOC_MALA && !(ch.status & ST_GRAD_VALID)) {
@@ -240,7 +261,10 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
             accept = true;  // alpha = 1 where p(x) q(x, y) = 0
         } else {
             float lr = lpy - ch.lp;
-            if (LOC == LOC_MALA) {
+            if (MH && large) {
+                // independence proposal: q(x, y) = u(y)
+                lr += ch.lu - luy;
+            } else if (LOC == LOC_MALA) {
                 // ln q(x->y) = -|z|^2 / 2 ;  ln q(y->x) = -|x - y - h g(y)|^2 / (2 eps^2);
                 // x - y is exact in float32 for neighbouring states (Sterbenz)
                 float rr = 0.0f;
@@ -272,7 +296,8 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
 }
 
 __device__ __forceinline__ void add_counters(unsigned long long *counters, unsigned long long t,
-                                             unsigned long long acc, unsigned long long kil) {
+                                             unsigned long long acc, unsigned long long kil,
+                                             unsigned long long large = 0, unsigned long long large_acc = 0) {
     // one lane per wave publishes the wave's ballot counts
     const unsigned long long active = __ballot(1);
     if ((unsigned)lane_id() == (unsigned)(__ffsll((long long)active) - 1)) {
@@ -280,6 +305,8 @@ __device__ __forceinline__ void add_counters(unsigned long long *counters, unsig
         atomicAdd(line + CNT_TRANSITIONS, t);
         atomicAdd(line + CNT_ACCEPTS, acc);
         atomicAdd(line + CNT_KILLS, kil);
+        if (large) atomicAdd(line + CNT_LARGE, large);
+        if (large_acc) atomicAdd(line + CNT_LARGE_ACCEPTS, large_acc);
     }
 }
 

@@ -20,6 +20,7 @@ struct KernelSet {
     const void *drain_lds = nullptr;
     const void *step_binned = nullptr;       // image integrand: binned splats
     const void *step_binned_lds = nullptr;
+    const void *step_mh = nullptr;           // the MH reference chain M^l (c_tilde = 0)
 };
 
 // Binned splats of one step launch into the image: per-band LDS

@@ -66,7 +66,8 @@ SplatPlan splat_plan(const restore_config *cfg, int tgt) {
     SplatPlan sp;
     if (tgt != TGT_PSS || !(cfg->integrands & RESTORE_INTEGRAND_PIXEL)) return sp;
     sp.batches = image_batches_of(cfg);
-    if (cfg->flags & RESTORE_FLAG_SPLAT_DIRECT) return sp;
+    // the MH chain's kernel splats directly
+    if ((cfg->flags & RESTORE_FLAG_SPLAT_DIRECT) || cfg->c_tilde == 0.0) return sp;
     const int64_t n_pix = (int64_t)cfg->image_w * cfg->image_h * sp.batches;
     const int64_t band = 1LL << SPLAT_BAND_SHIFT;
     const int64_t n_bins = (n_pix + band - 1) / band;
@@ -168,11 +169,12 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
         return fail(RESTORE_E_INVALID_ARG, "MALA needs step > 0");
     if (!(lk->large_step_prob >= 0.0f && lk->large_step_prob <= 1.0f))
         return fail(RESTORE_E_INVALID_ARG, "large_step_prob outside [0,1]");
-    if (lk->large_step_prob != 0.0f)
-        return fail(RESTORE_E_UNSUPPORTED, "restore runs the small-step chain M^0: large_step_prob must be 0");
     if (cfg->n_chains < 1 || cfg->n_chains > 0x7fffffffLL)
         return fail(RESTORE_E_INVALID_ARG, "n_chains %lld outside 1..2^31-1", (long long)cfg->n_chains);
     if (!std::isfinite(cfg->c_tilde) || cfg->c_tilde < 0.0) return fail(RESTORE_E_INVALID_ARG, "c_tilde must be >= 0");
+    if (lk->large_step_prob != 0.0f && cfg->c_tilde > 0.0)
+        return fail(RESTORE_E_UNSUPPORTED,
+                    "restore runs the small-step chain M^0: large_step_prob must be 0 unless c_tilde = 0 (MH chain)");
     if (cfg->drain_cap < 0) return fail(RESTORE_E_INVALID_ARG, "drain_cap must be >= 0");
     if (cfg->block_size != 0 && (cfg->block_size < 64 || cfg->block_size > 256 || cfg->block_size % 64))
         return fail(RESTORE_E_INVALID_ARG, "block_size must be a multiple of 64 in 64..256");
@@ -355,8 +357,10 @@ struct restore_ctx {
     int block = 256;
     bool lds = false;
     bool drained = false;
+    bool mh = false;            // c_tilde = 0: the MH chain M^l
     int32_t steps_taken = 0;
     float step = 0.0f;
+    float large_prob = 0.0f;
     float *image = nullptr;
     restore_mu mu{};
     SplatPlan splat{};
@@ -396,6 +400,7 @@ void fill_args(restore_ctx *c) {
     a.no_kill = c->cfg.c_tilde == 0.0 ? 1 : 0;
     a.log_c = c->cfg.c_tilde > 0.0 ? (float)std::log(c->cfg.c_tilde) : 0.0f;
     a.step = c->step;
+    a.large_prob = c->large_prob;
     a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
     a.key1 = (uint32_t)(c->cfg.seed >> 32);
     a.target_id = (uint32_t)c->cfg.target_id;
@@ -427,6 +432,23 @@ __global__ void zero_u32_kernel(uint32_t *p, int n) {
 __global__ void zero_u64_kernel(unsigned long long *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
+}
+
+__global__ void zero_f32_kernel(float *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+__global__ void reset_sums_kernel(float *a_cur, float *t_cur, double *a_done, double *t_done, uint32_t *n_done,
+                                  int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        a_cur[i] = 0.0f;
+        t_cur[i] = 0.0f;
+        a_done[i] = 0.0;
+        t_done[i] = 0.0;
+        n_done[i] = 0u;
+    }
 }
 
 }  // namespace
@@ -484,6 +506,8 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     c->block = cfg->block_size ? cfg->block_size : 256;
     c->lds = (cfg->flags & RESTORE_FLAG_PARAMS_LDS) != 0;
     c->step = local->step;
+    c->mh = cfg->c_tilde == 0.0;
+    c->large_prob = local->large_step_prob;
     c->image = (cfg->integrands & RESTORE_INTEGRAND_PIXEL) ? image_dev : nullptr;
     c->mu = *mu;
     c->splat = sp;
@@ -543,7 +567,11 @@ static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_recor
     void *kargs[] = {&a, &np};
     const size_t shm = c->lds ? (size_t)c->n_params * sizeof(float) : 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!c->splat.n_bins) {
+    if (c->mh) {
+        // the MH chain: parameters through the scalar cache, direct splats
+        hipError_t e = hipLaunchKernel(c->ks.step_mh, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, 0, s);
+        if (e != hipSuccess) return hip_fail(e, "MH step launch");
+    } else if (!c->splat.n_bins) {
         const void *fn = c->lds ? c->ks.step_lds : c->ks.step;
         hipError_t e = hipLaunchKernel(fn, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, shm, s);
         if (e != hipSuccess) return hip_fail(e, "step launch");
@@ -591,6 +619,11 @@ restore_status restore_step_record(restore_ctx *c, int32_t n_steps, int64_t n_re
 restore_status restore_drain(restore_ctx *c, void *stream) {
     if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
     if (c->drained) return fail(RESTORE_E_BAD_STATE, "restore_drain called twice");
+    if (c->mh) {
+        // no tours in flight
+        c->drained = true;
+        return RESTORE_OK;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint32_t *counts = at<uint32_t>(c, c->lay.counts);
     uint32_t *lists[2] = {at<uint32_t>(c, c->lay.list0), at<uint32_t>(c, c->lay.list1)};
@@ -678,6 +711,29 @@ restore_status restore_estimate(restore_ctx *c, restore_estimate_out *out, void 
     out->accept_rate = cnt[CNT_TRANSITIONS] ? (double)cnt[CNT_ACCEPTS] / (double)cnt[CNT_TRANSITIONS] : 0.0;
     out->kill_rate = cnt[CNT_TRANSITIONS] ? (double)cnt[CNT_KILLS] / (double)cnt[CNT_TRANSITIONS] : 0.0;
     out->image_scale = N > 0 ? ct / N : 0.0;
+    out->large_steps = (int64_t)cnt[CNT_LARGE];
+    out->large_accepts = (int64_t)cnt[CNT_LARGE_ACCEPTS];
+    return RESTORE_OK;
+}
+
+restore_status restore_reset_sums(restore_ctx *c, void *stream) {
+    if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
+    if (!c->mh)
+        return fail(RESTORE_E_BAD_STATE, "sums are reset only for the MH chain (c_tilde = 0): a restore tour in "
+                                         "flight would lose its start");
+    if (c->drained) return fail(RESTORE_E_BAD_STATE, "restore_reset_sums after restore_drain");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const StepArgs &a = c->args;
+    hipLaunchKernelGGL(reset_sums_kernel, grid_for(c->cfg.n_chains, 256), dim3(256), 0, s, a.a_cur, a.t_cur,
+                       a.a_done, a.t_done, a.n_done, (int64_t)c->cfg.n_chains);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(CNT_SPREAD * CNT_LINE / 256), dim3(256), 0, s, c->args.counters,
+                       CNT_SPREAD * CNT_LINE);
+    if (c->image) {
+        const int64_t n = (int64_t)c->cfg.image_w * c->cfg.image_h * image_batches_of(&c->cfg);
+        hipLaunchKernelGGL(zero_f32_kernel, grid_for(n, 256), dim3(256), 0, s, c->image, n);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "reset launch");
     return RESTORE_OK;
 }
 

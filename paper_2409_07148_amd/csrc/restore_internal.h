@@ -8,7 +8,7 @@ namespace restore {
 enum TargetKind : int { TGT_ISO = 0, TGT_FULL = 1, TGT_PSS = 2 };
 enum LocalKind : int { LOC_RWMH = 0, LOC_MALA = 1 };
 enum MuKind : int { MU_UNIFORM = 0, MU_GMM = 1 };
-enum Purpose : uint32_t { PURPOSE_INIT = 0, PURPOSE_STEP = 1 };
+enum Purpose : uint32_t { PURPOSE_INIT = 0, PURPOSE_STEP = 1, PURPOSE_LARGE = 2 };
 
 enum StatusBits : uint32_t {
     ST_ALIVE = 1u,       // tour in flight
@@ -16,9 +16,12 @@ enum StatusBits : uint32_t {
     ST_LAST_KILL = 4u,   // last executed step was a termination
     ST_LAST_ACCEPT = 8u, // last executed step accepted a local move
     ST_GRAD_VALID = 16u, // the cached grad log p(x) belongs to x (MALA)
+    ST_LAST_LARGE = 32u, // MH chain: the last step proposed a large step
 };
 
-enum CounterSlot : int { CNT_TRANSITIONS = 0, CNT_ACCEPTS = 1, CNT_KILLS = 2, CNT_SLOTS = 8 };
+enum CounterSlot : int {
+    CNT_TRANSITIONS = 0, CNT_ACCEPTS = 1, CNT_KILLS = 2, CNT_LARGE = 3, CNT_LARGE_ACCEPTS = 4, CNT_SLOTS = 8
+};
 // The run counters are spread over CNT_SPREAD copies, one per 256-byte line
 // (CNT_LINE 64-bit words apart), chosen by workgroup: the waves of a launch
 // then add into many lines instead of queueing on one.  Readers sum the
@@ -79,6 +82,7 @@ struct StepArgs {
     float log_c;       // ln c_tilde
     int32_t no_kill;   // c_tilde == 0
     float step;        // sigma or epsilon
+    float large_prob;  // MH chain: large-step probability l
     uint32_t key0, key1;
     uint32_t target_id;
     uint32_t s0;       // first step index of this launch

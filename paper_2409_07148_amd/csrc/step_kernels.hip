@@ -22,8 +22,10 @@
 
 namespace restore {
 
-// Steps with regeneration for every chain.
-template <int D, int TGT, int LOC, int MU, bool LDS>
+// Steps with regeneration for every chain.  With MH: steps of the
+// Metropolis-Hastings reference chain M^l (no killing, large steps from mu
+// with probability l; see step_once).
+template <int D, int TGT, int LOC, int MU, bool LDS, bool MH = false>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_floats) {
     extern __shared__ float smem[];
     const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
@@ -31,7 +33,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_float
     if (c >= a.n_chains) return;
     Chain<D, LOC> ch;
     load_chain(a, (uint32_t)c, ch);
-    unsigned long long n_acc = 0, n_kill = 0;
+    unsigned long long n_acc = 0, n_kill = 0, n_large = 0, n_large_acc = 0;
     bool kill = false, accept = false;
     const bool rec = a.rec_x != nullptr && c < a.rec_chains;
     for (int it = 0; it < a.n_steps; ++it) {
@@ -40,17 +42,23 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_float
 #pragma unroll
             for (int i = 0; i < D; ++i) xo[i] = ch.x[i];
         }
-        step_once<D, TGT, LOC, MU, false>(a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch, kill, accept);
+        step_once<D, TGT, LOC, MU, false, decltype(P), false, MH>(a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch,
+                                                                 kill, accept);
         if (rec) a.rec_w[(int64_t)it * a.rec_chains + c] = ch.last_dt;
         n_acc += __popcll(__ballot(accept));
         n_kill += __popcll(__ballot(kill));
+        if constexpr (MH) {
+            const bool large = (ch.status & ST_LAST_LARGE) != 0u;
+            n_large += __popcll(__ballot(large));
+            n_large_acc += __popcll(__ballot(large && accept));
+        }
     }
     ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT)) | (kill ? ST_LAST_KILL : 0u) |
                 (accept ? ST_LAST_ACCEPT : 0u);
     if (TGT == TGT_PSS && a.image) flush_splat(a, ch.splat_pix, ch.splat_acc);
     store_chain(a, (uint32_t)c, ch);
     const unsigned long long lanes = __popcll(__ballot(1));
-    add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill);
+    add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill, n_large, n_large_acc);
 }
 
 // Binning of the records staged in LDS: rows [0, rows) of this thread's
@@ -260,6 +268,7 @@ static KernelSet make_set() {
     k.refresh = (const void *)refresh_kernel<D, TGT, LOC, MU>;
     k.step = (const void *)step_kernel<D, TGT, LOC, MU, false>;
     k.step_lds = (const void *)step_kernel<D, TGT, LOC, MU, true>;
+    k.step_mh = (const void *)step_kernel<D, TGT, LOC, MU, false, true>;
     k.drain = (const void *)drain_kernel<D, TGT, LOC, MU, false>;
     k.drain_lds = (const void *)drain_kernel<D, TGT, LOC, MU, true>;
     if constexpr (TGT == TGT_PSS) {

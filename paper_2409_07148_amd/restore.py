@@ -25,7 +25,7 @@ MU_UNIFORM_BOX, MU_GMM_DIAG = 0, 1
 LOCAL_RWMH, LOCAL_MALA = 0, 1
 INTEGRAND_ONE, INTEGRAND_P, INTEGRAND_PIXEL = 1, 2, 4
 FLAG_PARAMS_LDS, FLAG_SPLAT_DIRECT, FLAG_SPLAT_TIGHT, FLAG_RB_DT = 1, 2, 4, 8
-ST_ALIVE, ST_CENSORED, ST_LAST_KILL, ST_LAST_ACCEPT, ST_GRAD_VALID = 1, 2, 4, 8, 16
+ST_ALIVE, ST_CENSORED, ST_LAST_KILL, ST_LAST_ACCEPT, ST_GRAD_VALID, ST_LAST_LARGE = 1, 2, 4, 8, 16, 32
 
 
 class RestoreError(RuntimeError):
@@ -62,7 +62,8 @@ class restore_estimate_out(C.Structure):
                 ("tours_done", C.c_int64), ("tours_censored", C.c_int64), ("transitions", C.c_int64),
                 ("accepts", C.c_int64), ("kills", C.c_int64), ("nonfinite", C.c_int64),
                 ("censored_time_frac", C.c_double), ("accept_rate", C.c_double),
-                ("kill_rate", C.c_double), ("image_scale", C.c_double)]
+                ("kill_rate", C.c_double), ("image_scale", C.c_double), ("large_steps", C.c_int64),
+                ("large_accepts", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -104,7 +105,7 @@ EXPORTS = ["restore_state_bytes", "restore_init", "restore_step", "restore_drain
            "restore_batch_get_tiling", "restore_batch_run", "restore_batch_estimates", "restore_batch_chain_sums",
            "restore_batch_autotune", "restore_batch_destroy", "restore_step_record", "restore_mlp_param_count",
            "restore_mlp_forward", "restore_mlp_backward", "restore_gmm_nll_workspace_bytes", "restore_gmm_nll",
-           "restore_adam_step", "restore_image_estimate", "restore_last_error"]
+           "restore_adam_step", "restore_image_estimate", "restore_reset_sums", "restore_last_error"]
 
 
 def _load() -> C.CDLL:
@@ -119,6 +120,7 @@ def _load() -> C.CDLL:
                                  P(restore_config), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
     lib.restore_step.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
     lib.restore_drain.argtypes = [C.c_void_p, C.c_void_p]
+    lib.restore_reset_sums.argtypes = [C.c_void_p, C.c_void_p]
     lib.restore_estimate.argtypes = [C.c_void_p, P(restore_estimate_out), C.c_void_p]
     lib.restore_image_estimate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.restore_get_state_view.argtypes = [C.c_void_p, P(restore_state_view)]
@@ -194,6 +196,10 @@ def restore_step(ctx, n_steps: int, stream=None) -> None:
 
 def restore_drain(ctx, stream=None) -> None:
     _check(_lib.restore_drain(ctx, C.c_void_p(_stream(stream))))
+
+
+def restore_reset_sums(ctx, stream=None) -> None:
+    _check(_lib.restore_reset_sums(ctx, C.c_void_p(_stream(stream))))
 
 
 def restore_estimate(ctx, stream=None) -> restore_estimate_out:
@@ -368,7 +374,8 @@ class Problem:
 def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: float, n_chains: int,
                  c_tilde: float, seed: int, drain_cap: int, target_id: int = 0, integrand_p: bool = True,
                  image: Optional[tuple] = None, lds: bool = False, block_size: int = 0,
-                 mu: Optional[dict] = None, flags: int = 0, image_batches: int = 0) -> Problem:
+                 mu: Optional[dict] = None, flags: int = 0, image_batches: int = 0,
+                 large_step_prob: float = 0.0) -> Problem:
     flat = target_params(kind, d, K, params)
     t = restore_target(_KIND[kind], d, K if kind != "pss" else 0, 0,
                        flat.ctypes.data_as(C.POINTER(C.c_double)), flat.size)
@@ -385,7 +392,7 @@ def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: f
         mu_t = torch.cat([torch.as_tensor(np.asarray(mu[k], dtype=np.float32).ravel())
                           for k in ("logits", "means", "log_std")]).cuda()
         m = restore_mu(MU_GMM_DIAG, int(np.asarray(mu["logits"]).size), float(mu["beta"]), 0, mu_t.data_ptr())
-    lk = restore_local_kernel(LOCAL_MALA if local == "mala" else LOCAL_RWMH, float(step), 0.0, 0)
+    lk = restore_local_kernel(LOCAL_MALA if local == "mala" else LOCAL_RWMH, float(step), float(large_step_prob), 0)
     integrands = INTEGRAND_ONE | (INTEGRAND_P if integrand_p else 0) | (INTEGRAND_PIXEL if image else 0)
     w, h = (image or (0, 0))
     cfg = restore_config(int(seed), int(n_chains), int(target_id), integrands, float(c_tilde), int(drain_cap),
@@ -440,6 +447,10 @@ class Run:
 
     def drain(self):
         restore_drain(self.ctx, self.stream)
+
+    def reset_sums(self):
+        """End of the MH chain's burn-in (c_tilde = 0): zero the sums."""
+        restore_reset_sums(self.ctx, self.stream)
 
     def estimate(self) -> dict:
         return restore_estimate(self.ctx, self.stream).as_dict()

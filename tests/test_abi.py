@@ -88,11 +88,18 @@ def test_target_validation(R):
 
 
 def test_local_kernel_validation(R):
+    # large steps belong to the MH chain (c_tilde = 0); restore runs M^0
     p = _problem(R)
     p.local.large_step_prob = 0.3
     with pytest.raises(R.RestoreError) as e:
         R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
     assert e.value.status == R.E_UNSUPPORTED
+    p.cfg.c_tilde = 0.0
+    assert R.restore_state_bytes(p.target, p.mu, p.local, p.cfg) > 0
+    p.local.large_step_prob = 1.5
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_INVALID_ARG
     p = _problem(R)
     p.local.step = 0.0   # MALA needs a positive step
     with pytest.raises(R.RestoreError) as e:
@@ -167,3 +174,23 @@ def test_nll_and_mlp_argument_validation(R):
     with pytest.raises(R.RestoreError) as e:
         R.restore_adam_step(0, 0, 0, 0, 10, 1, 1e-3, stream=0)
     assert e.value.status == R.E_INVALID_ARG
+
+
+def test_reset_sums_rejects_null_context(R):
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_reset_sums(None, stream=0)
+    assert e.value.status == R.E_INVALID_ARG
+
+
+def test_batch_rejects_the_mh_chain(R):
+    """Batched targets are restore problems; c_tilde = 0 (the MH chain)
+    runs on the single-target path."""
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=1000)
+    p = R.make_problem("gmm_full", wl.d, wl.K, wl.params, local="rwmh", step=0.02, n_chains=1000,
+                       c_tilde=1.0, seed=1, drain_cap=64)
+    assert R.restore_batch_state_bytes([p.target], [p.local], [p.cfg]) > 0
+    p.cfg.c_tilde = 0.0
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_batch_state_bytes([p.target], [p.local], [p.cfg])
+    assert e.value.status == R.E_UNSUPPORTED

@@ -573,8 +573,10 @@ def test_no_killing_is_a_plain_mh_chain(R):
     run.step(60)
     run.drain()
     est = run.estimate()
-    assert est["kills"] == 0 and est["accepts"] > 0
-    assert est["tours_censored"] == 4096
+    # no tours: nothing completed, nothing censored, every step counted
+    assert est["kills"] == 0 and est["accepts"] > 0 and est["large_steps"] == 0
+    assert est["tours_done"] == 0 and est["tours_censored"] == 0
+    assert est["transitions"] == 4096 * 60
     run.close()
 
 

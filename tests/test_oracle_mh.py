@@ -1,6 +1,6 @@
 """Pins of the oracle's Metropolis-Hastings reference chain M^l -- no GPU.
 
-M^l (Sec. 4, eq. (mixture-proposal-kernel); Sec. 8) is the MH chain whose
+M^l (Sec. 5, eq. (mixture-proposal-kernel); Sec. 8) is the MH chain whose
 proposal is the large-step distribution mu with probability l and the small
 step kernel otherwise, taken as the mixture of two MH kernels
 K_l = l K_1 + (1 - l) K_0 (Theorem B of the supplement).  With c_tilde = 0

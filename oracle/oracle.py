@@ -14,7 +14,7 @@ double precision, built by ``oracle/build.py`` with gcc), marshals a
                              (the quantity Theorem B of the supplement orders).
 
 With ``c_tilde = 0`` and a large-step probability ``l > 0`` the same runs are
-the paper's reference chain M^l (Sec. 4, eq. (mixture-proposal-kernel);
+the paper's reference chain M^l (Sec. 5, eq. (mixture-proposal-kernel);
 Sec. 8): a Metropolis-Hastings chain with the mixture proposal, whose
 ergodic average after a burn-in estimates pi f.
 

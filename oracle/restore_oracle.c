@@ -22,7 +22,7 @@
  *   - Sec. 6.3 / 7.4: the tour decomposition, the estimates
  *     p_lambda ~ (c_tilde / j) sum tau_i and lambda(p f) ~ (c_tilde / j)
  *     int f dt, and the time-weighted left-rectangle sums of eq. (approx).
- *   - Sec. 4, eq. (mixture-proposal-kernel), and the reference chain of
+ *   - Sec. 5, eq. (mixture-proposal-kernel), and the reference chain of
  *     Sec. 8 (practical setup): with large-step probability l a local
  *     update proposes y ~ mu instead of a small step.  The mixture is taken
  *     as a mixture of two Metropolis-Hastings kernels, K_l = l K_1 +

@@ -253,6 +253,64 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
     return res
 
 
+def restore_vs_mh(wl, replicates: int = 8, ell: float = 0.3, burn_in: int = 10000) -> dict:
+    """The paper's central comparison (Sec. 8, Sec. 9) on a synthetic target:
+    the restore process (the workload's c~, uniform mu, small-step kernel
+    M^0) against the Metropolis-Hastings chain M^l with the mixture proposal
+    (large steps from the same uniform mu with l = 0.3, the same small-step
+    kernel, and the first 10,000 iterations discarded as burn-in, the
+    paper's settings for its MH baselines).  Both run the workload's chain
+    count; MH averages the workload's step budget after its burn-in.  Both
+    estimate pi f with f = p; `replicates` fresh seeds per method, each
+    timed on the wall clock from init to estimate, scored against the
+    stored closed-form truth."""
+    import numpy as np
+    import torch
+    from paper_2409_07148_amd import restore as R
+
+    with open(os.path.join(ROOT, "tests", "golden", "truths.json")) as f:
+        truth = json.load(f)[wl.name]["pi_f"]
+
+    def one(mh: bool, r: int):
+        prob = (R.problem_from_workload(wl, c_tilde=0.0, large_step_prob=ell, seed=5005 + 31 * r,
+                                        flags=R.FLAG_RB_DT) if mh else
+                R.problem_from_workload(wl, seed=5005 + 31 * r))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run = R.Run(prob)
+        if mh:
+            run.step(burn_in)
+            run.reset_sums()
+        run.step(wl.n_steps)
+        run.drain()
+        est = run.estimate()
+        sec = time.perf_counter() - t
+        run.close()
+        return sec, est
+
+    out = {"quantity": "pi_f (f = p)", "truth": truth, "replicates": replicates}
+    for name, mh in (("restore", False), ("mh", True)):
+        rr = [one(mh, r) for r in range(replicates)]
+        secs = float(np.mean([t for t, _ in rr]))
+        rel = np.array([(e["pi_f"] - truth) / truth for _, e in rr])
+        mse = float((rel ** 2).mean())
+        o = {"seconds_per_run": secs, "rel_rmse": math.sqrt(mse), "rel_bias": float(rel.mean()),
+             "mean_reported_rel_se": float(np.mean([e["pi_f_se"] / truth for _, e in rr])),
+             "mse_x_time": mse * secs, "transitions": int(rr[0][1]["transitions"])}
+        if mh:
+            la = sum(e["large_accepts"] for _, e in rr)
+            ls = sum(e["large_steps"] for _, e in rr)
+            o.update({"large_step_prob": ell, "burn_in": burn_in, "steps_after_burn_in": wl.n_steps,
+                      "holding_time": "1 per step (discrete-time average)",
+                      "large_step_accept_rate": la / max(1, ls)})
+        else:
+            o.update({"c_tilde": wl.c_tilde, "budget_steps": wl.n_steps, "drain_cap": wl.drain_cap,
+                      "censored_tours": int(sum(e["tours_censored"] for _, e in rr))})
+        out[name] = o
+    out["mse_x_time_ratio_mh_over_restore"] = out["mh"]["mse_x_time"] / out["restore"]["mse_x_time"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +322,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mse-time", action="store_true",
                     help="skip the learned-mu MSE x time comparison (8-D workload only)")
+    ap.add_argument("--no-mh", action="store_true",
+                    help="skip the comparison with the MH chain M^l (mixture proposal, burn-in)")
     ap.add_argument("--no-image", action="store_true",
                     help="diagnostic: run the rendering-shaped workload without its pixel integrand")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -397,6 +457,10 @@ def main():
         line["copy_calibration_bytes"] = src.numel() * 4
     if wl.name == "gmm_full_8d" and not args.no_mse_time:
         line["mse_time"] = mse_time(wl)
+    if wl.name in ("gmm_full_8d", "gmm_iso_2d") and not args.no_mh:
+        line["restore_vs_mh"] = {wl.name: restore_vs_mh(wl)}
+        if wl.name == "gmm_full_8d":
+            line["restore_vs_mh"]["gmm_iso_2d"] = restore_vs_mh(gmm_iso_2d())
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

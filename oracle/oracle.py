@@ -37,7 +37,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 TARGET_GMM, TARGET_PSS = 0, 1
 MU_UNIFORM, MU_GMM_DIAG = 0, 1
-LOCAL_RWMH, LOCAL_MALA = 0, 1
+LOCAL_RWMH, LOCAL_MALA, LOCAL_HMC = 0, 1, 2
 FLAG_KILL, FLAG_ACCEPT, FLAG_OUTSIDE, FLAG_LARGE = 1, 2, 4, 8
 
 _dp = C.POINTER(C.c_double)
@@ -58,7 +58,7 @@ class OrMu(C.Structure):
 
 
 class OrLocal(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("step", C.c_double),
+    _fields_ = [("kind", C.c_int32), ("n_leapfrog", C.c_int32), ("step", C.c_double),
                 ("large_step_prob", C.c_double)]
 
 
@@ -106,6 +106,8 @@ def load():
                                C.POINTER(OrConfig), C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                C.c_int32, C.POINTER(OrOutputs)]
     lib.oracle_run.restype = C.c_int
+    lib.oracle_leapfrog.argtypes = [C.POINTER(OrTarget), C.c_int, C.c_double, _dp, _dp, _dp, _dp]
+    lib.oracle_leapfrog.restype = C.c_int
     _lib = lib
     return lib
 
@@ -147,7 +149,7 @@ class Problem:
                  c_tilde: Optional[float] = None, seed: Optional[int] = None,
                  integrand_p: bool = True, image: Optional[tuple] = None,
                  step: Optional[float] = None, local: Optional[str] = None, rb_dt: bool = False,
-                 large_step_prob: float = 0.0, burn_in: int = 0):
+                 large_step_prob: float = 0.0, burn_in: int = 0, n_leapfrog: Optional[int] = None):
         self.wl = wl
         self.d = wl.d
         self._keep = []
@@ -201,7 +203,8 @@ class Problem:
 
         lk = OrLocal()
         local = local or wl.local
-        lk.kind = LOCAL_MALA if local == "mala" else LOCAL_RWMH
+        lk.kind = {"rwmh": LOCAL_RWMH, "mala": LOCAL_MALA, "hmc": LOCAL_HMC}[local]
+        lk.n_leapfrog = int(getattr(wl, "n_leapfrog", 0) if n_leapfrog is None else n_leapfrog)
         lk.step = float(wl.step if step is None else step)
         # l is a float32 at the library boundary; the oracle compares the
         # (float32-exact) uniform with the same value
@@ -254,6 +257,19 @@ def log_target(prob: Problem, x: np.ndarray, grad: bool = False):
         lp[i] = lib.oracle_log_target(C.byref(prob.target), _ptr(xi), _ptr(gi) if grad else _dp())
         g[i] = gi
     return (lp, g) if grad else lp
+
+
+def leapfrog(prob: Problem, q, rho, n: int, e: float):
+    """n leapfrog steps of size e from (q, rho): returns (q, rho, log p(q),
+    grad log p(q), inside) at the end point."""
+    lib = load()
+    q = _f64(q).copy()
+    rho = _f64(rho).copy()
+    lp0, g = log_target(prob, q, grad=True)
+    g = np.ascontiguousarray(g[0])
+    lp = C.c_double(float(lp0[0]))
+    inside = lib.oracle_leapfrog(C.byref(prob.target), int(n), float(e), _ptr(q), _ptr(rho), C.byref(lp), _ptr(g))
+    return q, rho, lp.value, g, bool(inside)
 
 
 def log_mu(prob: Problem, y: np.ndarray) -> np.ndarray:

@@ -19,6 +19,12 @@
  *   - Alg. 1 with the acceptance function of eq. (optimal-acceptance-
  *     function): accept iff U < alpha(x, y), alpha = min(1, p(y)q(y,x) /
  *     (p(x)q(x,y))) when p(x)q(x,y) > 0, else 1.
+ *   - The small-step kernels the paper's study derives from diffusions
+ *     (Sec. 9): a Gaussian random walk (Brownian motion), the Langevin
+ *     proposal (MALA), and Hamiltonian Monte Carlo: a momentum rho ~ N(0, I)
+ *     and n leapfrog steps of size e of the dynamics with potential -log p
+ *     and unit mass, accepted with exp(-H(y, rho_n) + H(x, rho_0)),
+ *     H = -log p + |rho|^2 / 2.
  *   - Sec. 6.3 / 7.4: the tour decomposition, the estimates
  *     p_lambda ~ (c_tilde / j) sum tau_i and lambda(p f) ~ (c_tilde / j)
  *     int f dt, and the time-weighted left-rectangle sums of eq. (approx).
@@ -61,7 +67,7 @@
 
 enum { OR_TARGET_GMM = 0, OR_TARGET_PSS = 1 };
 enum { OR_MU_UNIFORM = 0, OR_MU_GMM_DIAG = 1 };
-enum { OR_LOCAL_RWMH = 0, OR_LOCAL_MALA = 1 };
+enum { OR_LOCAL_RWMH = 0, OR_LOCAL_MALA = 1, OR_LOCAL_HMC = 2 };
 enum { OR_PURPOSE_INIT = 0, OR_PURPOSE_STEP = 1, OR_PURPOSE_LARGE = 2 };
 enum { OR_FLAG_KILL = 1, OR_FLAG_ACCEPT = 2, OR_FLAG_OUTSIDE = 4, OR_FLAG_LARGE = 8 };
 
@@ -91,8 +97,9 @@ typedef struct {
 } or_mu;
 
 typedef struct {
-    int32_t kind, pad;
-    double step;              /* random-walk sigma, or MALA epsilon       */
+    int32_t kind;
+    int32_t n_leapfrog;       /* HMC: leapfrog steps per update            */
+    double step;              /* random-walk sigma, MALA or HMC epsilon   */
     double large_step_prob;   /* l of eq. (mixture-proposal-kernel)        */
 } or_local;
 
@@ -358,6 +365,26 @@ static double log_q(const or_local *lk, int d, const double *a, const double *ga
     return -s / (2.0 * e * e);
 }
 
+/* Leapfrog integration of dq/dt = rho, drho/dt = grad log p(q) (unit
+ * mass): half a momentum step, then n position steps separated by full
+ * momentum steps, then half a momentum step.  On entry g holds
+ * grad log p(q); on return q, rho, *lp = log p(q) and g are those of the
+ * end point.  Off the support the gradient is taken as 0.  Returns 0 if a
+ * visited point has p = 0 (the trajectory is then rejected). */
+int oracle_leapfrog(const or_target *t, int n, double e, double *q, double *rho, double *lp, double *g)
+{
+    int d = t->d, inside = 1;
+    for (int i = 0; i < d; ++i) rho[i] += 0.5 * e * g[i];
+    for (int l = 0; l < n; ++l) {
+        for (int i = 0; i < d; ++i) q[i] += e * rho[i];
+        *lp = oracle_log_target(t, q, g);
+        if (*lp == -INFINITY) inside = 0;
+        double h = (l == n - 1) ? 0.5 * e : e;
+        for (int i = 0; i < d; ++i) rho[i] += h * g[i];
+    }
+    return inside;
+}
+
 /* Initial state: x_0 ~ mu (purpose INIT, step 0). */
 void oracle_init_state(const or_target *t, const or_mu *mu, const or_config *cfg,
                        uint32_t chain, or_state *st)
@@ -407,9 +434,17 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
             large = ul[0] < lk->large_step_prob;
         }
         double z[OR_MAXD], y[OR_MAXD], gy[OR_MAXD];
+        int hmc = !large && lk->kind == OR_LOCAL_HMC, inside = 1;
+        double kinetic = 0.0;   /* HMC: |rho_0|^2 / 2 - |rho_n|^2 / 2 */
         if (large) {
             fl |= OR_FLAG_LARGE;
             sample_mu(mu, head[3], cand, y, &margins[2]);
+        } else if (hmc) {
+            box_muller(d, cand, z);
+            double rho[OR_MAXD], lq;
+            for (int i = 0; i < d; ++i) { y[i] = st->x[i]; rho[i] = z[i]; gy[i] = st->g[i]; }
+            inside = oracle_leapfrog(t, lk->n_leapfrog, lk->step, y, rho, &lq, gy);
+            for (int i = 0; i < d; ++i) kinetic += 0.5 * (z[i] * z[i] - rho[i] * rho[i]);
         } else {
             box_muller(d, cand, z);
             for (int i = 0; i < d; ++i) {
@@ -425,6 +460,8 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
         else {
             if (large)   /* independence proposal: q(x, y) = u(y) */
                 lratio = (lpy + st->lu) - (st->lp + luy);
+            else if (hmc)   /* leapfrog is volume-preserving and reversible */
+                lratio = inside ? (lpy - st->lp) + kinetic : -INFINITY;
             else
                 lratio = lpy + log_q(lk, d, y, gy, st->x) - st->lp - log_q(lk, d, st->x, st->g, y);
             alpha = lratio >= 0.0 ? 1.0 : exp(lratio);

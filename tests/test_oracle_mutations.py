@@ -8,6 +8,7 @@ import subprocess
 import pytest
 
 from oracle import oracle as O
+from tests import test_oracle_hmc as hmc
 from tests import test_oracle_mh as mh
 from tests import test_oracle_pins as pins
 
@@ -71,6 +72,18 @@ MUTATIONS = {
     # the MH chain's burn-in steps accumulated
     "mh_burn_in_ignored": ("int counted = !mh || s >= cfg->burn_in;", "int counted = 1;",
                            [lambda: mh.test_mh_ergodic_average_matches_erf_truth(None, True)]),
+    # HMC kinetic energy difference with the wrong sign
+    "hmc_kinetic_sign": ("kinetic += 0.5 * (z[i] * z[i] - rho[i] * rho[i]);",
+                         "kinetic += 0.5 * (rho[i] * rho[i] - z[i] * z[i]);",
+                         [lambda: hmc.test_one_leapfrog_step_is_mala(None),
+                          lambda: hmc.test_hmc_is_pi_invariant(None)]),
+    # leapfrog without the closing half momentum step
+    "leapfrog_full_last_kick": ("double h = (l == n - 1) ? 0.5 * e : e;", "double h = e;",
+                                [lambda: hmc.test_leapfrog_is_reversible_and_volume_preserving(None)]),
+    # leapfrog opening half step against the gradient
+    "leapfrog_first_kick_sign": ("for (int i = 0; i < d; ++i) rho[i] += 0.5 * e * g[i];",
+                                 "for (int i = 0; i < d; ++i) rho[i] -= 0.5 * e * g[i];",
+                                 [lambda: hmc.test_one_leapfrog_step_is_mala(None)]),
     # a completed tour not counted
     "tour_not_counted": ("a_done += a_cur; t_done += t_cur; ++n_done;",
                          "a_done += a_cur; t_done += t_cur;",

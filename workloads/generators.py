@@ -35,8 +35,10 @@ class Workload:
     d:           state dimension.
     K:           number of mixture components (0 for "pss").
     params:      canonical float64 parameters (see each generator).
-    local:       "rwmh" (Gaussian random walk) | "mala" (Langevin proposal).
-    step:        random-walk sigma or MALA epsilon.
+    local:       "rwmh" (Gaussian random walk) | "mala" (Langevin proposal)
+                 | "hmc" (Hamiltonian Monte Carlo, leapfrog).
+    step:        random-walk sigma, MALA epsilon or HMC leapfrog step size.
+    n_leapfrog:  leapfrog steps per HMC update (0 for the other kernels).
     n_chains:    chain population size.
     n_steps:     step budget B (steps with regeneration).
     drain_cap:   extra steps allowed to finish the tour straddling B.
@@ -63,6 +65,7 @@ class Workload:
     problem_seed: int
     image: Optional[tuple] = None
     image_batches: int = 0
+    n_leapfrog: int = 0
 
     def with_(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)

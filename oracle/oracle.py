@@ -26,6 +26,7 @@ side computes its own Cholesky factors.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 from typing import Optional
@@ -66,7 +67,7 @@ class OrConfig(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("target_id", C.c_uint32), ("pad", C.c_uint32),
                 ("c_tilde", C.c_double), ("integrand_p", C.c_int32),
                 ("image_w", C.c_int32), ("image_h", C.c_int32), ("rb_dt", C.c_int32),
-                ("burn_in", C.c_int32), ("pad2", C.c_int32)]
+                ("burn_in", C.c_int32), ("tile_px", C.c_int32), ("n_chains_total", C.c_int64)]
 
 
 class OrOutputs(C.Structure):
@@ -149,7 +150,8 @@ class Problem:
                  c_tilde: Optional[float] = None, seed: Optional[int] = None,
                  integrand_p: bool = True, image: Optional[tuple] = None,
                  step: Optional[float] = None, local: Optional[str] = None, rb_dt: bool = False,
-                 large_step_prob: float = 0.0, burn_in: int = 0, n_leapfrog: Optional[int] = None):
+                 large_step_prob: float = 0.0, burn_in: int = 0, n_leapfrog: Optional[int] = None,
+                 tile_px: int = 0, n_chains_total: Optional[int] = None):
         self.wl = wl
         self.d = wl.d
         self._keep = []
@@ -218,6 +220,10 @@ class Problem:
         cfg.integrand_p = 1 if integrand_p else 0
         cfg.rb_dt = 1 if rb_dt else 0
         cfg.burn_in = int(burn_in)
+        cfg.tile_px = int(tile_px)
+        cfg.n_chains_total = int(wl.n_chains if n_chains_total is None else n_chains_total)
+        if tile_px and (mu is not None or not (image if image is not None else wl.image)):
+            raise ValueError("tile-stratified runs need the image integrand and the uniform mu")
         img = image if image is not None else wl.image
         if img:
             cfg.image_w, cfg.image_h = int(img[0]), int(img[1])
@@ -466,3 +472,74 @@ def batch_ranges(n_chains: int, batches: int):
     """Chain ranges of the image batches: chain c belongs to batch
     floor(c batches / n_chains)."""
     return [(-(-b * n_chains // batches), -(-(b + 1) * n_chains // batches)) for b in range(batches)]
+
+
+# ---------------------------------------------------------------------------
+# tile-stratified runs
+# ---------------------------------------------------------------------------
+
+def tiles(prob: Problem):
+    """Pixel ranges (px0, px1, py0, py1) of the tiles, in tile order (row by
+    row), and each tile's share A_t of the unit square."""
+    P, W, H = prob.cfg.tile_px, prob.cfg.image_w, prob.cfg.image_h
+    out = []
+    for ty in range(-(-H // P)):
+        for tx in range(-(-W // P)):
+            px0, py0 = tx * P, ty * P
+            out.append((px0, min(W, px0 + P), py0, min(H, py0 + P)))
+    area = np.array([(a1 - a0) * (b1 - b0) / (W * H) for a0, a1, b0, b1 in out])
+    return out, area
+
+
+def tile_of_chain(prob: Problem, chains) -> np.ndarray:
+    """Chain c of C works on tile floor(c T / C)."""
+    T = len(tiles(prob)[0])
+    return (np.asarray(chains, dtype=np.int64) * T) // int(prob.cfg.n_chains_total)
+
+
+def estimate_tiles(prob: Problem, r: RunResult, c0: int = 0) -> dict:
+    """Stratified estimates of a tile-stratified run over chains [c0, ...):
+    each tile t is a restore problem with constant c_tilde A_t, so
+    p_lambda = sum_t c_tilde A_t T_t / N_t and lambda(p f) = sum_t c_tilde
+    A_t A_t' / N_t (Sec. 6.3 per tile, tiles added); pi f is their ratio.
+    Standard errors: per tile the delta-method variance and covariance of
+    the two tour ratios over the tile's chains, tiles independent, and the
+    delta method for the ratio pi f."""
+    _, area = tiles(prob)
+    c = r.c_tilde
+    tid = tile_of_chain(prob, np.arange(c0, c0 + len(r.n_done)))
+    P = L = vP = vL = cPL = 0.0
+    per_tile = []
+    for t in np.unique(tid):
+        m = tid == t
+        N, Tt, At = r.n_done[m].astype(np.float64), r.t_done[m], r.a_done[m]
+        n = m.sum()
+        RT, RA = Tt.sum() / N.sum(), At.sum() / N.sum()
+        eT, eA = Tt - RT * N, At - RA * N
+        den = (n - 1) * n * N.mean() ** 2
+        s_t = c * area[t]
+        P += s_t * RT
+        L += s_t * RA
+        vP += s_t ** 2 * (eT @ eT) / den
+        vL += s_t ** 2 * (eA @ eA) / den
+        cPL += s_t ** 2 * (eT @ eA) / den
+        per_tile.append({"tile": int(t), "p_lambda": s_t * RT, "p_lambda_se": s_t * math.sqrt((eT @ eT) / den),
+                         "tours": int(N.sum()), "chains": int(n)})
+    pi = L / P
+    v_pi = (vL - 2 * pi * cPL + pi * pi * vP) / (P * P)
+    return {"p_lambda": P, "p_lambda_se": math.sqrt(vP), "lam_pf": L, "lam_pf_se": math.sqrt(vL),
+            "pi_f": pi, "pi_f_se": math.sqrt(max(v_pi, 0.0)), "tiles": per_tile,
+            "tours_done": int(r.n_done.sum()), "tours_censored": int(r.censored.sum())}
+
+
+def image_estimate_tiles(prob: Problem, r: RunResult, c0: int = 0) -> np.ndarray:
+    """lambda(p h_j) per pixel j of a tile-stratified run: c_tilde A_t S_j /
+    N_t for the tile t that holds pixel j."""
+    rng, area = tiles(prob)
+    tid = tile_of_chain(prob, np.arange(c0, c0 + len(r.n_done)))
+    out = np.zeros_like(r.image)
+    for t, (a0, a1, b0, b1) in enumerate(rng):
+        m = tid == t
+        if m.any():
+            out[b0:b1, a0:a1] = r.c_tilde * area[t] * r.image[b0:b1, a0:a1] / r.n_done[m].sum()
+    return out

@@ -48,6 +48,17 @@
  *     u_cat); blocks 1.. give the d candidate uniforms.
  *   - k = +inf where p(x) = 0 (immediate kill, dt = 0); k = 0 when
  *     c_tilde = 0 (no killing, a plain MH chain).
+ *   - tile-stratified restore (the image integrand, tile_px > 0): the
+ *     pixel grid is cut into tiles of tile_px x tile_px pixels (ragged at
+ *     the right and bottom edges); chain c of C works on tile
+ *     floor(c T / C) only: its target is p restricted to the tile's points
+ *     (pixel of (x0, x1) inside the tile), its mu is uniform there,
+ *     sampled as x0 = fma(w, u0, px0) / W and x1 = fma(h, u1, py0) / H in
+ *     float32, the other coordinates as the uniform mu's, and its killing
+ *     rate is the unstratified one, k = c_tilde / p, i.e. the tile's own
+ *     constant is c_tilde A_t with A_t the tile's share of the box.  Each
+ *     tile is its own restore problem; its estimates carry the factor
+ *     c_tilde A_t / j_t (j_t its completed tours) and the tiles add up.
  *   - the large-step choice: u_L < l, with u_L the first uniform of its own
  *     Philox block (purpose LARGE, block 0), drawn only for local updates
  *     when l > 0; the large-step candidate is drawn from mu with the same
@@ -111,7 +122,8 @@ typedef struct {
     int32_t image_w, image_h; /* pixel integrand on (x0, x1); 0 = off */
     int32_t rb_dt;           /* return E[dt | x] = 1 / (1 + k(x)) instead of dt */
     int32_t burn_in;         /* c_tilde = 0: steps not accumulated at the start */
-    int32_t pad2;
+    int32_t tile_px;         /* > 0: tile-stratified restore (image integrand) */
+    int64_t n_chains_total;  /* C, for the chain -> tile map                    */
 } or_config;
 
 /* ----------------------------------------------------------------------- */
@@ -306,6 +318,47 @@ double oracle_log_mu(const or_mu *mu, const double *y)
     return log_sum_exp(mu->K + 1, a);
 }
 
+/* Tile of a chain in tile-stratified runs: pixel ranges [r[0], r[1]) x
+ * [r[2], r[3]).  Returns 0 when tiles are off. */
+static int chain_tile(const or_config *cfg, uint32_t chain, int r[4])
+{
+    if (cfg->tile_px <= 0) return 0;
+    int P = cfg->tile_px, W = cfg->image_w, H = cfg->image_h;
+    int tx_n = (W + P - 1) / P, ty_n = (H + P - 1) / P;
+    int64_t T = (int64_t)tx_n * ty_n;
+    int64_t t = (int64_t)chain * T / cfg->n_chains_total;
+    int tx = (int)(t % tx_n), ty = (int)(t / tx_n);
+    r[0] = tx * P; r[1] = r[0] + P < W ? r[0] + P : W;
+    r[2] = ty * P; r[3] = r[2] + P < H ? r[2] + P : H;
+    return 1;
+}
+
+/* pixel of (x0, x1), as the image splats compute it; -1 off the box */
+static int pixel_of(const or_config *cfg, const double *x, int *px, int *py)
+{
+    if (!(x[0] >= 0.0 && x[0] <= 1.0 && x[1] >= 0.0 && x[1] <= 1.0)) return 0;
+    *px = (int)floor(x[0] * cfg->image_w);
+    *py = (int)floor(x[1] * cfg->image_h);
+    if (*px >= cfg->image_w) *px = cfg->image_w - 1;
+    if (*py >= cfg->image_h) *py = cfg->image_h - 1;
+    return 1;
+}
+
+/* log of the chain's target: p, or in tile-stratified runs p restricted to
+ * the chain's tile */
+static double log_target_c(const or_target *t, const or_config *cfg, uint32_t chain, const double *x, double *g)
+{
+    double lp = oracle_log_target(t, x, g);
+    int r[4], px, py;
+    if (cfg && chain_tile(cfg, chain, r)) {
+        if (!pixel_of(cfg, x, &px, &py) || px < r[0] || px >= r[1] || py < r[2] || py >= r[3]) {
+            if (g) for (int i = 0; i < t->d; ++i) g[i] = 0.0;
+            return -INFINITY;
+        }
+    }
+    return lp;
+}
+
 /* y ~ mu from the step's category uniform and candidate uniforms; *margin
  * gets the distance of u_cat to the nearest category boundary (INFINITY for
  * uniform mu) */
@@ -346,6 +399,18 @@ static void sample_mu(const or_mu *mu, double u_cat, const double cand[OR_MAXD],
 /* one transition of Alg. 2                                                 */
 /* ----------------------------------------------------------------------- */
 
+/* the chain's mu: in tile-stratified runs the uniform mu on its tile */
+static void sample_mu_c(const or_mu *mu, const or_config *cfg, uint32_t chain, double u_cat,
+                        const double cand[OR_MAXD], double *y, double *margin)
+{
+    sample_mu(mu, u_cat, cand, y, margin);
+    int r[4];
+    if (chain_tile(cfg, chain, r)) {
+        y[0] = (double)(fmaf((float)(r[1] - r[0]), (float)cand[0], (float)r[0]) / (float)cfg->image_w);
+        y[1] = (double)(fmaf((float)(r[3] - r[2]), (float)cand[1], (float)r[2]) / (float)cfg->image_h);
+    }
+}
+
 typedef struct {
     double x[OR_MAXD];
     double lp, lu;
@@ -371,18 +436,24 @@ static double log_q(const or_local *lk, int d, const double *a, const double *ga
  * grad log p(q); on return q, rho, *lp = log p(q) and g are those of the
  * end point.  Off the support the gradient is taken as 0.  Returns 0 if a
  * visited point has p = 0 (the trajectory is then rejected). */
-int oracle_leapfrog(const or_target *t, int n, double e, double *q, double *rho, double *lp, double *g)
+static int leapfrog_c(const or_target *t, const or_config *cfg, uint32_t chain, int n, double e, double *q,
+                      double *rho, double *lp, double *g)
 {
     int d = t->d, inside = 1;
     for (int i = 0; i < d; ++i) rho[i] += 0.5 * e * g[i];
     for (int l = 0; l < n; ++l) {
         for (int i = 0; i < d; ++i) q[i] += e * rho[i];
-        *lp = oracle_log_target(t, q, g);
+        *lp = log_target_c(t, cfg, chain, q, g);
         if (*lp == -INFINITY) inside = 0;
         double h = (l == n - 1) ? 0.5 * e : e;
         for (int i = 0; i < d; ++i) rho[i] += h * g[i];
     }
     return inside;
+}
+
+int oracle_leapfrog(const or_target *t, int n, double e, double *q, double *rho, double *lp, double *g)
+{
+    return leapfrog_c(t, NULL, 0, n, e, q, rho, lp, g);
 }
 
 /* Initial state: x_0 ~ mu (purpose INIT, step 0). */
@@ -391,8 +462,8 @@ void oracle_init_state(const or_target *t, const or_mu *mu, const or_config *cfg
 {
     double head[4], cand[OR_MAXD], margin;
     draw_step(cfg, t->d, 0, chain, OR_PURPOSE_INIT, head, cand);
-    sample_mu(mu, head[3], cand, st->x, &margin);
-    st->lp = oracle_log_target(t, st->x, st->g);
+    sample_mu_c(mu, cfg, chain, head[3], cand, st->x, &margin);
+    st->lp = log_target_c(t, cfg, chain, st->x, st->g);
     st->lu = oracle_log_mu(mu, st->x);
 }
 
@@ -438,12 +509,12 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
         double kinetic = 0.0;   /* HMC: |rho_0|^2 / 2 - |rho_n|^2 / 2 */
         if (large) {
             fl |= OR_FLAG_LARGE;
-            sample_mu(mu, head[3], cand, y, &margins[2]);
+            sample_mu_c(mu, cfg, chain, head[3], cand, y, &margins[2]);
         } else if (hmc) {
             box_muller(d, cand, z);
             double rho[OR_MAXD], lq;
             for (int i = 0; i < d; ++i) { y[i] = st->x[i]; rho[i] = z[i]; gy[i] = st->g[i]; }
-            inside = oracle_leapfrog(t, lk->n_leapfrog, lk->step, y, rho, &lq, gy);
+            inside = leapfrog_c(t, cfg, chain, lk->n_leapfrog, lk->step, y, rho, &lq, gy);
             for (int i = 0; i < d; ++i) kinetic += 0.5 * (z[i] * z[i] - rho[i] * rho[i]);
         } else {
             box_muller(d, cand, z);
@@ -453,7 +524,7 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
             }
         }
         if (!in_box(d, y)) fl |= OR_FLAG_OUTSIDE;
-        double lpy = oracle_log_target(t, y, gy);
+        double lpy = log_target_c(t, cfg, chain, y, gy);
         double luy = oracle_log_mu(mu, y);
         double alpha, lratio;
         if (st->lp == -INFINITY) { alpha = 1.0; lratio = INFINITY; }
@@ -477,8 +548,8 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
         /* termination: regenerate from mu */
         dt = t2;
         fl |= OR_FLAG_KILL;
-        sample_mu(mu, head[3], cand, st->x, &margins[2]);
-        st->lp = oracle_log_target(t, st->x, st->g);
+        sample_mu_c(mu, cfg, chain, head[3], cand, st->x, &margins[2]);
+        st->lp = log_target_c(t, cfg, chain, st->x, st->g);
         st->lu = oracle_log_mu(mu, st->x);
     }
     *flags = fl;
@@ -505,7 +576,7 @@ void oracle_transitions(const or_target *t, const or_mu *mu, const or_local *lk,
         or_state st;
         for (int i = 0; i < d; ++i) st.x[i] = x[c * d + i];
         if (recompute) {
-            st.lp = oracle_log_target(t, st.x, st.g);
+            st.lp = log_target_c(t, cfg, chains[c], st.x, st.g);
             st.lu = oracle_log_mu(mu, st.x);
         } else {
             st.lp = lp[c]; st.lu = lu[c];

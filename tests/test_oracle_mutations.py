@@ -11,6 +11,7 @@ from oracle import oracle as O
 from tests import test_oracle_hmc as hmc
 from tests import test_oracle_mh as mh
 from tests import test_oracle_pins as pins
+from tests import test_oracle_tiles as tiles
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "restore_oracle.c")
@@ -84,6 +85,16 @@ MUTATIONS = {
     "leapfrog_first_kick_sign": ("for (int i = 0; i < d; ++i) rho[i] += 0.5 * e * g[i];",
                                  "for (int i = 0; i < d; ++i) rho[i] -= 0.5 * e * g[i];",
                                  [lambda: hmc.test_one_leapfrog_step_is_mala(None)]),
+    # tile-stratified chains not restricted to their tile
+    "tile_region_dropped": ("if (cfg && chain_tile(cfg, chain, r)) {", "if (0 && chain_tile(cfg, chain, r)) {",
+                            [lambda: tiles.test_chains_stay_in_their_tile(None)]),
+    # tile-uniform mu drawn from the wrong corner
+    "tile_sample_offset": ("(float)cand[0], (float)r[0])", "(float)cand[0], (float)r[1])",
+                           [lambda: tiles.test_initial_states_lie_in_their_tiles(None)]),
+    # chains dealt to tiles round-robin instead of in contiguous ranges
+    "tile_map_round_robin": ("int64_t t = (int64_t)chain * T / cfg->n_chains_total;",
+                             "int64_t t = (int64_t)chain % T;",
+                             [lambda: tiles.test_chains_stay_in_their_tile(None)]),
     # a completed tour not counted
     "tour_not_counted": ("a_done += a_cur; t_done += t_cur; ++n_done;",
                          "a_done += a_cur; t_done += t_cur;",

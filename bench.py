@@ -28,7 +28,7 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
 
 
-def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: float) -> dict:
+def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: float, n_leapfrog: int = 0) -> dict:
     """Algorithmic float32 operations of one transition (FMA = 2 flops; each
     exp / log / sqrt / sin / cos = 1), i.e. what the method must compute,
     dominated by the one target-density evaluation every step needs.
@@ -41,7 +41,10 @@ def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: flo
     A local step: clocks and accumulation 10, Box-Muller 5 per pair,
     proposal 3d, MALA reverse proposal density 3d + 3, acceptance 3, the
     density and gradient at the proposal, and -- once per tour -- the
-    gradient at the regenerated start.
+    gradient at the regenerated start.  An HMC local step with n leapfrog
+    steps: Box-Muller, 2d per half or full momentum step and per position
+    step, n density-and-gradient evaluations, the kinetic energies 4d and
+    the acceptance 3.
     Returns the per-transition count averaged with the measured kill rate."""
     mala = local == "mala"
     if target == "pss":
@@ -61,6 +64,12 @@ def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: flo
     else:
         raise ValueError(target)
     f_kill = K * lp + 2 + 10
+    if local == "hmc":
+        n = max(1, n_leapfrog)
+        f_local = (10 + 5 * math.ceil(d / 2) + 2 * d + n * 2 * d + (n - 1) * 2 * d + 2 * d
+                   + n * (K * (lp + gr) + 2) + 4 * d + 3 + kill_rate * K * gr)
+        return {"kill": float(f_kill), "local": float(f_local),
+                "mean": float(kill_rate * f_kill + (1.0 - kill_rate) * f_local)}
     f_local = (10 + 5 * math.ceil(d / 2) + 3 * d + 3 + K * lp + 2
                + ((3 * d + 3 + K * gr + kill_rate * K * gr) if mala else 0))
     return {"kill": float(f_kill), "local": float(f_local),
@@ -81,7 +90,7 @@ def measured_traffic(workload: str):
     return float(rec["traffic_bytes_per_launch"])
 
 
-STEP_KERNEL_SOURCES = ["step_kernels.hip", "chain_step.h", "targets.h", "device_common.h", "launch.h",
+STEP_KERNEL_SOURCES = ["step_kernels.hip", "step_kernels.h", "chain_step.h", "targets.h", "device_common.h", "launch.h",
                        "restore_internal.h"]
 
 
@@ -153,7 +162,7 @@ def bench_batched(args):
     trans = sum(e["transitions"] for e in est)
     flops = 0.0
     for w, e in zip(wls, est):
-        f = flops_per_transition(w.target, w.d, w.K, w.local, e["kill_rate"])
+        f = flops_per_transition(w.target, w.d, w.K, w.local, e["kill_rate"], w.n_leapfrog)
         flops += f["mean"] * e["transitions"]
     achieved = flops / (ev_g * 1e-3) / 1e12
     line = {
@@ -319,9 +328,14 @@ def main():
     ap.add_argument("--workload", default="gmm_full_8d",
                     choices=["gmm_full_8d", "gmm_iso_2d", "pss_render_12d", "batched_uneven"])
     ap.add_argument("--lds", action="store_true", help="stage mixture parameters in LDS")
+    ap.add_argument("--hmc", type=int, default=0, metavar="N",
+                    help="Gaussian-mixture workloads: Hamiltonian Monte Carlo local moves with N leapfrog "
+                         "steps of the workload's step size in place of its random-walk or MALA moves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mse-time", action="store_true",
                     help="skip the learned-mu MSE x time comparison (8-D workload only)")
+    ap.add_argument("--tiles", type=int, default=0, metavar="P",
+                    help="image workload: tile-stratified restore with P x P-pixel tiles")
     ap.add_argument("--no-mh", action="store_true",
                     help="skip the comparison with the MH chain M^l (mixture proposal, burn-in)")
     ap.add_argument("--no-image", action="store_true",
@@ -344,6 +358,14 @@ def main():
         return
 
     wl = {"gmm_full_8d": gmm_full, "gmm_iso_2d": gmm_iso_2d, "pss_render_12d": pss_render}[args.workload]()
+    if args.hmc:
+        if wl.target == "pss":
+            sys.exit("--hmc needs a Gaussian-mixture workload")
+        wl = wl.with_(local="hmc", n_leapfrog=args.hmc)
+    if args.tiles:
+        if wl.target != "pss":
+            sys.exit("--tiles needs the image workload")
+        wl = wl.with_(tile_px=args.tiles)
     if args.no_image:
         wl = wl.with_(image=None)
     prob = R.problem_from_workload(wl, lds=args.lds)
@@ -388,7 +410,9 @@ def main():
     step_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
     step_trans = wl.n_chains * wl.n_steps
     est = ests[-1]
-    fpt = flops_per_transition(wl.target, wl.d, wl.K, wl.local, est.kill_rate)
+    fpt = flops_per_transition(wl.target, wl.d, wl.K, wl.local, est.kill_rate, wl.n_leapfrog)
+    label = (wl.name + (f"_hmc{wl.n_leapfrog}" if wl.local == "hmc" else "")
+             + (f"_tiles{wl.tile_px}" if wl.tile_px else ""))
     achieved = fpt["mean"] * step_trans / (step_ms * 1e-3) / 1e12
     line = {
         "metric": "chain transitions/s + MSE×time vs uniform-mu restore at fixed rel. error",
@@ -404,9 +428,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": wl.name,
+            "workload": label,
             "description": (f"{wl.K}-component {'full-covariance' if wl.target == 'gmm_full' else 'isotropic'} "
-                            f"Gaussian mixture on [0,1]^{wl.d}, {wl.local} step {wl.step}, uniform mu, "
+                            f"Gaussian mixture on [0,1]^{wl.d}, {wl.local} step {wl.step}"
+                            f"{f' x {wl.n_leapfrog} leapfrog steps' if wl.local == 'hmc' else ''}, uniform mu, "
                             f"c_tilde {wl.c_tilde:g}") if wl.target != "pss" else
                            (f"12-D primary-sample-space integrand (2 textures x 8 sinusoids, 3 vMF lobes "
                             f"kappa 1e3) splatted to a {(wl.image or (0, 0))[0]}x{(wl.image or (0, 0))[1]} image, rwmh step {wl.step}, "
@@ -425,7 +450,7 @@ def main():
             "flops_per_transition": fpt,
             "kernel_ms": step_ms,
             "kernel_transitions_per_s": step_trans / (step_ms * 1e-3),
-            "traffic": measured_traffic(wl.name if not args.no_image else ""),
+            "traffic": measured_traffic(label if not args.no_image else ""),
         },
         "estimates": {k: est.as_dict()[k] for k in ("p_lambda", "p_lambda_se", "lam_pf", "lam_pf_se",
                                                     "tours_done", "tours_censored", "kill_rate",
@@ -446,7 +471,8 @@ def main():
         rel = (img_se / img_mean.clamp_min(1e-30)).flatten()
         line["image"] = {"width": prob.cfg.image_w, "height": prob.cfg.image_h,
                          "batches": max(1, prob.cfg.image_batches),
-                         "splats": "direct" if prob.cfg.flags & R.FLAG_SPLAT_DIRECT else "binned",
+                         "splats": ("tile-stratified, LDS tile per workgroup" if prob.cfg.tile_px else
+                                    "direct" if prob.cfg.flags & R.FLAG_SPLAT_DIRECT else "binned"),
                          "median_rel_se": float(rel.median().item()) if prob.cfg.image_batches > 1 else None,
                          "estimate_total": float(img_mean.double().sum().item())}
     if args.copy_calibration:
@@ -455,12 +481,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = src.numel() * 4
-    if wl.name == "gmm_full_8d" and not args.no_mse_time:
+    if wl.name == "gmm_full_8d" and wl.local != "hmc" and not args.no_mse_time:
         line["mse_time"] = mse_time(wl)
     if wl.name in ("gmm_full_8d", "gmm_iso_2d") and not args.no_mh:
+        # with --hmc both methods use the HMC moves (the paper's HMC and HMC restore)
         line["restore_vs_mh"] = {wl.name: restore_vs_mh(wl)}
         if wl.name == "gmm_full_8d":
-            line["restore_vs_mh"]["gmm_iso_2d"] = restore_vs_mh(gmm_iso_2d())
+            w2 = gmm_iso_2d()
+            line["restore_vs_mh"]["gmm_iso_2d"] = restore_vs_mh(
+                w2.with_(local="hmc", n_leapfrog=args.hmc) if args.hmc else w2)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

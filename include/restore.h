@@ -113,9 +113,19 @@ typedef struct {
     const float *params_dev;
 } restore_mu;
 
-/* ---- local dynamics: the small-step kernel zeta of Alg. 1 ------------- */
+/* ---- local dynamics: the small-step kernel zeta of Alg. 1 -------------
+ * The three diffusion-derived kernels of the paper's study (Sec. 9). */
 #define RESTORE_LOCAL_RWMH   0    /* y = x + step z                              */
 #define RESTORE_LOCAL_MALA   1    /* y = x + (step^2 / 2) grad log p(x) + step z  */
+#define RESTORE_LOCAL_HMC    2    /* Hamiltonian Monte Carlo: momentum rho_0 = z,
+                                     n_leapfrog leapfrog steps of size `step` of
+                                     dq/dt = rho, drho/dt = grad log p(q) (unit
+                                     mass; half momentum steps at both ends),
+                                     accepted with exp(-H(y, rho_n) + H(x, rho_0)),
+                                     H = -log p + |rho|^2 / 2; a trajectory that
+                                     visits a point with p = 0 is rejected.  One
+                                     leapfrog step is the MALA proposal.  Built
+                                     for the mixture targets with uniform mu. */
 
 typedef struct {
     int32_t kind;
@@ -132,7 +142,8 @@ typedef struct {
                                 accepted iff u_acc < p(y) u(x) / (p(x) u(y))
                                 (the kernel K_1 of Theorem B in the
                                 supplement); otherwise the small-step update */
-    int32_t reserved;
+    int32_t n_leapfrog;      /* HMC: leapfrog steps per update, 1..64; 0 for
+                                the other kernels                            */
 } restore_local_kernel;
 
 /* ---- run configuration ------------------------------------------------- */
@@ -172,7 +183,26 @@ typedef struct {
     int32_t image_batches;   /* PIXEL: chains split into this many contiguous
                                 ranges (chain c in batch floor(c B / C)),
                                 each splatting into its own image, for the
-                                per-pixel standard error; 0 or 1 = one image */
+                                per-pixel standard error; 0 or 1 = one image;
+                                with tile_px > 0 the ranges split each
+                                tile's chains instead                         */
+    int32_t tile_px;         /* PIXEL: 0, or 1..64 for tile-stratified restore:
+                                the image is cut into tiles of tile_px x
+                                tile_px pixels (ragged at the right and bottom)
+                                numbered row by row; chain c of C works on tile
+                                floor(c T / C) only, as its own restore problem
+                                (Sec. 6) with target p restricted to the
+                                tile's points (the pixel of (x0, x1) in the
+                                tile) and mu uniform on them (x0 = (px0 + w u0)
+                                / W, x1 = (py0 + h u1) / H in float32), and the
+                                killing constant c_tilde A_t (A_t the tile's
+                                share of the box), so the killing rate stays
+                                c_tilde / p.  The estimates add the tiles'
+                                tour ratios with the factor c_tilde A_t.  Each
+                                workgroup accumulates its tile's splats in
+                                LDS.  Needs the uniform mu, c_tilde > 0 and at
+                                least max(1, image_batches) chains per tile  */
+    int32_t reserved;
 } restore_config;
 
 /* ---- estimates (Sec. 6.3, Sec. 7.4) ----------------------------------- */
@@ -187,7 +217,9 @@ typedef struct {
     int64_t nonfinite;               /* chains whose sums are not finite */
     double censored_time_frac;       /* censored lifetime / total time   */
     double accept_rate, kill_rate;   /* per transition                   */
-    double image_scale;              /* c_tilde / j: multiplies the image sums */
+    double image_scale;              /* c_tilde / j: multiplies the image sums
+                                        (NaN for tile-stratified runs: per
+                                        tile c_tilde A_t / j_t)            */
     int64_t large_steps;             /* MH chain: large-step proposals     */
     int64_t large_accepts;           /* MH chain: accepted large steps     */
 } restore_estimate_out;
@@ -260,7 +292,7 @@ restore_status restore_image_estimate(restore_ctx *ctx, float *mean_dev, float *
 
 /* Device addresses of the chain state arrays, for tests and checkpointing.
  * Layout: x float32 [d][C]; logp, logu float32 [C]; grad float32 [d][C]
- * (MALA only, else NULL); a_cur, t_cur float32 [C]; a_done, t_done float64
+ * (MALA and HMC, else NULL); a_cur, t_cur float32 [C]; a_done, t_done float64
  * [C]; n_done uint32 [C]; status uint32 [C] (bit0 alive, bit1 censored,
  * bit2 last step killed, bit3 last step accepted); last_dt float32 [C]. */
 typedef struct {

@@ -151,7 +151,7 @@ class Problem:
                  integrand_p: bool = True, image: Optional[tuple] = None,
                  step: Optional[float] = None, local: Optional[str] = None, rb_dt: bool = False,
                  large_step_prob: float = 0.0, burn_in: int = 0, n_leapfrog: Optional[int] = None,
-                 tile_px: int = 0, n_chains_total: Optional[int] = None):
+                 tile_px: Optional[int] = None, n_chains_total: Optional[int] = None):
         self.wl = wl
         self.d = wl.d
         self._keep = []
@@ -220,7 +220,8 @@ class Problem:
         cfg.integrand_p = 1 if integrand_p else 0
         cfg.rb_dt = 1 if rb_dt else 0
         cfg.burn_in = int(burn_in)
-        cfg.tile_px = int(tile_px)
+        tile_px = int(getattr(wl, "tile_px", 0) if tile_px is None else tile_px)
+        cfg.tile_px = tile_px
         cfg.n_chains_total = int(wl.n_chains if n_chains_total is None else n_chains_total)
         if tile_px and (mu is not None or not (image if image is not None else wl.image)):
             raise ValueError("tile-stratified runs need the image integrand and the uniform mu")

@@ -77,10 +77,81 @@ struct Chain {
     float out_acc;
     // first pixel of this chain's batch image
     int32_t img_base;
+    // tile-stratified runs: the chain's tile (first pixel column and row,
+    // width and height in pixels)
+    int32_t tpx0, tpy0, tw, th;
 };
 
 __device__ __forceinline__ void flush_splat(const StepArgs &a, int32_t pix, float acc) {
     if (pix >= 0) atomicAdd(a.image + pix, acc);
+}
+
+// image index of a tile-local splat index (row stride tile_px); -1 stays -1
+__device__ __forceinline__ int32_t tile_to_image(const StepArgs &a, int32_t px0, int32_t py0, int32_t base,
+                                                 int32_t local) {
+    if (local < 0) return -1;
+    const int32_t ly = local / a.tile_px;
+    return base + (py0 + ly) * a.image_w + px0 + (local - ly * a.tile_px);
+}
+
+// Tile-stratified runs: chain c of C works on tile t = floor(c T / C) (tiles
+// row by row); the chains of tile t are [ceil(t C / T), ceil((t + 1) C / T)).
+struct TileOf {
+    int32_t px0, py0, w, h;
+    int64_t first, count;   // the tile's chain range
+};
+__device__ __forceinline__ TileOf tile_of_chain(const StepArgs &a, int64_t c) {
+    const int64_t T = a.n_tiles, C = a.n_chains;
+    const int64_t t = c * T / C;
+    TileOf r;
+    r.first = (t * C + T - 1) / T;
+    r.count = ((t + 1) * C + T - 1) / T - r.first;
+    r.px0 = (int32_t)(t % a.tiles_x) * a.tile_px;
+    r.py0 = (int32_t)(t / a.tiles_x) * a.tile_px;
+    r.w = min(a.tile_px, a.image_w - r.px0);
+    r.h = min(a.tile_px, a.image_h - r.py0);
+    return r;
+}
+
+// a chain's tile and the first pixel of its batch image in tile-stratified
+// runs: the batch images split each tile's chains (local index c') into
+// image_batches ranges, c' in floor(c' B / C_t)
+struct TileSlot {
+    int32_t px0, py0, w, h, img_base;
+};
+__device__ __forceinline__ TileSlot tile_slot(const StepArgs &a, int64_t c) {
+    const TileOf t = tile_of_chain(a, c);
+    TileSlot r;
+    r.px0 = t.px0;
+    r.py0 = t.py0;
+    r.w = t.w;
+    r.h = t.h;
+    r.img_base = a.image_batches > 1 ? (int32_t)((c - t.first) * a.image_batches / t.count) * a.image_pixels : 0;
+    return r;
+}
+
+// pixel column and row of (x0, x1) as the splats compute them; false off
+// the box
+__device__ __forceinline__ bool pixel_of(const StepArgs &a, float u0, float u1, int &px, int &py) {
+    if (!(u0 >= 0.0f && u0 <= 1.0f && u1 >= 0.0f && u1 <= 1.0f)) return false;
+    px = min(max((int)(u0 * (float)a.image_w), 0), a.image_w - 1);
+    py = min(max((int)(u1 * (float)a.image_h), 0), a.image_h - 1);
+    return true;
+}
+
+// is y in the tile (px0, py0, w, h)?
+__device__ __forceinline__ bool in_tile(const StepArgs &a, const float *y, int32_t px0, int32_t py0, int32_t w,
+                                        int32_t h) {
+    int px, py;
+    return pixel_of(a, y[0], y[1], px, py) && px >= px0 && px < px0 + w && py >= py0 && py < py0 + h;
+}
+
+// the tile-uniform mu: (x0, x1) = ((px0 + w u0) / W, (py0 + h u1) / H) in
+// float32 (one fused multiply-add and a correctly rounded division each)
+__device__ __forceinline__ void tile_sample(const StepArgs &a, int32_t px0, int32_t py0, int32_t w, int32_t h,
+                                            const float *cand, float *y) {
+    y[0] = __fdiv_rn(fmaf((float)w, cand[0], (float)px0), (float)a.image_w);
+    y[1] = __fdiv_rn(fmaf((float)h, cand[1], (float)py0), (float)a.image_h);
 }
 
 template <int D, int LOC>
@@ -88,7 +159,7 @@ __device__ __forceinline__ void load_chain(const StepArgs &a, uint32_t c, Chain<
     const int64_t C = a.n_chains;
 #pragma unroll
     for (int i = 0; i < D; ++i) ch.x[i] = a.x[i * C + c];
-    if (LOC == LOC_MALA) {
+    if (uses_grad(LOC)) {
 #pragma unroll
         for (int i = 0; i < D; ++i) ch.g[i] = a.grad[i * C + c];
     }
@@ -105,6 +176,16 @@ __device__ __forceinline__ void load_chain(const StepArgs &a, uint32_t c, Chain<
     ch.splat_acc = 0.0f;
     ch.out_pix = -1;
     ch.out_acc = 0.0f;
+    ch.tpx0 = ch.tpy0 = ch.tw = ch.th = 0;
+    if (a.tile_px > 0) {
+        const TileSlot t = tile_slot(a, c);
+        ch.tpx0 = t.px0;
+        ch.tpy0 = t.py0;
+        ch.tw = t.w;
+        ch.th = t.h;
+        ch.img_base = t.img_base;
+        return;
+    }
     // chains are split into image_batches contiguous ranges: c in batch
     // floor(c batches / C)
     ch.img_base = a.image_batches > 1
@@ -117,7 +198,7 @@ __device__ __forceinline__ void store_chain(const StepArgs &a, uint32_t c, const
     const int64_t C = a.n_chains;
 #pragma unroll
     for (int i = 0; i < D; ++i) a.x[i * C + c] = ch.x[i];
-    if (LOC == LOC_MALA) {
+    if (uses_grad(LOC)) {
 #pragma unroll
         for (int i = 0; i < D; ++i) a.grad[i * C + c] = ch.g[i];
     }
@@ -144,7 +225,8 @@ __device__ __forceinline__ void store_chain(const StepArgs &a, uint32_t c, const
 // large-step kernel K_1 of Theorem B in the supplement), otherwise it is the
 // small-step update; dt f(x_{i-1}) goes straight to the float64 chain sums,
 // as the chain has no tours.  ST_LAST_LARGE reports the large-step choice.
-template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT, bool BIN = false, bool MH = false>
+template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT, bool BIN = false, bool MH = false,
+          bool TILED = false>
 __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                                           uint32_t chain, Chain<D, LOC> &ch, bool &kill, bool &accept) {
     constexpr int NB = NBlocks<D>::value;
@@ -192,12 +274,17 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     }
     if (TGT == TGT_PSS && a.image) {
         // f = 1_pixel(x0, x1) at the pre-transition state (p = 0 off the box)
-        const float u0 = ch.x[0], u1 = ch.x[1];
         int32_t pix = -1;
-        if (u0 >= 0.0f && u0 <= 1.0f && u1 >= 0.0f && u1 <= 1.0f) {
-            const int px = min(max((int)(u0 * (float)a.image_w), 0), a.image_w - 1);
-            const int py = min(max((int)(u1 * (float)a.image_h), 0), a.image_h - 1);
-            pix = ch.img_base + py * a.image_w + px;
+        int px, py;
+        if (pixel_of(a, ch.x[0], ch.x[1], px, py)) {
+            if constexpr (TILED) {
+                // the index within the chain's tile (row stride tile_px);
+                // a state outside the tile has p = 0 and dt = 0: no splat
+                const int lx = px - ch.tpx0, ly = py - ch.tpy0;
+                pix = (lx >= 0 && lx < ch.tw && ly >= 0 && ly < ch.th) ? ly * a.tile_px + lx : -1;
+            } else {
+                pix = ch.img_base + py * a.image_w + px;
+            }
         }
         if (BIN) ch.out_pix = -1;
         if (pix != ch.splat_pix) {
@@ -205,7 +292,8 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                 ch.out_pix = ch.splat_pix;
                 ch.out_acc = ch.splat_acc;
             } else {
-                flush_splat(a, ch.splat_pix, ch.splat_acc);
+                flush_splat(a, TILED ? tile_to_image(a, ch.tpx0, ch.tpy0, ch.img_base, ch.splat_pix) : ch.splat_pix,
+                            ch.splat_acc);
             }
             ch.splat_pix = pix;
             ch.splat_acc = 0.0f;
@@ -231,28 +319,59 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     float y[D];
     float zz = 0.0f;
     const float h = 0.5f * a.step * a.step;
+    float rho[D];          // HMC: momentum before the closing half step
+    bool inside = true;    // HMC: every leapfrog point has p > 0
     if (kill || large) {
         sample_mu<D, MU, 4 * NB>(a, head[3], cand, y);
+        if constexpr (TILED) tile_sample(a, ch.tpx0, ch.tpy0, ch.tw, ch.th, cand, y);
     } else {
-        if (LOC == LOC_MALA && !(ch.status & ST_GRAD_VALID)) {
+        if (uses_grad(LOC) && !(ch.status & ST_GRAD_VALID)) {
             (void)log_target<D, TGT, true>(P, a.n_comp, ch.x, ch.g);
             ch.status |= ST_GRAD_VALID;
         }
         float z[D];
         box_muller<D, 4 * NB>(cand, z);
+        if constexpr (LOC == LOC_HMC) {
+            // leapfrog with unit mass from (x, rho_0 = z): half a momentum
+            // step, n position steps separated by full momentum steps; the
+            // closing half step uses grad log p(y) of the final evaluation
+            const float e = a.step;
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            float delta = a.step * z[i];
-            if (LOC == LOC_MALA) {
-                delta = fmaf(h, ch.g[i], delta);
+            for (int i = 0; i < D; ++i) {
                 zz = fmaf(z[i], z[i], zz);
+                rho[i] = fmaf(0.5f * e, ch.g[i], z[i]);
+                y[i] = ch.x[i];
             }
-            y[i] = ch.x[i] + delta;
+            for (int l = 1; l < a.n_leapfrog; ++l) {
+                float gq[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) y[i] = fmaf(e, rho[i], y[i]);
+                const float lq = log_target<D, TGT, true>(P, a.n_comp, y, gq);
+                inside = inside && lq > -INFINITY;
+#pragma unroll
+                for (int i = 0; i < D; ++i) rho[i] = fmaf(e, gq[i], rho[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i) y[i] = fmaf(e, rho[i], y[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                float delta = a.step * z[i];
+                if (LOC == LOC_MALA) {
+                    delta = fmaf(h, ch.g[i], delta);
+                    zz = fmaf(z[i], z[i], zz);
+                }
+                y[i] = ch.x[i] + delta;
+            }
         }
     }
 
     float gy[D];
-    const float lpy = log_target<D, TGT, LOC == LOC_MALA>(P, a.n_comp, y, gy, !kill);
+    float lpy = log_target<D, TGT, uses_grad(LOC)>(P, a.n_comp, y, gy, !kill);
+    if constexpr (TILED) {
+        // the chain's target is p restricted to its tile
+        if (!in_tile(a, y, ch.tpx0, ch.tpy0, ch.tw, ch.th)) lpy = -INFINITY;
+    }
     const float luy = log_mu<D, MU>(a, y);
 
     accept = false;
@@ -274,6 +393,16 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                     rr = fmaf(r, r, rr);
                 }
                 lr += 0.5f * zz - rr / (2.0f * a.step * a.step);
+            } else if (LOC == LOC_HMC) {
+                // H = -log p + |rho|^2 / 2; the leapfrog map is volume-
+                // preserving and reversible, so alpha = exp(-dH)
+                float kk = 0.0f;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const float r = fmaf(0.5f * a.step, gy[i], rho[i]);
+                    kk = fmaf(r, r, kk);
+                }
+                lr = inside ? lr + 0.5f * (zz - kk) : -INFINITY;
             }
             accept = logf(head[2]) < lr;
         }
@@ -281,7 +410,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     if (kill || accept) {
 #pragma unroll
         for (int i = 0; i < D; ++i) ch.x[i] = y[i];
-        if (LOC == LOC_MALA) {
+        if (uses_grad(LOC)) {
             if (accept) {
 #pragma unroll
                 for (int i = 0; i < D; ++i) ch.g[i] = gy[i];

@@ -21,6 +21,8 @@ struct KernelSet {
     const void *step_binned = nullptr;       // image integrand: binned splats
     const void *step_binned_lds = nullptr;
     const void *step_mh = nullptr;           // the MH reference chain M^l (c_tilde = 0)
+    const void *step_tiled = nullptr;        // image integrand, tile-stratified
+    const void *drain_tiled = nullptr;
 };
 
 // Binned splats of one step launch into the image: per-band LDS
@@ -47,12 +49,15 @@ struct ImageEstimateArgs {
     int32_t batches;
     int64_t n_pix;
     double c_tilde;
-    double *tours;           // [batches] scratch: completed tours per batch
+    double *tours;           // [max(1, n_tiles)][batches] scratch: completed tours per batch
     float *mean, *se;        // [n_pix]
+    // tile-stratified runs (n_tiles > 0): tile edge, tiles per row, image size
+    int32_t tile_px, tiles_x, n_tiles, image_w, image_h;
 };
 hipError_t launch_image_estimate(const ImageEstimateArgs &a, hipStream_t stream);
 
 KernelSet find_kernels(int tgt, int d, int loc, int mu);
+KernelSet find_kernels_hmc(int tgt, int d, int mu);   // loc = LOC_HMC
 
 // Float64 reduction of the per-chain tour sums (see reduce_kernels.hip).
 struct ReduceArgs {
@@ -72,5 +77,21 @@ enum ReduceSlot : int {
 };
 
 hipError_t launch_reduce(const ReduceArgs &r, hipStream_t stream);
+
+// Per-tile float64 reduction of tile-stratified runs: for tile t (chains
+// [ceil(t C / T), ceil((t + 1) C / T))), results[t][TR_*].
+enum TileReduceSlot : int {
+    TR_N = 0, TR_T, TR_A, TR_CENS, TR_CENS_T, TR_NONFINITE, TR_SS_TT, TR_SS_AA, TR_SS_TA, TR_CHAINS,
+    TR_SLOTS = 16
+};
+struct TileReduceArgs {
+    const double *a_done, *t_done;
+    const uint32_t *n_done, *status;
+    const float *t_cur;
+    int64_t n_chains;
+    int32_t n_tiles;
+    double *results;    // [n_tiles][TR_SLOTS]
+};
+hipError_t launch_tile_reduce(const TileReduceArgs &r, hipStream_t stream);
 
 }  // namespace restore

@@ -85,4 +85,61 @@ hipError_t launch_reduce(const ReduceArgs &r, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// Tile-stratified runs: one workgroup per tile, the same two passes over
+// the tile's chains (fixed strides and trees: bit-reproducible), giving the
+// tile's sums and the residual sums of squares and products of its two
+// tour ratios T/N and A/N.
+__global__ __launch_bounds__(RED_THREADS) void tile_reduce_kernel(TileReduceArgs r) {
+    __shared__ double sh[6 * RED_THREADS];
+    __shared__ double res[9];
+    const int64_t T = r.n_tiles, t = blockIdx.x;
+    const int64_t lo = (t * r.n_chains + T - 1) / T, hi = ((t + 1) * r.n_chains + T - 1) / T;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t c = lo + threadIdx.x; c < hi; c += RED_THREADS) {
+        if (!(isfinite(r.t_done[c]) && isfinite(r.a_done[c]))) {
+            v[5] += 1.0;
+            continue;
+        }
+        v[0] += (double)r.n_done[c];
+        v[1] += r.t_done[c];
+        v[2] += r.a_done[c];
+        if (r.status[c] & ST_CENSORED) {
+            v[3] += 1.0;
+            v[4] += (double)r.t_cur[c];
+        }
+    }
+    block_sum(sh, v, 6, res);
+    __syncthreads();
+    const double N = res[0], RT = N > 0 ? res[1] / N : 0.0, RA = N > 0 ? res[2] / N : 0.0;
+    double w[3] = {0, 0, 0};
+    for (int64_t c = lo + threadIdx.x; c < hi; c += RED_THREADS) {
+        if (!(isfinite(r.t_done[c]) && isfinite(r.a_done[c]))) continue;
+        const double n = (double)r.n_done[c];
+        const double eT = r.t_done[c] - RT * n, eA = r.a_done[c] - RA * n;
+        w[0] += eT * eT;
+        w[1] += eA * eA;
+        w[2] += eT * eA;
+    }
+    block_sum(sh, w, 3, res + 6);
+    if (threadIdx.x == 0) {
+        double *o = r.results + t * TR_SLOTS;
+        for (int s = 0; s < TR_SLOTS; ++s) o[s] = 0.0;
+        o[TR_N] = res[0];
+        o[TR_T] = res[1];
+        o[TR_A] = res[2];
+        o[TR_CENS] = res[3];
+        o[TR_CENS_T] = res[4];
+        o[TR_NONFINITE] = res[5];
+        o[TR_SS_TT] = res[6];
+        o[TR_SS_AA] = res[7];
+        o[TR_SS_TA] = res[8];
+        o[TR_CHAINS] = (double)(hi - lo);
+    }
+}
+
+hipError_t launch_tile_reduce(const TileReduceArgs &r, hipStream_t stream) {
+    hipLaunchKernelGGL(tile_reduce_kernel, dim3(r.n_tiles), dim3(RED_THREADS), 0, stream, r);
+    return hipGetLastError();
+}
+
 }  // namespace restore

@@ -44,7 +44,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     size_t x, logp, logu, grad, a_cur, t_cur, last_dt, a_done, t_done, n_done, status;
     size_t list0, list1, counts, counters, params, mu, partials, results;
-    size_t bin_pix, bin_val, bin_count, bin_partial, img_tours, total;
+    size_t bin_pix, bin_val, bin_count, bin_partial, img_tours, tile_results, total;
 };
 
 // Binned splats (image integrand): bands of 2^SPLAT_BAND_SHIFT pixels, each
@@ -58,6 +58,9 @@ struct SplatPlan {
     int64_t cap = 0;
     int64_t n_pix = 0;   // pixels of all batch images
     int batches = 0;     // image batches (0: no image)
+    // tile-stratified runs: tiles of tile_px x tile_px pixels, tiles_x per
+    // row, n_tiles in all (0: off)
+    int tile_px = 0, tiles_x = 0, n_tiles = 0;
 };
 
 int image_batches_of(const restore_config *cfg) { return cfg->image_batches > 1 ? cfg->image_batches : 1; }
@@ -66,6 +69,13 @@ SplatPlan splat_plan(const restore_config *cfg, int tgt) {
     SplatPlan sp;
     if (tgt != TGT_PSS || !(cfg->integrands & RESTORE_INTEGRAND_PIXEL)) return sp;
     sp.batches = image_batches_of(cfg);
+    if (cfg->tile_px > 0) {
+        // tile-stratified: splats go to each workgroup's LDS copy of its tile
+        sp.tile_px = cfg->tile_px;
+        sp.tiles_x = (cfg->image_w + cfg->tile_px - 1) / cfg->tile_px;
+        sp.n_tiles = sp.tiles_x * ((cfg->image_h + cfg->tile_px - 1) / cfg->tile_px);
+        return sp;
+    }
     // the MH chain's kernel splats directly
     if ((cfg->flags & RESTORE_FLAG_SPLAT_DIRECT) || cfg->c_tilde == 0.0) return sp;
     const int64_t n_pix = (int64_t)cfg->image_w * cfg->image_h * sp.batches;
@@ -88,7 +98,7 @@ int n_param_floats(int tgt, int d, int K) {
     return comp_stride(tgt, d) * K;
 }
 
-Layout make_layout(int64_t C, int d, bool mala, int n_params, int n_mu_floats, const SplatPlan &sp) {
+Layout make_layout(int64_t C, int d, bool grad, int n_params, int n_mu_floats, const SplatPlan &sp) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
@@ -96,7 +106,7 @@ Layout make_layout(int64_t C, int d, bool mala, int n_params, int n_mu_floats, c
     L.x = take(4 * c * d);
     L.logp = take(4 * c);
     L.logu = take(4 * c);
-    L.grad = mala ? take(4 * c * d) : (size_t)-1;
+    L.grad = grad ? take(4 * c * d) : (size_t)-1;
     L.a_cur = take(4 * c);
     L.t_cur = take(4 * c);
     L.last_dt = take(4 * c);
@@ -117,7 +127,8 @@ Layout make_layout(int64_t C, int d, bool mala, int n_params, int n_mu_floats, c
     L.bin_val = nb ? take(4 * nb * (size_t)sp.cap) : (size_t)-1;
     L.bin_count = nb ? take(4 * (size_t)SPLAT_MAX_BANDS * SPLAT_COUNTER_STRIDE) : (size_t)-1;
     L.bin_partial = nb ? take(4 * (size_t)sp.n_slices * (nb << SPLAT_BAND_SHIFT)) : (size_t)-1;
-    L.img_tours = sp.batches ? take(8 * (size_t)sp.batches) : (size_t)-1;
+    L.img_tours = sp.batches ? take(8 * (size_t)sp.batches * std::max(1, sp.n_tiles)) : (size_t)-1;
+    L.tile_results = sp.n_tiles ? take(8 * (size_t)sp.n_tiles * TR_SLOTS) : (size_t)-1;
     L.total = o;
     return L;
 }
@@ -162,11 +173,13 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
                         RESTORE_MAX_COMP);
         if (!(mu->beta >= 0.0f && mu->beta <= 1.0f)) return fail(RESTORE_E_INVALID_ARG, "mu beta outside [0,1]");
     }
-    if (lk->kind != RESTORE_LOCAL_RWMH && lk->kind != RESTORE_LOCAL_MALA)
+    if (lk->kind != RESTORE_LOCAL_RWMH && lk->kind != RESTORE_LOCAL_MALA && lk->kind != RESTORE_LOCAL_HMC)
         return fail(RESTORE_E_INVALID_ARG, "unknown local kernel %d", lk->kind);
     if (!std::isfinite(lk->step) || lk->step < 0.0f) return fail(RESTORE_E_INVALID_ARG, "step must be >= 0");
-    if (lk->kind == RESTORE_LOCAL_MALA && !(lk->step > 0.0f))
-        return fail(RESTORE_E_INVALID_ARG, "MALA needs step > 0");
+    if (lk->kind != RESTORE_LOCAL_RWMH && !(lk->step > 0.0f))
+        return fail(RESTORE_E_INVALID_ARG, "MALA and HMC need step > 0");
+    if (lk->kind == RESTORE_LOCAL_HMC ? (lk->n_leapfrog < 1 || lk->n_leapfrog > 64) : lk->n_leapfrog != 0)
+        return fail(RESTORE_E_INVALID_ARG, "n_leapfrog must be 1..64 for HMC and 0 otherwise");
     if (!(lk->large_step_prob >= 0.0f && lk->large_step_prob <= 1.0f))
         return fail(RESTORE_E_INVALID_ARG, "large_step_prob outside [0,1]");
     if (cfg->n_chains < 1 || cfg->n_chains > 0x7fffffffLL)
@@ -192,10 +205,22 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
     } else if (cfg->image_batches > 1) {
         return fail(RESTORE_E_INVALID_ARG, "image_batches needs the PIXEL integrand");
     }
+    if (cfg->tile_px != 0) {
+        if (cfg->tile_px < 1 || cfg->tile_px > 64) return fail(RESTORE_E_INVALID_ARG, "tile_px must be in 0..64");
+        if (!(cfg->integrands & RESTORE_INTEGRAND_PIXEL))
+            return fail(RESTORE_E_INVALID_ARG, "tile-stratified runs need the PIXEL integrand");
+        if (mu->kind != RESTORE_MU_UNIFORM_BOX || cfg->c_tilde == 0.0)
+            return fail(RESTORE_E_UNSUPPORTED, "tile-stratified runs are restore runs with the uniform mu");
+        const int64_t T = (int64_t)((cfg->image_w + cfg->tile_px - 1) / cfg->tile_px) *
+                          ((cfg->image_h + cfg->tile_px - 1) / cfg->tile_px);
+        if (cfg->n_chains / T < std::max(1, cfg->image_batches))
+            return fail(RESTORE_E_INVALID_ARG, "every tile needs at least max(1, image_batches) chains (%lld tiles)",
+                        (long long)T);
+    }
     v->tgt = t->kind == RESTORE_TARGET_GMM_ISO ? TGT_ISO : t->kind == RESTORE_TARGET_GMM_FULL ? TGT_FULL : TGT_PSS;
     v->d = d;
     v->K = t->kind == RESTORE_TARGET_PSS ? 0 : K;
-    v->loc = lk->kind == RESTORE_LOCAL_MALA ? LOC_MALA : LOC_RWMH;
+    v->loc = lk->kind == RESTORE_LOCAL_MALA ? LOC_MALA : lk->kind == RESTORE_LOCAL_HMC ? LOC_HMC : LOC_RWMH;
     v->mu = mu->kind == RESTORE_MU_GMM_DIAG ? MU_GMM : MU_UNIFORM;
     return RESTORE_OK;
 }
@@ -361,6 +386,7 @@ struct restore_ctx {
     int32_t steps_taken = 0;
     float step = 0.0f;
     float large_prob = 0.0f;
+    int32_t n_leapfrog = 0;
     float *image = nullptr;
     restore_mu mu{};
     SplatPlan splat{};
@@ -401,6 +427,7 @@ void fill_args(restore_ctx *c) {
     a.log_c = c->cfg.c_tilde > 0.0 ? (float)std::log(c->cfg.c_tilde) : 0.0f;
     a.step = c->step;
     a.large_prob = c->large_prob;
+    a.n_leapfrog = c->n_leapfrog;
     a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
     a.key1 = (uint32_t)(c->cfg.seed >> 32);
     a.target_id = (uint32_t)c->cfg.target_id;
@@ -412,6 +439,9 @@ void fill_args(restore_ctx *c) {
     a.image_h = c->cfg.image_h;
     a.image_batches = image_batches_of(&c->cfg);
     a.image_pixels = c->cfg.image_w * c->cfg.image_h;
+    a.tile_px = c->splat.tile_px;
+    a.tiles_x = c->splat.tiles_x;
+    a.n_tiles = c->splat.n_tiles;
     a.rec_x = nullptr;
     a.rec_w = nullptr;
     a.rec_chains = 0;
@@ -464,7 +494,7 @@ restore_status restore_state_bytes(const restore_target *target, const restore_m
     Validated v;
     restore_status st = validate(target, mu, local, cfg, &v);
     if (st != RESTORE_OK) return st;
-    *bytes_out = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_param_floats(v.tgt, v.d, v.K),
+    *bytes_out = make_layout(cfg->n_chains, v.d, uses_grad(v.loc), n_param_floats(v.tgt, v.d, v.K),
                              v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0, splat_plan(cfg, v.tgt)).total;
     return RESTORE_OK;
 }
@@ -485,7 +515,7 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     const int n_params = n_param_floats(v.tgt, v.d, v.K);
     const int n_mu = v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0;
     const SplatPlan sp = splat_plan(cfg, v.tgt);
-    const Layout lay = make_layout(cfg->n_chains, v.d, v.loc == LOC_MALA, n_params, n_mu, sp);
+    const Layout lay = make_layout(cfg->n_chains, v.d, uses_grad(v.loc), n_params, n_mu, sp);
     if (state_bytes < lay.total)
         return fail(RESTORE_E_BUFFER_TOO_SMALL, "state buffer holds %zu bytes, %zu needed", state_bytes, lay.total);
     KernelSet ks = find_kernels(v.tgt, v.d, v.loc, v.mu);
@@ -508,6 +538,7 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     c->step = local->step;
     c->mh = cfg->c_tilde == 0.0;
     c->large_prob = local->large_step_prob;
+    c->n_leapfrog = local->n_leapfrog;
     c->image = (cfg->integrands & RESTORE_INTEGRAND_PIXEL) ? image_dev : nullptr;
     c->mu = *mu;
     c->splat = sp;
@@ -571,6 +602,12 @@ static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_recor
         // the MH chain: parameters through the scalar cache, direct splats
         hipError_t e = hipLaunchKernel(c->ks.step_mh, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, 0, s);
         if (e != hipSuccess) return hip_fail(e, "MH step launch");
+    } else if (c->splat.n_tiles) {
+        // tile-stratified: an LDS copy of the workgroup's tile takes the splats
+        const size_t tile_shm = (size_t)c->splat.tile_px * c->splat.tile_px * sizeof(float);
+        hipError_t e = hipLaunchKernel(c->ks.step_tiled, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs,
+                                       tile_shm, s);
+        if (e != hipSuccess) return hip_fail(e, "tiled step launch");
     } else if (!c->splat.n_bins) {
         const void *fn = c->lds ? c->ks.step_lds : c->ks.step;
         hipError_t e = hipLaunchKernel(fn, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, shm, s);
@@ -628,8 +665,9 @@ restore_status restore_drain(restore_ctx *c, void *stream) {
     uint32_t *counts = at<uint32_t>(c, c->lay.counts);
     uint32_t *lists[2] = {at<uint32_t>(c, c->lay.list0), at<uint32_t>(c, c->lay.list1)};
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, counts, 4);
-    const void *fn = c->lds ? c->ks.drain_lds : c->ks.drain;
-    const size_t shm = c->lds ? (size_t)c->n_params * sizeof(float) : 0;
+    const bool tiled = c->splat.n_tiles > 0;
+    const void *fn = tiled ? c->ks.drain_tiled : c->lds ? c->ks.drain_lds : c->ks.drain;
+    const size_t shm = (c->lds && !tiled) ? (size_t)c->n_params * sizeof(float) : 0;
     int32_t remaining = c->cfg.drain_cap;
     int32_t chunk = 1;
     uint32_t s0 = (uint32_t)c->steps_taken;
@@ -657,9 +695,95 @@ restore_status restore_drain(restore_ctx *c, void *stream) {
     return RESTORE_OK;
 }
 
+// Run counters summed over their spread copies (synchronises the stream).
+static restore_status read_counters(restore_ctx *c, hipStream_t s, unsigned long long cnt[CNT_SLOTS]) {
+    std::vector<unsigned long long> lines((size_t)CNT_SPREAD * CNT_LINE);
+    hipError_t e = hipMemcpyAsync(lines.data(), c->args.counters, lines.size() * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "counter readback");
+    for (int j = 0; j < CNT_SLOTS; ++j) cnt[j] = 0;
+    for (int l = 0; l < CNT_SPREAD; ++l)
+        for (int j = 0; j < CNT_SLOTS; ++j) cnt[j] += lines[(size_t)l * CNT_LINE + j];
+    return RESTORE_OK;
+}
+
+// Stratified estimates of a tile-stratified run: tile t is a restore problem
+// with constant c_tilde A_t (A_t its share of the box), so p_lambda =
+// sum_t c_tilde A_t T_t / N_t and lambda(p f) = sum_t c_tilde A_t A_t' / N_t
+// (Sec. 6.3 per tile); pi f is their ratio.  Standard errors: per tile the
+// delta-method variances and covariance of the two tour ratios over the
+// tile's chains, tiles independent, and the delta method for pi f.
+static restore_status estimate_tiles(restore_ctx *c, restore_estimate_out *out, hipStream_t s) {
+    const SplatPlan &sp = c->splat;
+    TileReduceArgs r;
+    r.a_done = c->args.a_done;
+    r.t_done = c->args.t_done;
+    r.n_done = c->args.n_done;
+    r.status = c->args.status;
+    r.t_cur = c->args.t_cur;
+    r.n_chains = c->cfg.n_chains;
+    r.n_tiles = sp.n_tiles;
+    r.results = at<double>(c, c->lay.tile_results);
+    hipError_t e = launch_tile_reduce(r, s);
+    if (e != hipSuccess) return hip_fail(e, "tile reduce launch");
+    std::vector<double> res((size_t)sp.n_tiles * TR_SLOTS);
+    e = hipMemcpyAsync(res.data(), r.results, res.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "tile estimate readback");
+    unsigned long long cnt[CNT_SLOTS];
+    restore_status st = read_counters(c, s, cnt);
+    if (st != RESTORE_OK) return st;
+    const double ct = c->cfg.c_tilde, W = c->cfg.image_w, H = c->cfg.image_h;
+    double P = 0, L = 0, vP = 0, vL = 0, cPL = 0, N = 0, T = 0, cens = 0, cens_t = 0, nonfin = 0;
+    bool ok = true;
+    for (int t = 0; t < sp.n_tiles; ++t) {
+        const double *o = res.data() + (size_t)t * TR_SLOTS;
+        const int tx = t % sp.tiles_x, ty = t / sp.tiles_x;
+        const double w = std::min<double>(sp.tile_px, W - tx * sp.tile_px);
+        const double h = std::min<double>(sp.tile_px, H - ty * sp.tile_px);
+        const double st_ = ct * w * h / (W * H);
+        const double n_ok = o[TR_CHAINS] - o[TR_NONFINITE];
+        N += o[TR_N];
+        T += o[TR_T];
+        cens += o[TR_CENS];
+        cens_t += o[TR_CENS_T];
+        nonfin += o[TR_NONFINITE];
+        if (!(o[TR_N] > 0) || n_ok < 2) {
+            ok = false;
+            continue;
+        }
+        P += st_ * o[TR_T] / o[TR_N];
+        L += st_ * o[TR_A] / o[TR_N];
+        const double den = (n_ok - 1) * n_ok * (o[TR_N] / n_ok) * (o[TR_N] / n_ok);
+        vP += st_ * st_ * o[TR_SS_TT] / den;
+        vL += st_ * st_ * o[TR_SS_AA] / den;
+        cPL += st_ * st_ * o[TR_SS_TA] / den;
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->p_lambda = ok ? P : NAN;
+    out->p_lambda_se = ok ? std::sqrt(vP) : NAN;
+    out->lam_pf = ok ? L : NAN;
+    out->lam_pf_se = ok ? std::sqrt(vL) : NAN;
+    const double pi = L / P;
+    out->pi_f = ok ? pi : NAN;
+    out->pi_f_se = ok ? std::sqrt(std::max(0.0, (vL - 2 * pi * cPL + pi * pi * vP) / (P * P))) : NAN;
+    out->tours_done = (int64_t)N;
+    out->tours_censored = (int64_t)cens;
+    out->transitions = (int64_t)cnt[CNT_TRANSITIONS];
+    out->accepts = (int64_t)cnt[CNT_ACCEPTS];
+    out->kills = (int64_t)cnt[CNT_KILLS];
+    out->nonfinite = (int64_t)nonfin;
+    out->censored_time_frac = T + cens_t > 0 ? cens_t / (T + cens_t) : 0.0;
+    out->accept_rate = cnt[CNT_TRANSITIONS] ? (double)cnt[CNT_ACCEPTS] / (double)cnt[CNT_TRANSITIONS] : 0.0;
+    out->kill_rate = cnt[CNT_TRANSITIONS] ? (double)cnt[CNT_KILLS] / (double)cnt[CNT_TRANSITIONS] : 0.0;
+    out->image_scale = NAN;   // per tile: c_tilde A_t / j_t (restore_image_estimate applies it)
+    return RESTORE_OK;
+}
+
 restore_status restore_estimate(restore_ctx *c, restore_estimate_out *out, void *stream) {
     if (!c || !out) return fail(RESTORE_E_INVALID_ARG, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (c->splat.n_tiles) return estimate_tiles(c, out, s);
     ReduceArgs r;
     r.a_done = c->args.a_done;
     r.t_done = c->args.t_done;
@@ -750,6 +874,11 @@ restore_status restore_image_estimate(restore_ctx *c, float *mean_dev, float *se
     a.n_pix = (int64_t)c->cfg.image_w * c->cfg.image_h;
     a.c_tilde = c->cfg.c_tilde;
     a.tours = at<double>(c, c->lay.img_tours);
+    a.tile_px = c->splat.tile_px;
+    a.tiles_x = c->splat.tiles_x;
+    a.n_tiles = c->splat.n_tiles;
+    a.image_w = c->cfg.image_w;
+    a.image_h = c->cfg.image_h;
     a.mean = mean_dev;
     a.se = se_dev;
     hipError_t e = launch_image_estimate(a, static_cast<hipStream_t>(stream));

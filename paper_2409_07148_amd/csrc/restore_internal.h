@@ -6,7 +6,9 @@
 namespace restore {
 
 enum TargetKind : int { TGT_ISO = 0, TGT_FULL = 1, TGT_PSS = 2 };
-enum LocalKind : int { LOC_RWMH = 0, LOC_MALA = 1 };
+enum LocalKind : int { LOC_RWMH = 0, LOC_MALA = 1, LOC_HMC = 2 };
+// the local kernels that use grad log p (cached per chain in the state)
+__host__ __device__ constexpr bool uses_grad(int loc) { return loc == LOC_MALA || loc == LOC_HMC; }
 enum MuKind : int { MU_UNIFORM = 0, MU_GMM = 1 };
 enum Purpose : uint32_t { PURPOSE_INIT = 0, PURPOSE_STEP = 1, PURPOSE_LARGE = 2 };
 
@@ -82,6 +84,7 @@ struct StepArgs {
     float log_c;       // ln c_tilde
     int32_t no_kill;   // c_tilde == 0
     float step;        // sigma or epsilon
+    int32_t n_leapfrog;  // HMC: leapfrog steps per update
     float large_prob;  // MH chain: large-step probability l
     uint32_t key0, key1;
     uint32_t target_id;
@@ -92,6 +95,9 @@ struct StepArgs {
     int32_t image_w, image_h;
     int32_t image_batches;  // chains split into contiguous ranges, one image each (>= 1)
     int32_t image_pixels;   // image_w * image_h
+    int32_t tile_px;        // tile-stratified runs: tile edge in pixels (0: off)
+    int32_t tiles_x;        // tiles per image row
+    int32_t n_tiles;        // tiles in the image
     // sample recording (restore_step_record): (x_{i-1}, dt_i) of chains < rec_chains
     float *rec_x;      // [n_steps][rec_chains][D]
     float *rec_w;      // [n_steps][rec_chains]

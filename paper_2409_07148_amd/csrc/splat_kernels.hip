@@ -71,13 +71,17 @@ hipError_t launch_splat_accumulate(const SplatArgs &s, hipStream_t stream) {
 // Completed tours of each image batch, in a fixed order: block b sums
 // n_done over the chains c with floor(c batches / C) = b, i.e. c in
 // [ceil(b C / batches), ceil((b + 1) C / batches)), skipping chains whose
-// sums are not finite (as the run estimate does).
+// sums are not finite (as the run estimate does).  In tile-stratified runs
+// block (b, t) does the same within tile t's chain range, whose batches
+// split the tile's chains.
 constexpr int IMG_THREADS = 256;
 __global__ __launch_bounds__(IMG_THREADS) void image_batch_tours_kernel(ImageEstimateArgs a) {
     __shared__ double sh[IMG_THREADS];
     const int b = blockIdx.x, t = threadIdx.x;
-    const int64_t B = a.batches, C = a.n_chains;
-    const int64_t lo = ((int64_t)b * C + B - 1) / B, hi = ((int64_t)(b + 1) * C + B - 1) / B;
+    const int64_t B = a.batches, T = a.n_tiles > 0 ? a.n_tiles : 1, tile = blockIdx.y;
+    const int64_t first = (tile * a.n_chains + T - 1) / T;
+    const int64_t C = (tile + 1 == T ? a.n_chains : ((tile + 1) * a.n_chains + T - 1) / T) - first;
+    const int64_t lo = first + ((int64_t)b * C + B - 1) / B, hi = first + ((int64_t)(b + 1) * C + B - 1) / B;
     double v = 0.0;
     for (int64_t c = lo + t; c < hi; c += IMG_THREADS)
         if (isfinite(a.t_done[c]) && isfinite(a.a_done[c])) v += (double)a.n_done[c];
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(IMG_THREADS) void image_batch_tours_kernel(ImageEst
         if (t < w) sh[t] += sh[t + w];
         __syncthreads();
     }
-    if (t == 0) a.tours[b] = sh[0];
+    if (t == 0) a.tours[tile * B + b] = sh[0];
 }
 
 // Per pixel j, with S_b the batch images and N_b the batches' tours: the
@@ -95,28 +99,40 @@ __global__ __launch_bounds__(IMG_THREADS) void image_batch_tours_kernel(ImageEst
 // whole run) and its delta-method standard error over batches,
 //   c_tilde sqrt(sum_b (S_b - R N_b)^2 / ((B - 1) B)) / mean N_b,
 // the chain-level formula of the run estimate with batches as units
-// (NaN for a single batch).
+// (NaN for a single batch).  In tile-stratified runs the pixel's tile t
+// supplies the tours N_b of its batches and the factor c_tilde A_t (A_t the
+// tile's share of the box) in place of c_tilde.
 __global__ __launch_bounds__(256) void image_estimate_kernel(ImageEstimateArgs a) {
     const int64_t px = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (px >= a.n_pix) return;
     const int B = a.batches;
+    const double *tours = a.tours;
+    double scale = a.c_tilde;
+    if (a.n_tiles > 0) {
+        const int x = (int)(px % a.image_w), y = (int)(px / a.image_w);
+        const int tx = x / a.tile_px, ty = y / a.tile_px;
+        tours += (int64_t)(ty * a.tiles_x + tx) * B;
+        const int w = min(a.tile_px, a.image_w - tx * a.tile_px), h = min(a.tile_px, a.image_h - ty * a.tile_px);
+        scale *= (double)w * h / ((double)a.image_w * a.image_h);
+    }
     double sS = 0.0, sN = 0.0;
     for (int b = 0; b < B; ++b) {
         sS += (double)a.image[(int64_t)b * a.n_pix + px];
-        sN += a.tours[b];
+        sN += tours[b];
     }
     const double R = sN > 0.0 ? sS / sN : 0.0;
     double ss = 0.0;
     for (int b = 0; b < B; ++b) {
-        const double e = (double)a.image[(int64_t)b * a.n_pix + px] - R * a.tours[b];
+        const double e = (double)a.image[(int64_t)b * a.n_pix + px] - R * tours[b];
         ss += e * e;
     }
-    a.mean[px] = (float)(a.c_tilde * R);
-    a.se[px] = B > 1 && sN > 0.0 ? (float)(a.c_tilde * sqrt(ss / ((double)(B - 1) * B)) / (sN / B)) : NAN;
+    a.mean[px] = (float)(scale * R);
+    a.se[px] = B > 1 && sN > 0.0 ? (float)(scale * sqrt(ss / ((double)(B - 1) * B)) / (sN / B)) : NAN;
 }
 
 hipError_t launch_image_estimate(const ImageEstimateArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL(image_batch_tours_kernel, dim3(a.batches), dim3(IMG_THREADS), 0, stream, a);
+    hipLaunchKernelGGL(image_batch_tours_kernel, dim3(a.batches, a.n_tiles > 0 ? a.n_tiles : 1), dim3(IMG_THREADS), 0,
+                       stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(image_estimate_kernel, dim3((unsigned)((a.n_pix + 255) / 256)), dim3(256), 0, stream, a);

@@ -1,0 +1,369 @@
+// gfx950 kernels of the Jump Restore chain population.
+//
+// One chain per lane.  A launch loads the chain's state into registers once,
+// runs n_steps steps of Alg. 2 entirely in registers and stores the state
+// once, so the only HBM traffic per launch is the state itself (the
+// parameters are a few KiB read through the scalar cache or LDS).
+//
+// Every step of Alg. 2 (Jump Restore):
+//   t1 ~ Exp(1) (holding time), t2 ~ Exp(k(x)) with k = c_tilde u / p
+//   (Sec. 6.2, eq. (killing-rate-simplified)); dt = min(t1, t2);
+//   the time integral gains dt f(x_{i-1}) (Sec. 7.4, eq. (approx));
+//   t1 < t2: one MH update (Alg. 1) with the small-step kernel;
+//   otherwise: the tour ends and x is regenerated from mu.
+// Both branches cost one proposal and one density evaluation, so lanes of a
+// wave do the same work whichever clock fired.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "chain_step.h"
+#include "launch.h"
+
+namespace restore {
+
+// Steps with regeneration for every chain.  With MH: steps of the
+// Metropolis-Hastings reference chain M^l (no killing, large steps from mu
+// with probability l; see step_once).
+template <int D, int TGT, int LOC, int MU, bool LDS, bool MH = false>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_floats) {
+    extern __shared__ float smem[];
+    const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_chains) return;
+    Chain<D, LOC> ch;
+    load_chain(a, (uint32_t)c, ch);
+    unsigned long long n_acc = 0, n_kill = 0, n_large = 0, n_large_acc = 0;
+    bool kill = false, accept = false;
+    const bool rec = a.rec_x != nullptr && c < a.rec_chains;
+    for (int it = 0; it < a.n_steps; ++it) {
+        if (rec) {
+            float *xo = a.rec_x + ((int64_t)it * a.rec_chains + c) * D;
+#pragma unroll
+            for (int i = 0; i < D; ++i) xo[i] = ch.x[i];
+        }
+        step_once<D, TGT, LOC, MU, false, decltype(P), false, MH>(a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch,
+                                                                 kill, accept);
+        if (rec) a.rec_w[(int64_t)it * a.rec_chains + c] = ch.last_dt;
+        n_acc += __popcll(__ballot(accept));
+        n_kill += __popcll(__ballot(kill));
+        if constexpr (MH) {
+            const bool large = (ch.status & ST_LAST_LARGE) != 0u;
+            n_large += __popcll(__ballot(large));
+            n_large_acc += __popcll(__ballot(large && accept));
+        }
+    }
+    ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT)) | (kill ? ST_LAST_KILL : 0u) |
+                (accept ? ST_LAST_ACCEPT : 0u);
+    if (TGT == TGT_PSS && a.image) flush_splat(a, ch.splat_pix, ch.splat_acc);
+    store_chain(a, (uint32_t)c, ch);
+    const unsigned long long lanes = __popcll(__ballot(1));
+    add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill, n_large, n_large_acc);
+}
+
+// Binning of the records staged in LDS: rows [0, rows) of this thread's
+// column.  Counts per band (LDS atomics), one global reservation per band
+// and workgroup, then each record goes to its band's bucket at the reserved
+// base plus its rank (or straight to the image if the bucket is full).
+// Every thread of the workgroup calls it the same number of times.
+__device__ __forceinline__ void splat_flush(const StepArgs &a, uint32_t (*rp)[256], float (*rv)[256], uint32_t *cnt,
+                                            uint32_t *base, int rows) {
+    const int t = threadIdx.x;
+    __syncthreads();
+    for (int r = 0; r < rows; ++r) {
+        const uint32_t p = rp[r][t];
+        if (p != SPLAT_NO_PIX) atomicAdd(&cnt[p >> SPLAT_BAND_SHIFT], 1u);
+    }
+    __syncthreads();
+    for (int b = t; b < a.n_bins; b += blockDim.x) {
+        const uint32_t k = cnt[b];
+        base[b] = k ? atomicAdd(a.bin_count + b * SPLAT_COUNTER_STRIDE, k) : 0u;
+        cnt[b] = 0u;
+    }
+    __syncthreads();
+    for (int r = 0; r < rows; ++r) {
+        const uint32_t p = rp[r][t];
+        if (p != SPLAT_NO_PIX) {
+            const uint32_t b = p >> SPLAT_BAND_SHIFT;
+            const uint32_t pos = base[b] + atomicAdd(&cnt[b], 1u);
+            const float v = rv[r][t];
+            if (pos < (uint32_t)a.bin_cap) {
+                const size_t o = (size_t)b * (size_t)a.bin_cap + pos;
+                a.bin_pix[o] = p;
+                a.bin_val[o] = v;
+            } else {
+                atomicAdd(a.image + p, v);
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = t; b < a.n_bins; b += blockDim.x) cnt[b] = 0u;
+}
+
+// Steps with regeneration for the image integrand, with binned splats.
+// Every lane stages the record (pixel, dt) its step closed, if any, in its
+// LDS column; every SPLAT_ROWS steps, and once more at the end with the
+// splat still open, the workgroup bins its records (splat_flush).  Lanes
+// past the last chain take part in the barriers only.
+template <int D, int TGT, int LOC, int MU, bool LDS>
+__global__ __launch_bounds__(256) void step_binned_kernel(StepArgs a, int n_param_floats) {
+    extern __shared__ float smem[];
+    __shared__ uint32_t rec_pix[SPLAT_ROWS + 1][256];
+    __shared__ float rec_val[SPLAT_ROWS + 1][256];
+    __shared__ uint32_t cnt[SPLAT_MAX_BANDS], base[SPLAT_MAX_BANDS];
+    const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
+    const int t = threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + t;
+    const bool active = c < a.n_chains;
+    for (int b = t; b < SPLAT_MAX_BANDS; b += blockDim.x) cnt[b] = 0u;
+    Chain<D, LOC> ch;
+    if (active) load_chain(a, (uint32_t)c, ch);
+    unsigned long long n_acc = 0, n_kill = 0;
+    bool kill = false, accept = false;
+    const bool rec = active && a.rec_x != nullptr && c < a.rec_chains;
+    int row = 0;
+    for (int it = 0; it < a.n_steps; ++it) {
+        uint32_t rp = SPLAT_NO_PIX;
+        float rv = 0.0f;
+        if (active) {
+            if (rec) {
+                float *xo = a.rec_x + ((int64_t)it * a.rec_chains + c) * D;
+#pragma unroll
+                for (int i = 0; i < D; ++i) xo[i] = ch.x[i];
+            }
+            step_once<D, TGT, LOC, MU, false, decltype(P), true>(a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch,
+                                                                 kill, accept);
+            if (rec) a.rec_w[(int64_t)it * a.rec_chains + c] = ch.last_dt;
+            if (ch.out_pix >= 0) {
+                rp = (uint32_t)ch.out_pix;
+                rv = ch.out_acc;
+            }
+        }
+        rec_pix[row][t] = rp;
+        rec_val[row][t] = rv;
+        n_acc += __popcll(__ballot(accept));
+        n_kill += __popcll(__ballot(kill));
+        if (++row == SPLAT_ROWS) {
+            splat_flush(a, rec_pix, rec_val, cnt, base, SPLAT_ROWS);
+            row = 0;
+        }
+    }
+    // the splat still open at the end of the launch
+    rec_pix[row][t] = (active && ch.splat_pix >= 0) ? (uint32_t)ch.splat_pix : SPLAT_NO_PIX;
+    rec_val[row][t] = active ? ch.splat_acc : 0.0f;
+    splat_flush(a, rec_pix, rec_val, cnt, base, row + 1);
+    if (active) {
+        ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT)) | (kill ? ST_LAST_KILL : 0u) |
+                    (accept ? ST_LAST_ACCEPT : 0u);
+        store_chain(a, (uint32_t)c, ch);
+    }
+    const unsigned long long lanes = __popcll(__ballot(active));
+    if (lanes) add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill);
+}
+
+// Steps with regeneration of tile-stratified runs (the image integrand):
+// chain c works on its own tile (p restricted to the tile, mu uniform on
+// it).  The workgroup accumulates the splats of its lanes that share the
+// (tile, batch image) of its first chain in an LDS copy of that tile (LDS
+// float atomics), and adds the copy to the image at the end of the launch;
+// other lanes (a workgroup that straddles two tiles or batches) add their
+// splats to the image directly.  Lanes past the last chain take part in
+// the barriers only.
+template <int D, int TGT, int LOC, int MU>
+__global__ __launch_bounds__(256) void step_tiled_kernel(StepArgs a, int n_param_floats) {
+    extern __shared__ float acc[];   // [tile_px * tile_px]
+    (void)n_param_floats;
+    const auto P = (const_fptr)a.params;
+    const int t = threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + t;
+    const bool active = c < a.n_chains;
+    const int n_acc_px = a.tile_px * a.tile_px;
+    for (int i = t; i < n_acc_px; i += blockDim.x) acc[i] = 0.0f;
+    // the workgroup's tile and batch image: those of its first chain
+    const TileSlot first = tile_slot(a, (int64_t)blockIdx.x * blockDim.x);
+    __syncthreads();
+    Chain<D, LOC> ch;
+    unsigned long long n_acc = 0, n_kill = 0;
+    bool kill = false, accept = false;
+    if (active) {
+        load_chain(a, (uint32_t)c, ch);
+        const bool mine = ch.tpx0 == first.px0 && ch.tpy0 == first.py0 && ch.img_base == first.img_base;
+        for (int it = 0; it < a.n_steps; ++it) {
+            step_once<D, TGT, LOC, MU, false, const_fptr, true, false, true>(a, P, a.s0 + (uint32_t)it,
+                                                                            (uint32_t)c, ch, kill, accept);
+            if (ch.out_pix >= 0) {
+                if (mine) atomicAdd(acc + ch.out_pix, ch.out_acc);
+                else atomicAdd(a.image + tile_to_image(a, ch.tpx0, ch.tpy0, ch.img_base, ch.out_pix), ch.out_acc);
+            }
+            n_acc += __popcll(__ballot(accept));
+            n_kill += __popcll(__ballot(kill));
+        }
+        // the splat still open at the end of the launch
+        if (ch.splat_pix >= 0) {
+            if (mine) atomicAdd(acc + ch.splat_pix, ch.splat_acc);
+            else atomicAdd(a.image + tile_to_image(a, ch.tpx0, ch.tpy0, ch.img_base, ch.splat_pix), ch.splat_acc);
+        }
+        ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT)) | (kill ? ST_LAST_KILL : 0u) |
+                    (accept ? ST_LAST_ACCEPT : 0u);
+        store_chain(a, (uint32_t)c, ch);
+    }
+    const unsigned long long lanes = __popcll(__ballot(active));
+    if (lanes) add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill);
+    __syncthreads();
+    // the tile copy into the image (zero entries skipped)
+    for (int i = t; i < n_acc_px; i += blockDim.x) {
+        const float v = acc[i];
+        const int ly = i / a.tile_px, lx = i - ly * a.tile_px;
+        if (v != 0.0f && lx < first.w && ly < first.h)
+            atomicAdd(a.image + first.img_base + (first.py0 + ly) * a.image_w + first.px0 + lx, v);
+    }
+}
+
+// Drain: the chains of the input list run on without regeneration until
+// their tour in flight is killed.  Survivors of this chunk are compacted
+// into the output list with one ballot and one atomic per wave; on the last
+// chunk they are marked censored instead.
+template <int D, int TGT, int LOC, int MU, bool LDS, bool TILED = false>
+__global__ __launch_bounds__(256) void drain_kernel(StepArgs a, int n_param_floats, uint32_t *list_out,
+                                                     uint32_t *count_out, uint32_t *count_zero,
+                                                     int last_chunk) {
+    extern __shared__ float smem[];
+    const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_zero = 0u;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n_in = a.list ? (int64_t)*a.list_count : a.n_chains;
+    if (idx >= n_in) return;
+    const uint32_t c = a.list ? a.list[idx] : (uint32_t)idx;
+    Chain<D, LOC> ch;
+    load_chain(a, c, ch);
+    bool alive = (ch.status & ST_ALIVE) != 0u;
+    unsigned long long n_t = 0, n_acc = 0, n_kill = 0;
+    bool stepped = false, kill_last = false, acc_last = false;
+    for (int it = 0; it < a.n_steps; ++it) {
+        const unsigned long long live = __ballot(alive);
+        if (live == 0ull) break;
+        n_t += __popcll(live);
+        bool kill = false, accept = false;
+        if (alive) {
+            step_once<D, TGT, LOC, MU, true, decltype(P), false, false, TILED>(a, P, a.s0 + (uint32_t)it, c, ch,
+                                                                               kill, accept);
+            stepped = true;
+            kill_last = kill;
+            acc_last = accept;
+            alive = !kill;
+        }
+        n_acc += __popcll(__ballot(accept));
+        n_kill += __popcll(__ballot(kill));
+    }
+    if (stepped) {
+        ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT | ST_ALIVE)) | (alive ? ST_ALIVE : 0u) |
+                    (kill_last ? ST_LAST_KILL : 0u) | (acc_last ? ST_LAST_ACCEPT : 0u);
+    }
+    if (alive && last_chunk) ch.status |= ST_CENSORED;
+    if (TGT == TGT_PSS && a.image)
+        flush_splat(a, TILED ? tile_to_image(a, ch.tpx0, ch.tpy0, ch.img_base, ch.splat_pix) : ch.splat_pix,
+                    ch.splat_acc);
+    store_chain(a, c, ch);
+    add_counters(a.counters, n_t, n_acc, n_kill);
+    if (!last_chunk) {
+        const unsigned long long keep = __ballot(alive);
+        if (keep) {
+            const int leader = __ffsll((long long)keep) - 1;
+            uint32_t base = 0;
+            if (lane_id() == leader) base = atomicAdd(count_out, (uint32_t)__popcll(keep));
+            base = __shfl(base, leader);
+            if (alive) {
+                const uint32_t below = (uint32_t)__popcll(keep & ((1ull << lane_id()) - 1ull));
+                list_out[base + below] = c;
+            }
+        }
+    }
+}
+
+// x_0 ~ mu (purpose INIT, step 0), cached log p / log u / grad, zero sums.
+template <int D, int TGT, int LOC, int MU>
+__global__ __launch_bounds__(256) void init_kernel(StepArgs a) {
+    constexpr int NB = NBlocks<D>::value;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_chains) return;
+    float head[4], cand[4 * NB];
+    draw_step<NB>(0u, (uint32_t)c, a.target_id, PURPOSE_INIT, a.key0, a.key1, head, cand);
+    Chain<D, LOC> ch;
+    sample_mu<D, MU, 4 * NB>(a, head[3], cand, ch.x);
+    TileOf tile{};
+    if (TGT == TGT_PSS && a.tile_px > 0) {
+        // tile-stratified: x_0 from the uniform mu of the chain's tile
+        tile = tile_of_chain(a, c);
+        tile_sample(a, tile.px0, tile.py0, tile.w, tile.h, cand, ch.x);
+    }
+    ch.lp = log_target<D, TGT, uses_grad(LOC)>((const_fptr)a.params, a.n_comp, ch.x, ch.g);
+    if (TGT == TGT_PSS && a.tile_px > 0 && !in_tile(a, ch.x, tile.px0, tile.py0, tile.w, tile.h))
+        ch.lp = -INFINITY;
+    ch.lu = log_mu<D, MU>(a, ch.x);
+    ch.a_cur = ch.t_cur = 0.0f;
+    ch.a_done = ch.t_done = 0.0;
+    ch.n_done = 0u;
+    ch.status = ST_ALIVE | (uses_grad(LOC) ? ST_GRAD_VALID : 0u);
+    ch.last_dt = 0.0f;
+    store_chain(a, (uint32_t)c, ch);
+}
+
+// Recompute the cached log p, log u and grad log p from x.
+template <int D, int TGT, int LOC, int MU>
+__global__ __launch_bounds__(256) void refresh_kernel(StepArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_chains) return;
+    const int64_t C = a.n_chains;
+    float x[D], g[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) x[i] = a.x[i * C + c];
+    float lp = log_target<D, TGT, uses_grad(LOC)>((const_fptr)a.params, a.n_comp, x, g);
+    if (TGT == TGT_PSS && a.tile_px > 0) {
+        const TileOf t = tile_of_chain(a, c);
+        if (!in_tile(a, x, t.px0, t.py0, t.w, t.h)) lp = -INFINITY;
+    }
+    a.logp[c] = lp;
+    a.logu[c] = log_mu<D, MU>(a, x);
+    if (uses_grad(LOC)) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) a.grad[i * C + c] = g[i];
+        a.status[c] |= ST_GRAD_VALID;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch table
+// ---------------------------------------------------------------------------
+
+template <int D, int TGT, int LOC, int MU>
+static KernelSet make_set() {
+    KernelSet k;
+    k.init = (const void *)init_kernel<D, TGT, LOC, MU>;
+    k.refresh = (const void *)refresh_kernel<D, TGT, LOC, MU>;
+    k.step = (const void *)step_kernel<D, TGT, LOC, MU, false>;
+    k.step_lds = (const void *)step_kernel<D, TGT, LOC, MU, true>;
+    k.step_mh = (const void *)step_kernel<D, TGT, LOC, MU, false, true>;
+    k.drain = (const void *)drain_kernel<D, TGT, LOC, MU, false>;
+    k.drain_lds = (const void *)drain_kernel<D, TGT, LOC, MU, true>;
+    if constexpr (TGT == TGT_PSS) {
+        k.step_binned = (const void *)step_binned_kernel<D, TGT, LOC, MU, false>;
+        k.step_binned_lds = (const void *)step_binned_kernel<D, TGT, LOC, MU, true>;
+        k.step_tiled = (const void *)step_tiled_kernel<D, TGT, LOC, MU>;
+        k.drain_tiled = (const void *)drain_kernel<D, TGT, LOC, MU, false, true>;
+    }
+    return k;
+}
+
+#define RESTORE_SETS_FOR(TGT, LOC, MU)                                                                \
+    case 1: return make_set<1, TGT, LOC, MU>();   case 2: return make_set<2, TGT, LOC, MU>();           \
+    case 3: return make_set<3, TGT, LOC, MU>();   case 4: return make_set<4, TGT, LOC, MU>();           \
+    case 5: return make_set<5, TGT, LOC, MU>();   case 6: return make_set<6, TGT, LOC, MU>();           \
+    case 7: return make_set<7, TGT, LOC, MU>();   case 8: return make_set<8, TGT, LOC, MU>();           \
+    case 9: return make_set<9, TGT, LOC, MU>();   case 10: return make_set<10, TGT, LOC, MU>();         \
+    case 11: return make_set<11, TGT, LOC, MU>(); case 12: return make_set<12, TGT, LOC, MU>();         \
+    case 13: return make_set<13, TGT, LOC, MU>(); case 14: return make_set<14, TGT, LOC, MU>();         \
+    case 15: return make_set<15, TGT, LOC, MU>(); case 16: return make_set<16, TGT, LOC, MU>();
+
+}  // namespace restore

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "librestore.so")
 OK, E_INVALID_ARG, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_BAD_STATE, E_BUFFER_TOO_SMALL = 0, -1, -2, -3, -4, -5, -6
 TARGET_GMM_ISO, TARGET_GMM_FULL, TARGET_PSS = 0, 1, 2
 MU_UNIFORM_BOX, MU_GMM_DIAG = 0, 1
-LOCAL_RWMH, LOCAL_MALA = 0, 1
+LOCAL_RWMH, LOCAL_MALA, LOCAL_HMC = 0, 1, 2
 INTEGRAND_ONE, INTEGRAND_P, INTEGRAND_PIXEL = 1, 2, 4
 FLAG_PARAMS_LDS, FLAG_SPLAT_DIRECT, FLAG_SPLAT_TIGHT, FLAG_RB_DT = 1, 2, 4, 8
 ST_ALIVE, ST_CENSORED, ST_LAST_KILL, ST_LAST_ACCEPT, ST_GRAD_VALID, ST_LAST_LARGE = 1, 2, 4, 8, 16, 32
@@ -46,14 +46,15 @@ class restore_mu(C.Structure):
 
 class restore_local_kernel(C.Structure):
     _fields_ = [("kind", C.c_int32), ("step", C.c_float), ("large_step_prob", C.c_float),
-                ("reserved", C.c_int32)]
+                ("n_leapfrog", C.c_int32)]
 
 
 class restore_config(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("n_chains", C.c_int64), ("target_id", C.c_int32),
                 ("integrands", C.c_int32), ("c_tilde", C.c_double), ("drain_cap", C.c_int32),
                 ("image_w", C.c_int32), ("image_h", C.c_int32), ("flags", C.c_int32),
-                ("block_size", C.c_int32), ("image_batches", C.c_int32)]
+                ("block_size", C.c_int32), ("image_batches", C.c_int32), ("tile_px", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class restore_estimate_out(C.Structure):
@@ -375,7 +376,7 @@ def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: f
                  c_tilde: float, seed: int, drain_cap: int, target_id: int = 0, integrand_p: bool = True,
                  image: Optional[tuple] = None, lds: bool = False, block_size: int = 0,
                  mu: Optional[dict] = None, flags: int = 0, image_batches: int = 0,
-                 large_step_prob: float = 0.0) -> Problem:
+                 large_step_prob: float = 0.0, n_leapfrog: int = 0, tile_px: int = 0) -> Problem:
     flat = target_params(kind, d, K, params)
     t = restore_target(_KIND[kind], d, K if kind != "pss" else 0, 0,
                        flat.ctypes.data_as(C.POINTER(C.c_double)), flat.size)
@@ -392,12 +393,13 @@ def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: f
         mu_t = torch.cat([torch.as_tensor(np.asarray(mu[k], dtype=np.float32).ravel())
                           for k in ("logits", "means", "log_std")]).cuda()
         m = restore_mu(MU_GMM_DIAG, int(np.asarray(mu["logits"]).size), float(mu["beta"]), 0, mu_t.data_ptr())
-    lk = restore_local_kernel(LOCAL_MALA if local == "mala" else LOCAL_RWMH, float(step), float(large_step_prob), 0)
+    kind = {"rwmh": LOCAL_RWMH, "mala": LOCAL_MALA, "hmc": LOCAL_HMC}[local]
+    lk = restore_local_kernel(kind, float(step), float(large_step_prob), int(n_leapfrog))
     integrands = INTEGRAND_ONE | (INTEGRAND_P if integrand_p else 0) | (INTEGRAND_PIXEL if image else 0)
     w, h = (image or (0, 0))
     cfg = restore_config(int(seed), int(n_chains), int(target_id), integrands, float(c_tilde), int(drain_cap),
                          int(w), int(h), (FLAG_PARAMS_LDS if lds else 0) | int(flags), int(block_size),
-                         int(image_batches))
+                         int(image_batches), int(tile_px), 0)
     return Problem(t, m, lk, cfg, flat, mu_t)
 
 
@@ -407,7 +409,8 @@ def problem_from_workload(wl, **overrides) -> Problem:
     image)."""
     kw = dict(local=wl.local, step=wl.step, n_chains=wl.n_chains, c_tilde=wl.c_tilde, seed=wl.seed,
               drain_cap=wl.drain_cap, image=getattr(wl, "image", None),
-              image_batches=getattr(wl, "image_batches", 0) if getattr(wl, "image", None) else 0)
+              image_batches=getattr(wl, "image_batches", 0) if getattr(wl, "image", None) else 0,
+              n_leapfrog=getattr(wl, "n_leapfrog", 0), tile_px=getattr(wl, "tile_px", 0))
     kw.update(overrides)
     return make_problem(wl.target, wl.d, wl.K, wl.params, **kw)
 

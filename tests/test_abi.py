@@ -100,6 +100,17 @@ def test_local_kernel_validation(R):
     with pytest.raises(R.RestoreError) as e:
         R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
     assert e.value.status == R.E_INVALID_ARG
+    # HMC needs 1..64 leapfrog steps; the other kernels take none
+    for kind, n, ok in ((R.LOCAL_HMC, 8, True), (R.LOCAL_HMC, 0, False), (R.LOCAL_HMC, 65, False),
+                        (R.LOCAL_MALA, 1, False)):
+        p = _problem(R)
+        p.local.kind, p.local.n_leapfrog = kind, n
+        if ok:
+            assert R.restore_state_bytes(p.target, p.mu, p.local, p.cfg) > 0
+        else:
+            with pytest.raises(R.RestoreError) as e:
+                R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+            assert e.value.status == R.E_INVALID_ARG
     p = _problem(R)
     p.local.step = 0.0   # MALA needs a positive step
     with pytest.raises(R.RestoreError) as e:

@@ -39,6 +39,7 @@ class Workload:
                  | "hmc" (Hamiltonian Monte Carlo, leapfrog).
     step:        random-walk sigma, MALA epsilon or HMC leapfrog step size.
     n_leapfrog:  leapfrog steps per HMC update (0 for the other kernels).
+    tile_px:     image integrand: tile edge of a tile-stratified run (0 off).
     n_chains:    chain population size.
     n_steps:     step budget B (steps with regeneration).
     drain_cap:   extra steps allowed to finish the tour straddling B.
@@ -66,6 +67,7 @@ class Workload:
     image: Optional[tuple] = None
     image_batches: int = 0
     n_leapfrog: int = 0
+    tile_px: int = 0
 
     def with_(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)

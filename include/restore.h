@@ -388,7 +388,8 @@ restore_status restore_batch_destroy(restore_batch *b);
  * output: x_out float32 [n_steps][n_record][d], w_out float32
  * [n_steps][n_record] (caller-owned device memory).  The time-weighted
  * pairs are draws of pi in the sense of Sec. 7.4, eq. (approx): the
- * training data of the learned regeneration distribution. */
+ * training data of the learned regeneration distribution.  UNSUPPORTED for
+ * tile-stratified runs (their chains sample p on one tile each). */
 restore_status restore_step_record(restore_ctx *ctx, int32_t n_steps, int64_t n_record, float *x_out,
                                    float *w_out, void *stream);
 

@@ -650,6 +650,7 @@ restore_status restore_step_record(restore_ctx *c, int32_t n_steps, int64_t n_re
     if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
     if (n_record < 1 || n_record > c->cfg.n_chains || !x_out || !w_out)
         return fail(RESTORE_E_INVALID_ARG, "n_record must be in 1..n_chains with non-null buffers");
+    if (c->splat.n_tiles) return fail(RESTORE_E_UNSUPPORTED, "no sample recording in tile-stratified runs");
     return step_impl(c, n_steps, n_record, x_out, w_out, stream);
 }
 

@@ -316,7 +316,8 @@ restore_status restore_destroy(restore_ctx *ctx);
 
 /* ---- batched targets ---------------------------------------------------
  * Many independent targets (full-covariance mixtures of uneven dimension,
- * component count and chain count; random-walk MH local moves; uniform mu)
+ * component count and chain count; random-walk MH local moves; each with
+ * the uniform mu or its own regeneration distribution of the learned form)
  * advanced together.  Each target is its own restore problem exactly as
  * above (Alg. 2 with the killing rate of eq. (killing-rate-simplified));
  * target i uses Philox target id cfgs[i].target_id, so its chains follow
@@ -325,7 +326,8 @@ restore_status restore_destroy(restore_ctx *ctx);
  * tours in flight (cfgs[i].drain_cap) and the per-target reduction.  The
  * work is split into tiles of block_size chains of one target; persistent
  * workgroups pop tiles from a queue in longest-processing-time-first or
- * target order, optionally one queue per dimension range. */
+ * target order, optionally one queue per dimension range; targets with the
+ * uniform and with the learned-form mu take separate queues. */
 #define RESTORE_BATCH_ORDER_LPT      0
 #define RESTORE_BATCH_ORDER_TARGET   1
 #define RESTORE_BATCH_BUCKETS_ONE    0   /* one persistent kernel for every dimension   */
@@ -356,14 +358,19 @@ typedef struct restore_batch restore_batch;
  * queue, parameter slabs, per-chain results). */
 restore_status restore_batch_state_bytes(int32_t n_targets, const restore_target *targets,
                                          const restore_local_kernel *locals, const restore_config *cfgs,
-                                         size_t *bytes_out);
+                                         const restore_mu *mus, size_t *bytes_out);
 /* Validate, factorise every target's parameters in float64, upload, and
  * build the work queue for the default tiling (256, LPT, one kernel).
  * Arrays have n_targets entries; cfgs[i].n_chains, c_tilde, seed,
- * target_id, integrands and drain_cap are used per target. */
+ * target_id, integrands and drain_cap are used per target.  `mus` is NULL
+ * (every target regenerates from the uniform mu) or n_targets descriptors
+ * as for restore_init: a GMM_DIAG entry's caller-owned device row is read
+ * once here and factorised in float64, so that target's chains follow a
+ * single-target run with the same mu bit for bit. */
 restore_status restore_batch_init(restore_batch **out, int32_t n_targets, const restore_target *targets,
                                   const restore_local_kernel *locals, const restore_config *cfgs,
-                                  int32_t n_steps, void *state_dev, size_t state_bytes, void *stream);
+                                  const restore_mu *mus, int32_t n_steps, void *state_dev, size_t state_bytes,
+                                  void *stream);
 /* Change the tiling (rebuilds the queue, synchronous; results are
  * independent of the tiling). */
 restore_status restore_batch_set_tiling(restore_batch *b, const restore_batch_tiling *tiling);

@@ -21,8 +21,15 @@ struct BatchTarget {
     int32_t n_steps;      // budget B
     int32_t drain_cap;
     int32_t integrand_p;
+    int32_t mu_kind;      // MU_UNIFORM or MU_GMM (the learned-mu form)
+    int32_t mu_comp;      // MU_GMM: components
+    float mu_beta;        // MU_GMM: defensive uniform share
+    int32_t mu_offset;    // MU_GMM: floats into the slab (layout of the learned-mu slab)
     int32_t pad;
 };
+
+// Queue heads: one per bucket (dimension range and mu kind), plus one.
+constexpr int BATCH_HEADS = 16;
 
 // A tile of chains of one target: one lane per chain.
 struct WorkItem {
@@ -55,12 +62,13 @@ struct BatchArgs {
     double *results;               // [n_targets][BS_SLOTS]
 };
 
-// Kernels for items whose dimension lies in [dlo, dhi].
+// Kernels for items whose dimension lies in [dlo, dhi] and whose target's
+// regeneration distribution is of kind mu.
 struct BatchKernels {
     const void *persistent = nullptr;
     const void *per_target = nullptr;
 };
-BatchKernels find_batch_kernels(int dlo, int dhi);
+BatchKernels find_batch_kernels(int dlo, int dhi, int mu);
 
 hipError_t launch_batch_zero(const BatchArgs &b, hipStream_t s);
 hipError_t launch_batch_reduce(const BatchArgs &b, hipStream_t s);

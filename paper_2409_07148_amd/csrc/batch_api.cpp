@@ -22,6 +22,8 @@ using namespace restore;
 // defined in restore_api.cpp
 restore_status restore_internal_fail(restore_status code, const char *msg);
 restore_status restore_internal_pack_full(const restore_target *t, std::vector<float> *out);
+restore_status restore_internal_pack_mu(const std::vector<float> &raw, int K, int d, float beta,
+                                        std::vector<float> *out);
 
 namespace {
 
@@ -39,7 +41,9 @@ struct BLayout {
     int64_t total_chains;
 };
 
-BLayout make_layout(int n, const restore_target *t, const restore_config *c) {
+bool learned(const restore_mu *mus, int i) { return mus && mus[i].kind == RESTORE_MU_GMM_DIAG; }
+
+BLayout make_layout(int n, const restore_target *t, const restore_config *c, const restore_mu *mus) {
     BLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
@@ -49,13 +53,14 @@ BLayout make_layout(int n, const restore_target *t, const restore_config *c) {
     for (int i = 0; i < n; ++i) {
         L.max_items += (size_t)((c[i].n_chains + 63) / 64);
         L.n_param_floats += (size_t)comp_stride(TGT_FULL, t[i].dim) * t[i].n_comp;
+        if (learned(mus, i)) L.n_param_floats += (size_t)mu_slab_floats(t[i].dim, mus[i].n_comp);
         L.total_chains += c[i].n_chains;
     }
     const size_t C = (size_t)L.total_chains;
     L.targets = take(sizeof(BatchTarget) * n);
     L.items = take(sizeof(WorkItem) * L.max_items);
     L.params = take(4 * L.n_param_floats);
-    L.heads = take(4 * 8);
+    L.heads = take(4 * BATCH_HEADS);
     L.counters = take(8 * BC_SLOTS * (size_t)n);
     L.results = take(8 * BS_SLOTS * (size_t)n);
     L.n_done = take(4 * C);
@@ -67,12 +72,23 @@ BLayout make_layout(int n, const restore_target *t, const restore_config *c) {
     return L;
 }
 
-restore_status validate(int n, const restore_target *t, const restore_local_kernel *lk, const restore_config *c) {
+restore_status validate(int n, const restore_target *t, const restore_local_kernel *lk, const restore_config *c,
+                        const restore_mu *mus) {
     if (n < 1 || n > (1 << 16)) return fail(RESTORE_E_INVALID_ARG, "n_targets outside 1..65536");
     if (!t || !lk || !c) return fail(RESTORE_E_INVALID_ARG, "null descriptor array");
     int64_t total = 0;
     for (int i = 0; i < n; ++i) {
         const std::string at = "target " + std::to_string(i) + ": ";
+        if (mus) {
+            if (mus[i].kind != RESTORE_MU_UNIFORM_BOX && mus[i].kind != RESTORE_MU_GMM_DIAG)
+                return fail(RESTORE_E_INVALID_ARG, at + "unknown mu kind");
+            if (mus[i].kind == RESTORE_MU_GMM_DIAG) {
+                if (mus[i].n_comp < 1 || mus[i].n_comp > RESTORE_MAX_COMP || !mus[i].params_dev)
+                    return fail(RESTORE_E_INVALID_ARG, at + "GMM_DIAG mu needs 1..64 components and device params");
+                if (!(mus[i].beta >= 0.0f && mus[i].beta <= 1.0f))
+                    return fail(RESTORE_E_INVALID_ARG, at + "mu beta outside [0,1]");
+            }
+        }
         if (t[i].kind != RESTORE_TARGET_GMM_FULL)
             return fail(RESTORE_E_UNSUPPORTED, at + "the batched path takes full-covariance mixtures");
         if (t[i].dim < 1 || t[i].dim > RESTORE_MAX_DIM) return fail(RESTORE_E_INVALID_ARG, at + "dim outside 1..16");
@@ -100,7 +116,7 @@ restore_status validate(int n, const restore_target *t, const restore_local_kern
 }
 
 struct Bucket {
-    int dlo, dhi;
+    int dlo, dhi, mu;
     BatchKernels k;
     size_t item_begin, item_count;
     int grid;
@@ -161,18 +177,21 @@ restore_status build_items(restore_batch *b, hipStream_t s) {
     else ranges = {{1, 16}};
     std::vector<WorkItem> all;
     b->buckets.clear();
+    for (int mu : {(int)MU_UNIFORM, (int)MU_GMM})
     for (auto r : ranges) {
         Bucket bk{};
         bk.dlo = r.first;
         bk.dhi = r.second;
-        bk.k = find_batch_kernels(r.first, r.second);
+        bk.mu = mu;
+        bk.k = find_batch_kernels(r.first, r.second, mu);
         if (!bk.k.persistent) return fail(RESTORE_E_UNSUPPORTED, "batch kernels for this dimension range are not built");
         std::vector<std::pair<double, WorkItem>> items;
         for (int i = 0; i < b->n; ++i) {
             const BatchTarget &t = b->targets[i];
-            if (t.d < r.first || t.d > r.second) continue;
-            // cost of a tile ~ chains x components x (d^2 + 3d) per step
-            const double per_chain = (double)t.K * (t.d * t.d + 3 * t.d + 7);
+            if (t.d < r.first || t.d > r.second || t.mu_kind != mu) continue;
+            // cost of a tile ~ chains x (components x (d^2 + 3d) + mu components x 3d) per step
+            const double per_chain = (double)t.K * (t.d * t.d + 3 * t.d + 7) +
+                                     (mu == MU_GMM ? (double)t.mu_comp * (3 * t.d + 9) : 0.0);
             for (int f = 0; f < t.n_chains; f += block) {
                 WorkItem w{};
                 w.target = i;
@@ -220,7 +239,7 @@ hipError_t enqueue_persistent(restore_batch *b, hipStream_t s) {
 
 // zero kernel also clears the queue heads of every bucket
 __global__ void heads_zero_kernel(int32_t *h) {
-    if (threadIdx.x < 8) h[threadIdx.x] = 0;
+    if (threadIdx.x < BATCH_HEADS) h[threadIdx.x] = 0;
 }
 
 }  // namespace
@@ -229,25 +248,26 @@ extern "C" {
 
 restore_status restore_batch_state_bytes(int32_t n_targets, const restore_target *targets,
                                          const restore_local_kernel *locals, const restore_config *cfgs,
-                                         size_t *bytes_out) {
+                                         const restore_mu *mus, size_t *bytes_out) {
     if (!bytes_out) return fail(RESTORE_E_INVALID_ARG, "null bytes_out");
-    restore_status st = validate(n_targets, targets, locals, cfgs);
+    restore_status st = validate(n_targets, targets, locals, cfgs, mus);
     if (st != RESTORE_OK) return st;
-    *bytes_out = make_layout(n_targets, targets, cfgs).total;
+    *bytes_out = make_layout(n_targets, targets, cfgs, mus).total;
     return RESTORE_OK;
 }
 
 restore_status restore_batch_init(restore_batch **out, int32_t n_targets, const restore_target *targets,
-                                  const restore_local_kernel *locals, const restore_config *cfgs, int32_t n_steps,
-                                  void *state_dev, size_t state_bytes, void *stream) {
+                                  const restore_local_kernel *locals, const restore_config *cfgs,
+                                  const restore_mu *mus, int32_t n_steps, void *state_dev, size_t state_bytes,
+                                  void *stream) {
     if (!out) return fail(RESTORE_E_INVALID_ARG, "null out");
     *out = nullptr;
-    restore_status st = validate(n_targets, targets, locals, cfgs);
+    restore_status st = validate(n_targets, targets, locals, cfgs, mus);
     if (st != RESTORE_OK) return st;
     if (n_steps < 0) return fail(RESTORE_E_INVALID_ARG, "n_steps must be >= 0");
     if (!state_dev || reinterpret_cast<uintptr_t>(state_dev) % ALIGN)
         return fail(RESTORE_E_INVALID_ARG, "state buffer must be non-null and 256-byte aligned");
-    const BLayout lay = make_layout(n_targets, targets, cfgs);
+    const BLayout lay = make_layout(n_targets, targets, cfgs, mus);
     if (state_bytes < lay.total) return fail(RESTORE_E_BUFFER_TOO_SMALL, "batch state buffer too small");
     for (int i = 0; i < n_targets; ++i)
         if ((int64_t)n_steps + cfgs[i].drain_cap > 0x7fffffffLL) return fail(RESTORE_E_INVALID_ARG, "step counter overflow");
@@ -260,6 +280,7 @@ restore_status restore_batch_init(restore_batch **out, int32_t n_targets, const 
     b->base = static_cast<char *>(state_dev);
     std::vector<float> slab, one;
     int64_t offset = 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
     for (int i = 0; i < n_targets; ++i) {
         st = restore_internal_pack_full(&targets[i], &one);
         if (st != RESTORE_OK) { delete b; return st; }
@@ -279,11 +300,28 @@ restore_status restore_batch_init(restore_batch **out, int32_t n_targets, const 
         t.drain_cap = cfgs[i].drain_cap;
         t.integrand_p = (cfgs[i].integrands & RESTORE_INTEGRAND_P) ? 1 : 0;
         slab.insert(slab.end(), one.begin(), one.end());
+        t.mu_kind = MU_UNIFORM;
+        if (learned(mus, i)) {
+            // the learned-mu form: the caller's device row, read once and
+            // factorised in float64 as for a single-target run
+            const int K = mus[i].n_comp, d = t.d;
+            std::vector<float> raw((size_t)K * (1 + 2 * d));
+            hipError_t e = hipMemcpyAsync(raw.data(), mus[i].params_dev, raw.size() * sizeof(float),
+                                          hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) { delete b; return hip_fail(e, "mu parameter read"); }
+            st = restore_internal_pack_mu(raw, K, d, mus[i].beta, &one);
+            if (st != RESTORE_OK) { delete b; return st; }
+            t.mu_kind = MU_GMM;
+            t.mu_comp = K;
+            t.mu_beta = mus[i].beta;
+            t.mu_offset = (int32_t)slab.size();
+            slab.insert(slab.end(), one.begin(), one.end());
+        }
         b->targets.push_back(t);
         b->c_tilde.push_back(cfgs[i].c_tilde);
         offset += cfgs[i].n_chains;
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0;
     hipDeviceProp_t prop;
     hipError_t e = hipGetDevice(&dev);
@@ -362,7 +400,7 @@ restore_status restore_batch_run(restore_batch *b, int32_t mode, void *stream) {
             const BatchTarget &t = b->targets[i];
             const Bucket *bk = nullptr;
             for (const Bucket &x : b->buckets)
-                if (t.d >= x.dlo && t.d <= x.dhi) bk = &x;
+                if (t.d >= x.dlo && t.d <= x.dhi && t.mu_kind == x.mu) bk = &x;
             if (!bk) return fail(RESTORE_E_UNSUPPORTED, "no bucket for a target");
             BatchArgs a = args_for(b, bk, 0);
             int32_t ti = i;
@@ -446,6 +484,8 @@ static uint64_t batch_key(const restore_batch *b) {
         mix((uint64_t)t.K);
         mix((uint64_t)t.n_chains);
         mix((uint64_t)t.drain_cap);
+        mix((uint64_t)t.mu_kind);
+        mix((uint64_t)t.mu_comp);
     }
     return h;
 }

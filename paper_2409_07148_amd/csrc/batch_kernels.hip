@@ -17,7 +17,7 @@
 
 namespace restore {
 
-template <int D>
+template <int D, int MU>
 __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &t, const WorkItem &w) {
     constexpr int NB = NBlocks<D>::value;
     if ((int)threadIdx.x >= w.count) return;
@@ -34,16 +34,21 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
     a.target_id = t.target_id;
     a.integrand_p = t.integrand_p;
     a.image = nullptr;
+    if (MU == MU_GMM) {
+        a.mu_params = b.params + t.mu_offset;
+        a.mu_comp = t.mu_comp;
+        a.mu_beta = t.mu_beta;
+    }
     const const_fptr P = (const_fptr)(b.params + t.param_offset);
 
-    // x_0 ~ mu (uniform on the box), cached log p; zero sums
+    // x_0 ~ mu, cached log p and log u; zero sums
     Chain<D, LOC_RWMH> ch;
     {
         float head[4], cand[4 * NB];
         draw_step<NB>(0u, chain, t.target_id, PURPOSE_INIT, t.key0, t.key1, head, cand);
-        sample_mu<D, MU_UNIFORM, 4 * NB>(a, head[3], cand, ch.x);
+        sample_mu<D, MU, 4 * NB>(a, head[3], cand, ch.x);
         ch.lp = log_target<D, TGT_FULL, false>(P, t.K, ch.x, ch.g);
-        ch.lu = log_mu<D, MU_UNIFORM>(a, ch.x);
+        ch.lu = log_mu<D, MU>(a, ch.x);
         ch.a_cur = ch.t_cur = 0.0f;
         ch.a_done = ch.t_done = 0.0;
         ch.n_done = 0u;
@@ -55,7 +60,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
     unsigned long long n_t = 0, n_acc = 0, n_kill = 0;
     bool kill = false, accept = false;
     for (int s = 0; s < t.n_steps; ++s) {
-        step_once<D, TGT_FULL, LOC_RWMH, MU_UNIFORM, false>(a, P, (uint32_t)s, chain, ch, kill, accept);
+        step_once<D, TGT_FULL, LOC_RWMH, MU, false>(a, P, (uint32_t)s, chain, ch, kill, accept);
         n_acc += __popcll(__ballot(accept));
         n_kill += __popcll(__ballot(kill));
     }
@@ -68,7 +73,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
         n_t += __popcll(live);
         bool k = false, ac = false;
         if (alive) {
-            step_once<D, TGT_FULL, LOC_RWMH, MU_UNIFORM, true>(a, P, (uint32_t)s, chain, ch, k, ac);
+            step_once<D, TGT_FULL, LOC_RWMH, MU, true>(a, P, (uint32_t)s, chain, ch, k, ac);
             alive = !k;
         }
         n_acc += __popcll(__ballot(ac));
@@ -89,10 +94,10 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
     }
 }
 
-template <int DLO, int DHI>
+template <int DLO, int DHI, int MU>
 __device__ __forceinline__ void run_item_dispatch(const BatchArgs &b, const BatchTarget &t, const WorkItem &w) {
 #define RESTORE_BATCH_CASE(D) \
-    case D: if constexpr (D >= DLO && D <= DHI) run_item<D>(b, t, w); break;
+    case D: if constexpr (D >= DLO && D <= DHI) run_item<D, MU>(b, t, w); break;
     switch (t.d) {
         RESTORE_BATCH_CASE(1) RESTORE_BATCH_CASE(2) RESTORE_BATCH_CASE(3) RESTORE_BATCH_CASE(4)
         RESTORE_BATCH_CASE(5) RESTORE_BATCH_CASE(6) RESTORE_BATCH_CASE(7) RESTORE_BATCH_CASE(8)
@@ -105,7 +110,7 @@ __device__ __forceinline__ void run_item_dispatch(const BatchArgs &b, const Batc
 
 // Persistent: every workgroup pops items until the queue is empty, so every
 // wave reaches the exit once all items are taken.
-template <int DLO, int DHI>
+template <int DLO, int DHI, int MU>
 __global__ __launch_bounds__(256) void batch_persistent_kernel(BatchArgs b) {
     __shared__ int32_t item_sh;
     for (;;) {
@@ -116,12 +121,12 @@ __global__ __launch_bounds__(256) void batch_persistent_kernel(BatchArgs b) {
         if (item >= b.n_items) break;
         const WorkItem w = b.items[item];
         const BatchTarget t = b.targets[w.target];
-        run_item_dispatch<DLO, DHI>(b, t, w);
+        run_item_dispatch<DLO, DHI, MU>(b, t, w);
     }
 }
 
 // One launch per target (the comparison mode): block i takes the i-th tile.
-template <int DLO, int DHI>
+template <int DLO, int DHI, int MU>
 __global__ __launch_bounds__(256) void batch_target_kernel(BatchArgs b, int32_t target) {
     const BatchTarget t = b.targets[target];
     WorkItem w;
@@ -130,13 +135,13 @@ __global__ __launch_bounds__(256) void batch_target_kernel(BatchArgs b, int32_t 
     w.count = min((int32_t)blockDim.x, t.n_chains - w.first);
     w.pad = 0;
     if (w.count <= 0) return;
-    run_item_dispatch<DLO, DHI>(b, t, w);
+    run_item_dispatch<DLO, DHI, MU>(b, t, w);
 }
 
 __global__ void batch_zero_kernel(BatchArgs b) {
-    // queue_head points at the first of the 8 bucket queue heads
+    // queue_head points at the first of the bucket queue heads
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 8) b.queue_head[i] = 0;
+    if (i < BATCH_HEADS) b.queue_head[i] = 0;
     if (i < b.n_targets * BC_SLOTS) b.counters[i] = 0ull;
 }
 
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(BR_THREADS) void batch_reduce_kernel(BatchArgs b) {
 }
 
 hipError_t launch_batch_zero(const BatchArgs &b, hipStream_t s) {
-    const int n = b.n_targets * BC_SLOTS + 8;
+    const int n = b.n_targets * BC_SLOTS + BATCH_HEADS;
     hipLaunchKernelGGL(batch_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, s, b);
     return hipGetLastError();
 }
@@ -204,13 +209,15 @@ hipError_t launch_batch_reduce(const BatchArgs &b, hipStream_t s) {
     return hipGetLastError();
 }
 
-BatchKernels find_batch_kernels(int dlo, int dhi) {
+BatchKernels find_batch_kernels(int dlo, int dhi, int mu) {
     BatchKernels k;
-#define RESTORE_BATCH_RANGE(LO, HI)                                                   \
-    if (dlo == LO && dhi == HI) {                                                     \
-        k.persistent = (const void *)batch_persistent_kernel<LO, HI>;                 \
-        k.per_target = (const void *)batch_target_kernel<LO, HI>;                     \
-        return k;                                                                     \
+#define RESTORE_BATCH_RANGE(LO, HI)                                                                       \
+    if (dlo == LO && dhi == HI) {                                                                         \
+        k.persistent = mu == MU_GMM ? (const void *)batch_persistent_kernel<LO, HI, MU_GMM>               \
+                                    : (const void *)batch_persistent_kernel<LO, HI, MU_UNIFORM>;          \
+        k.per_target = mu == MU_GMM ? (const void *)batch_target_kernel<LO, HI, MU_GMM>                   \
+                                    : (const void *)batch_target_kernel<LO, HI, MU_UNIFORM>;              \
+        return k;                                                                                         \
     }
     RESTORE_BATCH_RANGE(1, 16)
     RESTORE_BATCH_RANGE(1, 4)

@@ -362,6 +362,11 @@ restore_status pack_mu(const std::vector<float> &raw, int K, int d, float beta, 
 // Entry points shared with the batched runtime (batch_api.cpp).
 restore_status restore_internal_fail(restore_status code, const char *msg) { return fail(code, "%s", msg); }
 
+restore_status restore_internal_pack_mu(const std::vector<float> &raw, int K, int d, float beta,
+                                        std::vector<float> *out) {
+    return pack_mu(raw, K, d, beta, out);
+}
+
 restore_status restore_internal_pack_full(const restore_target *t, std::vector<float> *out) {
     Validated v{};
     v.tgt = TGT_FULL;

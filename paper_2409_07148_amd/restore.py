@@ -128,9 +128,10 @@ def _load() -> C.CDLL:
     lib.restore_refresh_cache.argtypes = [C.c_void_p, C.c_void_p]
     lib.restore_destroy.argtypes = [C.c_void_p]
     lib.restore_batch_state_bytes.argtypes = [C.c_int32, P(restore_target), P(restore_local_kernel),
-                                              P(restore_config), P(C.c_size_t)]
+                                              P(restore_config), P(restore_mu), P(C.c_size_t)]
     lib.restore_batch_init.argtypes = [P(C.c_void_p), C.c_int32, P(restore_target), P(restore_local_kernel),
-                                       P(restore_config), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]
+                                       P(restore_config), P(restore_mu), C.c_int32, C.c_void_p, C.c_size_t,
+                                       C.c_void_p]
     lib.restore_batch_set_tiling.argtypes = [C.c_void_p, P(restore_batch_tiling)]
     lib.restore_batch_get_tiling.argtypes = [C.c_void_p, P(restore_batch_tiling)]
     lib.restore_batch_run.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
@@ -238,21 +239,22 @@ def _arr(cls, items):
     return a
 
 
-def restore_batch_state_bytes(targets, locals_, cfgs) -> int:
+def restore_batch_state_bytes(targets, locals_, cfgs, mus=None) -> int:
     out = C.c_size_t(0)
     n = len(targets)
     _check(_lib.restore_batch_state_bytes(n, _arr(restore_target, targets), _arr(restore_local_kernel, locals_),
-                                          _arr(restore_config, cfgs), C.byref(out)))
+                                          _arr(restore_config, cfgs), _arr(restore_mu, mus) if mus else None,
+                                          C.byref(out)))
     return out.value
 
 
 def restore_batch_init(targets, locals_, cfgs, n_steps: int, state_ptr: int, state_bytes: int,
-                       stream=None) -> C.c_void_p:
+                       stream=None, mus=None) -> C.c_void_p:
     b = C.c_void_p()
     n = len(targets)
     _check(_lib.restore_batch_init(C.byref(b), n, _arr(restore_target, targets), _arr(restore_local_kernel, locals_),
-                                   _arr(restore_config, cfgs), int(n_steps), C.c_void_p(state_ptr), state_bytes,
-                                   C.c_void_p(_stream(stream))))
+                                   _arr(restore_config, cfgs), _arr(restore_mu, mus) if mus else None, int(n_steps),
+                                   C.c_void_p(state_ptr), state_bytes, C.c_void_p(_stream(stream))))
     return b
 
 
@@ -522,17 +524,22 @@ class Batch:
     """Many targets advanced together on the current GPU: owns the torch
     state buffer and the library's batch handle."""
 
-    def __init__(self, workloads, n_steps: int, stream=None):
+    def __init__(self, workloads, n_steps: int, stream=None, mus=None):
+        """mus: None (uniform mu everywhere) or one entry per workload, None
+        or a regeneration distribution as make_problem takes it."""
         self.stream = stream
-        self.probs = [problem_from_workload(w, target_id=i, integrand_p=True) for i, w in enumerate(workloads)]
+        mus = list(mus) if mus is not None else [None] * len(workloads)
+        self.probs = [problem_from_workload(w, target_id=i, integrand_p=True, mu=m)
+                      for i, (w, m) in enumerate(zip(workloads, mus))]
         targets = [p.target for p in self.probs]
         locs = [p.local for p in self.probs]
         cfgs = [p.cfg for p in self.probs]
+        mu_desc = [p.mu for p in self.probs] if any(m is not None for m in mus) else None
         self.n = len(self.probs)
-        nbytes = restore_batch_state_bytes(targets, locs, cfgs)
+        nbytes = restore_batch_state_bytes(targets, locs, cfgs, mu_desc)
         self.state = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         ptr = (self.state.data_ptr() + 255) // 256 * 256
-        self.handle = restore_batch_init(targets, locs, cfgs, n_steps, ptr, nbytes, stream)
+        self.handle = restore_batch_init(targets, locs, cfgs, n_steps, ptr, nbytes, stream, mu_desc)
 
     def run(self, mode: int = BATCH_MODE_GRAPH):
         restore_batch_run(self.handle, mode, self.stream)

@@ -205,3 +205,23 @@ def test_batch_rejects_the_mh_chain(R):
     with pytest.raises(R.RestoreError) as e:
         R.restore_batch_state_bytes([p.target], [p.local], [p.cfg])
     assert e.value.status == R.E_UNSUPPORTED
+
+
+def test_batch_mu_descriptors(R):
+    """A learned-form mu adds its slab to the batch state; invalid entries
+    are rejected on the host."""
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=1000)
+    p = R.make_problem("gmm_full", wl.d, wl.K, wl.params, local="rwmh", step=0.02, n_chains=1000,
+                       c_tilde=1.0, seed=1, drain_cap=64)
+    base = R.restore_batch_state_bytes([p.target], [p.local], [p.cfg])
+    uni = R.restore_mu(R.MU_UNIFORM_BOX, 0, 0.0, 0, None)
+    assert R.restore_batch_state_bytes([p.target], [p.local], [p.cfg], [uni]) == base
+    # the device row is only read by restore_batch_init: any non-null address sizes the state
+    gmm = R.restore_mu(R.MU_GMM_DIAG, 64, 0.1, 0, 256)
+    assert R.restore_batch_state_bytes([p.target], [p.local], [p.cfg], [gmm]) > base
+    for bad in (R.restore_mu(R.MU_GMM_DIAG, 0, 0.1, 0, 256), R.restore_mu(R.MU_GMM_DIAG, 8, 1.5, 0, 256),
+                R.restore_mu(R.MU_GMM_DIAG, 8, 0.1, 0, None), R.restore_mu(7, 8, 0.1, 0, 256)):
+        with pytest.raises(R.RestoreError) as e:
+            R.restore_batch_state_bytes([p.target], [p.local], [p.cfg], [bad])
+        assert e.value.status == R.E_INVALID_ARG

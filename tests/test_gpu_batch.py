@@ -56,6 +56,42 @@ def test_batch_targets_reproduce_single_target_runs(R):
     b.close()
 
 
+@pytest.mark.parametrize("buckets", [0, 1])
+def test_batch_with_learned_form_mu_reproduces_single_target_runs(R, buckets):
+    """Targets of one batch with their own regeneration distribution of the
+    learned form (a defensive diagonal mixture built from each target's
+    components) next to uniform-mu targets: every target's chains equal a
+    single-target run with the same mu and target id, bit for bit, in every
+    launch mode and with one or four dimension buckets."""
+    from tests import helpers as H
+    from workloads import gmm_full
+    wls = [gmm_full(d=d, K=K, n_chains=n, n_steps=40, local="rwmh", step=0.02, problem_seed=900 + d + K,
+                    c_tilde=ct)
+           for d, K, n, ct in ((2, 4, 1500, 30.0), (8, 16, 2100, 1e4), (8, 6, 700, 1e3), (2, 3, 333, 5.0))]
+    mus = [H.mixture_mu_from_target(wls[0]), None, H.mixture_mu_from_target(wls[2], beta=0.2), None]
+    b = R.Batch(wls, n_steps=40, mus=mus)
+    b.set_tiling(buckets=buckets)
+    for mode in (R.BATCH_MODE_GRAPH, R.BATCH_MODE_PERSISTENT, R.BATCH_MODE_SEPARATE):
+        b.run(mode)
+        for t, wl in enumerate(wls):
+            run = R.Run(R.problem_from_workload(wl, target_id=t, mu=mus[t]))
+            run.step(wl.n_steps)
+            run.drain()
+            arr = run.arrays()
+            got = _sums(b, t)
+            for k in ("n_done", "t_done", "a_done"):
+                assert np.array_equal(got[k], arr[k].cpu().numpy()), (mode, t, k)
+            if mode == R.BATCH_MODE_GRAPH:
+                est = run.estimate()
+                bt = b.estimates()[t]
+                assert abs(bt["p_lambda"] / est["p_lambda"] - 1) < 1e-12 and bt["kills"] == est["kills"]
+                _say(f"[batch learned mu buckets={buckets}] target {t} (d={wl.d}, mu "
+                     f"{'learned form' if mus[t] is not None else 'uniform'}): identical; p_lambda "
+                     f"{est['p_lambda']:.4g}, kill rate {est['kill_rate']:.3f}")
+            run.close()
+    b.close()
+
+
 def test_batch_results_do_not_depend_on_tiling_or_mode(R):
     wls = _small_batch(n_targets=10)
     b = R.Batch(wls, n_steps=wls[0].n_steps)

@@ -179,7 +179,9 @@ typedef struct {
     int32_t image_w, image_h;/* pixel grid on (x0, x1) if PIXEL is set      */
     int32_t flags;           /* RESTORE_FLAG_*                               */
     int32_t block_size;      /* threads per workgroup (64..256, multiple of
-                                64); 0 = library default                    */
+                                64); 0 = library default: 256, or 64 below
+                                2^16 chains (spreads a small population's
+                                waves over more compute units)              */
     int32_t image_batches;   /* PIXEL: chains split into this many contiguous
                                 ranges (chain c in batch floor(c B / C)),
                                 each splatting into its own image, for the

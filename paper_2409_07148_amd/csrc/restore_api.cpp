@@ -538,7 +538,10 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     c->lay = lay;
     c->base = static_cast<char *>(state_dev);
     c->n_params = n_params;
-    c->block = cfg->block_size ? cfg->block_size : 256;
+    // default: 256 threads; populations too small to give every CU a
+    // workgroup of 256 (fewer than 2^16 chains) run one wave per workgroup,
+    // which spreads their few waves over more CUs (their runs are latency-bound)
+    c->block = cfg->block_size ? cfg->block_size : (cfg->n_chains < (1LL << 16) ? 64 : 256);
     c->lds = (cfg->flags & RESTORE_FLAG_PARAMS_LDS) != 0;
     c->step = local->step;
     c->mh = cfg->c_tilde == 0.0;
@@ -674,11 +677,13 @@ restore_status restore_drain(restore_ctx *c, void *stream) {
     const bool tiled = c->splat.n_tiles > 0;
     const void *fn = tiled ? c->ks.drain_tiled : c->lds ? c->ks.drain_lds : c->ks.drain;
     const size_t shm = (c->lds && !tiled) ? (size_t)c->n_params * sizeof(float) : 0;
+    // chunks of 1, 2, 4, ... steps: survivors are compacted between chunks
+    // while many chains retire, and the long tail takes few launches
     int32_t remaining = c->cfg.drain_cap;
-    int32_t chunk = 1;
+    int64_t chunk = 1;
     uint32_t s0 = (uint32_t)c->steps_taken;
     for (int j = 0;; ++j) {
-        const int32_t L = remaining < chunk ? remaining : chunk;
+        const int32_t L = remaining < chunk ? remaining : (int32_t)chunk;
         const int last = (remaining - L) == 0 ? 1 : 0;
         StepArgs a = c->args;
         a.list = j == 0 ? nullptr : lists[(j - 1) % 2];
@@ -695,7 +700,7 @@ restore_status restore_drain(restore_ctx *c, void *stream) {
         s0 += (uint32_t)L;
         remaining -= L;
         if (last) break;
-        chunk = chunk < 128 ? chunk * 2 : 128;
+        chunk *= 2;
     }
     c->drained = true;
     return RESTORE_OK;

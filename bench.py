@@ -262,6 +262,65 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
     return res
 
 
+def mse_time_image(wl, replicates: int = 8, log=None) -> dict:
+    """The learned regeneration distribution on the rendering-shaped
+    workload: a 64-component mixture (d = 12) from the same MLP, trained in
+    3 refits (refit 0 records with uniform mu at c~_U / 10, where tours last
+    long enough to find the lobes), against uniform mu, each at its provable
+    c~ and at c~_U / 10 and c~_U / 100; `replicates` fresh seeds per method
+    and c~, timed from init to the image estimate.  Scored: relative RMS
+    error of p_lambda and of the image in 8 x 8-pixel tiles, against the
+    stored per-pixel truth."""
+    import numpy as np
+    import torch
+    from paper_2409_07148_amd import restore as R
+    from paper_2409_07148_amd.learned_mu import MlpGmm, provable_c_tilde, refit
+
+    tr = json.load(open(os.path.join(ROOT, "tests", "golden", "truths.json")))[wl.name]
+    t, tt = tr["tile"], np.asarray(tr["tiles"], dtype=np.float64)
+    W, H = wl.image
+    model = MlpGmm(d=wl.d, K=64, in_dim=12, hidden=64, beta=0.1, seed=3004)
+    ct_l = provable_c_tilde(wl.c_tilde, model.beta)
+    t0 = time.perf_counter()
+    hist = refit(wl, model, ct_l, refits=3, record_steps=4, epochs=300, lr=2e-2, seed=3004,
+                 c_tilde_explore=wl.c_tilde / 10, log=log or (lambda *a: None))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    mu = model.mu()
+
+    def config(mu_, ct):
+        secs, pl, img = [], [], []
+        for r in range(replicates):
+            prob = R.problem_from_workload(wl, mu=mu_, c_tilde=ct, seed=2004 + 17 * r)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            run = R.Run(prob)
+            run.step(wl.n_steps)
+            run.drain()
+            est = run.estimate()
+            mean, _ = run.image_estimate()
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t1)
+            tiles = mean.double().cpu().numpy().reshape(H // t, t, W // t, t).sum(axis=(1, 3))
+            img.append(float(np.sqrt(np.mean(((tiles - tt) / tt) ** 2))))
+            pl.append((est["p_lambda"] - tr["p_lambda"]) / tr["p_lambda"])
+            run.close()
+        s = float(np.mean(secs))
+        mse_pl, mse_img = float(np.mean(np.square(pl))), float(np.mean(np.square(img)))
+        return {"c_tilde": ct, "seconds_per_run": s, "p_lambda_rel_rmse": math.sqrt(mse_pl),
+                "image_tile_rel_rmse": math.sqrt(mse_img), "p_lambda_mse_x_time": mse_pl * s,
+                "image_mse_x_time": mse_img * s}
+
+    res = {"replicates": replicates, "training_s": train_s, "training_refits": hist,
+           "uniform": [config(None, ct) for ct in (wl.c_tilde, wl.c_tilde / 10, wl.c_tilde / 100)],
+           "learned": [config(mu, ct) for ct in (ct_l, wl.c_tilde / 10, wl.c_tilde / 100)]}
+    for key in ("p_lambda_mse_x_time", "image_mse_x_time"):
+        res[key + "_ratio_at_provable_c_tilde"] = res["uniform"][0][key] / res["learned"][0][key]
+        res[key + "_ratio_at_best_c_tilde"] = (min(c[key] for c in res["uniform"]) /
+                                               min(c[key] for c in res["learned"]))
+    return res
+
+
 def restore_vs_mh(wl, replicates: int = 8, ell: float = 0.3, burn_in: int = 10000) -> dict:
     """The paper's central comparison (Sec. 8, Sec. 9) on a synthetic target:
     the restore process (the workload's c~, uniform mu, small-step kernel
@@ -333,7 +392,7 @@ def main():
                          "steps of the workload's step size in place of its random-walk or MALA moves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mse-time", action="store_true",
-                    help="skip the learned-mu MSE x time comparison (8-D workload only)")
+                    help="skip the learned-mu MSE x time comparisons (8-D and image workloads)")
     ap.add_argument("--tiles", type=int, default=0, metavar="P",
                     help="image workload: tile-stratified restore with P x P-pixel tiles")
     ap.add_argument("--no-mh", action="store_true",
@@ -483,6 +542,8 @@ def main():
         line["copy_calibration_bytes"] = src.numel() * 4
     if wl.name == "gmm_full_8d" and wl.local != "hmc" and not args.no_mse_time:
         line["mse_time"] = mse_time(wl)
+    if wl.name == "pss_render_12d" and not wl.tile_px and not args.no_image and not args.no_mse_time:
+        line["mse_time_image"] = mse_time_image(wl)
     if wl.name in ("gmm_full_8d", "gmm_iso_2d") and not args.no_mh:
         # with --hmc both methods use the HMC moves (the paper's HMC and HMC restore)
         line["restore_vs_mh"] = {wl.name: restore_vs_mh(wl)}

@@ -19,6 +19,8 @@ KernelSet find_kernels(int tgt, int d, int loc, int mu) {
                          case 8: return make_set<8, TGT_FULL, LOC_RWMH, MU_GMM>(); default: break; }
         }
         if (tgt == TGT_ISO && loc == LOC_RWMH && d == 2) return make_set<2, TGT_ISO, LOC_RWMH, MU_GMM>();
+        // the rendering-shaped integrand (image splats, binned or direct)
+        if (tgt == TGT_PSS && loc == LOC_RWMH && d == 12) return make_set<12, TGT_PSS, LOC_RWMH, MU_GMM>();
         return KernelSet{};
     }
     if (tgt == TGT_PSS) {

@@ -139,7 +139,7 @@ def record_samples(wl, mu: Optional[dict], c_tilde: float, seed: int, record_ste
     the pairs (x_{i-1}, dt_i) of the last record_steps steps of chains
     [0, n_record) (default: every chain)."""
     n_record = wl.n_chains if n_record is None else n_record
-    prob = R.problem_from_workload(wl, mu=mu, seed=seed, c_tilde=c_tilde, integrand_p=False)
+    prob = R.problem_from_workload(wl, mu=mu, seed=seed, c_tilde=c_tilde, integrand_p=False, image=None)
     run = R.Run(prob)
     if wl.n_steps > record_steps:
         run.step(wl.n_steps - record_steps)

@@ -414,6 +414,9 @@ def problem_from_workload(wl, **overrides) -> Problem:
               image_batches=getattr(wl, "image_batches", 0) if getattr(wl, "image", None) else 0,
               n_leapfrog=getattr(wl, "n_leapfrog", 0), tile_px=getattr(wl, "tile_px", 0))
     kw.update(overrides)
+    if not kw["image"]:
+        # no pixel integrand: no image batches or tiles either
+        kw["image_batches"], kw["tile_px"] = 0, 0
     return make_problem(wl.target, wl.d, wl.K, wl.params, **kw)
 
 

@@ -275,6 +275,40 @@ def test_single_transitions_8d_learned_mu(R, c_tilde):
     assert k > 200 and a > 200
 
 
+def _pss_lobe_mu(wl, K=6, beta=0.2, seed=12):
+    """A learned-form mu for the 12-D integrand: components narrow in one
+    lobe's coordinate pair (near the lobe's direction) and wide elsewhere."""
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(0.2, 0.8, size=(K, 12))
+    log_std = np.full((K, 12), np.log(0.3))
+    for k in range(K):
+        l = k % 3
+        z = np.asarray(wl.params["lobe_dirs"]).reshape(-1)[3 * l + 2]
+        means[k, 2 * l] = (1 - z) / 2
+        log_std[k, 2 * l:2 * l + 2] = np.log(0.02)
+    return {"logits": rng.normal(size=K), "means": means, "log_std": log_std, "beta": beta}
+
+
+def test_init_and_single_transitions_pss_learned_mu(R):
+    """The 12-D image integrand with a learned-form mu: x_0 ~ mu against
+    the oracle, then single transitions after a warm-up (regenerations
+    from the mixture and local moves), splats into the image."""
+    from oracle import oracle as O
+    from workloads import pss_render
+    wl = pss_render(n_chains=8192, image=(128, 128), image_batches=2)
+    mu = _pss_lobe_mu(wl)
+    run = R.Run(R.problem_from_workload(wl, mu=mu))
+    _sync()
+    x = run.arrays()["x"].cpu().numpy().T.astype(np.float64)
+    run.close()
+    st = O.init_states(O.Problem(wl, mu=mu), np.arange(wl.n_chains))
+    err = np.abs(x - st.x) / np.maximum(1.0, np.abs(st.x))
+    _say(f"[pss learned mu init] max state rel err {err.max():.2e}")
+    assert err.max() <= 1e-6
+    k, a, m = _single_step_check(R, wl, warm=5, c_tilde=3.0, mu=mu, label="pss learned mu warm", lp_atol=4e-5)
+    assert k > 100 and a > 100
+
+
 # ---------------------------------------------------------------------------
 # whole runs
 # ---------------------------------------------------------------------------

@@ -225,3 +225,35 @@ def test_batch_mu_descriptors(R):
         with pytest.raises(R.RestoreError) as e:
             R.restore_batch_state_bytes([p.target], [p.local], [p.cfg], [bad])
         assert e.value.status == R.E_INVALID_ARG
+
+
+def test_tile_stratified_validation(R):
+    """Tiles need the pixel integrand, the uniform mu, c_tilde > 0, an edge
+    of 1..64 pixels and max(1, image_batches) chains per tile; they shrink
+    the state (no splat buckets)."""
+    p = _pss_problem(R)
+    binned = R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    p.cfg.tile_px = 64
+    tiled = R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert 0 < tiled < binned
+    # 16 tiles of 16 x 16 on the 64 x 64 image: 62 or 63 chains per tile
+    for field, value, status in (("tile_px", 65, R.E_INVALID_ARG), ("tile_px", -1, R.E_INVALID_ARG),
+                                 ("c_tilde", 0.0, R.E_UNSUPPORTED), ("image_batches", 63, R.E_INVALID_ARG)):
+        q = _pss_problem(R)
+        q.cfg.tile_px = 16
+        setattr(q.cfg, field, value)
+        with pytest.raises(R.RestoreError) as e:
+            R.restore_state_bytes(q.target, q.mu, q.local, q.cfg)
+        assert e.value.status == status, (field, value)
+    q = _pss_problem(R)
+    q.cfg.tile_px = 16
+    q.cfg.integrands &= ~R.INTEGRAND_PIXEL
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(q.target, q.mu, q.local, q.cfg)
+    assert e.value.status == R.E_INVALID_ARG
+    q = _pss_problem(R)
+    q.cfg.tile_px = 16
+    q.mu = R.restore_mu(R.MU_GMM_DIAG, 8, 0.1, 0, 256)
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(q.target, q.mu, q.local, q.cfg)
+    assert e.value.status == R.E_UNSUPPORTED

@@ -183,6 +183,8 @@ def bench_batched(args):
                      "pass_ms_events": ev_g, "traffic": None},
     }
     b.close()
+    if not args.no_mse_time:
+        line["mse_time_shared_mu"] = mse_time_batch()
     print(json.dumps(line), flush=True)
 
 
@@ -318,6 +320,67 @@ def mse_time_image(wl, replicates: int = 8, log=None) -> dict:
         res[key + "_ratio_at_provable_c_tilde"] = res["uniform"][0][key] / res["learned"][0][key]
         res[key + "_ratio_at_best_c_tilde"] = (min(c[key] for c in res["uniform"]) /
                                                min(c[key] for c in res["learned"]))
+    return res
+
+
+def mse_time_batch(replicates: int = 4, log=None) -> dict:
+    """Learned regeneration distributions for batched targets from one
+    shared network: 16 targets of dimension 8 (batched_family), one seeded
+    context vector each, one MLP whose G = 16 output rows are the targets'
+    mixtures, trained on the sum of the targets' losses (5 refits).  The
+    batch then runs every target with its own learned mixture at its
+    provable c~ against the same batch with uniform mu at the uniform rule's
+    c~: `replicates` fresh seeds per method, each pass timed (graph replay,
+    after a capturing warm-up) from launch to the per-target estimates;
+    scored by the relative error of every target's p_lambda against its
+    stored truth."""
+    import numpy as np
+    import torch
+    from paper_2409_07148_amd import restore as R
+    from paper_2409_07148_amd.learned_mu import MlpGmm, provable_c_tilde, refit_shared
+    from workloads import batched_family
+
+    fam = batched_family()
+    truth = np.asarray(json.load(open(os.path.join(ROOT, "tests", "golden", "truths.json")))
+                       ["batched_family_8d"]["p_lambda"])
+    model = MlpGmm(d=8, K=64, in_dim=12, hidden=64, beta=0.1, seed=3004, G=len(fam))
+    t0 = time.perf_counter()
+    hist = refit_shared(fam, model, refits=5, record_steps=4, epochs=300, lr=2e-2, seed=3004,
+                        c_tilde_explore=1.0, log=log or (lambda *a: None))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    def method(learned: bool):
+        secs, rel, se = [], [], []
+        for r in range(replicates):
+            wls = [w.with_(seed=2006 + 17 * r,
+                           c_tilde=provable_c_tilde(w.c_tilde, model.beta) if learned else w.c_tilde) for w in fam]
+            mus = [model.mu(g) for g in range(len(fam))] if learned else None
+            b = R.Batch(wls, n_steps=fam[0].n_steps, mus=mus)
+            b.run()                      # captures the pass
+            b.estimates()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            b.run()
+            est = b.estimates()
+            secs.append(time.perf_counter() - t1)
+            pl = np.array([e["p_lambda"] for e in est])
+            rel.append((pl - truth) / truth)
+            se.append(np.array([e["p_lambda_se"] for e in est]) / truth)
+            b.close()
+        rel = np.array(rel)
+        s = float(np.mean(secs))
+        mse = float(np.mean(rel ** 2))
+        per_target = np.sqrt(np.mean(rel ** 2, axis=0))
+        return {"seconds_per_pass": s, "p_lambda_rel_rmse": math.sqrt(mse),
+                "p_lambda_rel_rmse_per_target": [float(v) for v in per_target],
+                "p_lambda_rel_rmse_median_target": float(np.median(per_target)),
+                "mean_reported_rel_se": float(np.mean(se)), "mse_x_time": mse * s}
+
+    res = {"targets": len(fam), "dim": 8, "chains_per_target": fam[0].n_chains, "steps": fam[0].n_steps,
+           "replicates": replicates, "training_s": train_s, "training_refits": hist,
+           "mlp_rows": model.G, "uniform": method(False), "learned": method(True)}
+    res["mse_x_time_ratio_uniform_over_learned"] = res["uniform"]["mse_x_time"] / res["learned"]["mse_x_time"]
     return res
 
 

@@ -14,6 +14,11 @@ eq. (approx)), then take full-batch Adam steps on the time-weighted negative
 log-likelihood -sum dt log u_theta(x) / sum dt.  Every step (MLP forward/backward on the
 matrix cores, NLL and its gradient, Adam) runs in the library's kernels;
 this module only allocates the buffers and sequences the calls.
+
+With G > 1 context rows, one MLP gives one mixture per row: the batched
+targets' regeneration distributions from one shared network (one seeded
+context vector per target), trained on the sum of the targets' losses, so
+that the layers run as G-row GEMMs on the matrix cores.
 """
 from __future__ import annotations
 
@@ -30,7 +35,7 @@ from . import restore as R
 @dataclass
 class MlpGmm:
     """Parameters, optimiser state and work buffers of one MLP -> GMM map
-    on the current GPU (G = 1 context row)."""
+    on the current GPU, for G context rows (one mixture per row)."""
     d: int
     K: int = 64
     in_dim: int = 12
@@ -38,6 +43,7 @@ class MlpGmm:
     beta: float = 0.1
     seed: int = 3004
     init_std: float = 0.15
+    G: int = 1
     t: int = 0
     history: list = field(default_factory=list)
 
@@ -64,31 +70,32 @@ class MlpGmm:
         self.m = torch.zeros_like(self.theta)
         self.v = torch.zeros_like(self.theta)
         self.grad = torch.zeros_like(self.theta)
-        self.ctx = torch.from_numpy(rng.standard_normal((1, self.in_dim)).astype(np.float32)).to(dev)
-        self.act = torch.empty((1, n_act), dtype=torch.float32, device=dev)
-        self.out = torch.empty((1, O), dtype=torch.float32, device=dev)
-        self.dout = torch.empty((1, O), dtype=torch.float32, device=dev)
-        self.work = torch.empty((2, self.hidden), dtype=torch.float32, device=dev)
-        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.ctx = torch.from_numpy(rng.standard_normal((self.G, self.in_dim)).astype(np.float32)).to(dev)
+        self.act = torch.empty((self.G, n_act), dtype=torch.float32, device=dev)
+        self.out = torch.empty((self.G, O), dtype=torch.float32, device=dev)
+        self.dout = torch.empty((self.G, O), dtype=torch.float32, device=dev)
+        self.work = torch.empty((2 * self.G, self.hidden), dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(self.G, dtype=torch.float64, device=dev)
         ws = R.restore_gmm_nll_workspace_bytes()
         self.workspace = torch.empty(ws, dtype=torch.uint8, device=dev)
         self.forward()
 
     # --- one pass of each library call --------------------------------------
     def forward(self) -> torch.Tensor:
-        R.restore_mlp_forward(self.shape, self.theta.data_ptr(), self.ctx.data_ptr(), 1, self.act.data_ptr(),
+        R.restore_mlp_forward(self.shape, self.theta.data_ptr(), self.ctx.data_ptr(), self.G, self.act.data_ptr(),
                               self.out.data_ptr())
         return self.out
 
-    def nll_and_grad(self, x: torch.Tensor, w: torch.Tensor) -> None:
-        """loss and dL/d(out) on (x [n][d], w [n]) for the current out."""
+    def nll_and_grad(self, x: torch.Tensor, w: torch.Tensor, g: int = 0) -> None:
+        """loss[g] and dL/d(out[g]) on (x [n][d], w [n]) for the current out."""
         n = w.numel()
-        R.restore_gmm_nll(self.K, self.d, self.beta, self.out.data_ptr(), x.data_ptr(), w.data_ptr(), n,
-                          self.dout.data_ptr(), self.loss.data_ptr(), self.workspace.data_ptr(),
+        R.restore_gmm_nll(self.K, self.d, self.beta, self.out[g].data_ptr(), x.data_ptr(), w.data_ptr(), n,
+                          self.dout[g].data_ptr(), self.loss[g:].data_ptr(), self.workspace.data_ptr(),
                           self.workspace.numel())
 
     def backward(self) -> None:
-        R.restore_mlp_backward(self.shape, self.theta.data_ptr(), self.ctx.data_ptr(), 1, self.act.data_ptr(),
+        """grad = d(sum_g dout[g] . out[g]) / d theta."""
+        R.restore_mlp_backward(self.shape, self.theta.data_ptr(), self.ctx.data_ptr(), self.G, self.act.data_ptr(),
                                self.dout.data_ptr(), self.work.data_ptr(), self.grad.data_ptr())
 
     def adam(self, lr: float) -> None:
@@ -96,31 +103,41 @@ class MlpGmm:
         R.restore_adam_step(self.theta.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
                             self.n_params, self.t, lr)
 
-    def fit(self, x: torch.Tensor, w: torch.Tensor, epochs: int, lr: float, log_every: int = 0) -> list:
-        """Full-batch Adam on the weighted NLL of (x, w); returns the loss
-        after each logged epoch (losses are read back only when logged)."""
-        x = x.reshape(-1, self.d).contiguous()
-        w = w.reshape(-1).contiguous()
+    def fit(self, x, w, epochs: int, lr: float, log_every: int = 0) -> list:
+        """Full-batch Adam on the weighted NLL of (x, w) -- with G rows,
+        x and w are lists of G sample sets and the objective is the sum of
+        the rows' losses; returns the (summed) loss after each logged epoch
+        (losses are read back only when logged)."""
+        xs = list(x) if self.G > 1 else [x]
+        ws = list(w) if self.G > 1 else [w]
+        assert len(xs) == self.G and len(ws) == self.G
+        xs = [xi.reshape(-1, self.d).contiguous() for xi in xs]
+        ws = [wi.reshape(-1).contiguous() for wi in ws]
+
+        def losses_of_rows():
+            for g in range(self.G):
+                self.nll_and_grad(xs[g], ws[g], g)
+
         losses = []
         for e in range(epochs):
             self.forward()
-            self.nll_and_grad(x, w)
+            losses_of_rows()
             self.backward()
             self.adam(lr)
             if log_every and (e % log_every == 0 or e == epochs - 1):
-                losses.append((e, float(self.loss.item())))
+                losses.append((e, float(self.loss.sum().item())))
         self.forward()
-        self.nll_and_grad(x, w)
-        losses.append((epochs, float(self.loss.item())))
+        losses_of_rows()
+        losses.append((epochs, float(self.loss.sum().item())))
         self.history.append(losses)
         return losses
 
-    def mu(self) -> dict:
-        """restore_mu descriptor fields for the current parameters (the
-        device row is copied by restore_init, so later training does not
-        touch a run that has started)."""
+    def mu(self, g: int = 0) -> dict:
+        """restore_mu descriptor fields of row g for the current parameters
+        (the device row is copied by restore_init, so later training does
+        not touch a run that has started)."""
         self.forward()
-        return {"params_dev": self.out, "n_comp": self.K, "beta": self.beta}
+        return {"params_dev": self.out[g], "n_comp": self.K, "beta": self.beta}
 
 
 def provable_c_tilde(c_tilde_uniform: float, beta: float) -> float:
@@ -187,4 +204,37 @@ def refit(wl, model: MlpGmm, c_tilde_eval: float, refits: int = 5, record_steps:
                     "nll_first": losses[0][1], "nll_last": losses[-1][1], "seconds": sec})
         mu = model.mu()
         del x, w
+    return out
+
+
+def refit_shared(wls, model: MlpGmm, refits: int = 3, record_steps: int = 4, epochs: int = 300,
+                 lr: float = 2e-2, seed: int = 3004, c_tilde_explore: float = 1.0, log=print) -> list:
+    """refit() for G targets of one dimension sharing one model (row g is
+    target g's mixture): every refit records each target with its current
+    mixture (uniform mu at c~_explore in refit 0; afterwards at its
+    provable c~) and fits the shared parameters on the sum of the targets'
+    losses.  Returns per-refit diagnostics."""
+    assert model.G == len(wls) and all(w.d == model.d for w in wls)
+    out = []
+    for r in range(refits):
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        xs, ws = [], []
+        for g, wl in enumerate(wls):
+            mu = None if r == 0 else model.mu(g)
+            ct = c_tilde_explore if r == 0 else provable_c_tilde(wl.c_tilde, model.beta)
+            x, w = record_samples(wl, mu, ct, seed + 7919 * r + 104729 * g, record_steps)
+            xs.append(x)
+            ws.append(w)
+        losses = model.fit(xs, ws, epochs, lr, log_every=max(1, epochs // 4))
+        t1.record()
+        torch.cuda.synchronize()
+        sec = t0.elapsed_time(t1) / 1e3
+        log(f"[shared refit {r}] {model.G} targets x {ws[0].numel()} samples, summed nll "
+            f"{losses[0][1]:.4f} -> {losses[-1][1]:.4f}, {sec:.2f} s")
+        out.append({"refit": r, "targets": model.G, "samples_per_target": int(ws[0].numel()),
+                    "nll_first": losses[0][1], "nll_last": losses[-1][1], "seconds": sec})
+        del xs, ws
     return out

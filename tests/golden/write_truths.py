@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import truth  # noqa: E402
-from workloads import gmm_full, gmm_iso_2d, pss_render  # noqa: E402
+from workloads import batched_family, gmm_full, gmm_iso_2d, pss_render  # noqa: E402
 
 PATH = os.path.join(HERE, "truths.json")
 WORKLOADS = {"gmm_full_8d": gmm_full, "gmm_iso_2d": gmm_iso_2d}
@@ -36,6 +36,9 @@ def compute() -> dict:
     out["pss_render_12d"] = {"problem_seed": wl.problem_seed, "p_lambda": float(img.sum()),
                              "image": [w, h], "tile": PSS_TILE,
                              "tiles": [[float(v) for v in row] for row in tiles]}
+    fam = batched_family()
+    out["batched_family_8d"] = {"problem_seed": fam[0].problem_seed,
+                                "p_lambda": [truth.gmm_full_p_lambda(t) for t in fam]}
     return out
 
 

@@ -12,6 +12,7 @@ from .generators import (  # noqa: F401
     gmm_full,
     pss_render,
     batched_uneven,
+    batched_family,
     one_d_three_mode,
     WORKLOADS,
     get_workload,

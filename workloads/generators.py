@@ -223,6 +223,25 @@ def batched_uneven(n_targets: int = 256, problem_seed: int = 1005,
     return out
 
 
+def batched_family(n_targets: int = 16, d: int = 8, problem_seed: int = 1006, seed: int = 2006,
+                   n_steps: int = 512, n_chains: int = 1 << 16) -> List[Workload]:
+    """A family of batched targets of one dimension (the shared learned-mu
+    study): d-D full-covariance mixtures as in gmm_full with K uniform in
+    {8..16}, n_chains chains each, random-walk MH with sigma 0.02, uniform
+    mu, c_tilde by the lifetime rule of batched_uneven.  Target t uses
+    Philox target id t."""
+    rng = np.random.default_rng(problem_seed)
+    out = []
+    for t in range(n_targets):
+        K = int(rng.integers(8, 17))
+        w, m, c = _full_cov_mixture(rng, d, K)
+        peak = float((w * (2 * math.pi) ** (-d / 2) / np.sqrt(np.linalg.det(c))).sum())
+        c_tilde = float(f"{max(1.0, 8.0 * peak / n_steps):.2e}")
+        out.append(Workload(f"family_{t}", "gmm_full", d, K, {"weights": w, "means": m, "covs": c}, "rwmh",
+                            0.02, n_chains, n_steps, 4 * n_steps, c_tilde, seed, problem_seed))
+    return out
+
+
 def one_d_three_mode(c: float = 0.25) -> Workload:
     """A 1-D three-mode mixture on [0,1] in the spirit of the paper's
     global-discovery example.  The paper prints no mode locations, so these

@@ -327,13 +327,14 @@ def mse_time_batch(replicates: int = 4, log=None) -> dict:
     """Learned regeneration distributions for batched targets from one
     shared network: 16 targets of dimension 8 (batched_family), one seeded
     context vector each, one MLP whose G = 16 output rows are the targets'
-    mixtures, trained on the sum of the targets' losses (5 refits).  The
-    batch then runs every target with its own learned mixture at its
-    provable c~ against the same batch with uniform mu at the uniform rule's
-    c~: `replicates` fresh seeds per method, each pass timed (graph replay,
-    after a capturing warm-up) from launch to the per-target estimates;
-    scored by the relative error of every target's p_lambda against its
-    stored truth."""
+    mixtures, trained on the sum of the targets' losses (5 refits; the
+    exploratory first refit records 2^18 chains per target, so that more of
+    the targets' modes are found).  The batch then runs every target with
+    its own learned mixture at its provable c~ against the same batch with
+    uniform mu at the uniform rule's c~: `replicates` fresh seeds per
+    method, each pass timed (graph replay, after a capturing warm-up) from
+    launch to the per-target estimates; scored by the relative error of
+    every target's p_lambda against its stored truth."""
     import numpy as np
     import torch
     from paper_2409_07148_amd import restore as R
@@ -346,7 +347,7 @@ def mse_time_batch(replicates: int = 4, log=None) -> dict:
     model = MlpGmm(d=8, K=64, in_dim=12, hidden=64, beta=0.1, seed=3004, G=len(fam))
     t0 = time.perf_counter()
     hist = refit_shared(fam, model, refits=5, record_steps=4, epochs=300, lr=2e-2, seed=3004,
-                        c_tilde_explore=1.0, log=log or (lambda *a: None))
+                        c_tilde_explore=1.0, explore_chains=1 << 18, log=log or (lambda *a: None))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
 

@@ -208,12 +208,14 @@ def refit(wl, model: MlpGmm, c_tilde_eval: float, refits: int = 5, record_steps:
 
 
 def refit_shared(wls, model: MlpGmm, refits: int = 3, record_steps: int = 4, epochs: int = 300,
-                 lr: float = 2e-2, seed: int = 3004, c_tilde_explore: float = 1.0, log=print) -> list:
+                 lr: float = 2e-2, seed: int = 3004, c_tilde_explore: float = 1.0, explore_chains: int = 0,
+                 log=print) -> list:
     """refit() for G targets of one dimension sharing one model (row g is
     target g's mixture): every refit records each target with its current
-    mixture (uniform mu at c~_explore in refit 0; afterwards at its
-    provable c~) and fits the shared parameters on the sum of the targets'
-    losses.  Returns per-refit diagnostics."""
+    mixture (uniform mu at c~_explore in refit 0, with explore_chains
+    chains if given; afterwards at its provable c~) and fits the shared
+    parameters on the sum of the targets' losses.  Returns per-refit
+    diagnostics."""
     assert model.G == len(wls) and all(w.d == model.d for w in wls)
     out = []
     for r in range(refits):
@@ -225,7 +227,8 @@ def refit_shared(wls, model: MlpGmm, refits: int = 3, record_steps: int = 4, epo
         for g, wl in enumerate(wls):
             mu = None if r == 0 else model.mu(g)
             ct = c_tilde_explore if r == 0 else provable_c_tilde(wl.c_tilde, model.beta)
-            x, w = record_samples(wl, mu, ct, seed + 7919 * r + 104729 * g, record_steps)
+            src = wl.with_(n_chains=explore_chains) if (r == 0 and explore_chains) else wl
+            x, w = record_samples(src, mu, ct, seed + 7919 * r + 104729 * g, record_steps)
             xs.append(x)
             ws.append(w)
         losses = model.fit(xs, ws, epochs, lr, log_every=max(1, epochs // 4))

@@ -41,9 +41,37 @@ def c_tilde_rule(wl, sig: int = 3) -> float:
     return float(f"{v:.{sig - 1}e}")
 
 
+def c_tilde_unadjusted(wl, grid: int = 201, sig: int = 2) -> float:
+    """Local dynamics that are not pi-invariant (the unadjusted random-walk
+    jump process) need k = (c_tilde u + Q^T p - p) / p >= 0 everywhere
+    (Sec. 6.1, eq. (killing-rate)), i.e. c_tilde >= sup_box (p - Q^T p) / u
+    with u = 1 (uniform mu).  The supremum is located on a grid over the box
+    (oracle densities), refined by Nelder-Mead from the best grid point,
+    and doubled for margin; the result is rounded up."""
+    from scipy.optimize import minimize
+    from oracle import oracle as O
+    prob = O.Problem(wl)
+
+    def excess(x):
+        x = np.clip(np.asarray(x, dtype=np.float64).reshape(-1, wl.d), 0.0, 1.0)
+        return np.exp(O.log_target(prob, x)) - np.exp(O.log_inflow(prob, x))
+
+    g = np.linspace(0.0, 1.0, grid)
+    X = np.stack(np.meshgrid(*([g] * wl.d), indexing="ij"), axis=-1).reshape(-1, wl.d)
+    e = excess(X)
+    best = minimize(lambda x: -excess(x)[0], X[np.argmax(e)], method="Nelder-Mead",
+                    options={"xatol": 1e-7, "fatol": 1e-10})
+    sup = max(float(e.max()), -float(best.fun))
+    v = 2.0 * sup
+    scale = 10.0 ** (math.floor(math.log10(v)) - (sig - 1))
+    return math.ceil(v / scale) * scale
+
+
 if __name__ == "__main__":
     sys.path.insert(0, __file__.rsplit("/oracle/", 1)[0])
     from workloads import gmm_full, gmm_iso_2d, pss_render
     print("gmm_iso_2d", c_tilde_rule(gmm_iso_2d()))
     print("gmm_full_8d", c_tilde_rule(gmm_full()))
     print("pss_render_12d", c_tilde_rule(pss_render()))
+    print("gmm_iso_2d with the unadjusted random-walk jump process",
+          c_tilde_unadjusted(gmm_iso_2d().with_(local="rw_unadjusted", c_tilde=1.0)))

@@ -38,8 +38,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 TARGET_GMM, TARGET_PSS = 0, 1
 MU_UNIFORM, MU_GMM_DIAG = 0, 1
-LOCAL_RWMH, LOCAL_MALA, LOCAL_HMC = 0, 1, 2
-FLAG_KILL, FLAG_ACCEPT, FLAG_OUTSIDE, FLAG_LARGE = 1, 2, 4, 8
+LOCAL_RWMH, LOCAL_MALA, LOCAL_HMC, LOCAL_RW_UNADJUSTED = 0, 1, 2, 3
+FLAG_KILL, FLAG_ACCEPT, FLAG_OUTSIDE, FLAG_LARGE, FLAG_NEGATIVE_RATE = 1, 2, 4, 8, 16
 
 _dp = C.POINTER(C.c_double)
 
@@ -101,8 +101,12 @@ def load():
                                        C.POINTER(OrConfig), C.c_int64, C.POINTER(C.c_uint32),
                                        C.POINTER(C.c_uint32), _dp, _dp, _dp, _dp, C.c_int,
                                        _dp, C.POINTER(C.c_int32), _dp]
-    lib.oracle_init_states.argtypes = [C.POINTER(OrTarget), C.POINTER(OrMu), C.POINTER(OrConfig),
-                                       C.c_int64, C.POINTER(C.c_uint32), _dp, _dp, _dp, _dp]
+    lib.oracle_init_states.argtypes = [C.POINTER(OrTarget), C.POINTER(OrMu), C.POINTER(OrLocal),
+                                       C.POINTER(OrConfig), C.c_int64, C.POINTER(C.c_uint32), _dp, _dp, _dp, _dp]
+    lib.oracle_log_inflow.argtypes = [C.POINTER(OrTarget), C.c_double, _dp]
+    lib.oracle_log_inflow.restype = C.c_double
+    lib.oracle_log_u_eff.argtypes = [C.POINTER(OrTarget), C.POINTER(OrMu), C.c_double, C.c_double, _dp, C.c_double]
+    lib.oracle_log_u_eff.restype = C.c_double
     lib.oracle_run.argtypes = [C.POINTER(OrTarget), C.POINTER(OrMu), C.POINTER(OrLocal),
                                C.POINTER(OrConfig), C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                C.c_int32, C.POINTER(OrOutputs)]
@@ -205,7 +209,8 @@ class Problem:
 
         lk = OrLocal()
         local = local or wl.local
-        lk.kind = {"rwmh": LOCAL_RWMH, "mala": LOCAL_MALA, "hmc": LOCAL_HMC}[local]
+        lk.kind = {"rwmh": LOCAL_RWMH, "mala": LOCAL_MALA, "hmc": LOCAL_HMC,
+                   "rw_unadjusted": LOCAL_RW_UNADJUSTED}[local]
         lk.n_leapfrog = int(getattr(wl, "n_leapfrog", 0) if n_leapfrog is None else n_leapfrog)
         lk.step = float(wl.step if step is None else step)
         # l is a float32 at the library boundary; the oracle compares the
@@ -225,6 +230,11 @@ class Problem:
         cfg.n_chains_total = int(wl.n_chains if n_chains_total is None else n_chains_total)
         if tile_px and (mu is not None or not (image if image is not None else wl.image)):
             raise ValueError("tile-stratified runs need the image integrand and the uniform mu")
+        if lk.kind == LOCAL_RW_UNADJUSTED:
+            # the closed form of Q^T p needs diagonal covariances; the killing
+            # rate of the non-invariant process needs c_tilde > 0 and M^0
+            if wl.target != "gmm_iso" or not cfg.c_tilde > 0 or lk.large_step_prob != 0.0:
+                raise ValueError("the unadjusted jump process needs the isotropic mixture, c_tilde > 0 and l = 0")
         img = image if image is not None else wl.image
         if img:
             cfg.image_w, cfg.image_h = int(img[0]), int(img[1])
@@ -279,6 +289,27 @@ def leapfrog(prob: Problem, q, rho, n: int, e: float):
     return q, rho, lp.value, g, bool(inside)
 
 
+def log_inflow(prob: Problem, x: np.ndarray, sigma: Optional[float] = None) -> np.ndarray:
+    """log (Q^T p)(x) = log int_box p(y) N(x; y, sigma^2 I) dy at each row
+    of x (sigma defaults to the problem's step)."""
+    lib = load()
+    x = _f64(x).reshape(-1, prob.d)
+    s = float(prob.local.step if sigma is None else sigma)
+    return np.array([lib.oracle_log_inflow(C.byref(prob.target), s, _ptr(np.ascontiguousarray(r))) for r in x])
+
+
+def log_u_eff(prob: Problem, x: np.ndarray) -> np.ndarray:
+    """log u_eff(x), u_eff = u + (Q^T p - p) / c_tilde, the density the
+    killing rate k = c_tilde u_eff / p of the unadjusted jump process uses
+    (NaN where u_eff < 0)."""
+    lib = load()
+    x = _f64(x).reshape(-1, prob.d)
+    lp = log_target(prob, x)
+    return np.array([lib.oracle_log_u_eff(C.byref(prob.target), C.byref(prob.mu), float(prob.local.step),
+                                          float(prob.c_tilde), _ptr(np.ascontiguousarray(r)), float(v))
+                     for r, v in zip(x, lp)])
+
+
 def log_mu(prob: Problem, y: np.ndarray) -> np.ndarray:
     lib = load()
     y = _f64(y).reshape(-1, prob.d)
@@ -305,7 +336,7 @@ def init_states(prob: Problem, chains) -> States:
     chains = np.ascontiguousarray(np.asarray(chains, dtype=np.uint32))
     n, d = chains.shape[0], prob.d
     st = States(np.zeros((n, d)), np.zeros(n), np.zeros(n), np.zeros((n, d)))
-    lib.oracle_init_states(C.byref(prob.target), C.byref(prob.mu), C.byref(prob.cfg), n,
+    lib.oracle_init_states(C.byref(prob.target), C.byref(prob.mu), C.byref(prob.local), C.byref(prob.cfg), n,
                            _ptr(chains, C.c_uint32), _ptr(st.x), _ptr(st.lp), _ptr(st.lu), _ptr(st.g))
     return st
 
@@ -402,8 +433,17 @@ def _ratio(num: np.ndarray, den: np.ndarray):
 def estimate(r: RunResult) -> dict:
     """Sec. 6.3: p_lambda ~ (c_tilde / j) sum tau_i; lambda(p f) ~ (c_tilde / j)
     int f dt; Sec. 7.4 eq. (approx): pi f ~ sum dt f / sum dt.  j counts the
-    completed tours of all chains; censored tours are excluded."""
+    completed tours of all chains; censored tours are excluded, and so are
+    chains whose sums are not finite (a negative killing rate of the
+    unadjusted jump process makes them NaN), which are counted."""
     c = r.c_tilde
+    ok = np.isfinite(r.t_done) & np.isfinite(r.a_done)
+    nonfinite = int((~ok).sum())
+    if nonfinite:
+        r = RunResult(r.n_done[ok], r.t_done[ok], r.a_done[ok], r.censored[ok], r.t_censored[ok],
+                      r.transitions[ok], r.accepts[ok], r.kills[ok], r.image, r.c_tilde,
+                      None if r.large_steps is None else r.large_steps[ok],
+                      None if r.large_accepts is None else r.large_accepts[ok])
     if r.n_done.sum() > 0:
         pl, pl_se = _ratio(r.t_done, r.n_done)
         lpf, lpf_se = _ratio(r.a_done, r.n_done)
@@ -423,6 +463,7 @@ def estimate(r: RunResult) -> dict:
         "kill_rate": float(r.kills.sum() / max(1, r.transitions.sum())),
         "large_steps": int(r.large_steps.sum()) if r.large_steps is not None else 0,
         "large_accepts": int(r.large_accepts.sum()) if r.large_accepts is not None else 0,
+        "nonfinite": nonfinite,
     }
 
 

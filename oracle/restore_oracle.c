@@ -28,6 +28,20 @@
  *   - Sec. 6.3 / 7.4: the tour decomposition, the estimates
  *     p_lambda ~ (c_tilde / j) sum tau_i and lambda(p f) ~ (c_tilde / j)
  *     int f dt, and the time-weighted left-rectangle sums of eq. (approx).
+ *   - Sec. 6.1, eq. (killing-rate), for local dynamics that are NOT
+ *     pi-invariant: k = (c_tilde u + L* p) / p, with L* the adjoint of the
+ *     local process's generator.  The local process here is the unadjusted
+ *     random-walk jump process (rate 1, every jump y = x + sigma z taken,
+ *     no acceptance test), whose adjoint generator gives
+ *     L* p = Q^T p - p with (Q^T p)(x) = int p(y) N(x; y, sigma^2 I) dy;
+ *     for mixtures with diagonal covariances on the box the integral is a
+ *     product of Gaussian and erf terms.  The state caches log u_eff with
+ *     u_eff = u + L* p / c_tilde, so that k = c_tilde u_eff / p keeps the
+ *     form of the invariant case.  k must be non-negative everywhere
+ *     (c_tilde >= sup (p - Q^T p) / u); a state with u_eff < 0 makes the
+ *     step's holding time NaN, so the chain's sums are NaN and the chain
+ *     is excluded and counted as non-finite.  A jump off the box lands
+ *     where p = 0: k = +inf, killed at once with dt = 0.
  *   - Sec. 5, eq. (mixture-proposal-kernel), and the reference chain of
  *     Sec. 8 (practical setup): with large-step probability l a local
  *     update proposes y ~ mu instead of a small step.  The mixture is taken
@@ -78,9 +92,9 @@
 
 enum { OR_TARGET_GMM = 0, OR_TARGET_PSS = 1 };
 enum { OR_MU_UNIFORM = 0, OR_MU_GMM_DIAG = 1 };
-enum { OR_LOCAL_RWMH = 0, OR_LOCAL_MALA = 1, OR_LOCAL_HMC = 2 };
+enum { OR_LOCAL_RWMH = 0, OR_LOCAL_MALA = 1, OR_LOCAL_HMC = 2, OR_LOCAL_RW_UNADJUSTED = 3 };
 enum { OR_PURPOSE_INIT = 0, OR_PURPOSE_STEP = 1, OR_PURPOSE_LARGE = 2 };
-enum { OR_FLAG_KILL = 1, OR_FLAG_ACCEPT = 2, OR_FLAG_OUTSIDE = 4, OR_FLAG_LARGE = 8 };
+enum { OR_FLAG_KILL = 1, OR_FLAG_ACCEPT = 2, OR_FLAG_OUTSIDE = 4, OR_FLAG_LARGE = 8, OR_FLAG_NEGATIVE_RATE = 16 };
 
 /* Target density p on the unit box.
  * GMM: p(x) = sum_k w_k N(x; m_k, S_k) for x in [0,1]^d, 0 outside.
@@ -413,9 +427,61 @@ static void sample_mu_c(const or_mu *mu, const or_config *cfg, uint32_t chain, d
 
 typedef struct {
     double x[OR_MAXD];
-    double lp, lu;
+    double lp, lu;   /* log p(x); log u(x), or log u_eff(x) for the unadjusted jump process */
     double g[OR_MAXD];
 } or_state;
+
+/* log (Q^T p)(x) for the unadjusted random-walk jump process with jump
+ * N(0, sigma^2 I): the density at x of y + sigma z with y ~ p on the box,
+ * (Q^T p)(x) = int_box p(y) N(x; y, sigma^2 I) dy.  Needs a mixture whose
+ * components have diagonal covariances; per component and coordinate the
+ * Gaussian product identity
+ *   N(y; m, v) N(x; y, s) = N(x; m, v + s) N(y; c, t),
+ *   c = (m s + x v) / (v + s),   t = v s / (v + s),
+ * leaves the mass of N(c, t) on [0, 1]:
+ *   (erf((1 - c) / sqrt(2 t)) + erf(c / sqrt(2 t))) / 2. */
+double oracle_log_inflow(const or_target *t, double sigma, const double *x)
+{
+    int d = t->d;
+    double s = sigma * sigma, a[OR_MAXK];
+    for (int k = 0; k < t->K; ++k) {
+        const double *m = t->mean + (size_t)k * d;
+        const double *P = t->prec + (size_t)k * d * d;
+        double ak = t->log_w[k];
+        for (int i = 0; i < d; ++i) {
+            double v = 1.0 / P[i * d + i];
+            double c = (m[i] * s + x[i] * v) / (v + s);
+            double r = sqrt(2.0 * v * s / (v + s));
+            double dx = x[i] - m[i];
+            ak += -0.5 * log(2.0 * M_PI * (v + s)) - 0.5 * dx * dx / (v + s)
+                  + log(0.5 * (erf((1.0 - c) / r) + erf(c / r)));
+        }
+        a[k] = ak;
+    }
+    return log_sum_exp(t->K, a);
+}
+
+/* log u_eff(x), u_eff = u + (Q^T p - p) / c_tilde: the killing rate of
+ * eq. (killing-rate) is then k = c_tilde u_eff / p.  NAN where u_eff < 0. */
+double oracle_log_u_eff(const or_target *t, const or_mu *mu, double sigma, double c_tilde, const double *x,
+                        double lp)
+{
+    double u = exp(oracle_log_mu(mu, x));
+    double q = exp(oracle_log_inflow(t, sigma, x));
+    double p = lp == -INFINITY ? 0.0 : exp(lp);
+    double ue = u + (q - p) / c_tilde;
+    return ue >= 0.0 ? log(ue) : NAN;
+}
+
+/* the cached second density of a state: log u, or log u_eff for the
+ * unadjusted jump process */
+static double state_lu(const or_target *t, const or_mu *mu, const or_local *lk, const or_config *cfg,
+                       const double *x, double lp)
+{
+    if (lk && lk->kind == OR_LOCAL_RW_UNADJUSTED)
+        return oracle_log_u_eff(t, mu, lk->step, cfg->c_tilde, x, lp);
+    return oracle_log_mu(mu, x);
+}
 
 /* log q(a -> b) of the local proposal, up to the constant that cancels in
  * the acceptance ratio */
@@ -457,14 +523,14 @@ int oracle_leapfrog(const or_target *t, int n, double e, double *q, double *rho,
 }
 
 /* Initial state: x_0 ~ mu (purpose INIT, step 0). */
-void oracle_init_state(const or_target *t, const or_mu *mu, const or_config *cfg,
+void oracle_init_state(const or_target *t, const or_mu *mu, const or_local *lk, const or_config *cfg,
                        uint32_t chain, or_state *st)
 {
     double head[4], cand[OR_MAXD], margin;
     draw_step(cfg, t->d, 0, chain, OR_PURPOSE_INIT, head, cand);
     sample_mu_c(mu, cfg, chain, head[3], cand, st->x, &margin);
     st->lp = log_target_c(t, cfg, chain, st->x, st->g);
-    st->lu = oracle_log_mu(mu, st->x);
+    st->lu = state_lu(t, mu, lk, cfg, st->x, st->lp);
 }
 
 /* One Jump Restore transition from st at step `step`.
@@ -487,12 +553,13 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
     double t2, log_k;
     if (cfg->c_tilde == 0.0) { log_k = -INFINITY; t2 = INFINITY; }
     else if (st->lp == -INFINITY) { log_k = INFINITY; t2 = 0.0; }
+    else if (isnan(st->lu)) { log_k = NAN; t2 = NAN; }   /* negative killing rate */
     else { log_k = log(cfg->c_tilde) + st->lu - st->lp; t2 = e2 * exp(-log_k); }
     margins[0] = log(e2) - log_k - log(t1);
     margins[1] = NAN;
     margins[2] = INFINITY;
 
-    int32_t fl = 0;
+    int32_t fl = isnan(t2) ? OR_FLAG_NEGATIVE_RATE : 0;
     double dt;
     if (t1 < t2) {
         /* local state transition: one MH update, with the large-step kernel
@@ -525,10 +592,12 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
         }
         if (!in_box(d, y)) fl |= OR_FLAG_OUTSIDE;
         double lpy = log_target_c(t, cfg, chain, y, gy);
-        double luy = oracle_log_mu(mu, y);
+        double luy = large ? oracle_log_mu(mu, y) : state_lu(t, mu, lk, cfg, y, lpy);
         double alpha, lratio;
-        if (st->lp == -INFINITY) { alpha = 1.0; lratio = INFINITY; }
-        else {
+        if (st->lp == -INFINITY || (!large && lk->kind == OR_LOCAL_RW_UNADJUSTED)) {
+            /* alpha = 1 where p(x) q(x, y) = 0; the unadjusted jump is always taken */
+            alpha = 1.0; lratio = INFINITY;
+        } else {
             if (large)   /* independence proposal: q(x, y) = u(y) */
                 lratio = (lpy + st->lu) - (st->lp + luy);
             else if (hmc)   /* leapfrog is volume-preserving and reversible */
@@ -550,7 +619,7 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
         fl |= OR_FLAG_KILL;
         sample_mu_c(mu, cfg, chain, head[3], cand, st->x, &margins[2]);
         st->lp = log_target_c(t, cfg, chain, st->x, st->g);
-        st->lu = oracle_log_mu(mu, st->x);
+        st->lu = state_lu(t, mu, lk, cfg, st->x, st->lp);
     }
     *flags = fl;
     if (cfg->rb_dt) {
@@ -577,7 +646,7 @@ void oracle_transitions(const or_target *t, const or_mu *mu, const or_local *lk,
         for (int i = 0; i < d; ++i) st.x[i] = x[c * d + i];
         if (recompute) {
             st.lp = log_target_c(t, cfg, chains[c], st.x, st.g);
-            st.lu = oracle_log_mu(mu, st.x);
+            st.lu = state_lu(t, mu, lk, cfg, st.x, st.lp);
         } else {
             st.lp = lp[c]; st.lu = lu[c];
             for (int i = 0; i < d; ++i) st.g[i] = g[c * d + i];
@@ -588,14 +657,14 @@ void oracle_transitions(const or_target *t, const or_mu *mu, const or_local *lk,
     }
 }
 
-void oracle_init_states(const or_target *t, const or_mu *mu, const or_config *cfg,
+void oracle_init_states(const or_target *t, const or_mu *mu, const or_local *lk, const or_config *cfg,
                         int64_t n, const uint32_t *chains, double *x, double *lp,
                         double *lu, double *g)
 {
     int d = t->d;
     for (int64_t c = 0; c < n; ++c) {
         or_state st;
-        oracle_init_state(t, mu, cfg, chains[c], &st);
+        oracle_init_state(t, mu, lk, cfg, chains[c], &st);
         for (int i = 0; i < d; ++i) { x[c * d + i] = st.x[i]; g[c * d + i] = st.g[i]; }
         lp[c] = st.lp; lu[c] = st.lu;
     }
@@ -632,7 +701,7 @@ static void run_chain(const or_job *job, int64_t c)
 {
     const or_target *t = job->t; const or_config *cfg = job->cfg;
     or_state st;
-    oracle_init_state(t, job->mu, cfg, (uint32_t)c, &st);
+    oracle_init_state(t, job->mu, job->lk, cfg, (uint32_t)c, &st);
     double a_cur = 0.0, t_cur = 0.0, a_done = 0.0, t_done = 0.0;
     int64_t n_done = 0, trans = 0, acc = 0, kills = 0, large = 0, large_acc = 0;
     int alive = 1;

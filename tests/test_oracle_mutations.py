@@ -8,6 +8,7 @@ import subprocess
 import pytest
 
 from oracle import oracle as O
+from tests import test_oracle_general as gen
 from tests import test_oracle_hmc as hmc
 from tests import test_oracle_mh as mh
 from tests import test_oracle_pins as pins
@@ -95,6 +96,24 @@ MUTATIONS = {
     "tile_map_round_robin": ("int64_t t = (int64_t)chain * T / cfg->n_chains_total;",
                              "int64_t t = (int64_t)chain % T;",
                              [lambda: tiles.test_chains_stay_in_their_tile(None)]),
+    # inflow density of the unadjusted jump process without the jump variance
+    "inflow_variance_without_jump": ("ak += -0.5 * log(2.0 * M_PI * (v + s)) - 0.5 * dx * dx / (v + s)",
+                                     "ak += -0.5 * log(2.0 * M_PI * v) - 0.5 * dx * dx / (v + s)",
+                                     [lambda: gen.test_inflow_matches_quadrature(None)]),
+    # truncation factor centred with the weights of x and m swapped
+    "inflow_center_swapped": ("double c = (m[i] * s + x[i] * v) / (v + s);",
+                              "double c = (x[i] * s + m[i] * v) / (v + s);",
+                              [lambda: gen.test_inflow_matches_quadrature(None)]),
+    # general killing rate without the outflow term -p of L* p
+    "general_rate_drops_outflow": ("double ue = u + (q - p) / c_tilde;", "double ue = u + q / c_tilde;",
+                                   [lambda: gen.test_kill_law_uses_the_general_rate(None, "mode")]),
+    # the unadjusted jump put through a Metropolis-Hastings test
+    "unadjusted_jump_gets_mh_test": ("if (st->lp == -INFINITY || (!large && lk->kind == OR_LOCAL_RW_UNADJUSTED)) {",
+                                     "if (st->lp == -INFINITY) {",
+                                     [lambda: gen.test_kill_law_uses_the_general_rate(None, "tail")]),
+    # a negative killing rate silently clamped to zero
+    "negative_rate_clamped": ("return ue >= 0.0 ? log(ue) : NAN;", "return log(fmax(ue, 0.0));",
+                              [lambda: gen.test_negative_rate_marks_the_chain(None)]),
     # a completed tour not counted
     "tour_not_counted": ("a_done += a_cur; t_done += t_cur; ++n_done;",
                          "a_done += a_cur; t_done += t_cur;",

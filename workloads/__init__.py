@@ -9,6 +9,7 @@ parameters and derive everything else on their own.
 from .generators import (  # noqa: F401
     Workload,
     gmm_iso_2d,
+    gmm_iso_2d_unadjusted,
     gmm_full,
     pss_render,
     batched_uneven,

@@ -36,7 +36,8 @@ class Workload:
     K:           number of mixture components (0 for "pss").
     params:      canonical float64 parameters (see each generator).
     local:       "rwmh" (Gaussian random walk) | "mala" (Langevin proposal)
-                 | "hmc" (Hamiltonian Monte Carlo, leapfrog).
+                 | "hmc" (Hamiltonian Monte Carlo, leapfrog) | "rw_unadjusted"
+                 (random-walk jumps without acceptance test: not pi-invariant).
     step:        random-walk sigma, MALA epsilon or HMC leapfrog step size.
     n_leapfrog:  leapfrog steps per HMC update (0 for the other kernels).
     tile_px:     image integrand: tile edge of a tile-stratified run (0 off).
@@ -118,6 +119,23 @@ def gmm_iso_2d(n_chains: int = 4096, n_steps: int = 1000,
     }
     return Workload("gmm_iso_2d", "gmm_iso", 2, 4, params, "rwmh", 0.02,
                     n_chains, n_steps, 4 * n_steps, 1.0, seed, problem_seed)
+
+
+# c_tilde of the 2-D workload with the unadjusted random-walk jump process:
+# twice sup over the box of (p - Q^T p) / u, so that the killing rate
+# (c_tilde u + Q^T p - p) / p stays positive everywhere.  Written by
+# oracle/choose_c_tilde.py.
+C_TILDE_GMM_ISO_2D_UNADJUSTED = 7.7
+
+
+def gmm_iso_2d_unadjusted(n_chains: int = 4096, n_steps: int = 1000, problem_seed: int = 1001,
+                          seed: int = 2001) -> Workload:
+    """The 2-D target with local dynamics that are not pi-invariant: the
+    unadjusted random-walk jump process (rate 1, every jump x + sigma z
+    taken, sigma 0.02), whose killing rate carries the adjoint generator
+    term L* p = Q^T p - p."""
+    return gmm_iso_2d(n_chains, n_steps, problem_seed, seed).with_(
+        name="gmm_iso_2d_unadjusted", local="rw_unadjusted", c_tilde=C_TILDE_GMM_ISO_2D_UNADJUSTED)
 
 
 # c_tilde of the 8-D workload: 8 * P / B with P = sum_k w_k (2 pi)^(-d/2)
@@ -258,6 +276,7 @@ def one_d_three_mode(c: float = 0.25) -> Workload:
 
 WORKLOADS = {
     "gmm_iso_2d": gmm_iso_2d,
+    "gmm_iso_2d_unadjusted": gmm_iso_2d_unadjusted,
     "gmm_full_8d": gmm_full,
     "pss_render_12d": pss_render,
 }

@@ -45,6 +45,11 @@ def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: flo
     steps: Box-Muller, 2d per half or full momentum step and per position
     step, n density-and-gradient evaluations, the kinetic energies 4d and
     the acceptance 3.
+    The unadjusted random-walk jump process (isotropic mixture) needs the
+    inflow density Q^T p at every new state as well: per component and
+    coordinate 13 (offset, square, centre, two erf arguments, two erf, the
+    truncation factor), per component 8 (weight, log, log-sum-exp), and 10
+    to combine u_eff; its jump has no acceptance test.
     Returns the per-transition count averaged with the measured kill rate."""
     mala = local == "mala"
     if target == "pss":
@@ -64,6 +69,12 @@ def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: flo
     else:
         raise ValueError(target)
     f_kill = K * lp + 2 + 10
+    if local == "rw_unadjusted":
+        inflow = K * (13 * d + 8) + 10
+        f_kill += inflow
+        f_local = 10 + 5 * math.ceil(d / 2) + 3 * d + K * lp + 2 + inflow
+        return {"kill": float(f_kill), "local": float(f_local),
+                "mean": float(kill_rate * f_kill + (1.0 - kill_rate) * f_local)}
     if local == "hmc":
         n = max(1, n_leapfrog)
         f_local = (10 + 5 * math.ceil(d / 2) + 2 * d + n * 2 * d + (n - 1) * 2 * d + 2 * d
@@ -443,13 +454,66 @@ def restore_vs_mh(wl, replicates: int = 8, ell: float = 0.3, burn_in: int = 1000
     return out
 
 
+def general_vs_invariant(wl, replicates: int = 16) -> dict:
+    """Restore with local dynamics that are not pi-invariant (Sec. 6.1, eq.
+    (killing-rate): the unadjusted random-walk jump process, whose killing
+    rate carries L* p) against restore with the pi-invariant random-walk MH
+    kernel of the same step size (eq. (killing-rate-simplified)), on the
+    same 2-D target: the general process at its c~ (twice the smallest
+    c~ that keeps its rate non-negative), the invariant one at the 2-D
+    workload's c~ = 1 and at the general process's c~.  `replicates` fresh
+    seeds per configuration, each run timed on the wall clock from init to
+    estimate; relative errors of p_lambda, lambda(p f) and pi f (f = p)
+    against the stored closed-form truths."""
+    import numpy as np
+    import torch
+    from paper_2409_07148_amd import restore as R
+    from workloads import gmm_iso_2d
+
+    with open(os.path.join(ROOT, "tests", "golden", "truths.json")) as f:
+        tr = json.load(f)["gmm_iso_2d"]
+    inv = gmm_iso_2d(wl.n_chains, wl.n_steps)
+
+    def config(w, ct):
+        secs, rel, nonfin = [], {k: [] for k in ("p_lambda", "lam_pf", "pi_f")}, 0
+        for r in range(replicates):
+            prob = R.problem_from_workload(w, c_tilde=ct, seed=6006 + 37 * r)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            run = R.Run(prob)
+            run.step(w.n_steps)
+            run.drain()
+            est = run.estimate()
+            secs.append(time.perf_counter() - t)
+            run.close()
+            nonfin += est["nonfinite"]
+            for k in rel:
+                rel[k].append(est[k] / tr[k] - 1)
+        s = float(np.mean(secs))
+        out = {"local": w.local, "c_tilde": ct, "seconds_per_run": s, "nonfinite_chains": int(nonfin),
+               "kill_rate": est["kill_rate"], "transitions": int(est["transitions"])}
+        for k, v in rel.items():
+            v = np.asarray(v)
+            out[k] = {"rel_rmse": float(np.sqrt((v ** 2).mean())), "rel_bias": float(v.mean()),
+                      "mse_x_time": float((v ** 2).mean()) * s}
+        return out
+
+    res = {"replicates": replicates, "chains": wl.n_chains, "budget_steps": wl.n_steps,
+           "general": config(wl, wl.c_tilde), "invariant": config(inv, inv.c_tilde),
+           "invariant_same_c_tilde": config(inv, wl.c_tilde)}
+    res["mse_x_time_ratio_invariant_over_general"] = {
+        k: res["invariant"][k]["mse_x_time"] / res["general"][k]["mse_x_time"] for k in ("p_lambda", "lam_pf", "pi_f")}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gmm_full_8d",
-                    choices=["gmm_full_8d", "gmm_iso_2d", "pss_render_12d", "batched_uneven"])
+                    choices=["gmm_full_8d", "gmm_iso_2d", "gmm_iso_2d_unadjusted", "pss_render_12d",
+                             "batched_uneven"])
     ap.add_argument("--lds", action="store_true", help="stage mixture parameters in LDS")
     ap.add_argument("--hmc", type=int, default=0, metavar="N",
                     help="Gaussian-mixture workloads: Hamiltonian Monte Carlo local moves with N leapfrog "
@@ -474,16 +538,17 @@ def main():
 
     import torch
     from paper_2409_07148_amd import restore as R
-    from workloads import gmm_full, gmm_iso_2d, pss_render
+    from workloads import gmm_full, gmm_iso_2d, gmm_iso_2d_unadjusted, pss_render
 
     if args.workload == "batched_uneven":
         bench_batched(args)
         return
 
-    wl = {"gmm_full_8d": gmm_full, "gmm_iso_2d": gmm_iso_2d, "pss_render_12d": pss_render}[args.workload]()
+    wl = {"gmm_full_8d": gmm_full, "gmm_iso_2d": gmm_iso_2d, "gmm_iso_2d_unadjusted": gmm_iso_2d_unadjusted,
+          "pss_render_12d": pss_render}[args.workload]()
     if args.hmc:
-        if wl.target == "pss":
-            sys.exit("--hmc needs a Gaussian-mixture workload")
+        if wl.target == "pss" or wl.local == "rw_unadjusted":
+            sys.exit("--hmc needs a Gaussian-mixture workload with pi-invariant local moves")
         wl = wl.with_(local="hmc", n_leapfrog=args.hmc)
     if args.tiles:
         if wl.target != "pss":
@@ -580,8 +645,10 @@ def main():
                                                     "accept_rate")},
     }
     truths = json.load(open(os.path.join(ROOT, "tests", "golden", "truths.json")))
-    if wl.name in truths:
-        tr = truths[wl.name]
+    # the unadjusted-jump workload has the 2-D workload's target
+    truth_key = "gmm_iso_2d" if wl.name == "gmm_iso_2d_unadjusted" else wl.name
+    if truth_key in truths:
+        tr = truths[truth_key]
         line["estimates"]["rel_err_vs_truth"] = {
             k: (line["estimates"][k] - tr[k]) / tr[k] for k in ("p_lambda", "lam_pf") if k in tr}
     if image is not None and wl.name in truths and list(truths[wl.name]["image"]) == [prob.cfg.image_w,
@@ -615,6 +682,8 @@ def main():
             w2 = gmm_iso_2d()
             line["restore_vs_mh"]["gmm_iso_2d"] = restore_vs_mh(
                 w2.with_(local="hmc", n_leapfrog=args.hmc) if args.hmc else w2)
+    if wl.name == "gmm_iso_2d_unadjusted":
+        line["general_vs_invariant"] = general_vs_invariant(wl)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

@@ -114,7 +114,9 @@ typedef struct {
 } restore_mu;
 
 /* ---- local dynamics: the small-step kernel zeta of Alg. 1 -------------
- * The three diffusion-derived kernels of the paper's study (Sec. 9). */
+ * The three diffusion-derived kernels of the paper's study (Sec. 9), all
+ * pi-invariant MH updates, and one local process that is not
+ * pi-invariant (the general restore process of Sec. 6.1). */
 #define RESTORE_LOCAL_RWMH   0    /* y = x + step z                              */
 #define RESTORE_LOCAL_MALA   1    /* y = x + (step^2 / 2) grad log p(x) + step z  */
 #define RESTORE_LOCAL_HMC    2    /* Hamiltonian Monte Carlo: momentum rho_0 = z,
@@ -126,10 +128,29 @@ typedef struct {
                                      visits a point with p = 0 is rejected.  One
                                      leapfrog step is the MALA proposal.  Built
                                      for the mixture targets with uniform mu. */
+#define RESTORE_LOCAL_RW_UNADJUSTED 3 /* local dynamics that are NOT pi-invariant
+                                     (Sec. 6.1): the unadjusted random-walk jump
+                                     process, every holding-clock firing jumps
+                                     y = x + step z with no acceptance test.  The
+                                     killing rate is then the general one of eq.
+                                     (killing-rate), k = (c_tilde u + L* p) / p
+                                     with L* p = Q^T p - p and (Q^T p)(x) =
+                                     int p(y) N(x; y, step^2 I) dy over the box
+                                     (closed form with erf for the isotropic
+                                     mixture).  Needs c_tilde >= sup (p - Q^T p)
+                                     / u for k >= 0; a chain that reaches a
+                                     state where k < 0 gets NaN sums and is
+                                     counted in `nonfinite`.  A jump off the box
+                                     lands where p = 0 and is killed at the next
+                                     step with dt = 0.  The state's log u slot
+                                     holds log u_eff, u_eff = u + L* p / c_tilde.
+                                     Built for GMM_ISO with the uniform mu;
+                                     c_tilde > 0 (INVALID_ARG otherwise). */
 
 typedef struct {
     int32_t kind;
-    float step;              /* random-walk sigma or MALA epsilon (>= 0)        */
+    float step;              /* random-walk or jump sigma, MALA or HMC epsilon
+                                (>= 0; > 0 except for RWMH)                  */
     float large_step_prob;   /* l in [0,1] of eq. (mixture-proposal-kernel).
                                 The restore process (c_tilde > 0) uses the
                                 pure small-step chain M^0 (Sec. 8), so l must

@@ -17,7 +17,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librestore.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["step_kernels.hip", "step_kernels_hmc.hip", "splat_kernels.hip", "reduce_kernels.hip", "batch_kernels.hip", "learn_kernels.hip",
+SOURCES = ["step_kernels.hip", "step_kernels_hmc.hip", "step_kernels_rwu.hip", "splat_kernels.hip", "reduce_kernels.hip", "batch_kernels.hip", "learn_kernels.hip",
            "restore_api.cpp", "batch_api.cpp", "learn_api.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-x", "hip",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

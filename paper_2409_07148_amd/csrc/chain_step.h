@@ -46,6 +46,30 @@ __device__ __forceinline__ float log_mu(const StepArgs &a, const float y[D]) {
     }
 }
 
+// The second cached density of a state.  For the pi-invariant local
+// kernels it is log u, and k = c_tilde u / p (Sec. 6.2, eq.
+// (killing-rate-simplified)).  For the unadjusted random-walk jump process
+// it is log u_eff with u_eff = u + (Q^T p - p) / c_tilde, so that the same
+// k = c_tilde u_eff / p is the rate (c_tilde u + L* p) / p of Sec. 6.1,
+// eq. (killing-rate) (L* p = Q^T p - p).  Where u_eff < 0 (c_tilde below
+// sup (p - Q^T p) / u) the value is NaN: the step's holding time is then
+// NaN and the chain's sums are reported as non-finite.  Off the box (p = 0,
+// k = inf) it is not used and set to 0.
+template <int D, int TGT, int LOC, int MU, class PT>
+__device__ __forceinline__ float log_u_state(const StepArgs &a, PT P, const float y[D], float lp) {
+    const float lu = log_mu<D, MU>(a, y);
+    if constexpr (LOC == LOC_RWU && TGT == TGT_ISO) {
+        if (lp == -INFINITY) return 0.0f;
+        const float lq = GmmIsoInflow<D>::log_inflow(P, a.n_comp, y) - a.log_c;
+        const float M = fmaxf(lu, lq);
+        const float v = expf(lu - M) + expf(lq - M) - expf((lp - a.log_c) - M);
+        return v >= 0.0f ? M + logf(v) : NAN;
+    } else {
+        (void)P; (void)lp;
+        return lu;
+    }
+}
+
 template <int D, int MU, int NC>
 __device__ __forceinline__ void sample_mu(const StepArgs &a, float u_cat, const float cand[NC], float y[D]) {
     if constexpr (MU == MU_GMM) {
@@ -372,12 +396,12 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         // the chain's target is p restricted to its tile
         if (!in_tile(a, y, ch.tpx0, ch.tpy0, ch.tw, ch.th)) lpy = -INFINITY;
     }
-    const float luy = log_mu<D, MU>(a, y);
+    const float luy = (MH && large) ? log_mu<D, MU>(a, y) : log_u_state<D, TGT, LOC, MU>(a, P, y, lpy);
 
     accept = false;
     if (!kill) {
-        if (ch.lp == -INFINITY) {
-            accept = true;  // alpha = 1 where p(x) q(x, y) = 0
+        if (ch.lp == -INFINITY || LOC == LOC_RWU) {
+            accept = true;  // alpha = 1 where p(x) q(x, y) = 0; the unadjusted jump is always taken
         } else {
             float lr = lpy - ch.lp;
             if (MH && large) {

@@ -58,6 +58,7 @@ hipError_t launch_image_estimate(const ImageEstimateArgs &a, hipStream_t stream)
 
 KernelSet find_kernels(int tgt, int d, int loc, int mu);
 KernelSet find_kernels_hmc(int tgt, int d, int mu);   // loc = LOC_HMC
+KernelSet find_kernels_rwu(int tgt, int d, int mu);   // loc = LOC_RWU
 
 // Float64 reduction of the per-chain tour sums (see reduce_kernels.hip).
 struct ReduceArgs {

@@ -93,9 +93,9 @@ SplatPlan splat_plan(const restore_config *cfg, int tgt) {
     return sp;
 }
 
-int n_param_floats(int tgt, int d, int K) {
+int n_param_floats(int tgt, int loc, int d, int K) {
     if (tgt == TGT_PSS) return PSS_SLAB;
-    return comp_stride(tgt, d) * K;
+    return comp_stride(tgt, d) * K + (loc == LOC_RWU ? INFLOW_STRIDE * K : 0);
 }
 
 Layout make_layout(int64_t C, int d, bool grad, int n_params, int n_mu_floats, const SplatPlan &sp) {
@@ -135,6 +135,7 @@ Layout make_layout(int64_t C, int d, bool grad, int n_params, int n_mu_floats, c
 
 struct Validated {
     int tgt, d, K, loc, mu;
+    double step;   // jump sigma of the unadjusted random-walk process (LOC_RWU)
 };
 
 bool all_finite(const double *p, int64_t n) {
@@ -173,11 +174,21 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
                         RESTORE_MAX_COMP);
         if (!(mu->beta >= 0.0f && mu->beta <= 1.0f)) return fail(RESTORE_E_INVALID_ARG, "mu beta outside [0,1]");
     }
-    if (lk->kind != RESTORE_LOCAL_RWMH && lk->kind != RESTORE_LOCAL_MALA && lk->kind != RESTORE_LOCAL_HMC)
+    if (lk->kind != RESTORE_LOCAL_RWMH && lk->kind != RESTORE_LOCAL_MALA && lk->kind != RESTORE_LOCAL_HMC &&
+        lk->kind != RESTORE_LOCAL_RW_UNADJUSTED)
         return fail(RESTORE_E_INVALID_ARG, "unknown local kernel %d", lk->kind);
     if (!std::isfinite(lk->step) || lk->step < 0.0f) return fail(RESTORE_E_INVALID_ARG, "step must be >= 0");
     if (lk->kind != RESTORE_LOCAL_RWMH && !(lk->step > 0.0f))
-        return fail(RESTORE_E_INVALID_ARG, "MALA and HMC need step > 0");
+        return fail(RESTORE_E_INVALID_ARG, "MALA, HMC and the unadjusted jump process need step > 0");
+    if (lk->kind == RESTORE_LOCAL_RW_UNADJUSTED) {
+        // Q^T p in closed form needs diagonal covariances; the killing rate
+        // (c_tilde u + L* p) / p needs c_tilde > 0; only the uniform mu is built
+        if (t->kind != RESTORE_TARGET_GMM_ISO || mu->kind != RESTORE_MU_UNIFORM_BOX)
+            return fail(RESTORE_E_UNSUPPORTED,
+                        "the unadjusted random-walk jump process is built for the isotropic mixture with uniform mu");
+        if (!(cfg->c_tilde > 0.0))
+            return fail(RESTORE_E_INVALID_ARG, "the unadjusted random-walk jump process needs c_tilde > 0");
+    }
     if (lk->kind == RESTORE_LOCAL_HMC ? (lk->n_leapfrog < 1 || lk->n_leapfrog > 64) : lk->n_leapfrog != 0)
         return fail(RESTORE_E_INVALID_ARG, "n_leapfrog must be 1..64 for HMC and 0 otherwise");
     if (!(lk->large_step_prob >= 0.0f && lk->large_step_prob <= 1.0f))
@@ -220,7 +231,10 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
     v->tgt = t->kind == RESTORE_TARGET_GMM_ISO ? TGT_ISO : t->kind == RESTORE_TARGET_GMM_FULL ? TGT_FULL : TGT_PSS;
     v->d = d;
     v->K = t->kind == RESTORE_TARGET_PSS ? 0 : K;
-    v->loc = lk->kind == RESTORE_LOCAL_MALA ? LOC_MALA : lk->kind == RESTORE_LOCAL_HMC ? LOC_HMC : LOC_RWMH;
+    v->loc = lk->kind == RESTORE_LOCAL_MALA ? LOC_MALA
+             : lk->kind == RESTORE_LOCAL_HMC ? LOC_HMC
+             : lk->kind == RESTORE_LOCAL_RW_UNADJUSTED ? LOC_RWU : LOC_RWMH;
+    v->step = lk->step;
     v->mu = mu->kind == RESTORE_MU_GMM_DIAG ? MU_GMM : MU_UNIFORM;
     return RESTORE_OK;
 }
@@ -232,14 +246,24 @@ restore_status pack_params(const restore_target *t, const Validated &v, std::vec
     const double LN2PI = std::log(2.0 * M_PI);
     if (v.tgt == TGT_ISO) {
         const int S = comp_stride(TGT_ISO, d);
-        out->assign((size_t)S * K, 0.0f);
+        out->assign((size_t)n_param_floats(v.tgt, v.loc, d, K), 0.0f);
         const double *w = p, *m = p + K, *s = p + K + (size_t)K * d;
+        const double j2 = v.step * v.step;
         for (int k = 0; k < K; ++k) {
             if (!(w[k] >= 0.0) || !(s[k] > 0.0)) return fail(RESTORE_E_INVALID_ARG, "weights >= 0, sigmas > 0");
             float *o = out->data() + (size_t)k * S;
             o[0] = (float)(std::log(w[k]) - 0.5 * d * (LN2PI + 2.0 * std::log(s[k])));
             for (int i = 0; i < d; ++i) o[1 + i] = (float)m[(size_t)k * d + i];
             o[1 + d] = (float)(1.0 / (s[k] * s[k]));
+            if (v.loc == LOC_RWU) {
+                // Q^T p terms (layout in restore_internal.h)
+                const double s2 = s[k] * s[k], tot = s2 + j2, alpha = s2 / tot;
+                float *q = out->data() + (size_t)K * S + (size_t)k * INFLOW_STRIDE;
+                q[0] = (float)(std::log(w[k]) - 0.5 * d * (LN2PI + std::log(tot)));
+                q[1] = (float)(1.0 / tot);
+                q[2] = (float)alpha;
+                q[3] = (float)(1.0 / std::sqrt(2.0 * alpha * j2));
+            }
         }
         return RESTORE_OK;
     }
@@ -499,7 +523,7 @@ restore_status restore_state_bytes(const restore_target *target, const restore_m
     Validated v;
     restore_status st = validate(target, mu, local, cfg, &v);
     if (st != RESTORE_OK) return st;
-    *bytes_out = make_layout(cfg->n_chains, v.d, uses_grad(v.loc), n_param_floats(v.tgt, v.d, v.K),
+    *bytes_out = make_layout(cfg->n_chains, v.d, uses_grad(v.loc), n_param_floats(v.tgt, v.loc, v.d, v.K),
                              v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0, splat_plan(cfg, v.tgt)).total;
     return RESTORE_OK;
 }
@@ -517,7 +541,7 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
         return fail(RESTORE_E_INVALID_ARG, "state buffer must be 256-byte aligned");
     if ((cfg->integrands & RESTORE_INTEGRAND_PIXEL) && !image_dev)
         return fail(RESTORE_E_INVALID_ARG, "pixel integrand needs an image buffer");
-    const int n_params = n_param_floats(v.tgt, v.d, v.K);
+    const int n_params = n_param_floats(v.tgt, v.loc, v.d, v.K);
     const int n_mu = v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0;
     const SplatPlan sp = splat_plan(cfg, v.tgt);
     const Layout lay = make_layout(cfg->n_chains, v.d, uses_grad(v.loc), n_params, n_mu, sp);

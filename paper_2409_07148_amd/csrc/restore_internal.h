@@ -6,7 +6,9 @@
 namespace restore {
 
 enum TargetKind : int { TGT_ISO = 0, TGT_FULL = 1, TGT_PSS = 2 };
-enum LocalKind : int { LOC_RWMH = 0, LOC_MALA = 1, LOC_HMC = 2 };
+// LOC_RWU: the unadjusted random-walk jump process (every jump taken, not
+// pi-invariant; its killing rate carries the adjoint generator term)
+enum LocalKind : int { LOC_RWMH = 0, LOC_MALA = 1, LOC_HMC = 2, LOC_RWU = 3 };
 // the local kernels that use grad log p (cached per chain in the state)
 __host__ __device__ constexpr bool uses_grad(int loc) { return loc == LOC_MALA || loc == LOC_HMC; }
 enum MuKind : int { MU_UNIFORM = 0, MU_GMM = 1 };
@@ -39,6 +41,12 @@ constexpr int CNT_LINE = 32;
 __host__ __device__ constexpr int comp_stride(int kind, int d) {
     return kind == TGT_ISO ? ((2 + d + 3) / 4) * 4 : ((1 + d + d * (d + 1) / 2 + 3) / 4) * 4;
 }
+// ISO with the unadjusted random-walk jump process (jump N(0, sigma^2 I)):
+// after the K components, K groups of INFLOW_STRIDE floats for Q^T p,
+//   [ c'_k | 1/(s_k^2 + sigma^2) | alpha_k | beta_k ],
+//   c'_k = ln w_k - d/2 ln(2 pi (s_k^2 + sigma^2)),  alpha_k = s_k^2 / (s_k^2 + sigma^2),
+//   beta_k = 1 / sqrt(2 alpha_k sigma^2).
+constexpr int INFLOW_STRIDE = 4;
 
 // Rendering-shaped integrand slab (float32):
 //   [0,16)  texture A frequencies (8 x 2)      [16,24) amplitudes / 8   [24,32) phases / (2 pi)

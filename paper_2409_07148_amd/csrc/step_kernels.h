@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void init_kernel(StepArgs a) {
     ch.lp = log_target<D, TGT, uses_grad(LOC)>((const_fptr)a.params, a.n_comp, ch.x, ch.g);
     if (TGT == TGT_PSS && a.tile_px > 0 && !in_tile(a, ch.x, tile.px0, tile.py0, tile.w, tile.h))
         ch.lp = -INFINITY;
-    ch.lu = log_mu<D, MU>(a, ch.x);
+    ch.lu = log_u_state<D, TGT, LOC, MU>(a, (const_fptr)a.params, ch.x, ch.lp);
     ch.a_cur = ch.t_cur = 0.0f;
     ch.a_done = ch.t_done = 0.0;
     ch.n_done = 0u;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void refresh_kernel(StepArgs a) {
         if (!in_tile(a, x, t.px0, t.py0, t.w, t.h)) lp = -INFINITY;
     }
     a.logp[c] = lp;
-    a.logu[c] = log_mu<D, MU>(a, x);
+    a.logu[c] = log_u_state<D, TGT, LOC, MU>(a, (const_fptr)a.params, x, lp);
     if (uses_grad(LOC)) {
 #pragma unroll
         for (int i = 0; i < D; ++i) a.grad[i * C + c] = g[i];

@@ -8,6 +8,7 @@ namespace restore {
 
 KernelSet find_kernels(int tgt, int d, int loc, int mu) {
     if (loc == LOC_HMC) return find_kernels_hmc(tgt, d, mu);
+    if (loc == LOC_RWU) return find_kernels_rwu(tgt, d, mu);
     if (mu == MU_GMM) {
         // learned regeneration distribution: the mixtures of the learned-mu workloads
         if (tgt == TGT_FULL && loc == LOC_MALA) {

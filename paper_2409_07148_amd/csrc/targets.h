@@ -58,6 +58,40 @@ struct GmmIso {
     }
 };
 
+// log (Q^T p)(y) of the isotropic mixture for the unadjusted random-walk
+// jump process with jump N(0, sigma^2 I): the density at y of x + sigma z
+// with x ~ p on the box, (Q^T p)(y) = int_box p(x) N(y; x, sigma^2 I) dx.
+// Per component and coordinate the Gaussian product identity leaves
+// N(y_i; m_i, s^2 + sigma^2) times the box mass of a Gaussian centred at
+// c_i = m_i + alpha (y_i - m_i) with 1 / sqrt(2 var) = beta:
+//   (erf(beta (1 - c_i)) + erf(beta c_i)) / 2.
+// The parameters (INFLOW_STRIDE per component) follow the K components.
+template <int D>
+struct GmmIsoInflow {
+    template <class PT>
+    __device__ __forceinline__ static float log_inflow(PT P, int K, const float y[D]) {
+        const auto A = P + K * GmmIso<D>::STRIDE;
+        float M = -INFINITY, S = 0.0f;
+        for (int k = 0; k < K; ++k) {
+            const auto pk = P + k * GmmIso<D>::STRIDE;
+            const auto qk = A + k * INFLOW_STRIDE;
+            const float ivar = qk[1], alpha = qk[2], beta = qk[3];
+            float q = 0.0f, mass = 1.0f;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const float dx = y[i] - pk[1 + i];
+                q = fmaf(dx, dx, q);
+                const float c = fmaf(alpha, dx, pk[1 + i]);
+                mass *= 0.5f * (erff(beta * (1.0f - c)) + erff(beta * c));
+            }
+            const float ak = fmaf(-0.5f * ivar, q, qk[0]) + logf(mass);
+            float sc, w;
+            lse_push(M, S, ak, sc, w);
+        }
+        return M + logf(S);
+    }
+};
+
 // Full-covariance Gaussian mixture with whitening factors W_k = L_k^-1
 // (S_k = L_k L_k^T, W_k lower triangular):
 //   v_k = W_k (y - m_k),  a_k = c_k - |v_k|^2 / 2,

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "librestore.so")
 OK, E_INVALID_ARG, E_UNSUPPORTED, E_HIP, E_NONFINITE, E_BAD_STATE, E_BUFFER_TOO_SMALL = 0, -1, -2, -3, -4, -5, -6
 TARGET_GMM_ISO, TARGET_GMM_FULL, TARGET_PSS = 0, 1, 2
 MU_UNIFORM_BOX, MU_GMM_DIAG = 0, 1
-LOCAL_RWMH, LOCAL_MALA, LOCAL_HMC = 0, 1, 2
+LOCAL_RWMH, LOCAL_MALA, LOCAL_HMC, LOCAL_RW_UNADJUSTED = 0, 1, 2, 3
 INTEGRAND_ONE, INTEGRAND_P, INTEGRAND_PIXEL = 1, 2, 4
 FLAG_PARAMS_LDS, FLAG_SPLAT_DIRECT, FLAG_SPLAT_TIGHT, FLAG_RB_DT = 1, 2, 4, 8
 ST_ALIVE, ST_CENSORED, ST_LAST_KILL, ST_LAST_ACCEPT, ST_GRAD_VALID, ST_LAST_LARGE = 1, 2, 4, 8, 16, 32
@@ -395,7 +395,7 @@ def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: f
         mu_t = torch.cat([torch.as_tensor(np.asarray(mu[k], dtype=np.float32).ravel())
                           for k in ("logits", "means", "log_std")]).cuda()
         m = restore_mu(MU_GMM_DIAG, int(np.asarray(mu["logits"]).size), float(mu["beta"]), 0, mu_t.data_ptr())
-    kind = {"rwmh": LOCAL_RWMH, "mala": LOCAL_MALA, "hmc": LOCAL_HMC}[local]
+    kind = {"rwmh": LOCAL_RWMH, "mala": LOCAL_MALA, "hmc": LOCAL_HMC, "rw_unadjusted": LOCAL_RW_UNADJUSTED}[local]
     lk = restore_local_kernel(kind, float(step), float(large_step_prob), int(n_leapfrog))
     integrands = INTEGRAND_ONE | (INTEGRAND_P if integrand_p else 0) | (INTEGRAND_PIXEL if image else 0)
     w, h = (image or (0, 0))

@@ -118,6 +118,35 @@ def test_local_kernel_validation(R):
     assert e.value.status == R.E_INVALID_ARG
 
 
+def test_unadjusted_jump_process_validation(R):
+    """The unadjusted random-walk jump process (not pi-invariant, general
+    killing rate) is built for the isotropic mixture with the uniform mu
+    and needs c_tilde > 0 and a positive jump size; its slab carries the
+    Q^T p terms (4 floats per component more)."""
+    from workloads import gmm_iso_2d, gmm_iso_2d_unadjusted
+    wl = gmm_iso_2d_unadjusted(n_chains=1000)
+    p = R.problem_from_workload(wl)
+    assert p.local.kind == R.LOCAL_RW_UNADJUSTED
+    n_rwu = R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    q = R.problem_from_workload(gmm_iso_2d(n_chains=1000))
+    assert n_rwu >= R.restore_state_bytes(q.target, q.mu, q.local, q.cfg) > 0
+    p = R.problem_from_workload(wl)
+    p.cfg.c_tilde = 0.0
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_INVALID_ARG
+    p = R.problem_from_workload(wl)
+    p.local.step = 0.0
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_INVALID_ARG
+    p = _problem(R)   # full-covariance target: no closed-form Q^T p
+    p.local.kind = R.LOCAL_RW_UNADJUSTED
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_UNSUPPORTED
+
+
 def test_init_rejects_null_and_small_buffers(R):
     p = _problem(R)
     n = R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)

@@ -545,6 +545,35 @@ def test_whole_run_8d_learned_mu_matches_oracle_and_truth(R):
         assert abs(est[key] - tr[key]) < 3 * est[key + "_se"]
 
 
+def test_full_size_8d_learned_mu_sampled_chains_match_oracle(R):
+    """The 8-D workload at full size (2^20 chains x 512 steps + drain) with a
+    regeneration distribution of the learned form at its provable c~
+    (c~_U / beta), the configuration of the learned-mu MSE x time runs; 128
+    chains spread over the population are rerun by the oracle."""
+    from workloads import gmm_full
+    from oracle import oracle as O
+    from tests import helpers as H
+    wl = gmm_full()
+    mu = H.mixture_mu_from_target(wl)
+    ct = wl.c_tilde / mu["beta"]
+    _say("[full 8d learned mu] gpu run 2^20 x 512")
+    est, arr = _gpu_run(R, wl, mu=mu, c_tilde=ct)
+    _say(f"[full 8d learned mu] transitions {est['transitions']} tours {est['tours_done']} "
+         f"censored {est['tours_censored']}")
+    rng = np.random.default_rng(4)
+    ids = np.unique(np.concatenate([rng.integers(0, wl.n_chains, 124), [0, 1, wl.n_chains - 2, wl.n_chains - 1]]))
+    oprob = O.Problem(wl, mu=mu, c_tilde=ct)
+    same = 0
+    for c in ids:
+        r = O.run(oprob, int(c), int(c) + 1, threads=1)
+        same += (int(arr["n_done"][c]) == int(r.n_done[0]) and
+                 abs(arr["t_done"][c] - r.t_done[0]) <= 1e-4 * max(1e-30, abs(r.t_done[0])) and
+                 abs(arr["a_done"][c] - r.a_done[0]) <= 1e-3 * max(1e-30, abs(r.a_done[0])))
+    _say(f"[full 8d learned mu] sampled chains identical to the oracle: {same}/{len(ids)}")
+    assert same >= len(ids) - 2
+    assert est["tours_censored"] == 0
+
+
 # ---------------------------------------------------------------------------
 # determinism and edge cases
 # ---------------------------------------------------------------------------

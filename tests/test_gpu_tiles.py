@@ -109,7 +109,8 @@ def test_tiled_single_transitions(R):
 def test_tiled_full_size_matches_truth(R):
     """The image workload at full size, 2^20 chains x 256 steps on 512^2
     pixels in 64 x 64 tiles with 16 batch images: estimate against the
-    truth, image tiles against the per-pixel truth, SE calibration."""
+    truth, image tiles against the per-pixel truth, and 128 sampled
+    chains against the oracle."""
     import json, os
     from workloads import pss_render
     wl = pss_render().with_(tile_px=64)
@@ -130,4 +131,18 @@ def test_tiled_full_size_matches_truth(R):
          f"(z {z:.2f}); image {t}x{t}-block rel RMSE {np.sqrt(np.mean(rel ** 2)):.3f}; censored "
          f"{est['tours_censored']}")
     assert abs(z) < 4 and est["tours_censored"] == 0
+    # chains spread over the population (and so over the tiles) rerun by the
+    # oracle from the same counters, each with its own tile
+    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done")}
     run.close()
+    from oracle import oracle as O
+    oprob = O.Problem(wl)
+    rng = np.random.default_rng(6)
+    ids = np.unique(np.concatenate([rng.integers(0, wl.n_chains, 124), [0, 1, wl.n_chains - 2, wl.n_chains - 1]]))
+    same = 0
+    for c in ids:
+        r = O.run(oprob, int(c), int(c) + 1, threads=1)
+        same += (int(arr["n_done"][c]) == int(r.n_done[0]) and
+                 abs(arr["t_done"][c] - r.t_done[0]) <= 1e-4 * max(1e-30, abs(r.t_done[0])))
+    _say(f"[tiles full] sampled chains identical to the oracle: {same}/{len(ids)}")
+    assert same >= len(ids) - 2

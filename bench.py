@@ -194,6 +194,23 @@ def bench_batched(args):
                      "pass_ms_events": ev_g, "traffic": None},
     }
     b.close()
+    truths = json.load(open(os.path.join(ROOT, "tests", "golden", "truths.json")))
+    if "batched_uneven" in truths:
+        import numpy as np
+        tr = np.asarray(truths["batched_uneven"]["p_lambda"])
+        pl = np.array([e["p_lambda"] for e in est])
+        se = np.array([e["p_lambda_se"] for e in est])
+        rel = pl / tr - 1
+        z = (pl - tr) / se
+        dims = np.array([w.d for w in wls])
+        line["estimates"] = {
+            "p_lambda_rel_err_vs_truth": {"median_abs": float(np.median(np.abs(rel))),
+                                          "max_abs": float(np.abs(rel).max()),
+                                          "median_abs_d_le_4": float(np.median(np.abs(rel[dims <= 4]))),
+                                          "median_abs_d_ge_12": float(np.median(np.abs(rel[dims >= 12])))},
+            "fraction_within_3_se": float(np.mean(np.abs(z) < 3)),
+            "tours_censored": int(sum(e["tours_censored"] for e in est)),
+        }
     if not args.no_mse_time:
         line["mse_time_shared_mu"] = mse_time_batch()
     print(json.dumps(line), flush=True)

@@ -17,14 +17,21 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import truth  # noqa: E402
-from workloads import batched_family, gmm_full, gmm_iso_2d, pss_render  # noqa: E402
+from workloads import batched_family, batched_uneven, gmm_full, gmm_iso_2d, pss_render  # noqa: E402
 
 PATH = os.path.join(HERE, "truths.json")
 WORKLOADS = {"gmm_full_8d": gmm_full, "gmm_iso_2d": gmm_iso_2d}
 PSS_TILE = 8   # the image truth is stored as sums over 8 x 8-pixel tiles
 
 
-def compute() -> dict:
+def _uneven_p_lambda(i: int) -> float:
+    return truth.gmm_full_p_lambda(batched_uneven()[i])
+
+
+def compute(uneven_targets=None) -> dict:
+    """All stored truths; `uneven_targets` limits the 256 batched targets
+    to the given indices (the pins check a sample: the full set takes
+    minutes of Genz integration)."""
     out = {}
     for name, make in WORKLOADS.items():
         wl = make()
@@ -39,6 +46,14 @@ def compute() -> dict:
     fam = batched_family()
     out["batched_family_8d"] = {"problem_seed": fam[0].problem_seed,
                                 "p_lambda": [truth.gmm_full_p_lambda(t) for t in fam]}
+    # the 256 batched targets (d up to 16, K up to 32): p_lambda only,
+    # the box probabilities of their components by Genz's method
+    from multiprocessing import Pool
+    uneven = batched_uneven()
+    idx = range(len(uneven)) if uneven_targets is None else list(uneven_targets)
+    with Pool(min(8, os.cpu_count() or 1)) as pool:
+        pl = pool.map(_uneven_p_lambda, idx)
+    out["batched_uneven"] = {"problem_seed": uneven[0].problem_seed, "p_lambda": [float(v) for v in pl]}
     return out
 
 

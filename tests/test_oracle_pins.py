@@ -480,7 +480,13 @@ def test_stored_truths_match_the_oracle():
     import write_truths
     with open(write_truths.PATH) as f:
         stored = json.load(f)
-    fresh = write_truths.compute()
+    # the batched targets: the first, the last and the largest, and a seeded sample
+    from workloads import batched_uneven
+    ts = batched_uneven()
+    big = max(range(len(ts)), key=lambda i: ts[i].d * ts[i].K)
+    sample = sorted({0, len(ts) - 1, big, *np.random.default_rng(8).choice(len(ts), 5, replace=False).tolist()})
+    fresh = write_truths.compute(uneven_targets=sample)
+    stored["batched_uneven"]["p_lambda"] = [stored["batched_uneven"]["p_lambda"][i] for i in sample]
     assert stored.keys() == fresh.keys()
     for name in fresh:
         for k, v in fresh[name].items():

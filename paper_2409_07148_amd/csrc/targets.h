@@ -30,6 +30,11 @@ struct GmmIso {
         float G[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) G[i] = 0.0f;
+        // unrolled by four: the parameters of four neighbouring components
+        // are then fetched with wide scalar loads and one wait, instead of a
+        // wait per component (a small launch has no other wave on the SIMD
+        // to hide the scalar-load latency)
+#pragma unroll 4
         for (int k = 0; k < K; ++k) {
             const auto pk = P + k * STRIDE;
             const float ivar = pk[1 + D];
@@ -72,6 +77,8 @@ struct GmmIsoInflow {
     __device__ __forceinline__ static float log_inflow(PT P, int K, const float y[D]) {
         const auto A = P + K * GmmIso<D>::STRIDE;
         float M = -INFINITY, S = 0.0f;
+        // unrolled by four for wide scalar loads, as in GmmIso::eval
+#pragma unroll 4
         for (int k = 0; k < K; ++k) {
             const auto pk = P + k * GmmIso<D>::STRIDE;
             const auto qk = A + k * INFLOW_STRIDE;

@@ -147,3 +147,26 @@ def test_unadjusted_single_transitions_other_shapes(R, d, K):
     for lds in (False, True):
         _single_step_check(R, wl, x_init=x0, label=f"rwu d{d} K{K} pi lds={lds}", lds=lds)
         _single_step_check(R, wl, warm=4, label=f"rwu d{d} K{K} warm lds={lds}", lds=lds)
+
+
+def test_unadjusted_rao_blackwellised_holding_time(R):
+    """With RESTORE_FLAG_RB_DT the general process accumulates
+    E[dt | x] = 1 / (1 + k) with its own rate k = c_tilde u_eff / p: single
+    transitions after warm-up against the oracle with the same option, and
+    the whole 2-D workload within 3 SE of the oracle's run and of the truth,
+    with the same tours as the sampled run and no larger SE."""
+    from oracle import oracle as O, truth
+    from workloads import gmm_iso_2d_unadjusted
+    _single_step_check(R, gmm_iso_2d_unadjusted(n_chains=8192), warm=5, label="rwu rb warm", rb=True)
+    wl = gmm_iso_2d_unadjusted()
+    est, _ = _gpu_run(R, wl, flags=R.FLAG_RB_DT)
+    ref, _ = _gpu_run(R, wl)
+    oest = O.estimate(O.run(O.Problem(wl, rb_dt=True), 0, wl.n_chains))
+    tr = truth.truths(wl)
+    assert est["tours_done"] == ref["tours_done"] and est["transitions"] == ref["transitions"]
+    for key in ("p_lambda", "lam_pf", "pi_f"):
+        _say(f"[rwu rb] {key}: gpu {est[key]:.6g} +- {est[key + '_se']:.2g} (sampled dt: +- {ref[key + '_se']:.2g}) "
+             f"oracle {oest[key]:.6g} truth {tr[key]:.6g}")
+        assert abs(est[key] - oest[key]) < 3 * math.hypot(est[key + "_se"], oest[key + "_se"])
+        assert abs(est[key] - tr[key]) < 3 * est[key + "_se"]
+        assert est[key + "_se"] <= 1.02 * ref[key + "_se"]

@@ -702,9 +702,13 @@ restore_status restore_drain(restore_ctx *c, void *stream) {
     const void *fn = tiled ? c->ks.drain_tiled : c->lds ? c->ks.drain_lds : c->ks.drain;
     const size_t shm = (c->lds && !tiled) ? (size_t)c->n_params * sizeof(float) : 0;
     // chunks of 1, 2, 4, ... steps: survivors are compacted between chunks
-    // while many chains retire, and the long tail takes few launches
+    // while many chains retire, and the long tail takes few launches.  A
+    // population below 2^16 chains has too few waves to fill the chip, so
+    // the lanes a long chunk leaves idle cost nothing: one launch runs the
+    // whole cap (each wave ends when its last lane retires) and saves the
+    // launches and compactions.  Each chain takes the same steps either way.
     int32_t remaining = c->cfg.drain_cap;
-    int64_t chunk = 1;
+    int64_t chunk = c->cfg.n_chains < (1LL << 16) ? std::max<int64_t>(1, c->cfg.drain_cap) : 1;
     uint32_t s0 = (uint32_t)c->steps_taken;
     for (int j = 0;; ++j) {
         const int32_t L = remaining < chunk ? remaining : (int32_t)chunk;

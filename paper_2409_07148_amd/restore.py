@@ -165,6 +165,16 @@ def _check(status: int) -> None:
         raise RestoreError(status, _lib.restore_last_error().decode())
 
 
+def _record_on(stream, *tensors) -> None:
+    """Tell torch's caching allocator that kernels on `stream` (a torch
+    stream other than the current one) use these buffers, so their memory
+    is not reused before that stream's work is done."""
+    if isinstance(stream, torch.cuda.Stream) and stream != torch.cuda.current_stream():
+        for t in tensors:
+            if t is not None:
+                t.record_stream(stream)
+
+
 def _stream(stream) -> int:
     if stream is None:
         return torch.cuda.current_stream().cuda_stream
@@ -437,6 +447,7 @@ class Run:
             nb = max(1, prob.cfg.image_batches)
             shape = (nb, prob.cfg.image_h, prob.cfg.image_w) if nb > 1 else (prob.cfg.image_h, prob.cfg.image_w)
             self.image = torch.zeros(shape, dtype=torch.float32, device="cuda")
+        _record_on(stream, self.state, self.image)
         self.ctx = restore_init(prob.target, prob.mu, prob.local, prob.cfg, self._state_ptr, nbytes,
                                 self.image.data_ptr() if self.image is not None else 0, stream)
         self.n_chains = prob.cfg.n_chains
@@ -542,6 +553,7 @@ class Batch:
         nbytes = restore_batch_state_bytes(targets, locs, cfgs, mu_desc)
         self.state = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         ptr = (self.state.data_ptr() + 255) // 256 * 256
+        _record_on(stream, self.state)
         self.handle = restore_batch_init(targets, locs, cfgs, n_steps, ptr, nbytes, stream, mu_desc)
 
     def run(self, mode: int = BATCH_MODE_GRAPH):

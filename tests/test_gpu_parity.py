@@ -610,6 +610,27 @@ def test_drain_lds_matches_scalar_params(R):
     assert e1["p_lambda"] == e2["p_lambda"] and e1["transitions"] == e2["transitions"]
 
 
+def test_side_stream_gives_the_same_chains(R):
+    """A run enqueued on a torch stream other than the current one (default
+    priority) gives chains bit-identical to the run on the current stream;
+    the binding records its buffers on that stream."""
+    import torch
+    from workloads import gmm_iso_2d
+    wl = gmm_iso_2d(n_chains=4096, n_steps=300)
+    ref, arr_ref = _gpu_run(R, wl)
+    side = torch.cuda.Stream()
+    run = R.Run(R.problem_from_workload(wl), stream=side)
+    run.step(wl.n_steps)
+    run.drain()
+    est = run.estimate()
+    side.synchronize()
+    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done", "a_done")}
+    run.close()
+    for k in ("n_done", "t_done", "a_done"):
+        assert np.array_equal(arr[k], arr_ref[k]), k
+    assert est["p_lambda"] == ref["p_lambda"] and est["transitions"] == ref["transitions"]
+
+
 @pytest.mark.parametrize("n_chains", [1, 63, 65, 1000])
 def test_ragged_chain_counts(R, n_chains):
     from workloads import gmm_iso_2d

@@ -285,8 +285,10 @@ restore_status restore_step(restore_ctx *ctx, int32_t n_steps, void *stream);
  * tour in flight is killed (it then retires) or drain_cap further steps
  * have passed (the tour is censored: excluded from the estimates, counted
  * and reported).  Retired chains are compacted out of the launches with
- * wavefront ballots.  After restore_drain no further restore_step.  For
- * the MH chain (c_tilde = 0) there is nothing to finish: no launch. */
+ * wavefront ballots (launches of 1, 2, 4, ... steps; below 2^16 chains one
+ * launch over the whole cap); the chains are the same either way.  After
+ * restore_drain no further restore_step.  For the MH chain (c_tilde = 0)
+ * there is nothing to finish: no launch. */
 restore_status restore_drain(restore_ctx *ctx, void *stream);
 
 /* Burn-in of the MH chain (c_tilde = 0; the paper's MH baselines discard

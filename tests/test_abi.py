@@ -286,3 +286,20 @@ def test_tile_stratified_validation(R):
     with pytest.raises(R.RestoreError) as e:
         R.restore_state_bytes(q.target, q.mu, q.local, q.cfg)
     assert e.value.status == R.E_UNSUPPORTED
+
+
+def test_binding_refuses_to_load_without_the_library(tmp_path):
+    """No fallback: a copy of the binding next to no library raises
+    ImportError on import (the product path never runs without the HIP
+    kernels)."""
+    import shutil
+    import sys
+    pkg = tmp_path / "pkg_copy"
+    pkg.mkdir()
+    here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2409_07148_amd")
+    shutil.copy(os.path.join(here, "restore.py"), pkg / "restore.py")
+    (pkg / "__init__.py").write_text("")
+    r = subprocess.run([sys.executable, "-c", "import pkg_copy.restore"], cwd=tmp_path, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "no fallback" in r.stderr

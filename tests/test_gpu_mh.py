@@ -153,6 +153,42 @@ def test_mh_whole_run_matches_oracle_and_truth(R, rb):
     run.close()
 
 
+def test_mh_whole_run_8d_learned_mu_matches_oracle(R):
+    """M^l on the 8-D mixture with MALA small steps and large steps from a
+    mixture mu of the learned form (the pairing of the benchmark's MH
+    comparison with the learned mixture; 4096 chains, 2000-step burn-in, 512
+    steps, unit holding times): the ergodic average within 3 SE of the Genz
+    truth and of the oracle's run of the first 1024 chains, whose sums it
+    reproduces chain by chain."""
+    from oracle import oracle as O, truth
+    from tests import helpers as H
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=4096)
+    mu = H.mixture_mu_from_target(wl)
+    burn, n = 2000, 512
+    _say("[mh run 8d learned mu] start")
+    run = R.Run(R.problem_from_workload(wl, c_tilde=0.0, mu=mu, large_step_prob=ELL, flags=R.FLAG_RB_DT))
+    run.step(burn)
+    run.reset_sums()
+    run.step(n)
+    run.drain()
+    est = run.estimate()
+    a_g = run.arrays()["a_done"].cpu().numpy()
+    run.close()
+    tr = truth.truths(wl)
+    c_or = 1024
+    r = O.run(O.Problem(wl, c_tilde=0.0, mu=mu, large_step_prob=ELL, burn_in=burn, rb_dt=True), 0, c_or,
+              n_steps=burn + n)
+    eo = O.estimate(r)
+    same = np.abs(a_g[:c_or] - r.a_done) <= 1e-4 * np.abs(r.a_done)
+    _say(f"[mh run 8d learned mu] gpu pi_f {est['pi_f']:.6g} +- {est['pi_f_se']:.2g}, oracle (first {c_or}) "
+         f"{eo['pi_f']:.6g} +- {eo['pi_f_se']:.2g}, truth {tr['pi_f']:.6g}; chains with equal sums {same.mean():.3f}; "
+         f"large-step acceptance {est['large_accepts'] / est['large_steps']:.3f}")
+    assert same.mean() > 0.9
+    assert abs(est["pi_f"] - tr["pi_f"]) < 3 * est["pi_f_se"]
+    assert abs(est["pi_f"] - eo["pi_f"]) < 3 * math.hypot(est["pi_f_se"], eo["pi_f_se"])
+
+
 def test_reset_sums_only_for_the_mh_chain(R):
     from workloads import gmm_iso_2d
     wl = gmm_iso_2d(n_chains=1024)

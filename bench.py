@@ -139,6 +139,24 @@ def cpu_baseline(wl, target_seconds: float = 12.0) -> dict:
             "one_core_rate": float(one_core), "one_core_sample": "chains 0..1023, one thread"}
 
 
+def cpu_baseline_batched(wls, chains_per_target: int = 512) -> dict:
+    """The FP64 oracle on the host cores for the batched workload: the first
+    min(C_t, chains_per_target) chains of every target (its own Philox
+    target id, full budget and drain), timed as one job."""
+    from oracle import oracle as O
+    threads = len(os.sched_getaffinity(0))
+    probs = [O.Problem(w, target_id=i) for i, w in enumerate(wls)]
+    t0 = time.perf_counter()
+    trans = 0
+    for w, pr in zip(wls, probs):
+        r = O.run(pr, 0, min(w.n_chains, chains_per_target), threads=threads)
+        trans += int(r.transitions.sum())
+    el = time.perf_counter() - t0
+    return {"value": trans / el, "unit": "transitions/s", "cores": threads, "kind": "oracle",
+            "sample": f"chains 0..{chains_per_target - 1} (or all) of each of the {len(wls)} targets, full "
+                      f"{wls[0].n_steps}-step budget + drain, {trans} transitions in {el:.1f} s"}
+
+
 def bench_batched(args):
     """256 uneven full-covariance targets: the autotuned persistent launch
     replayed from a hipGraph against one launch per target."""
@@ -213,6 +231,8 @@ def bench_batched(args):
         }
     if not args.no_mse_time:
         line["mse_time_shared_mu"] = mse_time_batch()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batched(wls)
     print(json.dumps(line), flush=True)
 
 

@@ -310,8 +310,10 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
                               for ct in sorted({cts[0], res[name + "_best"]["c_tilde"]}, reverse=True)]
     res["t_1pct_learned_amortised_s"] = (res["learned"]["lam_pf"]["t_1pct_s"] + train_s / replicates)
     # the paper's MH comparison with the learned mixture on both sides:
-    # restore regenerating from it, M^l proposing its large steps from it
-    res["restore_vs_mh_learned_mu"] = restore_vs_mh(wl, mu=mu, c_tilde=ct_learned)
+    # restore regenerating from it (at its provable c~ and at the best c~ of
+    # its sweep), M^l proposing its large steps from it
+    res["restore_vs_mh_learned_mu"] = restore_vs_mh(wl, mu=mu, c_tilde=ct_learned,
+                                                    c_tilde_best=res["learned_best"]["c_tilde"])
     return res
 
 
@@ -437,7 +439,7 @@ def mse_time_batch(replicates: int = 4, log=None) -> dict:
 
 
 def restore_vs_mh(wl, replicates: int = 8, ell: float = 0.3, burn_in: int = 10000, mu=None,
-                  c_tilde=None) -> dict:
+                  c_tilde=None, c_tilde_best=None) -> dict:
     """The paper's central comparison (Sec. 8, Sec. 9) on a synthetic target:
     the restore process (the workload's c~, uniform mu, small-step kernel
     M^0) against the Metropolis-Hastings chain M^l with the mixture proposal
@@ -449,7 +451,8 @@ def restore_vs_mh(wl, replicates: int = 8, ell: float = 0.3, burn_in: int = 1000
     timed on the wall clock from init to estimate, scored against the
     stored closed-form truth.  With `mu` (a learned regeneration
     distribution) both methods use it: restore regenerates from it at
-    `c_tilde`, and M^l draws its large steps from it."""
+    `c_tilde` (and, if given, also at `c_tilde_best`), and M^l draws its
+    large steps from it."""
     import numpy as np
     import torch
     from paper_2409_07148_amd import restore as R
@@ -459,10 +462,10 @@ def restore_vs_mh(wl, replicates: int = 8, ell: float = 0.3, burn_in: int = 1000
 
     ct_restore = wl.c_tilde if c_tilde is None else c_tilde
 
-    def one(mh: bool, r: int):
+    def one(mh: bool, r: int, ct=None):
         prob = (R.problem_from_workload(wl, mu=mu, c_tilde=0.0, large_step_prob=ell, seed=5005 + 31 * r,
                                         flags=R.FLAG_RB_DT) if mh else
-                R.problem_from_workload(wl, mu=mu, c_tilde=ct_restore, seed=5005 + 31 * r))
+                R.problem_from_workload(wl, mu=mu, c_tilde=ct_restore if ct is None else ct, seed=5005 + 31 * r))
         torch.cuda.synchronize()
         t = time.perf_counter()
         run = R.Run(prob)
@@ -478,8 +481,11 @@ def restore_vs_mh(wl, replicates: int = 8, ell: float = 0.3, burn_in: int = 1000
 
     out = {"quantity": "pi_f (f = p)", "truth": truth, "replicates": replicates,
            "mu": "uniform" if mu is None else "learned"}
-    for name, mh in (("restore", False), ("mh", True)):
-        rr = [one(mh, r) for r in range(replicates)]
+    methods = [("restore", False, None), ("mh", True, None)]
+    if c_tilde_best is not None:
+        methods.append(("restore_best", False, c_tilde_best))
+    for name, mh, ct in methods:
+        rr = [one(mh, r, ct) for r in range(replicates)]
         secs = float(np.mean([t for t, _ in rr]))
         rel = np.array([(e["pi_f"] - truth) / truth for _, e in rr])
         mse = float((rel ** 2).mean())
@@ -493,11 +499,13 @@ def restore_vs_mh(wl, replicates: int = 8, ell: float = 0.3, burn_in: int = 1000
                       "holding_time": "1 per step (discrete-time average)",
                       "large_step_accept_rate": la / max(1, ls)})
         else:
-            o.update({"c_tilde": ct_restore, "budget_steps": wl.n_steps,
+            o.update({"c_tilde": ct_restore if ct is None else ct, "budget_steps": wl.n_steps,
                       "drain_cap": wl.drain_cap,
                       "censored_tours": int(sum(e["tours_censored"] for _, e in rr))})
         out[name] = o
     out["mse_x_time_ratio_mh_over_restore"] = out["mh"]["mse_x_time"] / out["restore"]["mse_x_time"]
+    if c_tilde_best is not None:
+        out["mse_x_time_ratio_mh_over_restore_best"] = out["mh"]["mse_x_time"] / out["restore_best"]["mse_x_time"]
     return out
 
 

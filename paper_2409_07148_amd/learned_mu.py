@@ -45,6 +45,7 @@ class MlpGmm:
     init_std: float = 0.15
     G: int = 1
     t: int = 0
+    rollbacks: int = 0
     history: list = field(default_factory=list)
 
     def __post_init__(self):
@@ -103,7 +104,7 @@ class MlpGmm:
         R.restore_adam_step(self.theta.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
                             self.n_params, self.t, lr)
 
-    def fit(self, x, w, epochs: int, lr: float, log_every: int = 0) -> list:
+    def fit(self, x, w, epochs: int, lr: float, log_every: int = 0, rise_tol: float = 0.5) -> list:
         """Full-batch Adam on the weighted NLL of (x, w) -- with G rows,
         x and w are lists of G sample sets and the objective is the sum of
         the rows' losses; returns the (summed) loss after each logged epoch
@@ -118,19 +119,55 @@ class MlpGmm:
             for g in range(self.G):
                 self.nll_and_grad(xs[g], ws[g], g)
 
+        # Adam can leave the stable region (heavy-tailed time weights make
+        # single samples dominate the gradient): at every check the loss on
+        # this fixed data set must be finite and must not have risen by more
+        # than `rise_tol` nats per context row over the last good check (the
+        # loss is the sum of the rows' losses); otherwise the
+        # parameters and the optimiser state roll back to that check and the
+        # learning rate is halved for the rest of the fit
+        log_every = log_every or max(1, epochs // 4)
+        self.forward()
+        losses_of_rows()
+        best = float(self.loss.sum().item())
+        good = self._snapshot()
         losses = []
         for e in range(epochs):
             self.forward()
             losses_of_rows()
             self.backward()
             self.adam(lr)
-            if log_every and (e % log_every == 0 or e == epochs - 1):
-                losses.append((e, float(self.loss.sum().item())))
+            if e % log_every == 0 or e == epochs - 1:
+                loss = float(self.loss.sum().item())
+                if (math.isfinite(loss) and loss <= best + rise_tol * self.G
+                        and bool(torch.isfinite(self.theta).all())):
+                    losses.append((e, loss))
+                    best = min(best, loss)
+                    good = self._snapshot()
+                else:
+                    self._restore(good)
+                    lr *= 0.5
+                    self.rollbacks += 1
+                    losses.append((e, float("nan")))
         self.forward()
         losses_of_rows()
+        if not math.isfinite(float(self.loss.sum().item())):
+            self._restore(good)
+            self.forward()
+            losses_of_rows()
         losses.append((epochs, float(self.loss.sum().item())))
         self.history.append(losses)
         return losses
+
+    def _snapshot(self):
+        return (self.theta.clone(), self.m.clone(), self.v.clone(), self.t)
+
+    def _restore(self, snap) -> None:
+        theta, m, v, t = snap
+        self.theta.copy_(theta)
+        self.m.copy_(m)
+        self.v.copy_(v)
+        self.t = t
 
     def mu(self, g: int = 0) -> dict:
         """restore_mu descriptor fields of row g for the current parameters

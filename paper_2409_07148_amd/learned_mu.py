@@ -132,15 +132,18 @@ class MlpGmm:
         best = float(self.loss.sum().item())
         good = self._snapshot()
         losses = []
+
+        def acceptable(loss: float) -> bool:
+            return (math.isfinite(loss) and loss <= best + rise_tol * self.G
+                    and bool(torch.isfinite(self.theta).all()))
+
         for e in range(epochs):
             self.forward()
             losses_of_rows()
-            self.backward()
-            self.adam(lr)
             if e % log_every == 0 or e == epochs - 1:
+                # the loss of the current parameters, before this epoch's step
                 loss = float(self.loss.sum().item())
-                if (math.isfinite(loss) and loss <= best + rise_tol * self.G
-                        and bool(torch.isfinite(self.theta).all())):
+                if acceptable(loss):
                     losses.append((e, loss))
                     best = min(best, loss)
                     good = self._snapshot()
@@ -149,10 +152,15 @@ class MlpGmm:
                     lr *= 0.5
                     self.rollbacks += 1
                     losses.append((e, float("nan")))
+                    self.forward()
+                    losses_of_rows()
+            self.backward()
+            self.adam(lr)
         self.forward()
         losses_of_rows()
-        if not math.isfinite(float(self.loss.sum().item())):
+        if not acceptable(float(self.loss.sum().item())):
             self._restore(good)
+            self.rollbacks += 1
             self.forward()
             losses_of_rows()
         losses.append((epochs, float(self.loss.sum().item())))

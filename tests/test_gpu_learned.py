@@ -428,3 +428,28 @@ def test_shared_network_gives_each_batched_target_its_mu(R):
     err_u = np.mean([abs(uest[g]["p_lambda"] / truth[g] - 1) for g in range(4)])
     _say(f"[shared mu] mean relative error learned {err_l:.2e}, uniform {err_u:.2e}")
     assert err_l < err_u
+
+
+def test_fit_rolls_back_unstable_adam_stretches(R):
+    """Full-batch Adam at a learning rate far too large (1.0) leaves the
+    basin at once: the checks roll the parameters back to the last good
+    state and halve the rate until the fit is stable, so the fit ends with
+    a finite loss below the starting one, finite parameters, and at least
+    one recorded rollback (on the GPU, NaN or exploding values are ordinary
+    float results of the training kernels, not faults)."""
+    import math
+    import torch
+    from paper_2409_07148_amd.learned_mu import MlpGmm, record_samples
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=1 << 14)
+    x, w = record_samples(wl, None, 1.0, 3004, 4)
+    model = MlpGmm(d=8, K=64, seed=3004)
+    model.forward()
+    model.nll_and_grad(x.reshape(-1, 8).contiguous(), w.reshape(-1).contiguous())
+    start = float(model.loss.sum().item())
+    losses = model.fit(x, w, 120, 1.0, log_every=10)
+    _say(f"[rollback] start loss {start:.4f}, final {losses[-1][1]:.4f}, rollbacks {model.rollbacks}, "
+         f"checks {[round(l, 3) if l == l else None for _, l in losses]}")
+    assert model.rollbacks >= 1
+    assert math.isfinite(losses[-1][1]) and losses[-1][1] < start
+    assert bool(torch.isfinite(model.theta).all())

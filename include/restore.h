@@ -249,9 +249,12 @@ typedef struct {
 
 typedef struct restore_ctx restore_ctx;
 
-/* Bytes of device memory the state buffer must provide for this problem
- * (chain state in structure-of-arrays layout, packed parameters, reduction
- * and drain scratch).  Pure host computation. */
+/* Bytes of device memory the state buffer must provide for this problem:
+ * the per-chain state of Alg. 2 (x, the cached log p, log u and grad log p,
+ * the running and completed tour sums of Sec. 6.3) in structure-of-arrays
+ * layout, the packed parameters, reduction and drain scratch, and the
+ * splat buckets of the image integrand.  Pure host computation; the same
+ * validation as restore_init (INVALID_ARG, UNSUPPORTED, NONFINITE). */
 restore_status restore_state_bytes(const restore_target *target, const restore_mu *mu,
                                    const restore_local_kernel *local,
                                    const restore_config *cfg, size_t *bytes_out);
@@ -281,7 +284,8 @@ restore_status restore_init(restore_ctx **out, const restore_target *target,
  * the chains are the same either way. */
 restore_status restore_step(restore_ctx *ctx, int32_t n_steps, void *stream);
 
-/* End of the budget: run every chain on, without regeneration, until its
+/* End of the budget (the estimators of Sec. 7.4 assume a run that ends at
+ * a tour completion): run every chain on, without regeneration, until its
  * tour in flight is killed (it then retires) or drain_cap further steps
  * have passed (the tour is censored: excluded from the estimates, counted
  * and reported).  Retired chains are compacted out of the launches with
@@ -299,8 +303,14 @@ restore_status restore_drain(restore_ctx *ctx, void *stream);
  * and bias the estimates) or after restore_drain.  Enqueue only. */
 restore_status restore_reset_sums(restore_ctx *ctx, void *stream);
 
-/* Reduce the per-chain tour sums in float64 and fill *out (host memory).
- * Synchronises `stream`. */
+/* Reduce the per-chain tour sums in float64 and fill *out (host memory,
+ * caller-owned): p_lambda = c_tilde sum T / sum N and lam_pf = c_tilde
+ * sum A / sum N over completed tours (Sec. 6.3, the tour decomposition),
+ * pi_f = sum A / sum T (Sec. 7.4, eq. (approx)), each with the
+ * delta-method standard error over chains; censored tours are excluded and
+ * reported, chains with non-finite sums excluded and counted (nonfinite).
+ * With c_tilde = 0 only pi_f exists (the others are NaN).  Synchronises
+ * `stream`; HIP_ERROR reports a failure of the enqueued work. */
 restore_status restore_estimate(restore_ctx *ctx, restore_estimate_out *out, void *stream);
 
 /* Per-pixel estimate of the image integrand, lambda(p h_j) = c_tilde
@@ -329,14 +339,18 @@ typedef struct {
     int32_t steps_taken;     /* steps with regeneration so far            */
 } restore_state_view;
 
+/* Fill *view (host struct) with the device addresses above and the step
+ * count; no device work.  Library bookkeeping, no passage of the paper. */
 restore_status restore_get_state_view(const restore_ctx *ctx, restore_state_view *view);
 
-/* Recompute logp, logu and grad from x for every chain (after a caller has
- * written x, e.g. to restore a checkpoint or to set up a parity test).
- * `status` bits are not touched.  Enqueue only. */
+/* Recompute the cached values of Alg. 2's state (log p, log u -- log u_eff
+ * for the unadjusted jump process -- and grad log p) from x for every chain
+ * (after a caller has written x, e.g. to restore a checkpoint or to set up
+ * a parity test).  `status` bits are not touched.  Enqueue only. */
 restore_status restore_refresh_cache(restore_ctx *ctx, void *stream);
 
-/* Release the context (device buffers stay the caller's). */
+/* Release the context (device buffers stay the caller's); NULL is a
+ * no-op.  Library bookkeeping, no passage of the paper. */
 restore_status restore_destroy(restore_ctx *ctx);
 
 /* ---- batched targets ---------------------------------------------------
@@ -399,12 +413,16 @@ restore_status restore_batch_init(restore_batch **out, int32_t n_targets, const 
 /* Change the tiling (rebuilds the queue, synchronous; results are
  * independent of the tiling). */
 restore_status restore_batch_set_tiling(restore_batch *b, const restore_batch_tiling *tiling);
+/* The tiling in use (host struct). */
 restore_status restore_batch_get_tiling(const restore_batch *b, restore_batch_tiling *tiling);
 /* Enqueue one full pass.  GRAPH captures the pass into a hipGraph on the
  * first call (on a private stream) and replays it on `stream`. */
 restore_status restore_batch_run(restore_batch *b, int32_t mode, void *stream);
 /* Per-target estimates of the last pass into out[n_targets]; synchronises. */
 restore_status restore_batch_estimates(restore_batch *b, restore_estimate_out *out, void *stream);
+/* Device addresses of one target's per-chain tour sums of the last pass
+ * (for tests; the layout of restore_chain_sums); INVALID_ARG for a target
+ * outside 0..n_targets-1. */
 restore_status restore_batch_chain_sums(const restore_batch *b, int32_t target, restore_chain_sums *out);
 /* Time every tiling (block 64/128/256 x order x bucketing) on this batch
  * with HIP events, keep the fastest and write it to `cache_path` (JSON,
@@ -412,6 +430,8 @@ restore_status restore_batch_chain_sums(const restore_batch *b, int32_t target, 
  * applied without timing.  cache_path may be NULL. */
 restore_status restore_batch_autotune(restore_batch *b, const char *cache_path, restore_batch_tiling *chosen,
                                       double *best_ms, void *stream);
+/* Release the batch handle and its graph (device memory stays the
+ * caller's).  Library bookkeeping, no passage of the paper. */
 restore_status restore_batch_destroy(restore_batch *b);
 
 /* ---- sample collection -------------------------------------------------
@@ -457,20 +477,30 @@ restore_status restore_mlp_forward(const restore_mlp_shape *shape, const float *
  * floats of scratch.  Device pointers, caller-owned; enqueue only. */
 restore_status restore_mlp_backward(const restore_mlp_shape *shape, const float *theta, const float *ctx, int32_t G,
                                     const float *act, const float *dout, float *work, float *grad, void *stream);
-/* Weighted NLL of samples x[n][d] with weights w[n] under the defensive
- * mixture of one MLP output row gmm[O]: *loss_dev (float64, device) =
- * -sum w log u / sum w and dout[O] = its gradient with respect to gmm.
- * Float32 arithmetic on centred scores, float64 accumulation, fixed-order
- * reduction (bit-reproducible).  workspace: restore_gmm_nll_workspace_bytes. */
+/* Bytes of device workspace restore_gmm_nll needs (per-block float64
+ * partial sums). */
 restore_status restore_gmm_nll_workspace_bytes(size_t *bytes);
+/* Weighted NLL of samples x[n][d] with weights w[n] under the defensive
+ * mixture of one MLP output row gmm[O] (the training loss of the learned
+ * mu above; the weights are the holding times of Sec. 7.4, eq. (approx)):
+ * *loss_dev (float64, device) = -sum w log u / sum w and dout[O] = its
+ * gradient with respect to gmm.  Float32 arithmetic on centred scores,
+ * float64 accumulation, fixed-order reduction (bit-reproducible).  Device
+ * pointers, caller-owned; INVALID_ARG for K outside 1..64, d outside
+ * 1..16, beta outside [0, 1), a null pointer or n < 1; BUFFER_TOO_SMALL for
+ * a workspace below restore_gmm_nll_workspace_bytes.  Enqueue only. */
 restore_status restore_gmm_nll(int32_t n_comp, int32_t dim, float beta, const float *gmm, const float *x,
                                const float *w, int64_t n, float *dout, double *loss_dev, void *workspace,
                                size_t workspace_bytes, void *stream);
-/* One Adam step (t >= 1) on float32 master weights. */
+/* One Adam step (t >= 1) on float32 master weights theta[n] with moments
+ * m[n], v[n] (device, caller-owned, updated in place) from grad[n]: the
+ * optimiser of the learned mu's training.  Enqueue only. */
 restore_status restore_adam_step(float *theta, const float *grad, float *m, float *v, int64_t n, int32_t t, float lr,
                                  float beta1, float beta2, float eps, void *stream);
 
-/* Message of the last failed call on this thread ("" if none). */
+/* Message of the last failed call on this thread ("" if none); the string
+ * is owned by the library and valid until the next failing call on this
+ * thread. */
 const char *restore_last_error(void);
 
 #ifdef __cplusplus

@@ -510,7 +510,7 @@ def restore_vs_mh(wl, replicates: int = 8, ell: float = 0.3, burn_in: int = 1000
 
 
 def general_vs_invariant(wl, replicates: int = 16) -> dict:
-    """Restore with local dynamics that are not pi-invariant (Sec. 6.1, eq.
+    """Restore with local dynamics that are not pi-invariant (Sec. 6.2, eq.
     (killing-rate): the unadjusted random-walk jump process, whose killing
     rate carries L* p) against restore with the pi-invariant random-walk MH
     kernel of the same step size (eq. (killing-rate-simplified)), on the

@@ -10,7 +10,7 @@
  *   2. if t1 < t2, holds x for dt = t1 and makes one Metropolis-Hastings
  *      update with the small-step kernel (Alg. 1, acceptance function of
  *      eq. (optimal-acceptance-function)); otherwise holds x for dt = t2 and
- *      regenerates x ~ mu (the tour ends, Sec. 6.1 eq. (concatenation));
+ *      regenerates x ~ mu (the tour ends, Sec. 6, eq. (concatenation));
  *   3. adds dt * f(x_{i-1}) to the running tour integral (Sec. 7.4,
  *      eq. (approx); Sec. 6.3).
  * restore_estimate() turns the per-chain tour sums into the estimates of
@@ -64,7 +64,7 @@ typedef int32_t restore_status;
 #define RESTORE_MAX_DIM   16
 #define RESTORE_MAX_COMP  64
 
-/* ---- target density p (Sec. 3, eq. (targetdensity-assumption-1)) ------- */
+/* ---- target density p (Sec. 4, eq. (targetdensity-assumption-1)) ------- */
 #define RESTORE_TARGET_GMM_ISO    0
 #define RESTORE_TARGET_GMM_FULL   1
 #define RESTORE_TARGET_PSS        2
@@ -116,7 +116,7 @@ typedef struct {
 /* ---- local dynamics: the small-step kernel zeta of Alg. 1 -------------
  * The three diffusion-derived kernels of the paper's study (Sec. 9), all
  * pi-invariant MH updates, and one local process that is not
- * pi-invariant (the general restore process of Sec. 6.1). */
+ * pi-invariant (the general restore process of Sec. 6.2). */
 #define RESTORE_LOCAL_RWMH   0    /* y = x + step z                              */
 #define RESTORE_LOCAL_MALA   1    /* y = x + (step^2 / 2) grad log p(x) + step z  */
 #define RESTORE_LOCAL_HMC    2    /* Hamiltonian Monte Carlo: momentum rho_0 = z,
@@ -129,7 +129,7 @@ typedef struct {
                                      leapfrog step is the MALA proposal.  Built
                                      for the mixture targets with uniform mu. */
 #define RESTORE_LOCAL_RW_UNADJUSTED 3 /* local dynamics that are NOT pi-invariant
-                                     (Sec. 6.1): the unadjusted random-walk jump
+                                     (Sec. 6.2): the unadjusted random-walk jump
                                      process, every holding-clock firing jumps
                                      y = x + step z with no acceptance test.  The
                                      killing rate is then the general one of eq.

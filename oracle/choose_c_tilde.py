@@ -44,7 +44,7 @@ def c_tilde_rule(wl, sig: int = 3) -> float:
 def c_tilde_unadjusted(wl, grid: int = 201, sig: int = 2) -> float:
     """Local dynamics that are not pi-invariant (the unadjusted random-walk
     jump process) need k = (c_tilde u + Q^T p - p) / p >= 0 everywhere
-    (Sec. 6.1, eq. (killing-rate)), i.e. c_tilde >= sup_box (p - Q^T p) / u
+    (Sec. 6.2, eq. (killing-rate)), i.e. c_tilde >= sup_box (p - Q^T p) / u
     with u = 1 (uniform mu).  The supremum is located on a grid over the box
     (oracle densities), refined by Nelder-Mead from the best grid point,
     and doubled for margin; the result is rounded up."""

@@ -28,7 +28,7 @@
  *   - Sec. 6.3 / 7.4: the tour decomposition, the estimates
  *     p_lambda ~ (c_tilde / j) sum tau_i and lambda(p f) ~ (c_tilde / j)
  *     int f dt, and the time-weighted left-rectangle sums of eq. (approx).
- *   - Sec. 6.1, eq. (killing-rate), for local dynamics that are NOT
+ *   - Sec. 6.2, eq. (killing-rate), for local dynamics that are NOT
  *     pi-invariant: k = (c_tilde u + L* p) / p, with L* the adjoint of the
  *     local process's generator.  The local process here is the unadjusted
  *     random-walk jump process (rate 1, every jump y = x + sigma z taken,

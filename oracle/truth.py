@@ -3,7 +3,7 @@ infrastructure only.
 
 These are the quantities the restore estimates converge to:
 
-* p_lambda   = int_box p dlambda                     (Sec. 3, normalisation)
+* p_lambda   = int_box p dlambda                     (Sec. 4, eq. (targetdensity-assumption-1))
 * lam_pf     = lambda(p f) with f = p, i.e. int_box p^2
 * pi_f       = lam_pf / p_lambda
 

@@ -50,7 +50,7 @@ __device__ __forceinline__ float log_mu(const StepArgs &a, const float y[D]) {
 // kernels it is log u, and k = c_tilde u / p (Sec. 6.2, eq.
 // (killing-rate-simplified)).  For the unadjusted random-walk jump process
 // it is log u_eff with u_eff = u + (Q^T p - p) / c_tilde, so that the same
-// k = c_tilde u_eff / p is the rate (c_tilde u + L* p) / p of Sec. 6.1,
+// k = c_tilde u_eff / p is the rate (c_tilde u + L* p) / p of Sec. 6.2,
 // eq. (killing-rate) (L* p = Q^T p - p).  Where u_eff < 0 (c_tilde below
 // sup (p - Q^T p) / u) the value is NaN: the step's holding time is then
 // NaN and the chain's sums are reported as non-finite.  Off the box (p = 0,

@@ -122,10 +122,10 @@ class MlpGmm:
         # Adam can leave the stable region (heavy-tailed time weights make
         # single samples dominate the gradient): at every check the loss on
         # this fixed data set must be finite and must not have risen by more
-        # than `rise_tol` nats per context row over the last good check (the
-        # loss is the sum of the rows' losses); otherwise the
-        # parameters and the optimiser state roll back to that check and the
-        # learning rate is halved for the rest of the fit
+        # than `rise_tol` nats per context row over the lowest loss of the good
+        # checks so far (the loss is the sum of the rows' losses); otherwise
+        # the parameters and the optimiser state roll back to the last good
+        # check and the learning rate is halved for the rest of the fit
         log_every = log_every or max(1, epochs // 4)
         self.forward()
         losses_of_rows()

@@ -1,5 +1,5 @@
 """Parity of the HIP path with the FP64 oracle for restore with local
-dynamics that are not pi-invariant (Sec. 6.1, eq. (killing-rate)): the
+dynamics that are not pi-invariant (Sec. 6.2, eq. (killing-rate)): the
 unadjusted random-walk jump process on the 2-D isotropic mixture, whose
 killing rate k = (c_tilde u + Q^T p - p) / p needs the closed-form inflow
 density Q^T p at every new state.

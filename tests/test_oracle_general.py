@@ -5,7 +5,7 @@ The local process is the unadjusted random-walk jump process: at rate 1 it
 jumps x -> x + sigma z, z ~ N(0, I), with no acceptance test.  Its adjoint
 generator applied to p is L* p = Q^T p - p with
 (Q^T p)(x) = int_box p(y) N(x; y, sigma^2 I) dy, and the killing rate of
-Sec. 6.1, eq. (killing-rate), for a state-independent mu of density u is
+Sec. 6.2, eq. (killing-rate), for a state-independent mu of density u is
 k = (c_tilde u + L* p) / p (non-negative only for c_tilde >= sup (p - Q^T p)/u).
 
 Pinned against facts the oracle does not compute itself: Q^T p against

@@ -225,7 +225,18 @@ typedef struct {
                                 workgroup accumulates its tile's splats in
                                 LDS.  Needs the uniform mu, c_tilde > 0 and at
                                 least max(1, image_batches) chains per tile  */
-    int32_t reserved;
+    int32_t first_chain;     /* global id of this run's chain 0 (>= 0; first_chain
+                                + n_chains <= 2^32): chain c draws its random
+                                numbers with Philox counter word 1 = first_chain
+                                + c, so runs over the ranges [c0, c1) of one
+                                chain population follow exactly the
+                                trajectories of one run over all of them (tours
+                                spawned from mu are independent, Sec. 1: a
+                                population can be split across launches or
+                                devices with no start-up bias).  The image-batch
+                                map is over the run's own chains; UNSUPPORTED
+                                with tile_px > 0, whose chain-to-tile map
+                                depends on the whole population                */
 } restore_config;
 
 /* ---- estimates (Sec. 6.3, Sec. 7.4) ----------------------------------- */

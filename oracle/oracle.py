@@ -75,7 +75,8 @@ class OrOutputs(C.Structure):
                 ("censored", C.POINTER(C.c_int32)), ("t_censored", _dp),
                 ("transitions", C.POINTER(C.c_int64)), ("accepts", C.POINTER(C.c_int64)),
                 ("kills", C.POINTER(C.c_int64)), ("image", _dp),
-                ("large_steps", C.POINTER(C.c_int64)), ("large_accepts", C.POINTER(C.c_int64))]
+                ("large_steps", C.POINTER(C.c_int64)), ("large_accepts", C.POINTER(C.c_int64)),
+                ("min_margin", _dp), ("image_count", _dp), ("image_near", _dp)]
 
 
 _lib = None
@@ -345,7 +346,13 @@ def transitions(prob: Problem, states: States, steps, chains, recompute: bool = 
     """One Alg. 2 transition for each (state, step, chain).  With
     ``recompute`` the oracle recomputes log p, log u and grad log p of the
     input states in FP64 (the usual case: the input x is shared, the cached
-    values are each side's own).  Returns (new States, dt, flags, margins)."""
+    values are each side's own).  Returns (new States, dt, flags, margins);
+    margins[:, 0] is ln t2 - ln t1, margins[:, 1] ln u_acc - ln(ratio) (NaN
+    without an acceptance test), margins[:, 2] the distance of the category
+    uniform to the nearest mu category boundary, margins[:, 3:5] log p and
+    log u at the local proposal (NaN without one), margins[:, 5:7] log p and
+    log u of the input state, margins[:, 7] the distance of a small-step
+    proposal to the edge of the support (inf without one)."""
     lib = load()
     st = states.copy()
     st.x = _f64(st.x); st.lp = _f64(st.lp); st.lu = _f64(st.lu); st.g = _f64(st.g)
@@ -354,7 +361,7 @@ def transitions(prob: Problem, states: States, steps, chains, recompute: bool = 
     chains = np.ascontiguousarray(np.asarray(chains, dtype=np.uint32))
     dt = np.zeros(n)
     flags = np.zeros(n, dtype=np.int32)
-    margins = np.zeros((n, 3))
+    margins = np.zeros((n, 8))
     lib.oracle_transitions(C.byref(prob.target), C.byref(prob.mu), C.byref(prob.local),
                            C.byref(prob.cfg), n, _ptr(steps, C.c_uint32), _ptr(chains, C.c_uint32),
                            _ptr(st.x), _ptr(st.lp), _ptr(st.lu), _ptr(st.g), 1 if recompute else 0,
@@ -380,6 +387,13 @@ class RunResult:
     c_tilde: float
     large_steps: Optional[np.ndarray] = None
     large_accepts: Optional[np.ndarray] = None
+    # parity bookkeeping: per chain the smallest scaled kill and accept
+    # margins, the smallest category margin and the smallest distance of a
+    # proposal to the support's edge per local move since the last
+    # regeneration, over all its steps [n, 4]; splats per pixel and the dt of splats near a pixel edge
+    min_margin: Optional[np.ndarray] = None
+    image_count: Optional[np.ndarray] = None
+    image_near: Optional[np.ndarray] = None
 
 
 def run(prob: Problem, c0: int, c1: int, n_steps: Optional[int] = None,
@@ -403,11 +417,15 @@ def run(prob: Problem, c0: int, c1: int, n_steps: Optional[int] = None,
     out.transitions, out.accepts = _ptr(r.transitions, C.c_int64), _ptr(r.accepts, C.c_int64)
     out.kills = _ptr(r.kills, C.c_int64)
     out.large_steps, out.large_accepts = _ptr(r.large_steps, C.c_int64), _ptr(r.large_accepts, C.c_int64)
+    r.min_margin = np.full((n, 4), np.inf)
+    out.min_margin = _ptr(r.min_margin)
     if prob.cfg.image_w > 0:
         r.image = np.zeros((prob.cfg.image_h, prob.cfg.image_w))
-        out.image = _ptr(r.image)
+        r.image_count = np.zeros_like(r.image)
+        r.image_near = np.zeros_like(r.image)
+        out.image, out.image_count, out.image_near = _ptr(r.image), _ptr(r.image_count), _ptr(r.image_near)
     else:
-        out.image = _dp()
+        out.image = out.image_count = out.image_near = _dp()
     rc = lib.oracle_run(C.byref(prob.target), C.byref(prob.mu), C.byref(prob.local),
                         C.byref(prob.cfg), int(c0), int(c1), int(n_steps), int(drain_cap),
                         int(threads), C.byref(out))

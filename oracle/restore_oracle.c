@@ -373,6 +373,22 @@ static double log_target_c(const or_target *t, const or_config *cfg, uint32_t ch
     return lp;
 }
 
+/* distance of y to the edge of the chain's support: the faces of the unit
+ * box and, in tile-stratified runs, the edges of the chain's tile (parity
+ * bookkeeping: a proposal this close to the edge may fall on the other side
+ * in float32) */
+static double support_margin(const or_config *cfg, uint32_t chain, int d, const double *y)
+{
+    double m = INFINITY;
+    for (int i = 0; i < d; ++i) m = fmin(m, fmin(fabs(y[i]), fabs(1.0 - y[i])));
+    int r[4];
+    if (chain_tile(cfg, chain, r)) {
+        m = fmin(m, fmin(fabs(y[0] - (double)r[0] / cfg->image_w), fabs(y[0] - (double)r[1] / cfg->image_w)));
+        m = fmin(m, fmin(fabs(y[1] - (double)r[2] / cfg->image_h), fabs(y[1] - (double)r[3] / cfg->image_h)));
+    }
+    return m;
+}
+
 /* y ~ mu from the step's category uniform and candidate uniforms; *margin
  * gets the distance of u_cat to the nearest category boundary (INFINITY for
  * uniform mu) */
@@ -538,10 +554,14 @@ void oracle_init_state(const or_target *t, const or_mu *mu, const or_local *lk, 
  * ln t2 - ln t1 (kill iff <= 0), margins[1] is ln u_acc - ln(ratio)
  * (accept iff < 0; NAN when no acceptance test was made), margins[2] is the
  * distance of the category uniform to the nearest mu category boundary
- * (INFINITY unless a learned mu was sampled). */
+ * (INFINITY unless a learned mu was sampled), margins[3] and margins[4] are
+ * log p and log u at the local proposal (NAN when none was made), margins[5]
+ * and margins[6] log p and log u of the state the step starts from,
+ * margins[7] the distance of a small-step proposal to the edge of the
+ * support (INFINITY when none was made). */
 double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk,
                          const or_config *cfg, uint32_t step, uint32_t chain,
-                         or_state *st, int32_t *flags, double margins[3])
+                         or_state *st, int32_t *flags, double margins[8])
 {
     int d = t->d;
     double head[4], cand[OR_MAXD];
@@ -558,6 +578,11 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
     margins[0] = log(e2) - log_k - log(t1);
     margins[1] = NAN;
     margins[2] = INFINITY;
+    margins[3] = NAN;
+    margins[4] = NAN;
+    margins[5] = st->lp;
+    margins[6] = st->lu;
+    margins[7] = INFINITY;
 
     int32_t fl = isnan(t2) ? OR_FLAG_NEGATIVE_RATE : 0;
     double dt;
@@ -591,6 +616,7 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
             }
         }
         if (!in_box(d, y)) fl |= OR_FLAG_OUTSIDE;
+        if (!large) margins[7] = support_margin(cfg, chain, d, y);
         double lpy = log_target_c(t, cfg, chain, y, gy);
         double luy = large ? oracle_log_mu(mu, y) : state_lu(t, mu, lk, cfg, y, lpy);
         double alpha, lratio;
@@ -607,6 +633,8 @@ double oracle_transition(const or_target *t, const or_mu *mu, const or_local *lk
             alpha = lratio >= 0.0 ? 1.0 : exp(lratio);
         }
         margins[1] = log(head[2]) - lratio;
+        margins[3] = lpy;
+        margins[4] = luy;
         if (head[2] < alpha) {
             fl |= OR_FLAG_ACCEPT;
             for (int i = 0; i < d; ++i) { st->x[i] = y[i]; st->g[i] = gy[i]; }
@@ -651,7 +679,7 @@ void oracle_transitions(const or_target *t, const or_mu *mu, const or_local *lk,
             st.lp = lp[c]; st.lu = lu[c];
             for (int i = 0; i < d; ++i) st.g[i] = g[c * d + i];
         }
-        dt[c] = oracle_transition(t, mu, lk, cfg, steps[c], chains[c], &st, &flags[c], &margins[3 * c]);
+        dt[c] = oracle_transition(t, mu, lk, cfg, steps[c], chains[c], &st, &flags[c], &margins[8 * c]);
         for (int i = 0; i < d; ++i) { x[c * d + i] = st.x[i]; g[c * d + i] = st.g[i]; }
         lp[c] = st.lp; lu[c] = st.lu;
     }
@@ -687,6 +715,23 @@ typedef struct {
     double *image;        /* [image_h * image_w], summed dt splats, or NULL */
     int64_t *large_steps;   /* large-step proposals (l > 0)            */
     int64_t *large_accepts; /* accepted large steps                    */
+    /* Parity bookkeeping (each may be NULL).  min_margin[4 c + j]: over all
+     * of the chain's steps (a burn-in included), the smallest |kill margin| / (1 + |log p(x)| +
+     * |log u(x)|) (j = 0), |accept margin| / (1 + |log p(x)| + |log u(x)| +
+     * |log p(y)| + |log u(y)|) (j = 1) -- margins of a decision scaled by
+     * the size of the log densities it compares -- and the smallest
+     * category margin (j = 2), and the smallest distance of a small-step
+     * proposal to the edge of the support divided by (moves + 1) (j = 3;
+     * moves: accepted local moves since the state was last drawn from mu,
+     * each of which may round the float32 state once more).
+     * image_count: splats per pixel.
+     * image_near: the dt of every splat whose state lies within
+     * (moves + 1) 2^-21 of a pixel edge (moves: accepted local moves since
+     * the state was last drawn from mu), added to the 3 x 3 pixels around
+     * its pixel. */
+    double *min_margin;
+    double *image_count;
+    double *image_near;
 } or_outputs;
 
 typedef struct {
@@ -695,6 +740,7 @@ typedef struct {
     int32_t n_steps, drain_cap;
     const or_outputs *out;
     double *image;  /* this thread's image */
+    double *image_count, *image_near;
 } or_job;
 
 static void run_chain(const or_job *job, int64_t c)
@@ -703,7 +749,8 @@ static void run_chain(const or_job *job, int64_t c)
     or_state st;
     oracle_init_state(t, job->mu, job->lk, cfg, (uint32_t)c, &st);
     double a_cur = 0.0, t_cur = 0.0, a_done = 0.0, t_done = 0.0;
-    int64_t n_done = 0, trans = 0, acc = 0, kills = 0, large = 0, large_acc = 0;
+    int64_t n_done = 0, trans = 0, acc = 0, kills = 0, large = 0, large_acc = 0, moves = 0;
+    double mm[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
     int alive = 1;
     /* c_tilde = 0: the MH chain has no tours, so nothing is drained; the
        first burn_in steps are not accumulated */
@@ -718,8 +765,18 @@ static void run_chain(const or_job *job, int64_t c)
         memcpy(x_prev, st.x, sizeof(double) * t->d);
         double lp_prev = st.lp;
         or_state before = st;
-        int32_t fl; double mg[3];
+        int32_t fl; double mg[8];
         double dt = oracle_transition(t, job->mu, job->lk, cfg, (uint32_t)s, (uint32_t)c, &st, &fl, mg);
+        {
+            /* every step counts here, the burn-in's too: a decision there
+               shapes the rest of the trajectory */
+            double sx = 1.0 + fabs(before.lp) + fabs(before.lu);
+            if (isfinite(mg[0]) && isfinite(sx) && fabs(mg[0]) / sx < mm[0]) mm[0] = fabs(mg[0]) / sx;
+            double sy = sx + fabs(mg[3]) + fabs(mg[4]);
+            if (isfinite(mg[1]) && isfinite(sy) && fabs(mg[1]) / sy < mm[1]) mm[1] = fabs(mg[1]) / sy;
+            if (mg[2] < mm[2]) mm[2] = mg[2];
+            if (mg[7] / (double)(moves + 1) < mm[3]) mm[3] = mg[7] / (double)(moves + 1);
+        }
         if (!counted) continue;
         ++trans;
         double f = lp_prev == -INFINITY ? 0.0 : exp(lp_prev);
@@ -737,14 +794,26 @@ static void run_chain(const or_job *job, int64_t c)
                 if (px >= cfg->image_w) px = cfg->image_w - 1;
                 if (py >= cfg->image_h) py = cfg->image_h - 1;
                 job->image[(size_t)py * cfg->image_w + px] += dt;
+                if (job->image_count) job->image_count[(size_t)py * cfg->image_w + px] += 1.0;
+                if (job->image_near) {
+                    double ex = fabs(x_prev[0] * cfg->image_w - floor(x_prev[0] * cfg->image_w + 0.5)) / cfg->image_w;
+                    double ey = fabs(x_prev[1] * cfg->image_h - floor(x_prev[1] * cfg->image_h + 0.5)) / cfg->image_h;
+                    if (fmin(ex, ey) < (double)(moves + 1) * ldexp(1.0, -21)) {
+                        for (int qy = py - 1; qy <= py + 1; ++qy)
+                            for (int qx = px - 1; qx <= px + 1; ++qx)
+                                if (qx >= 0 && qy >= 0 && qx < cfg->image_w && qy < cfg->image_h)
+                                    job->image_near[(size_t)qy * cfg->image_w + qx] += dt;
+                    }
+                }
             }
         }
-        if (fl & OR_FLAG_ACCEPT) ++acc;
+        if (fl & OR_FLAG_ACCEPT) { ++acc; ++moves; }
         if (fl & OR_FLAG_LARGE) { ++large; if (fl & OR_FLAG_ACCEPT) ++large_acc; }
         if (fl & OR_FLAG_KILL) {
             ++kills;
             a_done += a_cur; t_done += t_cur; ++n_done;
             a_cur = 0.0; t_cur = 0.0;
+            moves = 0;
             if (drain) { alive = 0; st = before; }  /* retire: no regeneration */
         }
     }
@@ -756,6 +825,7 @@ static void run_chain(const or_job *job, int64_t c)
     o->transitions[c] = trans; o->accepts[c] = acc; o->kills[c] = kills;
     if (o->large_steps) o->large_steps[c] = large;
     if (o->large_accepts) o->large_accepts[c] = large_acc;
+    if (o->min_margin) for (int j = 0; j < 4; ++j) o->min_margin[4 * c + j] = mm[j];
 }
 
 static void *run_job(void *arg)
@@ -785,6 +855,7 @@ int oracle_run(const or_target *t, const or_mu *mu, const or_local *lk,
     shifted.accepts -= c0; shifted.kills -= c0;
     if (shifted.large_steps) shifted.large_steps -= c0;
     if (shifted.large_accepts) shifted.large_accepts -= c0;
+    if (shifted.min_margin) shifted.min_margin -= 4 * c0;
     for (int i = 0; i < n_threads; ++i) {
         jobs[i].t = t; jobs[i].mu = mu; jobs[i].lk = lk; jobs[i].cfg = cfg;
         jobs[i].c0 = c0 + n * i / n_threads;
@@ -792,6 +863,8 @@ int oracle_run(const or_target *t, const or_mu *mu, const or_local *lk,
         jobs[i].n_steps = n_steps; jobs[i].drain_cap = drain_cap;
         jobs[i].out = &shifted;
         jobs[i].image = (out->image && npix) ? (double *)calloc(npix, sizeof(double)) : NULL;
+        jobs[i].image_count = (out->image_count && npix) ? (double *)calloc(npix, sizeof(double)) : NULL;
+        jobs[i].image_near = (out->image_near && npix) ? (double *)calloc(npix, sizeof(double)) : NULL;
         pthread_create(&th[i], NULL, run_job, &jobs[i]);
     }
     for (int i = 0; i < n_threads; ++i) {
@@ -799,6 +872,14 @@ int oracle_run(const or_target *t, const or_mu *mu, const or_local *lk,
         if (jobs[i].image) {
             for (size_t p = 0; p < npix; ++p) out->image[p] += jobs[i].image[p];
             free(jobs[i].image);
+        }
+        if (jobs[i].image_count) {
+            for (size_t p = 0; p < npix; ++p) out->image_count[p] += jobs[i].image_count[p];
+            free(jobs[i].image_count);
+        }
+        if (jobs[i].image_near) {
+            for (size_t p = 0; p < npix; ++p) out->image_near[p] += jobs[i].image_near[p];
+            free(jobs[i].image_near);
         }
     }
     free(th); free(jobs);

@@ -25,7 +25,7 @@ struct BatchTarget {
     int32_t mu_comp;      // MU_GMM: components
     float mu_beta;        // MU_GMM: defensive uniform share
     int32_t mu_offset;    // MU_GMM: floats into the slab (layout of the learned-mu slab)
-    int32_t pad;
+    uint32_t chain0;      // global id of the target's chain 0 (Philox counter word 1)
 };
 
 // Queue heads: one per bucket (dimension range and mu kind), plus one.

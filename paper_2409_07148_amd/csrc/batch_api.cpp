@@ -108,6 +108,7 @@ restore_status validate(int n, const restore_target *t, const restore_local_kern
         if (c[i].c_tilde == 0.0)
             return fail(RESTORE_E_UNSUPPORTED, at + "c_tilde = 0 (the MH chain) runs on the single-target path");
         if (c[i].drain_cap < 0) return fail(RESTORE_E_INVALID_ARG, at + "drain_cap must be >= 0");
+        if (c[i].first_chain < 0) return fail(RESTORE_E_INVALID_ARG, at + "first_chain must be >= 0");
         if (c[i].integrands & RESTORE_INTEGRAND_PIXEL) return fail(RESTORE_E_UNSUPPORTED, at + "no pixel integrand in batches");
         total += c[i].n_chains;
     }
@@ -293,6 +294,7 @@ restore_status restore_batch_init(restore_batch **out, int32_t n_targets, const 
         t.target_id = (uint32_t)cfgs[i].target_id;
         t.key0 = (uint32_t)(cfgs[i].seed & 0xffffffffu);
         t.key1 = (uint32_t)(cfgs[i].seed >> 32);
+        t.chain0 = (uint32_t)cfgs[i].first_chain;
         t.chain_offset = offset;
         t.n_chains = (int32_t)cfgs[i].n_chains;
         t.param_offset = (int32_t)slab.size();

@@ -32,6 +32,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
     a.key0 = t.key0;
     a.key1 = t.key1;
     a.target_id = t.target_id;
+    a.chain0 = t.chain0;
     a.integrand_p = t.integrand_p;
     a.image = nullptr;
     if (MU == MU_GMM) {
@@ -45,7 +46,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
     Chain<D, LOC_RWMH> ch;
     {
         float head[4], cand[4 * NB];
-        draw_step<NB>(0u, chain, t.target_id, PURPOSE_INIT, t.key0, t.key1, head, cand);
+        draw_step<NB>(0u, t.chain0 + chain, t.target_id, PURPOSE_INIT, t.key0, t.key1, head, cand);
         sample_mu<D, MU, 4 * NB>(a, head[3], cand, ch.x);
         ch.lp = log_target<D, TGT_FULL, false>(P, t.K, ch.x, ch.g);
         ch.lu = log_mu<D, MU>(a, ch.x);

@@ -262,7 +262,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         P = (PT)pv;
     }
     float head[4], cand[4 * NB];
-    draw_step<NB>(s, chain, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
+    draw_step<NB>(s, a.chain0 + chain, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
 
     // the two exponential clocks
     const float t1 = -logf(head[0]);
@@ -284,7 +284,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     if constexpr (MH) {
         if (a.large_prob > 0.0f) {
             uint32_t r[4];
-            Philox::block(s, chain, a.target_id, PURPOSE_LARGE << 16, a.key0, a.key1, r);
+            Philox::block(s, a.chain0 + chain, a.target_id, PURPOSE_LARGE << 16, a.key0, a.key1, r);
             large = u01(r[0]) < a.large_prob;
         }
         ch.status = large ? (ch.status | ST_LAST_LARGE) : (ch.status & ~ST_LAST_LARGE);

@@ -195,6 +195,9 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
         return fail(RESTORE_E_INVALID_ARG, "large_step_prob outside [0,1]");
     if (cfg->n_chains < 1 || cfg->n_chains > 0x7fffffffLL)
         return fail(RESTORE_E_INVALID_ARG, "n_chains %lld outside 1..2^31-1", (long long)cfg->n_chains);
+    if (cfg->first_chain < 0) return fail(RESTORE_E_INVALID_ARG, "first_chain must be >= 0");
+    if (cfg->first_chain > 0 && cfg->tile_px != 0)
+        return fail(RESTORE_E_UNSUPPORTED, "first_chain > 0 with tile_px: the chain-to-tile map spans the whole population");
     if (!std::isfinite(cfg->c_tilde) || cfg->c_tilde < 0.0) return fail(RESTORE_E_INVALID_ARG, "c_tilde must be >= 0");
     if (lk->large_step_prob != 0.0f && cfg->c_tilde > 0.0)
         return fail(RESTORE_E_UNSUPPORTED,
@@ -460,6 +463,7 @@ void fill_args(restore_ctx *c) {
     a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
     a.key1 = (uint32_t)(c->cfg.seed >> 32);
     a.target_id = (uint32_t)c->cfg.target_id;
+    a.chain0 = (uint32_t)c->cfg.first_chain;
     a.s0 = 0;
     a.n_steps = 0;
     a.integrand_p = (c->cfg.integrands & RESTORE_INTEGRAND_P) ? 1 : 0;

@@ -96,6 +96,7 @@ struct StepArgs {
     float large_prob;  // MH chain: large-step probability l
     uint32_t key0, key1;
     uint32_t target_id;
+    uint32_t chain0;   // global id of chain 0 (Philox counter word 1 = chain0 + c)
     uint32_t s0;       // first step index of this launch
     int32_t n_steps;   // steps in this launch
     int32_t integrand_p;

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void init_kernel(StepArgs a) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n_chains) return;
     float head[4], cand[4 * NB];
-    draw_step<NB>(0u, (uint32_t)c, a.target_id, PURPOSE_INIT, a.key0, a.key1, head, cand);
+    draw_step<NB>(0u, a.chain0 + (uint32_t)c, a.target_id, PURPOSE_INIT, a.key0, a.key1, head, cand);
     Chain<D, LOC> ch;
     sample_mu<D, MU, 4 * NB>(a, head[3], cand, ch.x);
     TileOf tile{};

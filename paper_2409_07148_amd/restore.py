@@ -54,7 +54,7 @@ class restore_config(C.Structure):
                 ("integrands", C.c_int32), ("c_tilde", C.c_double), ("drain_cap", C.c_int32),
                 ("image_w", C.c_int32), ("image_h", C.c_int32), ("flags", C.c_int32),
                 ("block_size", C.c_int32), ("image_batches", C.c_int32), ("tile_px", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("first_chain", C.c_int32)]
 
 
 class restore_estimate_out(C.Structure):
@@ -388,7 +388,8 @@ def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: f
                  c_tilde: float, seed: int, drain_cap: int, target_id: int = 0, integrand_p: bool = True,
                  image: Optional[tuple] = None, lds: bool = False, block_size: int = 0,
                  mu: Optional[dict] = None, flags: int = 0, image_batches: int = 0,
-                 large_step_prob: float = 0.0, n_leapfrog: int = 0, tile_px: int = 0) -> Problem:
+                 large_step_prob: float = 0.0, n_leapfrog: int = 0, tile_px: int = 0,
+                 first_chain: int = 0) -> Problem:
     flat = target_params(kind, d, K, params)
     t = restore_target(_KIND[kind], d, K if kind != "pss" else 0, 0,
                        flat.ctypes.data_as(C.POINTER(C.c_double)), flat.size)
@@ -411,7 +412,7 @@ def make_problem(kind: str, d: int, K: int, params: dict, *, local: str, step: f
     w, h = (image or (0, 0))
     cfg = restore_config(int(seed), int(n_chains), int(target_id), integrands, float(c_tilde), int(drain_cap),
                          int(w), int(h), (FLAG_PARAMS_LDS if lds else 0) | int(flags), int(block_size),
-                         int(image_batches), int(tile_px), 0)
+                         int(image_batches), int(tile_px), int(first_chain))
     return Problem(t, m, lk, cfg, flat, mu_t)
 
 
@@ -538,13 +539,16 @@ class Batch:
     """Many targets advanced together on the current GPU: owns the torch
     state buffer and the library's batch handle."""
 
-    def __init__(self, workloads, n_steps: int, stream=None, mus=None):
+    def __init__(self, workloads, n_steps: int, stream=None, mus=None, first_chains=None):
         """mus: None (uniform mu everywhere) or one entry per workload, None
-        or a regeneration distribution as make_problem takes it."""
+        or a regeneration distribution as make_problem takes it.
+        first_chains: None (0 everywhere) or the global id of each target's
+        chain 0."""
         self.stream = stream
         mus = list(mus) if mus is not None else [None] * len(workloads)
-        self.probs = [problem_from_workload(w, target_id=i, integrand_p=True, mu=m)
-                      for i, (w, m) in enumerate(zip(workloads, mus))]
+        firsts = list(first_chains) if first_chains is not None else [0] * len(workloads)
+        self.probs = [problem_from_workload(w, target_id=i, integrand_p=True, mu=m, first_chain=f)
+                      for i, (w, m, f) in enumerate(zip(workloads, mus, firsts))]
         targets = [p.target for p in self.probs]
         locs = [p.local for p in self.probs]
         cfgs = [p.cfg for p in self.probs]

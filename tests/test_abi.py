@@ -60,6 +60,7 @@ def test_state_bytes_grows_with_chains(R):
 
 @pytest.mark.parametrize("field,value,status", [
     ("c_tilde", -1.0, -1), ("n_chains", 0, -1), ("drain_cap", -3, -1), ("block_size", 96, -1),
+    ("first_chain", -1, -1),
 ])
 def test_config_validation(R, field, value, status):
     p = _problem(R)
@@ -280,6 +281,13 @@ def test_tile_stratified_validation(R):
     with pytest.raises(R.RestoreError) as e:
         R.restore_state_bytes(q.target, q.mu, q.local, q.cfg)
     assert e.value.status == R.E_INVALID_ARG
+    # the chain-to-tile map spans the whole population: no chain offset
+    q = _pss_problem(R)
+    q.cfg.tile_px = 16
+    q.cfg.first_chain = 1000
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(q.target, q.mu, q.local, q.cfg)
+    assert e.value.status == R.E_UNSUPPORTED
     q = _pss_problem(R)
     q.cfg.tile_px = 16
     q.mu = R.restore_mu(R.MU_GMM_DIAG, 8, 0.1, 0, 256)

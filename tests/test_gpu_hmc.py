@@ -5,19 +5,21 @@ Tolerances as for the other kernels (test_gpu_parity), except moved
 states: the leapfrog adds n position steps of size e |rho| in float32, so
 the end point carries up to n roundings of a value below 1 (2^-24 each)
 plus the propagated float32 error of the n gradients (|e^2 dg| per step,
-dg ~1e-6 |g|); with n <= 8 and e |g| < 1 that is below 2e-6.
+dg ~1e-6 |g|): with the tested n <= 8 (e = 0.005, 8-D) and n = 5 (e = 0.02,
+2-D, |g| <= ~100) that is below 5e-7 + 2e-7, under the 1e-6 bar.
 """
 import math
 
 import numpy as np
 import pytest
 
-from tests.test_gpu_parity import _gpu_run, _pi_draws, _say, _single_step_check
+from tests import chain_parity as CP
+from tests.test_gpu_parity import _gpu_run, _oracle_chains, _pi_draws, _say, _single_step_check
 from tests.test_gpu_mh import _mh_step_check
 
 pytestmark = pytest.mark.gpu
 
-X_TOL = 2e-6
+X_TOL = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -84,9 +86,9 @@ def test_hmc_whole_run_2d_matches_oracle_and_truth(R):
              f"truth {tr[key]:.6g}")
         assert abs(est[key] - oest[key]) < 3 * math.hypot(est[key + "_se"], oest[key + "_se"])
         assert abs(est[key] - tr[key]) < 3 * est[key + "_se"]
-    same_n = np.mean(arr["n_done"].astype(np.int64) == ores.n_done)
-    _say(f"[hmc run 2d] chains with identical tour counts {same_n:.3f}, accept rate {est['accept_rate']:.3f}")
-    assert same_n > 0.5 and est["tours_censored"] == 0
+    CP.check_chain_sums(arr, ores, wl, say=_say, label="hmc run 2d")
+    _say(f"[hmc run 2d] accept rate {est['accept_rate']:.3f}")
+    assert est["tours_censored"] == 0
 
 
 def test_hmc_full_size_8d_sampled_chains_match_oracle(R):
@@ -99,13 +101,8 @@ def test_hmc_full_size_8d_sampled_chains_match_oracle(R):
     est, arr = _gpu_run(R, wl)
     rng = np.random.default_rng(85)
     ids = np.unique(np.concatenate([rng.integers(0, wl.n_chains, 92), [0, 1, wl.n_chains - 2, wl.n_chains - 1]]))
-    oprob = O.Problem(wl)
-    same = 0
-    for c in ids:
-        r = O.run(oprob, int(c), int(c) + 1, threads=1)
-        same += (int(arr["n_done"][c]) == int(r.n_done[0]) and
-                 abs(arr["t_done"][c] - r.t_done[0]) <= 1e-4 * max(1e-30, abs(r.t_done[0])) and
-                 abs(arr["a_done"][c] - r.a_done[0]) <= 1e-3 * max(1e-30, abs(r.a_done[0])))
+    ores = _oracle_chains(O.Problem(wl), ids)
     _say(f"[hmc full 8d] transitions {est['transitions']} accept rate {est['accept_rate']:.3f} kill rate "
-         f"{est['kill_rate']:.6f}; sampled chains identical to the oracle: {same}/{len(ids)}")
-    assert same >= len(ids) - 2
+         f"{est['kill_rate']:.6f}")
+    CP.check_chain_sums({k: arr[k][ids] for k in ("n_done", "t_done", "a_done")}, ores, wl, say=_say,
+                        label="hmc full 8d sampled chains")

@@ -14,7 +14,8 @@ import math
 import numpy as np
 import pytest
 
-from tests.test_gpu_parity import TAU_ACC, TAU_CAT, _c_max, _pi_draws, _say, _sync
+from tests import chain_parity as CP
+from tests.test_gpu_parity import TAU_CAT, _c_max, _pi_draws, _say, _sync
 
 pytestmark = pytest.mark.gpu
 
@@ -57,9 +58,11 @@ def _mh_step_check(R, wl, ell, x_init, mu=None, label="", x_tol=1e-6):
     acc_g = (status & R.ST_LAST_ACCEPT) != 0
     acc_o = (flags & O.FLAG_ACCEPT) != 0
     aflip = acc_g != acc_o
+    _, sa = CP.scaled_step_margins(margins)
     _say(f"[{label}] n={n} large={large_o.sum()} accepts={acc_o.sum()} (large {(acc_o & large_o).sum()}) "
-         f"accept flips={aflip.sum()} (max |margin| {np.abs(margins[aflip, 1]).max() if aflip.any() else 0:.2e})")
-    assert np.all(np.abs(margins[aflip, 1]) < TAU_ACC), "accept decision differs outside the near-tie margin"
+         f"near-ties {(sa < CP.TAU).sum()} accept flips={aflip.sum()} "
+         f"(max scaled margin {sa[aflip].max() if aflip.any() else 0:.2e})")
+    assert np.all(sa[aflip] < CP.TAU), "accept decision differs outside the near-tie margin"
     same = ~aflip
     stay = same & ~acc_o
     moved = same & acc_o
@@ -143,12 +146,12 @@ def test_mh_whole_run_matches_oracle_and_truth(R, rb):
     eo = O.estimate(r)
     assert eo["transitions"] == c_or * n
     # chains whose trajectories never met a near-tie agree to float32 accuracy
-    same = np.abs(a_g[:c_or] - r.a_done) <= 1e-4 * np.abs(r.a_done)
+    n_g = arr["n_done"].cpu().numpy()
+    CP.check_chain_sums({"n_done": n_g[:c_or], "t_done": t_g[:c_or], "a_done": a_g[:c_or]}, r, wl, say=_say,
+                        label=f"mh run rb={rb} first {c_or} chains")
     _say(f"[mh run rb={rb}] gpu pi_f {est['pi_f']:.6g} +- {est['pi_f_se']:.2g}, oracle (first {c_or} chains) "
-         f"{eo['pi_f']:.6g} +- {eo['pi_f_se']:.2g}, truth {tr['pi_f']:.6g}; "
-         f"chains with equal sums {same.mean():.3f}; large-step acceptance "
+         f"{eo['pi_f']:.6g} +- {eo['pi_f_se']:.2g}, truth {tr['pi_f']:.6g}; large-step acceptance "
          f"{est['large_accepts'] / est['large_steps']:.3f} vs {eo['large_accepts'] / eo['large_steps']:.3f}")
-    assert same.mean() > 0.9
     assert abs(est["pi_f"] - eo["pi_f"]) < 3 * math.hypot(est["pi_f_se"], eo["pi_f_se"])
     run.close()
 
@@ -173,18 +176,18 @@ def test_mh_whole_run_8d_learned_mu_matches_oracle(R):
     run.step(n)
     run.drain()
     est = run.estimate()
-    a_g = run.arrays()["a_done"].cpu().numpy()
+    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done", "a_done")}
     run.close()
     tr = truth.truths(wl)
     c_or = 1024
     r = O.run(O.Problem(wl, c_tilde=0.0, mu=mu, large_step_prob=ELL, burn_in=burn, rb_dt=True), 0, c_or,
               n_steps=burn + n)
     eo = O.estimate(r)
-    same = np.abs(a_g[:c_or] - r.a_done) <= 1e-4 * np.abs(r.a_done)
+    CP.check_chain_sums({k: v[:c_or] for k, v in arr.items()}, r, wl, mu=mu, say=_say,
+                        label=f"mh run 8d learned mu first {c_or} chains")
     _say(f"[mh run 8d learned mu] gpu pi_f {est['pi_f']:.6g} +- {est['pi_f_se']:.2g}, oracle (first {c_or}) "
-         f"{eo['pi_f']:.6g} +- {eo['pi_f_se']:.2g}, truth {tr['pi_f']:.6g}; chains with equal sums {same.mean():.3f}; "
+         f"{eo['pi_f']:.6g} +- {eo['pi_f_se']:.2g}, truth {tr['pi_f']:.6g}; "
          f"large-step acceptance {est['large_accepts'] / est['large_steps']:.3f}")
-    assert same.mean() > 0.9
     assert abs(est["pi_f"] - tr["pi_f"]) < 3 * est["pi_f_se"]
     assert abs(est["pi_f"] - eo["pi_f"]) < 3 * math.hypot(est["pi_f_se"], eo["pi_f_se"])
 

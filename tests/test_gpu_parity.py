@@ -6,11 +6,14 @@ Tolerances (derived from float32 arithmetic on states in [0,1]):
   * moved states: |x_gpu - x_oracle| <= 1e-6 max(1, |x|);
   * unmoved states: bit-exact;
   * decisions: identical, except near-ties -- a kill decision may differ
-    only where the oracle's |ln t2 - ln t1| < TAU_KILL, an accept decision
-    only where |ln u - ln alpha| < TAU_ACC.  Those margins bound the float32
-    error of the log-densities involved (|log p| <= ~50 with ~1e-6 relative
-    error, plus the rounding of y to float32 times |d ln alpha / dy|).
+    only where the oracle's |ln t2 - ln t1|, an accept decision only where
+    |ln u - ln alpha|, scaled by 1 + the magnitudes of the log densities the
+    decision compares, is below 1e-5 (tests/chain_parity.py: float32 log
+    densities are accurate to a few ulps of their own size).
   * dt: relative error <= 1e-4 (exp of a float32 log-rate).
+  * whole runs: every chain whose trajectory saw no near-tie has the
+    oracle's tour count and its tour sums within the float32 bounds of
+    tests/chain_parity.py; images agree pixel by pixel within theirs.
 """
 import math
 import os
@@ -19,11 +22,11 @@ import sys
 import numpy as np
 import pytest
 
+from tests import chain_parity as CP
+
 pytestmark = pytest.mark.gpu
 
-TAU_KILL = 1e-4
-TAU_ACC = 2e-4
-TAU_CAT = 1e-6   # a learned-mu category uniform this close to a boundary is a near-tie
+TAU_CAT = CP.TAU_CAT   # a learned-mu category uniform this close to a boundary is a near-tie
 
 
 def _sync():
@@ -82,11 +85,13 @@ def _single_step_check(R, wl, x_init=None, warm=3, c_tilde=None, label="", lp_at
     acc_o = (flags & O.FLAG_ACCEPT) != 0
     kflip = kill_g != kill_o
     aflip = (acc_g != acc_o) & ~kill_o & ~kill_g
-    _say(f"[{label}] n={n} kills={kill_o.sum()} accepts={acc_o.sum()} kill flips={kflip.sum()} "
-         f"(max |margin| {np.abs(margins[kflip, 0]).max() if kflip.any() else 0:.2e}) "
-         f"accept flips={aflip.sum()} (max |margin| {np.abs(margins[aflip, 1]).max() if aflip.any() else 0:.2e})")
-    assert np.all(np.abs(margins[kflip, 0]) < TAU_KILL), "kill decision differs outside the near-tie margin"
-    assert np.all(np.abs(margins[aflip, 1]) < TAU_ACC), "accept decision differs outside the near-tie margin"
+    sk, sa = CP.scaled_step_margins(margins)
+    _say(f"[{label}] n={n} kills={kill_o.sum()} accepts={acc_o.sum()} near-ties kill {(sk < CP.TAU).sum()} "
+         f"accept {(sa < CP.TAU).sum()}; kill flips={kflip.sum()} "
+         f"(max scaled margin {sk[kflip].max() if kflip.any() else 0:.2e}) "
+         f"accept flips={aflip.sum()} (max scaled margin {sa[aflip].max() if aflip.any() else 0:.2e})")
+    assert np.all(sk[kflip] < CP.TAU), "kill decision differs outside the near-tie margin"
+    assert np.all(sa[aflip] < CP.TAU), "accept decision differs outside the near-tie margin"
     same = ~kflip & ~aflip
     regen = same & kill_o
     moved = same & acc_o & ~kill_o
@@ -318,9 +323,46 @@ def _gpu_run(R, wl, **kw):
     run.step(wl.n_steps)
     run.drain()
     est = run.estimate()
-    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done", "a_done", "status")}
+    arr = {k: v.cpu().numpy() for k, v in run.arrays().items()
+           if k in ("n_done", "t_done", "a_done", "status", "t_cur")}
     run.close()
     return est, arr
+
+
+def _oracle_chains(oprob, ids):
+    """The oracle's runs of the single chains `ids` (global ids), stacked
+    into one result in that order."""
+    from oracle import oracle as O
+    rs = [O.run(oprob, int(c), int(c) + 1, threads=1) for c in ids]
+    cat = lambda f: np.concatenate([getattr(r, f) for r in rs])
+    return O.RunResult(cat("n_done"), cat("t_done"), cat("a_done"), cat("censored"), cat("t_censored"),
+                       cat("transitions"), cat("accepts"), cat("kills"), None, oprob.c_tilde,
+                       min_margin=np.concatenate([r.min_margin for r in rs]))
+
+
+def _check_estimate_is_the_oracle_formula(R, est, arr, c_tilde, label=""):
+    """restore_estimate against the oracle's estimate() applied to the GPU's
+    own per-chain arrays: the same float64 definitions (pooled ratios and
+    delta-method standard errors over chains), summed in another order."""
+    from oracle import oracle as O
+    cens = (arr["status"] & R.ST_CENSORED) != 0
+    n = len(arr["n_done"])
+    z = np.zeros(n, np.int64)
+    rr = O.RunResult(arr["n_done"].astype(np.uint32).astype(np.int64), arr["t_done"].astype(np.float64),
+                     arr["a_done"].astype(np.float64), cens.astype(np.int32),
+                     np.where(cens, arr["t_cur"].astype(np.float64), 0.0), z, z, z, None, c_tilde)
+    ref = O.estimate(rr)
+    worst = 0.0
+    for key in ("p_lambda", "p_lambda_se", "lam_pf", "lam_pf_se", "pi_f", "pi_f_se", "censored_time_frac"):
+        a, b = est[key], ref[key]
+        if math.isnan(b):
+            assert math.isnan(a), key
+            continue
+        rel = abs(a - b) / max(abs(b), 1e-300) if b != 0 else abs(a)
+        worst = max(worst, rel)
+        assert rel <= 1e-12, (key, a, b)
+    assert est["tours_done"] == ref["tours_done"] and est["tours_censored"] == ref["tours_censored"]
+    _say(f"[{label}] restore_estimate vs the oracle's formula on the GPU's chain sums: max rel diff {worst:.1e}")
 
 
 def test_single_transitions_rao_blackwellised_holding_time(R):
@@ -370,13 +412,15 @@ def test_whole_run_2d_matches_oracle_and_truth(R):
         assert abs(est[key] - oest[key]) < 3 * se
         assert abs(est[key] - tr[key]) < 3 * est[key + "_se"]
     assert est["tours_censored"] == 0 and oest["tours_censored"] == 0
-    assert est["transitions"] == est["transitions"]
-    same_n = np.mean(arr["n_done"].astype(np.int64) == ores.n_done)
-    _say(f"[run 2d] chains with identical tour counts: {same_n:.3f}; "
-         f"transitions gpu {est['transitions']} oracle {oest['transitions']}")
-    assert same_n > 0.5
-    assert abs(est["transitions"] - oest["transitions"]) < 0.01 * oest["transitions"]
+    m = CP.check_chain_sums(arr, ores, wl, say=_say, label="run 2d")
+    _say(f"[run 2d] transitions gpu {est['transitions']} oracle {oest['transitions']}")
+    if not m["mismatch"].any():
+        assert est["transitions"] == oest["transitions"]
+    else:
+        # a diverged near-tie chain runs at most the budget and the drain cap
+        assert abs(est["transitions"] - oest["transitions"]) <= m["mismatch"].sum() * (wl.n_steps + wl.drain_cap)
     assert np.all((arr["status"] & R.ST_ALIVE) == 0)
+    _check_estimate_is_the_oracle_formula(R, est, arr, wl.c_tilde, "run 2d")
 
 
 def test_full_size_8d_sampled_chains_match_oracle(R):
@@ -388,31 +432,59 @@ def test_full_size_8d_sampled_chains_match_oracle(R):
     wl = gmm_full()
     _say("[full 8d] gpu run 2^20 x 512")
     est, arr = _gpu_run(R, wl)
+    # The reported SE of this estimator (uniform mu in 8-D at the provable
+    # c~, every step a regeneration) is not a reliable error bar: the tour
+    # sums are so heavy-tailed that the rare draws near a mode decide the
+    # estimate, so the whole run is checked chain by chain against the
+    # oracle rather than within 3 SE of the truth; the relative error
+    # against the truth is printed (and reported by the benchmark line).
     _say(f"[full 8d] transitions {est['transitions']} tours {est['tours_done']} censored {est['tours_censored']}")
     rng = np.random.default_rng(3)
     ids = np.unique(np.concatenate([rng.integers(0, wl.n_chains, 380), [0, 1, wl.n_chains - 2, wl.n_chains - 1]]))
-    oprob = O.Problem(wl)
-    same = 0
-    for c in ids:
-        r = O.run(oprob, int(c), int(c) + 1, threads=1)
-        ok = (int(arr["n_done"][c]) == int(r.n_done[0]) and
-              abs(arr["t_done"][c] - r.t_done[0]) <= 1e-4 * max(1e-30, abs(r.t_done[0])) and
-              abs(arr["a_done"][c] - r.a_done[0]) <= 1e-3 * max(1e-30, abs(r.a_done[0])))
-        same += ok
-    _say(f"[full 8d] sampled chains identical to the oracle: {same}/{len(ids)}")
-    assert same >= len(ids) - 2
+    ores = _oracle_chains(O.Problem(wl), ids)
+    CP.check_chain_sums({k: arr[k][ids] for k in ("n_done", "t_done", "a_done")}, ores, wl, say=_say,
+                        label="full 8d sampled chains")
+    _check_estimate_is_the_oracle_formula(R, est, arr, wl.c_tilde, "full 8d")
     tr = truth.truths(wl)
     for key in ("p_lambda", "lam_pf"):
         _say(f"[full 8d] {key}: {est[key]:.6g} +- {est[key + '_se']:.2g}, truth {tr[key]:.6g}, "
              f"rel err {abs(est[key] / tr[key] - 1):.3f}")
 
 
+def _clean_image(R, wl, near, c0, label):
+    """GPU and oracle images of the chains [c0, c0 + len(near)) without a
+    near-tie: one GPU run per maximal clean range (its own chain ids through
+    first_chain) and the oracle's runs of the same ranges, summed."""
+    from oracle import oracle as O
+    g = o = cnt = edge = None
+    ranges = CP.clean_ranges(near, c0)
+    for lo, hi in ranges:
+        run = R.Run(R.problem_from_workload(wl, n_chains=hi - lo, image_batches=0, first_chain=lo))
+        run.step(wl.n_steps)
+        run.drain()
+        gi = run.image.double().cpu().numpy()
+        run.close()
+        r = O.run(O.Problem(wl), lo, hi)
+        if g is None:
+            g, o, cnt, edge = gi, r.image.copy(), r.image_count.copy(), r.image_near.copy()
+        else:
+            g += gi
+            o += r.image
+            cnt += r.image_count
+            edge += r.image_near
+    _say(f"[{label}] {int(near.sum())} near-tie chains left out: {len(ranges)} clean ranges run separately")
+    return g, o, cnt, edge
+
+
 def test_pss_image_matches_oracle_image(R):
     """Pixel splats of the 12-D rendering-shaped integrand in 4 image
-    batches: each GPU batch image of 8192 chains equals the oracle's image
-    of the same chain range (identical counters) up to float32
-    accumulation, tile by tile; the image total equals the summed tour
-    time; the image estimate agrees with the per-pixel truth."""
+    batches (8192 chains x 200 steps, 128 x 128 pixels): every chain without
+    a near-tie has the oracle's tour count and sums; each GPU batch image
+    equals the oracle's image of the same chain range pixel by pixel within
+    the float32 bound (a batch that holds near-tie chains is compared over
+    its clean sub-ranges, each run on its own with its global chain ids);
+    the image total equals the summed tour time; the estimate agrees with
+    the per-pixel truth."""
     from workloads import pss_render
     from oracle import oracle as O, truth
     wl = pss_render(n_chains=8192, n_steps=200, image=(128, 128), image_batches=4)
@@ -422,29 +494,23 @@ def test_pss_image_matches_oracle_image(R):
     est = run.estimate()
     img = run.image.cpu().numpy().astype(np.float64)
     assert img.shape == (4, 128, 128)
-    arrs = run.arrays()
-    n_done = arrs["n_done"].cpu().numpy().astype(np.int64)
-    t_done = arrs["t_done"].cpu().numpy()
-    cens = (arrs["status"].cpu().numpy() & R.ST_CENSORED) != 0
-    t_all = t_done.sum() + arrs["t_cur"].cpu().numpy()[cens].astype(np.float64).sum()
+    arrs = {k: v.cpu().numpy() for k, v in run.arrays().items()}
+    cens = (arrs["status"] & R.ST_CENSORED) != 0
+    t_all = arrs["t_done"].sum() + arrs["t_cur"][cens].astype(np.float64).sum()
     run.close()
-    tiles = lambda im: im.reshape(16, 8, 16, 8).sum(axis=(1, 3))
-    oimgs, ores_all = [], []
+    eps = CP.eps_dt(wl)
     for b, (lo, hi) in enumerate(O.batch_ranges(wl.n_chains, 4)):
         ores = O.run(O.Problem(wl), lo, hi)
-        ores_all.append(ores)
-        oimgs.append(ores.image)
-        tg, to = tiles(img[b]), tiles(ores.image)
-        rel = np.abs(tg - to) / np.maximum(to, 1e-30)
-        _say(f"[pss image] batch {b} chains {lo}..{hi}: tile rel diff median {np.median(rel):.2e} "
-             f"max {rel.max():.2e}, equal tours {np.mean(n_done[lo:hi] == ores.n_done):.3f}")
-        assert np.median(rel) < 1e-3
-    _say(f"[pss image] gpu sum {img.sum():.6g} oracle {sum(o.sum() for o in oimgs):.6g} sum T {t_all:.6g} "
-         f"censored {cens.sum()}")
+        m = CP.check_chain_sums({k: arrs[k][lo:hi] for k in ("n_done", "t_done", "a_done")}, ores, wl,
+                                say=_say, label=f"pss image batch {b} chains {lo}..{hi}")
+        if not m["near"].any():
+            CP.check_image(img[b], ores.image, ores.image_count, ores.image_near, eps, say=_say,
+                           label=f"pss image batch {b}")
+        else:
+            g, o, cnt, edge = _clean_image(R, wl, m["near"], lo, f"pss image batch {b}")
+            CP.check_image(g, o, cnt, edge, eps, say=_say, label=f"pss image batch {b}, clean chains")
+    _say(f"[pss image] gpu sum {img.sum():.6g} sum T {t_all:.6g} censored {cens.sum()}")
     assert abs(img.sum() / t_all - 1) < 1e-4
-    oest = [O.estimate(r) for r in ores_all]
-    o_pl = sum(e["p_lambda"] * e["tours_done"] for e in oest) / sum(e["tours_done"] for e in oest)
-    assert abs(est["p_lambda"] - o_pl) < 3 * math.sqrt(2) * est["p_lambda_se"]
     tr = truth.pss_pixel_truth(wl, gl_order=4)
     scale = est["image_scale"]
     _say(f"[pss image] p_lambda gpu {est['p_lambda']:.5f} +- {est['p_lambda_se']:.2g}, truth {tr.sum():.5f}, "
@@ -501,7 +567,8 @@ def test_full_size_pss_sampled_chains_match_oracle(R):
     run.step(wl.n_steps)
     run.drain()
     est = run.estimate()
-    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done", "t_cur", "status")}
+    arr = {k: v.cpu().numpy() for k, v in run.arrays().items()
+           if k in ("n_done", "t_done", "a_done", "t_cur", "status")}
     img_sum = float(run.image.double().sum().item())
     run.close()
     _say(f"[full pss] transitions {est['transitions']} tours {est['tours_done']} censored {est['tours_censored']} "
@@ -511,14 +578,9 @@ def test_full_size_pss_sampled_chains_match_oracle(R):
     assert abs(img_sum / t_all - 1) < 1e-3
     rng = np.random.default_rng(9)
     ids = np.unique(np.concatenate([rng.integers(0, wl.n_chains, 250), [0, wl.n_chains - 1]]))
-    oprob = O.Problem(wl, image=(0, 0))
-    same = 0
-    for c in ids:
-        r = O.run(oprob, int(c), int(c) + 1, threads=1)
-        same += (int(arr["n_done"][c]) == int(r.n_done[0]) and
-                 abs(arr["t_done"][c] - r.t_done[0]) <= 1e-4 * max(1e-30, abs(r.t_done[0])))
-    _say(f"[full pss] sampled chains identical to the oracle: {same}/{len(ids)}")
-    assert same >= len(ids) - 3
+    ores = _oracle_chains(O.Problem(wl, image=(0, 0)), ids)
+    CP.check_chain_sums({k: arr[k][ids] for k in ("n_done", "t_done", "a_done")}, ores, wl, say=_say,
+                        label="full pss sampled chains")
 
 
 def test_whole_run_8d_learned_mu_matches_oracle_and_truth(R):
@@ -562,16 +624,11 @@ def test_full_size_8d_learned_mu_sampled_chains_match_oracle(R):
          f"censored {est['tours_censored']}")
     rng = np.random.default_rng(4)
     ids = np.unique(np.concatenate([rng.integers(0, wl.n_chains, 124), [0, 1, wl.n_chains - 2, wl.n_chains - 1]]))
-    oprob = O.Problem(wl, mu=mu, c_tilde=ct)
-    same = 0
-    for c in ids:
-        r = O.run(oprob, int(c), int(c) + 1, threads=1)
-        same += (int(arr["n_done"][c]) == int(r.n_done[0]) and
-                 abs(arr["t_done"][c] - r.t_done[0]) <= 1e-4 * max(1e-30, abs(r.t_done[0])) and
-                 abs(arr["a_done"][c] - r.a_done[0]) <= 1e-3 * max(1e-30, abs(r.a_done[0])))
-    _say(f"[full 8d learned mu] sampled chains identical to the oracle: {same}/{len(ids)}")
-    assert same >= len(ids) - 2
+    ores = _oracle_chains(O.Problem(wl, mu=mu, c_tilde=ct), ids)
+    CP.check_chain_sums({k: arr[k][ids] for k in ("n_done", "t_done", "a_done")}, ores, wl, mu=mu, say=_say,
+                        label="full 8d learned mu sampled chains")
     assert est["tours_censored"] == 0
+    _check_estimate_is_the_oracle_formula(R, est, arr, ct, "full 8d learned mu")
 
 
 # ---------------------------------------------------------------------------
@@ -638,9 +695,11 @@ def test_ragged_chain_counts(R, n_chains):
     wl = gmm_iso_2d(n_chains=n_chains, n_steps=40)
     est, arr = _gpu_run(R, wl)
     ores = O.run(O.Problem(wl), 0, n_chains, threads=1)
-    match = np.mean(arr["n_done"].astype(np.int64) == ores.n_done)
-    assert match >= 0.9
+    m = CP.check_chain_sums(arr, ores, wl, say=_say, label=f"ragged {n_chains}")
+    if not m["mismatch"].any():
+        assert est["transitions"] == int(ores.transitions.sum())
     assert est["transitions"] >= n_chains * 40
+    _check_estimate_is_the_oracle_formula(R, est, arr, wl.c_tilde, f"ragged {n_chains}")
 
 
 def test_zero_drain_cap_censors_every_tour_in_flight(R):

@@ -3,17 +3,21 @@ oracle (the image integrand; each tile its own restore problem with the
 target restricted to the tile and mu uniform on it, splats accumulated in
 an LDS copy of the workgroup's tile).
 
-Tolerances as for the untiled image workload (test_gpu_parity): chain sums
-equal to float32 accuracy for chains whose trajectories meet no near-tie,
-image tile sums within 1e-3 (median) of the oracle's, estimates within 3
-combined SE of the oracle's and of the truth.
+Tolerances as for the untiled image workload (test_gpu_parity and
+tests/chain_parity.py): every chain whose trajectory meets no near-tie has
+the oracle's tour count and its sums within the float32 bounds; batch images
+and the image estimate agree pixel by pixel within theirs (a near-tie chain
+splats only into its own tile, so the tiles of near-tie chains are left out
+and counted); estimates within 3 combined SE of the oracle's and of the
+truth.
 """
 import math
 
 import numpy as np
 import pytest
 
-from tests.test_gpu_parity import _say, _single_step_check, _sync
+from tests import chain_parity as CP
+from tests.test_gpu_parity import _oracle_chains, _say, _single_step_check, _sync
 
 pytestmark = pytest.mark.gpu
 
@@ -27,11 +31,18 @@ def R():
 
 
 def _oracle_batch_images(O, wl, prob, B):
-    """Batch images of the oracle: tile t's chains split into B ranges."""
+    """Batch images of the oracle (tile t's chains split into B ranges),
+    with their splat counts and edge masses, the per-chain results of the
+    whole population, and the batch of every chain."""
     tiles, _ = O.tiles(prob)
     tid = O.tile_of_chain(prob, np.arange(wl.n_chains))
-    imgs = np.zeros((B, wl.image[1], wl.image[0]))
-    runs = []
+    shape = (B, wl.image[1], wl.image[0])
+    imgs, cnts, edges = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+    n = wl.n_chains
+    full = O.RunResult(np.zeros(n, np.int64), np.zeros(n), np.zeros(n), np.zeros(n, np.int32), np.zeros(n),
+                       np.zeros(n, np.int64), np.zeros(n, np.int64), np.zeros(n, np.int64), None, prob.c_tilde,
+                       min_margin=np.zeros((n, 4)))
+    batch = np.zeros(n, np.int64)
     for t in range(len(tiles)):
         lo_t, hi_t = np.flatnonzero(tid == t)[[0, -1]]
         n_t = hi_t + 1 - lo_t
@@ -40,8 +51,13 @@ def _oracle_batch_images(O, wl, prob, B):
             hi = lo_t + -(-(b + 1) * n_t // B)
             r = O.run(prob, int(lo), int(hi))
             imgs[b] += r.image
-            runs.append((int(lo), r))
-    return imgs, runs
+            cnts[b] += r.image_count
+            edges[b] += r.image_near
+            for f in ("n_done", "t_done", "a_done", "censored", "t_censored", "transitions", "min_margin"):
+                getattr(full, f)[lo:hi] = getattr(r, f)
+            batch[lo:hi] = b
+    full.image = imgs.sum(axis=0)
+    return imgs, cnts, edges, full, tid, batch
 
 
 @pytest.mark.parametrize("n_chains", [8192, 8192 + 77])
@@ -59,43 +75,41 @@ def test_tiled_image_and_estimates_match_oracle(R, n_chains):
     est = run.estimate()
     mean, se = run.image_estimate()
     img = run.image.cpu().numpy().astype(np.float64)
-    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done")}
+    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done", "a_done")}
     mean = mean.cpu().numpy().astype(np.float64)
     run.close()
     prob = O.Problem(wl)
-    oimgs, runs = _oracle_batch_images(O, wl, prob, 4)
-    # per-chain sums
-    n_o = np.zeros(n_chains, np.int64)
-    t_o = np.zeros(n_chains)
-    for lo, r in runs:
-        n_o[lo:lo + len(r.n_done)] = r.n_done
-        t_o[lo:lo + len(r.n_done)] = r.t_done
-    same = np.mean((arr["n_done"] == n_o) & (np.abs(arr["t_done"] - t_o) <= 1e-4 * np.maximum(t_o, 1e-30)))
-    tiles = lambda im: im.reshape(16, 4, 16, 4).sum(axis=(1, 3))
-    rel = [np.abs(tiles(img[b]) - tiles(oimgs[b])) / np.maximum(tiles(oimgs[b]), 1e-30) for b in range(4)]
-    med = max(float(np.median(r)) for r in rel)
-    _say(f"[tiles {n_chains}] chains with equal sums {same:.4f}; batch-image 4x4-block rel diff median {med:.2e}; "
-         f"image total {img.sum():.6g} chain time {arr['t_done'].sum():.6g}")
-    assert same > 0.97 and med < 1e-3
+    oimgs, cnts, edges, full, tid, batch = _oracle_batch_images(O, wl, prob, 4)
+    m = CP.check_chain_sums({k: arr[k] for k in ("n_done", "t_done", "a_done")}, full, wl, say=_say,
+                            label=f"tiles {n_chains}")
     assert abs(img.sum() - arr["t_done"].sum()) <= 1e-4 * arr["t_done"].sum()
+    # pixels of the tiles whose chains (in that batch image) saw no near-tie
+    tiles, _ = O.tiles(prob)
+    px_tile = np.zeros(wl.image[::-1], np.int64)
+    for t, (x0, x1, y0, y1) in enumerate(tiles):
+        px_tile[y0:y1, x0:x1] = t
+    eps = CP.eps_dt(wl)
+    for b in range(4):
+        bad_tiles = np.unique(tid[m["near"] & (batch == b)])
+        keep = ~np.isin(px_tile, bad_tiles)
+        CP.check_image(img[b][keep], oimgs[b][keep], cnts[b][keep], edges[b][keep], eps, say=_say,
+                       label=f"tiles {n_chains} batch {b} ({len(bad_tiles)} tiles with near-tie chains left out)")
     # stratified estimates: the oracle's over the same chains
-    full = O.RunResult(n_o, t_o, np.zeros(n_chains), np.zeros(n_chains, np.int32), np.zeros(n_chains),
-                       np.zeros(n_chains, np.int64), np.zeros(n_chains, np.int64), np.zeros(n_chains, np.int64),
-                       oimgs.sum(axis=0), prob.c_tilde)
-    for lo, r in runs:
-        full.a_done[lo:lo + len(r.n_done)] = r.a_done
     oest = O.estimate_tiles(prob, full)
     for key in ("p_lambda", "lam_pf", "pi_f"):
         _say(f"[tiles {n_chains}] {key}: gpu {est[key]:.6g} +- {est[key + '_se']:.2g} oracle {oest[key]:.6g} "
              f"+- {oest[key + '_se']:.2g}")
         assert abs(est[key] - oest[key]) < 3 * math.hypot(est[key + "_se"], oest[key + "_se"])
         assert abs(est[key + "_se"] / oest[key + "_se"] - 1) < 0.1
-    # the image estimate: c_tilde A_t S_j / N_t per tile, against the oracle's
+    # the image estimate c_tilde A_t S_j / N_t per tile, against the
+    # oracle's, pixel by pixel in the tiles without near-tie chains (N_t is
+    # then exact and S_j a float32 sum over the batches)
     oimg = O.image_estimate_tiles(prob, full)
-    d = np.abs(tiles(mean) - tiles(oimg)) / np.maximum(tiles(oimg), 1e-30)
-    _say(f"[tiles {n_chains}] image estimate 4x4-block rel diff median {np.median(d):.2e}; "
-         f"sum {mean.sum():.6g} vs p_lambda {est['p_lambda']:.6g}")
-    assert np.median(d) < 1e-3
+    bad_tiles = np.unique(tid[m["near"]])
+    keep = ~np.isin(px_tile, bad_tiles)
+    CP.check_image(mean[keep], oimg[keep], cnts.sum(axis=0)[keep] + 4, oimg[keep] / np.maximum(
+        oimgs.sum(axis=0)[keep], 1e-300) * edges.sum(axis=0)[keep], eps + 2.0 ** -23, say=_say,
+        label=f"tiles {n_chains} image estimate ({len(bad_tiles)} tiles left out)")
     assert abs(mean.sum() - est["p_lambda"]) < 1e-3 * est["p_lambda"]
 
 
@@ -133,16 +147,11 @@ def test_tiled_full_size_matches_truth(R):
     assert abs(z) < 4 and est["tours_censored"] == 0
     # chains spread over the population (and so over the tiles) rerun by the
     # oracle from the same counters, each with its own tile
-    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done")}
+    arr = {k: v.cpu().numpy() for k, v in run.arrays().items() if k in ("n_done", "t_done", "a_done")}
     run.close()
     from oracle import oracle as O
-    oprob = O.Problem(wl)
     rng = np.random.default_rng(6)
     ids = np.unique(np.concatenate([rng.integers(0, wl.n_chains, 124), [0, 1, wl.n_chains - 2, wl.n_chains - 1]]))
-    same = 0
-    for c in ids:
-        r = O.run(oprob, int(c), int(c) + 1, threads=1)
-        same += (int(arr["n_done"][c]) == int(r.n_done[0]) and
-                 abs(arr["t_done"][c] - r.t_done[0]) <= 1e-4 * max(1e-30, abs(r.t_done[0])))
-    _say(f"[tiles full] sampled chains identical to the oracle: {same}/{len(ids)}")
-    assert same >= len(ids) - 2
+    ores = _oracle_chains(O.Problem(wl), ids)
+    CP.check_chain_sums({k: arr[k][ids] for k in ("n_done", "t_done", "a_done")}, ores, wl, say=_say,
+                        label="tiles full sampled chains")

@@ -7,7 +7,13 @@
 namespace restore {
 
 constexpr int LEARN_MAX_DIM = 16;
-constexpr int NLL_MAX_BLOCKS = 2048;
+// The NLL statistics: at most NLL_MAX_BLOCKS workgroups of NLL_WAVES waves,
+// each writing nll_rows(d) x 64 float64 partial sums; the workspace holds
+// them and the totals, for any n, K and d (about 4.5 MB).
+constexpr int NLL_MAX_BLOCKS = 256;
+constexpr int NLL_WAVES = 8;
+__host__ __device__ constexpr int nll_rows(int D) { return 2 + 2 * D; }
+constexpr size_t NLL_WORKSPACE_DOUBLES = (size_t)(NLL_MAX_BLOCKS + 1) * 64 * (2 + 2 * LEARN_MAX_DIM);
 
 struct NllArgs {
     int32_t n_comp, dim;
@@ -17,8 +23,9 @@ struct NllArgs {
     const float *w;        // [n]
     int64_t n;
     int32_t n_blocks;      // <= NLL_MAX_BLOCKS
-    double *partials;      // [n_blocks][3 + 2 dim][64]
-    double *totals;        // [3 + 2 dim][64]
+    int64_t per_block;     // samples per workgroup (a multiple of 4 NLL_WAVES)
+    double *partials;      // [n_blocks][nll_rows(dim)][64]
+    double *totals;        // [nll_rows(dim)][64]
     float *dout;           // [K (1 + 2d)]
     double *loss;          // [1]
 };

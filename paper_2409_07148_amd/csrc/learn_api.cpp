@@ -111,7 +111,7 @@ restore_status restore_mlp_backward(const restore_mlp_shape *shape, const float 
 
 restore_status restore_gmm_nll_workspace_bytes(size_t *bytes) {
     if (!bytes) return fail(RESTORE_E_INVALID_ARG, "null bytes");
-    *bytes = ((size_t)NLL_MAX_BLOCKS + 1) * 64 * (3 + 2 * LEARN_MAX_DIM) * sizeof(double);
+    *bytes = NLL_WORKSPACE_DOUBLES * sizeof(double);
     return RESTORE_OK;
 }
 
@@ -132,11 +132,14 @@ restore_status restore_gmm_nll(int32_t n_comp, int32_t dim, float beta, const fl
     a.x = x;
     a.w = w;
     a.n = n;
-    // about 64 samples per wave, at most NLL_MAX_BLOCKS blocks of 4 waves
-    const int64_t want = (n + 255) / 256;
+    // contiguous sample ranges of at least 2048 samples (64 passes of 4 per
+    // wave) per workgroup, at most NLL_MAX_BLOCKS workgroups
+    const int64_t want = (n + 2047) / 2048;
     a.n_blocks = (int32_t)(want < NLL_MAX_BLOCKS ? want : NLL_MAX_BLOCKS);
+    const int64_t quantum = 4 * NLL_WAVES;
+    a.per_block = ((n + a.n_blocks - 1) / a.n_blocks + quantum - 1) / quantum * quantum;
     a.partials = static_cast<double *>(workspace);
-    a.totals = a.partials + (size_t)NLL_MAX_BLOCKS * 64 * (3 + 2 * LEARN_MAX_DIM);
+    a.totals = a.partials + (size_t)NLL_MAX_BLOCKS * 64 * nll_rows(dim);
     a.dout = dout;
     a.loss = loss_dev;
     hipError_t e = launch_gmm_nll(a, static_cast<hipStream_t>(stream));

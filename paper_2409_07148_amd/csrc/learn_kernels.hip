@@ -9,10 +9,11 @@
 //  * gemm_bf16_kernel: C = op(A) op(B) on the matrix cores
 //    (v_mfma_f32_32x32x16_bf16: bf16 operands, float32 accumulation), one
 //    wave per 32 x 32 output tile -- the MLP layers, forward and backward.
-//  * gmm_nll_kernel: per-component statistics of the weighted NLL in float32
-//    with centred scores z = (x - m)/s (one lane per component, samples
-//    broadcast to the wave), accumulated in float64; fixed-order block and
-//    grid reductions, so the result is bit-reproducible.
+//  * gmm_nll_kernel: the weighted NLL and its per-component statistics: the
+//    mixture densities in float32 (4 samples x 64 components per wave and
+//    pass, log-sum-exp over 16-lane rows), the responsibility-weighted
+//    moments on the FP64 matrix cores (v_mfma_f64_16x16x4f64); fixed-order
+//    block and grid reductions, so the result is bit-reproducible.
 //  * adam_kernel: Adam on float32 master weights.
 #include <hip/hip_runtime.h>
 
@@ -105,110 +106,225 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// Weighted NLL statistics.  Lane k of every wave is mixture component k;
-// the NLL_WAVES waves of a block take interleaved samples.  For each
-// sample x_i: a_k = ln(1-beta) + ln pi_k - d/2 ln 2 pi - sum ln s_k -
-// |z|^2/2 with z = (x_i - m_k)/s_k, log u(x_i) = LSE(a, ln beta 1_box),
-// r_k = exp(a_k - log u), and the weighted sums
-//   S0 = sum w r, S1 = sum w r z, S2 = sum w r z^2, LW = sum w log u,
-//   W = sum w,
-// accumulated in float64 per lane, combined over the block's waves in a
-// fixed order through LDS and written as one partial per block:
-// partials[block][j][k], j < nll_stats(D).
-constexpr int NLL_WAVES = 4;
-__host__ __device__ constexpr int nll_stats(int D) { return 3 + 2 * D; }
+// Lane exchange within a row of 16 lanes (DPP): quad_perm [1,0,3,2] and
+// [2,3,0,1], row_half_mirror, row_mirror.  Applied in that order with an
+// associative operation they leave every lane of the row with the
+// operation over the whole row.
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_max(float v) {
+    v = fmaxf(v, dpp_row<0xB1>(v));
+    v = fmaxf(v, dpp_row<0x4E>(v));
+    v = fmaxf(v, dpp_row<0x141>(v));
+    return fmaxf(v, dpp_row<0x140>(v));
+}
+__device__ __forceinline__ float row16_sum(float v) {
+    v += dpp_row<0xB1>(v);
+    v += dpp_row<0x4E>(v);
+    v += dpp_row<0x141>(v);
+    return v + dpp_row<0x140>(v);
+}
+
+// Weighted NLL statistics of one block's share of the samples, on the
+// FP64 matrix cores.
+//
+// A wave handles 4 samples x 64 components per pass, in the lane layout of
+// v_mfma_f64_16x16x4f64 (lane l provides A[l % 16][l / 16] and
+// B[l / 16][l % 16], and receives D[4 r + l / 16][l % 16], r < 4): lane l
+// takes sample l / 16 of the pass and components l % 16 + 16 t, t < 4.  For
+// each it evaluates a_k = c_k - |(x - m_k) / s_k|^2 / 2 in float32 (c_k =
+// ln(1 - beta) + ln pi_k - d/2 ln 2 pi - sum ln s_k); log u(x) = LSE(a,
+// ln beta 1_box) is reduced over the 16 lanes of the sample's row (DPP) and
+// the 4 tiles; the responsibility r_k = e^{a_k - M} / sum e^{a - M}.  Then
+//   A[k][s] = w_s r_sk (float64),   B[s][f] = x_sf (f < d), x_s,f-d^2 (f < 2d)
+// (exact in float64), and D += A B accumulates the uncentred moments
+//   P1_ki = sum w r x_i,  P2_ki = sum w r x_i^2
+// in float64, where the centring (x - m)^2 = x^2 - 2 m x + m^2 that the
+// gradient needs costs nothing (float32 would lose the m^2 / s^2 ~ 2500
+// cancelled digits).  S0_k = sum w r, LW = sum w log u and W = sum w go
+// through the vector unit.  The NLL_WAVES waves add their statistics into
+// LDS in wave order and the block writes one partial row set:
+// partials[block][row][64], rows: 0 S0, 1 + i P1_i, 1 + d + i P2_i,
+// 1 + 2d [LW, W].  Samples: the block's contiguous range in passes of 4,
+// wave v taking passes v, v + NLL_WAVES, ...
+__host__ __device__ constexpr int nll_feature_tiles(int D) { return (2 * D + 15) / 16; }
 
 template <int D>
 __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
-    constexpr int R = nll_stats(D);
-    __shared__ double red[NLL_WAVES - 1][64];
-    const int k = threadIdx.x % 64, wv = threadIdx.x / 64;
+    typedef double double4_t __attribute__((ext_vector_type(4)));
+    constexpr int NF = nll_feature_tiles(D);
+    constexpr int ROWS = nll_rows(D);
+    __shared__ double red[ROWS * 64];
+    __shared__ float lse_part[64];
+    const int l = threadIdx.x % 64, wv = threadIdx.x / 64;
     const int K = a.n_comp;
-    const bool act = k < K;
-    const float logit = act ? a.gmm[k] : -INFINITY;
-    const float lmax = wave_max(logit);
-    const float lse = lmax + logf(wave_sum(act ? expf(logit - lmax) : 0.0f));
-    float m[D], inv_s[D];
-    float c = act ? (a.beta < 1.0f ? log1pf(-a.beta) : -INFINITY) + logit - lse - 0.5f * D * 1.8378770664093453f
-                  : -INFINITY;
+    const int n_ct = (K + 15) / 16;  // component tiles in use
+
+    // the mixture weights ln pi = logits - LSE(logits) (one wave-wide pass)
+    {
+        const float logit = l < K ? a.gmm[l] : -INFINITY;
+        const float lmax = wave_max(logit);
+        const float lse = lmax + logf(wave_sum(l < K ? expf(logit - lmax) : 0.0f));
+        if (wv == 0) lse_part[l] = lse;
+    }
+    __syncthreads();
+    const float logit_lse = lse_part[0];
+    const float lbeta = a.beta > 0.0f ? logf(a.beta) : -INFINITY;
+    const float l1mb = a.beta < 1.0f ? log1pf(-a.beta) : -INFINITY;
+
+    // this lane's four components
+    float m[4][D], is[4][D], c[4];
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        m[i] = 0.0f;
-        inv_s[i] = 0.0f;
-        if (act) {
-            const float ls = a.gmm[K + K * D + k * D + i];
-            m[i] = a.gmm[K + k * D + i];
-            inv_s[i] = expf(-ls);
-            c -= ls;
+    for (int t = 0; t < 4; ++t) {
+        const int k = l % 16 + 16 * t;
+        const bool act = k < K;
+        c[t] = act ? l1mb + a.gmm[k] - logit_lse - 0.5f * D * 1.8378770664093453f : -INFINITY;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            m[t][i] = 0.0f;
+            is[t][i] = 0.0f;
+            if (act) {
+                const float ls = a.gmm[K + K * D + k * D + i];
+                m[t][i] = a.gmm[K + k * D + i];
+                is[t][i] = expf(-ls);
+                c[t] -= ls;
+            }
         }
     }
-    const float lbeta = a.beta > 0.0f ? logf(a.beta) : -INFINITY;
-    double acc[R];
+
+    double4_t acc[4][NF];
+    double s0[4], lw = 0.0, wsum = 0.0;
 #pragma unroll
-    for (int j = 0; j < R; ++j) acc[j] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * NLL_WAVES;
-    for (int64_t n = (int64_t)blockIdx.x * NLL_WAVES + wv; n < a.n; n += stride) {
-        const float w = a.w[n];
-        const float *x = a.x + n * D;
-        float z[D], q = 0.0f;
+    for (int t = 0; t < 4; ++t) {
+        s0[t] = 0.0;
+#pragma unroll
+        for (int u = 0; u < NF; ++u) acc[t][u] = double4_t{0.0, 0.0, 0.0, 0.0};
+    }
+    const int64_t lo = (int64_t)blockIdx.x * a.per_block;
+    const int64_t hi = lo + a.per_block < a.n ? lo + a.per_block : a.n;
+    const int sl = l / 16;  // this lane's sample within the pass
+    // this lane's column of B: feature f = 16 u + l % 16
+    for (int64_t p = lo + 4 * (int64_t)wv; p < hi; p += 4 * NLL_WAVES) {
+        const int64_t n = p + sl;
+        const bool valid = n < hi;
+        const float w = valid ? a.w[n] : 0.0f;
+        float x[D];
         bool in = true;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const float xi = x[i];
-            in = in && xi >= 0.0f && xi <= 1.0f;
-            z[i] = (xi - m[i]) * inv_s[i];
-            q = fmaf(z[i], z[i], q);
+            x[i] = valid ? a.x[n * D + i] : 0.5f;
+            in = in && x[i] >= 0.0f && x[i] <= 1.0f;
         }
-        const float ak = act ? fmaf(-0.5f, q, c) : -INFINITY;
-        const float au = in ? lbeta : -INFINITY;
-        const float M = fmaxf(wave_max(ak), au);
-        const float S = wave_sum(act ? expf(ak - M) : 0.0f) + (au > -INFINITY ? expf(au - M) : 0.0f);
-        const float logu = M + logf(S);
-        const double wr = (double)w * (double)(act ? expf(ak - logu) : 0.0f);
-        acc[0] += wr;
+        float at[4];
+        float mx = in ? lbeta : -INFINITY;
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            acc[1 + i] += wr * z[i];
-            acc[1 + D + i] += wr * z[i] * z[i];
+        for (int t = 0; t < 4; ++t) {
+            float q = 0.0f;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const float z = (x[i] - m[t][i]) * is[t][i];
+                q = fmaf(z, z, q);
+            }
+            at[t] = t < n_ct ? fmaf(-0.5f, q, c[t]) : -INFINITY;
+            mx = fmaxf(mx, at[t]);
         }
-        acc[1 + 2 * D] += (double)w * (double)logu;
-        acc[2 + 2 * D] += (double)w;
+        const float M = row16_max(mx);
+        float e[4], se = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            e[t] = at[t] > -INFINITY ? expf(at[t] - M) : 0.0f;
+            se += e[t];
+        }
+        // the defensive uniform share counts once per sample (lane 0 of the row)
+        const float eb = (l % 16 == 0 && in && a.beta > 0.0f) ? expf(lbeta - M) : 0.0f;
+        const float S = row16_sum(se + eb);
+        const float inv_s = S > 0.0f ? 1.0f / S : 0.0f;
+        const double wd = (double)w;
+        if (l % 16 == 0) {
+            lw += wd * (double)(M + logf(S));
+            wsum += wd;
+        }
+        double bf[NF];
+#pragma unroll
+        for (int u = 0; u < NF; ++u) {
+            const int f = 16 * u + l % 16;
+            const double xv = f < 2 * D ? (double)x[f < D ? f : f - D] : 0.0;
+            bf[u] = f < D ? xv : (f < 2 * D ? xv * xv : 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t < n_ct) {
+                const double wr = wd * (double)(e[t] * inv_s);
+                s0[t] += wr;
+#pragma unroll
+                for (int u = 0; u < NF; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(wr, bf[u], acc[t][u], 0, 0, 0);
+            }
+        }
     }
-    double *out = a.partials + (int64_t)blockIdx.x * R * 64;
+
+    // S0 and [LW, W] over the 4 sample rows of the wave
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        if (wv > 0) red[wv - 1][k] = acc[j];
-        __syncthreads();
-        if (wv == 0) {
-            double v = acc[j];
+    for (int t = 0; t < 4; ++t) {
+        s0[t] += __shfl_xor(s0[t], 16);
+        s0[t] += __shfl_xor(s0[t], 32);
+    }
+    lw += __shfl_xor(lw, 16);
+    lw += __shfl_xor(lw, 32);
+    wsum += __shfl_xor(wsum, 16);
+    wsum += __shfl_xor(wsum, 32);
+
+    // add the waves' statistics into LDS in wave order
+    for (int v = 0; v < NLL_WAVES; ++v) {
+        if (wv == v) {
+            const bool first = v == 0;
 #pragma unroll
-            for (int u = 0; u < NLL_WAVES - 1; ++u) v += red[u][k];
-            out[j * 64 + k] = v;
+            for (int t = 0; t < 4; ++t) {
+                if (l < 16) {
+                    double *r0 = &red[16 * t + l];
+                    *r0 = first ? s0[t] : *r0 + s0[t];
+                }
+#pragma unroll
+                for (int u = 0; u < NF; ++u) {
+                    const int f = 16 * u + l % 16;
+                    if (f < 2 * D) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            double *q = &red[(1 + f) * 64 + 16 * t + 4 * r + l / 16];
+                            *q = first ? acc[t][u][r] : *q + acc[t][u][r];
+                        }
+                    }
+                }
+            }
+            if (l == 0) {
+                double *q = &red[(1 + 2 * D) * 64];
+                q[0] = first ? lw : q[0] + lw;
+                q[1] = first ? wsum : q[1] + wsum;
+            }
+            if (first && l >= 2) red[(1 + 2 * D) * 64 + l] = 0.0;
         }
         __syncthreads();
     }
+    double *out = a.partials + (int64_t)blockIdx.x * ROWS * 64;
+    for (int j = threadIdx.x; j < ROWS * 64; j += 64 * NLL_WAVES) out[j] = red[j];
 }
 
-// totals[j][k] = sum over blocks b (fixed order) of partials[b][j][k]: one
-// block per statistic j; wave v takes blocks b = v, v + NW, ... and the
-// waves' sums are added in wave order.
-constexpr int NLL_SUM_WAVES = 16;
-__global__ __launch_bounds__(64 * NLL_SUM_WAVES) void gmm_nll_sum_kernel(const double *partials, int R,
-                                                                          int n_blocks, double *totals) {
-    __shared__ double red[NLL_SUM_WAVES][64];
-    const int k = threadIdx.x % 64, wv = threadIdx.x / 64, j = blockIdx.x;
+// totals[j] = sum over blocks b (fixed order) of partials[b][j].
+__global__ __launch_bounds__(256) void gmm_nll_sum_kernel(const double *partials, int entries, int n_blocks,
+                                                           double *totals) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= entries) return;
     double v = 0.0;
-    for (int b = wv; b < n_blocks; b += NLL_SUM_WAVES) v += partials[((int64_t)b * R + j) * 64 + k];
-    red[wv][k] = v;
-    __syncthreads();
-    if (wv == 0) {
-        double t = 0.0;
-        for (int u = 0; u < NLL_SUM_WAVES; ++u) t += red[u][k];
-        totals[j * 64 + k] = t;
-    }
+    for (int b = 0; b < n_blocks; ++b) v += partials[(int64_t)b * entries + j];
+    totals[j] = v;
 }
 
-// Gradient of L = -sum w log u / sum w with respect to the mixture outputs:
+// Gradient of L = -sum w log u / sum w with respect to the mixture outputs,
+// from the uncentred moments (float64): with S1 = sum w r (x - m) / s and
+// S2 = sum w r ((x - m) / s)^2,
+//   S1_ki = (P1_ki - m_ki S0_k) / s_ki
+//   S2_ki = (P2_ki - 2 m_ki P1_ki + m_ki^2 S0_k) / s_ki^2
 //   dL/dlogit_k = -(S0_k - pi_k sum_j S0_j) / W
 //   dL/dm_ki    = -S1_ki / (W s_ki)
 //   dL/dlog s_ki = -(S2_ki - S0_k) / W
@@ -217,7 +333,7 @@ __global__ __launch_bounds__(64) void gmm_nll_grad_kernel(NllArgs a, const doubl
     const int k = threadIdx.x;
     const int K = a.n_comp;
     const double *S = totals;
-    const double s0 = S[k], lw = S[(1 + 2 * D) * 64], W = S[(2 + 2 * D) * 64];
+    const double s0 = S[k], lw = S[(1 + 2 * D) * 64], W = S[(1 + 2 * D) * 64 + 1];
     const bool act = k < K;
     const float logit = act ? a.gmm[k] : -INFINITY;
     const float lmax = wave_max(logit);
@@ -229,9 +345,13 @@ __global__ __launch_bounds__(64) void gmm_nll_grad_kernel(NllArgs a, const doubl
         a.dout[k] = (float)(-(s0 - (double)pi * s0tot) / W);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const float inv_s = expf(-a.gmm[K + K * D + k * D + i]);
-            a.dout[K + k * D + i] = (float)(-S[(1 + i) * 64 + k] * inv_s / W);
-            a.dout[K + K * D + k * D + i] = (float)(-(S[(1 + D + i) * 64 + k] - s0) / W);
+            const double mk = (double)a.gmm[K + k * D + i];
+            const double inv_s = (double)expf(-a.gmm[K + K * D + k * D + i]);
+            const double p1 = S[(1 + i) * 64 + k], p2 = S[(1 + D + i) * 64 + k];
+            const double s1 = (p1 - mk * s0) * inv_s;
+            const double s2 = (p2 - 2.0 * mk * p1 + mk * mk * s0) * inv_s * inv_s;
+            a.dout[K + k * D + i] = (float)(-s1 * inv_s / W);
+            a.dout[K + K * D + k * D + i] = (float)(-(s2 - s0) / W);
         }
     }
     if (k == 0) a.loss[0] = -lw / W;
@@ -274,9 +394,10 @@ hipError_t launch_colsum(const float *d, float *db, int G, int n, hipStream_t s)
 
 template <int D>
 static void launch_nll_d(const NllArgs &a, hipStream_t s) {
+    const int entries = nll_rows(D) * 64;
     hipLaunchKernelGGL(gmm_nll_kernel<D>, dim3(a.n_blocks), dim3(64 * NLL_WAVES), 0, s, a);
-    hipLaunchKernelGGL(gmm_nll_sum_kernel, dim3(nll_stats(D)), dim3(64 * NLL_SUM_WAVES), 0, s,
-                       (const double *)a.partials, nll_stats(D), a.n_blocks, a.totals);
+    hipLaunchKernelGGL(gmm_nll_sum_kernel, dim3((entries + 255) / 256), dim3(256), 0, s, (const double *)a.partials,
+                       entries, a.n_blocks, a.totals);
     hipLaunchKernelGGL(gmm_nll_grad_kernel<D>, dim3(1), dim3(64), 0, s, a, (const double *)a.totals);
 }
 

@@ -195,7 +195,8 @@ def _nll_bound(row, x, w, beta, K, d):
 
 
 @pytest.mark.parametrize("K,d,n,beta", [(64, 8, 70001, 0.1), (5, 3, 2500, 0.25), (1, 1, 1, 0.1),
-                                        (17, 16, 1023, 0.05), (64, 8, 300, 0.0)])
+                                        (17, 16, 1023, 0.05), (64, 8, 300, 0.0), (64, 8, 1048613, 0.1),
+                                        (48, 12, 300007, 0.1), (33, 16, 524309, 0.02)])
 def test_gmm_nll_matches_oracle(R, K, d, n, beta):
     """Loss and gradient of the weighted defensive-mixture NLL against the
     oracle, within the derived float32 bound (samples near the components

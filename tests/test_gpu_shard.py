@@ -40,7 +40,7 @@ def test_chain_ranges_reproduce_the_whole_population(R, which):
     from oracle import oracle as O
     from workloads import gmm_full, gmm_iso_2d
     wl = {"gmm_iso_2d": lambda: gmm_iso_2d(),
-          "gmm_full_8d": lambda: gmm_full(n_chains=20000, n_steps=128, c_tilde=1e3)}[which]()
+          "gmm_full_8d": lambda: gmm_full(n_chains=20000, n_steps=128)}[which]()
     C = wl.n_chains
     est, ref = _run(R, wl, 0, C)
     for k in (2, 4):

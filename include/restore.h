@@ -503,6 +503,23 @@ restore_status restore_gmm_nll_workspace_bytes(size_t *bytes);
 restore_status restore_gmm_nll(int32_t n_comp, int32_t dim, float beta, const float *gmm, const float *x,
                                const float *w, int64_t n, float *dout, double *loss_dev, void *workspace,
                                size_t workspace_bytes, void *stream);
+/* restore_gmm_nll for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid hipMalloc): the same validation, kernels and result bit for bit,
+ * with the workspace taken from a library-owned device array instead of an
+ * argument.  That array (restore_gmm_nll_workspace_bytes, about 4.5 MB) is
+ * the largest workspace restore_gmm_nll can need -- partial sums of at most
+ * 256 workgroups of the largest mixture (d = 16) -- so every valid n, K and
+ * d fits; K outside 1..64 or d outside 1..16 is INVALID_ARG as for
+ * restore_gmm_nll.  Each GPU holds its own copy from the first call on it
+ * until the process ends; the call allocates nothing (no hipMalloc, hipFree
+ * or allocating library routine) and needs no zeroed memory (the kernels
+ * write every partial sum they read).  All calls on one GPU share its copy:
+ * calls that overlap on one GPU (on different streams, or from different
+ * threads without ordering) race and their results are undefined.  Device
+ * pointers, caller-owned; enqueue only. */
+restore_status restore_gmm_nll_noalloc(int32_t n_comp, int32_t dim, float beta, const float *gmm, const float *x,
+                                       const float *w, int64_t n, float *dout, double *loss_dev, void *stream);
 /* One Adam step (t >= 1) on float32 master weights theta[n] with moments
  * m[n], v[n] (device, caller-owned, updated in place) from grad[n]: the
  * optimiser of the learned mu's training.  Enqueue only. */

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "../../include/restore.h"
@@ -145,6 +146,47 @@ restore_status restore_gmm_nll(int32_t n_comp, int32_t dim, float beta, const fl
     hipError_t e = launch_gmm_nll(a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "gmm nll");
     return RESTORE_OK;
+}
+
+// Scratch of restore_gmm_nll_noalloc: the NLL workspace (partial sums of at
+// most NLL_MAX_BLOCKS workgroups and the totals, for d up to 16), one copy
+// per GPU, held until the process ends.  Host code never passes the
+// symbol itself to a kernel: its device address is looked up once per
+// device with hipGetSymbolAddress and kept in scratch_dev.
+static __device__ __align__(256) double scratch[NLL_WORKSPACE_DOUBLES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+restore_status scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(RESTORE_E_UNSUPPORTED, "device id beyond 63");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(RESTORE_E_HIP, "hipGetSymbolAddress(scratch) returned no address");
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return RESTORE_OK;
+}
+}  // namespace
+
+restore_status restore_gmm_nll_noalloc(int32_t n_comp, int32_t dim, float beta, const float *gmm, const float *x,
+                                       const float *w, int64_t n, float *dout, double *loss_dev, void *stream) {
+    void *ws = nullptr;
+    restore_status st = scratch_address(&ws);
+    if (st != RESTORE_OK) return st;
+    // the same validation, grid and kernels as restore_gmm_nll; the scratch
+    // is the largest workspace that call can ask for, so every valid n, K
+    // and d fits, and the kernels write every partial they later read
+    return restore_gmm_nll(n_comp, dim, beta, gmm, x, w, n, dout, loss_dev, ws, sizeof(scratch), stream);
 }
 
 restore_status restore_adam_step(float *theta, const float *grad, float *m, float *v, int64_t n, int32_t t, float lr,

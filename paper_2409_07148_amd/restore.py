@@ -106,7 +106,7 @@ EXPORTS = ["restore_state_bytes", "restore_init", "restore_step", "restore_drain
            "restore_batch_get_tiling", "restore_batch_run", "restore_batch_estimates", "restore_batch_chain_sums",
            "restore_batch_autotune", "restore_batch_destroy", "restore_step_record", "restore_mlp_param_count",
            "restore_mlp_forward", "restore_mlp_backward", "restore_gmm_nll_workspace_bytes", "restore_gmm_nll",
-           "restore_adam_step", "restore_image_estimate", "restore_reset_sums", "restore_last_error"]
+           "restore_gmm_nll_noalloc", "restore_adam_step", "restore_image_estimate", "restore_reset_sums", "restore_last_error"]
 
 
 def _load() -> C.CDLL:
@@ -149,6 +149,8 @@ def _load() -> C.CDLL:
     lib.restore_gmm_nll_workspace_bytes.argtypes = [P(C.c_size_t)]
     lib.restore_gmm_nll.argtypes = [C.c_int32, C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    lib.restore_gmm_nll_noalloc.argtypes = [C.c_int32, C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.restore_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                       C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]
     lib.restore_last_error.restype = C.c_char_p
@@ -341,6 +343,13 @@ def restore_gmm_nll(n_comp: int, dim: int, beta: float, gmm_ptr: int, x_ptr: int
     _check(_lib.restore_gmm_nll(int(n_comp), int(dim), float(beta), C.c_void_p(gmm_ptr), C.c_void_p(x_ptr),
                                 C.c_void_p(w_ptr), int(n), C.c_void_p(dout_ptr), C.c_void_p(loss_ptr),
                                 C.c_void_p(workspace_ptr), int(workspace_bytes), C.c_void_p(_stream(stream))))
+
+
+def restore_gmm_nll_noalloc(n_comp: int, dim: int, beta: float, gmm_ptr: int, x_ptr: int, w_ptr: int, n: int,
+                            dout_ptr: int, loss_ptr: int, stream=None) -> None:
+    _check(_lib.restore_gmm_nll_noalloc(int(n_comp), int(dim), float(beta), C.c_void_p(gmm_ptr), C.c_void_p(x_ptr),
+                                        C.c_void_p(w_ptr), int(n), C.c_void_p(dout_ptr), C.c_void_p(loss_ptr),
+                                        C.c_void_p(_stream(stream))))
 
 
 def restore_adam_step(theta_ptr: int, grad_ptr: int, m_ptr: int, v_ptr: int, n: int, t: int, lr: float,

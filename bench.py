@@ -25,10 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU x 2.4 GHz)
+PEAK_FP64_MATRIX_TFLOPS = 78.6  # MI355X FP64 matrix-core peak
 PEAK_HBM_GBS = 8000.0
 
 
-def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: float, n_leapfrog: int = 0) -> dict:
+def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: float, n_leapfrog: int = 0,
+                         mu_comp: int = 0) -> dict:
     """Algorithmic float32 operations of one transition (FMA = 2 flops; each
     exp / log / sqrt / sin / cos = 1), i.e. what the method must compute,
     dominated by the one target-density evaluation every step needs.
@@ -50,8 +52,19 @@ def flops_per_transition(target: str, d: int, K: int, local: str, kill_rate: flo
     coordinate 13 (offset, square, centre, two erf arguments, two erf, the
     truncation factor), per component 8 (weight, log, log-sum-exp), and 10
     to combine u_eff; its jump has no acceptance test.
+    A learned regeneration distribution (a diagonal mixture of mu_comp
+    components with a defensive uniform share) adds log u at every
+    candidate, per component 3d (centred score and its square) + 2 (a_k) +
+    5 (log-sum-exp), and at a regeneration the category pick (about 7
+    compares) and the draw m + s z (d FMA).
     Returns the per-transition count averaged with the measured kill rate."""
     mala = local == "mala"
+    if mu_comp:
+        base = flops_per_transition(target, d, K, local, kill_rate, n_leapfrog)
+        lu = mu_comp * (3 * d + 7) + 5
+        f_kill, f_local = base["kill"] + lu + 7 + d, base["local"] + lu
+        return {"kill": float(f_kill), "local": float(f_local),
+                "mean": float(kill_rate * f_kill + (1.0 - kill_rate) * f_local)}
     if target == "pss":
         # rendering-shaped integrand: two textures of 8 sinusoids (dot product
         # 2m, sine 1, FMA 2), three lobes (omega 8, difference 5, norm 5,
@@ -245,8 +258,13 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
     closed-form truth.  t_1% = time (rel. RMS error / 1%)^2 is the time a
     method needs to reach 1% relative error.  Each method is run at its
     provable c~ (every mean lifetime <= B/8) and over a sweep of smaller
-    values; the comparison is reported at the provable c~ and at each
-    method's best c~ of the sweep."""
+    values.  The primary comparison is at each method's best c~: chosen on
+    the sweep's seeds and scored on a fresh set of `replicates` seeds, so
+    that the choice does not flatter the score; the comparison at the
+    provable c~ is reported beside it.  Also measured: the step kernel's
+    roofline with the learned mu at its provable c~ and where local moves
+    dominate (the largest c~ of the learned sweep with a kill rate of at most
+    0.8), and the training's NLL kernel."""
     import numpy as np
     import torch
     from paper_2409_07148_amd import restore as R
@@ -263,10 +281,10 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
     train_s = time.perf_counter() - t0
     mu = model.mu()
 
-    def runs(mu_, ct, flags=0):
+    def runs(mu_, ct, flags=0, seed0=2004):
         out = []
         for r in range(replicates):
-            prob = R.problem_from_workload(wl, mu=mu_, c_tilde=ct, seed=2004 + 17 * r, flags=flags)
+            prob = R.problem_from_workload(wl, mu=mu_, c_tilde=ct, seed=seed0 + 17 * r, flags=flags)
             torch.cuda.synchronize()
             t = time.perf_counter()
             run = R.Run(prob)
@@ -297,11 +315,15 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
     for name, (mu_, cts) in sweeps.items():
         res["sweep"][name] = [summary(runs(mu_, ct), ct) for ct in cts]
         res[name] = res["sweep"][name][0]            # the provable c~
-        res[name + "_best"] = min(res["sweep"][name], key=lambda r: r["lam_pf"]["mse_x_time"])
-    res["mse_x_time_ratio_uniform_over_learned"] = (res["uniform"]["lam_pf"]["mse_x_time"]
-                                                    / res["learned"]["lam_pf"]["mse_x_time"])
+        chosen = min(res["sweep"][name], key=lambda r: r["lam_pf"]["mse_x_time"])["c_tilde"]
+        # scored on fresh seeds, not on the seeds that chose it
+        res[name + "_best"] = summary(runs(mu_, chosen, seed0=9004), chosen)
+    res["best_c_tilde_selection"] = "lowest MSE x time of the sweep (seeds 2004 + 17 r), scored on seeds 9004 + 17 r"
+    res["primary_ratio"] = "mse_x_time_ratio_at_best_c_tilde"
     res["mse_x_time_ratio_at_best_c_tilde"] = (res["uniform_best"]["lam_pf"]["mse_x_time"]
                                                / res["learned_best"]["lam_pf"]["mse_x_time"])
+    res["mse_x_time_ratio_uniform_over_learned"] = (res["uniform"]["lam_pf"]["mse_x_time"]
+                                                    / res["learned"]["lam_pf"]["mse_x_time"])
     # the conditional-mean holding time (RESTORE_FLAG_RB_DT) at the provable
     # and at the best c~ of each method
     res["rb_dt"] = {}
@@ -314,7 +336,95 @@ def mse_time(wl, replicates: int = 16, log=None) -> dict:
     # its sweep), M^l proposing its large steps from it
     res["restore_vs_mh_learned_mu"] = restore_vs_mh(wl, mu=mu, c_tilde=ct_learned,
                                                     c_tilde_best=res["learned_best"]["c_tilde"])
+    # rooflines of the learned-mu step kernel: at the provable c~ (almost
+    # every step a regeneration) and at the largest c~ of the sweep whose
+    # kill rate is at most 0.8, where local MALA moves take a large share of
+    # the steps
+    res["roofline_learned_mu"] = step_roofline(wl, mu, ct_learned)
+    local = [r for r in res["sweep"]["learned"] if r["kill_rate"] <= 0.8][0]
+    res["roofline_local_moves"] = step_roofline(wl, mu, local["c_tilde"])
+    # the training's NLL kernel (and a whole epoch) on 2^22 fresh samples;
+    # last, because it steps the optimiser of the model that mu reads from
+    res["roofline_training"] = training_roofline(wl, model, mu, ct_learned)
     return res
+
+
+def step_roofline(wl, mu, c_tilde, passes: int = 3) -> dict:
+    """The step kernel (B steps of the whole population) with HIP events on
+    the launch stream, against the FP32 vector peak; algorithmic flops from
+    flops_per_transition at the measured kill rate (learned mu included)."""
+    import numpy as np
+    import torch
+    from paper_2409_07148_amd import restore as R
+    stream = torch.cuda.current_stream()
+    ms, kill = [], []
+    for r in range(passes):
+        run = R.Run(R.problem_from_workload(wl, mu=mu, c_tilde=c_tilde, seed=8008 + 13 * r))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        run.step(wl.n_steps)
+        e1.record(stream)
+        run.drain()
+        est = run.estimate()
+        run.close()
+        ms.append(e0.elapsed_time(e1))
+        kill.append(est["kill_rate"])
+    kernel_ms = float(np.median(ms))
+    k = float(np.mean(kill))
+    fpt = flops_per_transition(wl.target, wl.d, wl.K, wl.local, k, wl.n_leapfrog,
+                               mu_comp=int(mu["n_comp"]) if mu is not None else 0)
+    achieved = fpt["mean"] * wl.n_chains * wl.n_steps / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": "step_kernel" + (" (learned mu)" if mu is not None else ""),
+            "c_tilde": c_tilde, "kill_rate": k, "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "kernel_ms": kernel_ms, "flops_per_transition": fpt,
+            "kernel_transitions_per_s": wl.n_chains * wl.n_steps / (kernel_ms * 1e-3), "traffic": None}
+
+
+def training_roofline(wl, model, mu, c_tilde, reps: int = 20) -> dict:
+    """The learned-mu training step on 2^22 recorded samples: the NLL kernel
+    (float32 mixture densities on the vector unit, responsibility-weighted
+    moments on the FP64 matrix cores) against the FP32 vector peak, its
+    matrix-core share against the FP64 matrix peak, and a whole epoch (MLP
+    forward, NLL and gradient, MLP backward, Adam), each timed with HIP
+    events over `reps` calls.  Algorithmic flops per (sample, component):
+    4d + 9 on the vector unit (centred score and its square 4d, a_k 2, the
+    exponential and its scaling 3, sum, max, responsibility 3, with FMA = 2),
+    and 2 x 2d for the moments on the matrix cores."""
+    import torch
+    from paper_2409_07148_amd.learned_mu import record_samples
+    x, w = record_samples(wl, mu, c_tilde, 9009, 4)
+    xs, ws = x.reshape(-1, wl.d).contiguous(), w.reshape(-1).contiguous()
+    n = ws.numel()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    model.forward()
+    nll_ms = timed(lambda: model.nll_and_grad(xs, ws))
+
+    def epoch():
+        model.forward()
+        model.nll_and_grad(xs, ws)
+        model.backward()
+        model.adam(1e-6)
+    epoch_ms = timed(epoch)
+    K, d = model.K, wl.d
+    valu = (4 * d + 9) * K * n / (nll_ms * 1e-3) / 1e12
+    mfma = 2 * 2 * d * K * n / (nll_ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": "gmm_nll_kernel", "samples": n, "components": K, "dim": d,
+            "achieved": valu, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": valu / PEAK_FP32_TFLOPS,
+            "mfma_fp64": {"achieved": mfma, "peak": PEAK_FP64_MATRIX_TFLOPS, "unit": "TFLOP/s",
+                          "frac": mfma / PEAK_FP64_MATRIX_TFLOPS},
+            "nll_ms": nll_ms, "epoch_ms": epoch_ms, "traffic": None}
 
 
 def mse_time_image(wl, replicates: int = 8, log=None) -> dict:
@@ -561,6 +671,26 @@ def general_vs_invariant(wl, replicates: int = 16) -> dict:
     return res
 
 
+def learned_pass(wl) -> dict:
+    """Profiling target for the learned part: one short training (refit 0
+    only: 2^22 samples recorded with uniform mu at c~ = 1, 100 Adam epochs)
+    and one pass of the workload with the learned mu at its provable c~ and
+    one at c~ = 3.34, where local moves take a large share of the steps."""
+    import torch
+    from paper_2409_07148_amd.learned_mu import MlpGmm, provable_c_tilde, refit
+    model = MlpGmm(d=wl.d, K=64, in_dim=12, hidden=64, beta=0.1, seed=3004)
+    ct = provable_c_tilde(wl.c_tilde, model.beta)
+    t0 = time.perf_counter()
+    refit(wl, model, ct, refits=1, record_steps=4, epochs=100, lr=2e-2, seed=3004, c_tilde_explore=1.0,
+          log=lambda *a: None)
+    torch.cuda.synchronize()
+    out = {"training_s": time.perf_counter() - t0, "epochs": 100}
+    mu = model.mu()
+    out["provable"] = step_roofline(wl, mu, ct, passes=1)
+    out["local_moves"] = step_roofline(wl, mu, 3.34, passes=1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -582,6 +712,9 @@ def main():
                     help="skip the comparison with the MH chain M^l (mixture proposal, burn-in)")
     ap.add_argument("--no-image", action="store_true",
                     help="diagnostic: run the rendering-shaped workload without its pixel integrand")
+    ap.add_argument("--learned-pass", action="store_true",
+                    help="profiling target: a short learned-mu training and one learned-mu pass at two c~ "
+                         "(8-D workload); prints one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -597,6 +730,9 @@ def main():
 
     if args.workload == "batched_uneven":
         bench_batched(args)
+        return
+    if args.learned_pass:
+        print(json.dumps({"learned_pass": learned_pass(gmm_full())}), flush=True)
         return
 
     wl = {"gmm_full_8d": gmm_full, "gmm_iso_2d": gmm_iso_2d, "gmm_iso_2d_unadjusted": gmm_iso_2d_unadjusted,
@@ -728,6 +864,11 @@ def main():
         line["copy_calibration_bytes"] = src.numel() * 4
     if wl.name == "gmm_full_8d" and wl.local != "hmc" and not args.no_mse_time:
         line["mse_time"] = mse_time(wl)
+        # the learned part's kernels against their rooflines, beside the
+        # headline's: the learned-mu step kernel where regenerations and
+        # where local moves dominate, and the training's NLL kernel
+        for key in ("roofline_learned_mu", "roofline_local_moves", "roofline_training"):
+            line[key] = line["mse_time"][key]
     if wl.name == "pss_render_12d" and not wl.tile_px and not args.no_image and not args.no_mse_time:
         line["mse_time_image"] = mse_time_image(wl)
     if wl.name in ("gmm_full_8d", "gmm_iso_2d") and not args.no_mh:

@@ -181,6 +181,11 @@ typedef struct {
 #define RESTORE_FLAG_SPLAT_TIGHT 4   /* PIXEL: 64-fold smaller splat buckets,
                                         so that overflowing records take the
                                         direct path (exercises that path)   */
+#define RESTORE_FLAG_INLINE_RNG  16  /* draw every step's random numbers in the
+                                        step kernel also for populations below
+                                        2^16 chains, which by default take
+                                        them from a chip-wide pre-pass (the
+                                        chains are the same either way)      */
 #define RESTORE_FLAG_RB_DT       8   /* accumulate the conditional mean
                                         E[dt | x] = 1 / (1 + k(x)) of the
                                         holding time in place of the sampled
@@ -263,8 +268,10 @@ typedef struct restore_ctx restore_ctx;
 /* Bytes of device memory the state buffer must provide for this problem:
  * the per-chain state of Alg. 2 (x, the cached log p, log u and grad log p,
  * the running and completed tour sums of Sec. 6.3) in structure-of-arrays
- * layout, the packed parameters, reduction and drain scratch, and the
- * splat buckets of the image integrand.  Pure host computation; the same
+ * layout, the packed parameters, reduction and drain scratch, the splat
+ * buckets of the image integrand, and for populations below 2^16 chains
+ * with the uniform mu the buffer (at most 32 MiB) of the random-input
+ * pre-pass of restore_step.  Pure host computation; the same
  * validation as restore_init (INVALID_ARG, UNSUPPORTED, NONFINITE). */
 restore_status restore_state_bytes(const restore_target *target, const restore_mu *mu,
                                    const restore_local_kernel *local,
@@ -291,8 +298,13 @@ restore_status restore_init(restore_ctx **out, const restore_target *target,
  * continuous-time chain with generator K_l - id).
  * With the PIXEL integrand (unless RESTORE_FLAG_SPLAT_DIRECT) the steps run
  * as launches of at most 64 steps whose splat records are binned by image
- * band in the state buffer and summed into the image after each launch;
- * the chains are the same either way. */
+ * band in the state buffer and summed into the image after each launch.
+ * Populations below 2^16 chains with the uniform mu (restore, no image, no
+ * LDS staging, no RESTORE_FLAG_INLINE_RNG) run chunks of steps, each a
+ * chip-wide pre-pass of the steps' state-independent random inputs (the
+ * Philox blocks, the clocks' exponentials, ln u_acc, the candidate
+ * uniforms and their Box-Muller normals) followed by the step launch that
+ * reads them.  The chains are the same either way. */
 restore_status restore_step(restore_ctx *ctx, int32_t n_steps, void *stream);
 
 /* End of the budget (the estimators of Sec. 7.4 assume a run that ends at

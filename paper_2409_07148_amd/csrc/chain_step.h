@@ -237,6 +237,19 @@ __device__ __forceinline__ void store_chain(const StepArgs &a, uint32_t c, const
     a.last_dt[c] = ch.last_dt;
 }
 
+// The state-independent random inputs of one step of one chain, as a
+// pre-pass computes them for small populations (uniform mu): the holding
+// and termination exponentials t1 = -ln u_E1 and e2 = -ln u_E2, ln u_acc,
+// the candidate uniforms (the regeneration's state) and their Box-Muller
+// normals (the local move's noise).  The same device code computes them
+// inline otherwise, so both paths give the same chains bit for bit.
+template <int D>
+struct StepRand {
+    float t1, e2, lacc;
+    float cand[D];
+    float z[D];
+};
+
 // One transition of Alg. 2 for one lane.  Returns kill / accept through the
 // flags.  In the drain (RETIRE) a terminated chain is not regenerated.
 // With BIN, a splat closed by this step is returned in ch.out_pix /
@@ -250,9 +263,11 @@ __device__ __forceinline__ void store_chain(const StepArgs &a, uint32_t c, const
 // small-step update; dt f(x_{i-1}) goes straight to the float64 chain sums,
 // as the chain has no tours.  ST_LAST_LARGE reports the large-step choice.
 template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT, bool BIN = false, bool MH = false,
-          bool TILED = false>
+          bool TILED = false, bool PRE = false>
 __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
-                                          uint32_t chain, Chain<D, LOC> &ch, bool &kill, bool &accept) {
+                                          uint32_t chain, Chain<D, LOC> &ch, bool &kill, bool &accept,
+                                          const StepRand<D> *pr = nullptr) {
+    static_assert(!PRE || (MU == MU_UNIFORM && !MH && !TILED), "precomputed inputs: uniform mu, restore only");
     constexpr int NB = NBlocks<D>::value;
     if constexpr (std::is_same<PT, const_fptr>::value) {
         // keep the scalar parameter loads inside the step: hoisted out of the
@@ -262,23 +277,30 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         P = (PT)pv;
     }
     float head[4], cand[4 * NB];
-    draw_step<NB>(s, a.chain0 + chain, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
-
-    // the two exponential clocks
-    const float t1 = -logf(head[0]);
-    const float e2 = -logf(head[1]);
+    float t1, e2;
+    if constexpr (PRE) {
+        t1 = pr->t1;
+        e2 = pr->e2;
+    } else {
+        draw_step<NB>(s, a.chain0 + chain, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
+        // the two exponential clocks
+        t1 = -logf(head[0]);
+        e2 = -logf(head[1]);
+    }
     float t2 = INFINITY;
     float inv_k = INFINITY;
     kill = false;
     if (!MH && !a.no_kill) {
         // t2 = E2 / k = E2 exp(log p - log u - ln c_tilde); p = 0 gives t2 = 0
-        inv_k = expf(ch.lp - ch.lu - a.log_c);
+        // (hardware 2^x: |x| 2^-24 relative, far inside the decision margins)
+        inv_k = exp_rel(ch.lp - ch.lu - a.log_c);
         t2 = e2 * inv_k;
         kill = !(t1 < t2);
     }
     // the holding time dt = min(t1, t2) ~ Exp(1 + k) whichever clock fires;
     // with rb_dt its conditional mean 1 / (1 + k) is accumulated instead
-    const float dt = a.rb_dt ? (inv_k > 1e30f ? 1.0f : inv_k / (1.0f + inv_k)) : (kill ? t2 : t1);
+    float dt = kill ? t2 : t1;
+    if (a.rb_dt) dt = inv_k > 1e30f ? 1.0f : inv_k / (1.0f + inv_k);
 
     bool large = false;
     if constexpr (MH) {
@@ -290,11 +312,11 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         ch.status = large ? (ch.status | ST_LAST_LARGE) : (ch.status & ~ST_LAST_LARGE);
         // no tours: dt f(x_{i-1}) goes to the chain sums
         ch.t_done += (double)dt;
-        if (a.integrand_p) ch.a_done = fma((double)dt, (double)expf(ch.lp), ch.a_done);
+        if (a.integrand_p) ch.a_done = fma((double)dt, (double)exp_rel(ch.lp), ch.a_done);
     } else {
         // accumulate dt f(x_{i-1}) into the tour in flight
         ch.t_cur += dt;
-        if (a.integrand_p) ch.a_cur = fmaf(dt, expf(ch.lp), ch.a_cur);
+        if (a.integrand_p) ch.a_cur = fmaf(dt, exp_rel(ch.lp), ch.a_cur);
     }
     if (TGT == TGT_PSS && a.image) {
         // f = 1_pixel(x0, x1) at the pre-transition state (p = 0 off the box)
@@ -325,7 +347,16 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         ch.splat_acc += dt;
     }
     ch.last_dt = dt;
-    if (kill) {
+    // random-walk kinds with precomputed inputs run branch-free (selects):
+    // the same arithmetic, fewer exec-mask switches on the serial step path
+    constexpr bool FLAT = PRE && !uses_grad(LOC) && LOC != LOC_HMC;
+    if constexpr (FLAT) {
+        ch.a_done += kill ? (double)ch.a_cur : 0.0;
+        ch.t_done += kill ? (double)ch.t_cur : 0.0;
+        ch.n_done += kill ? 1u : 0u;
+        ch.a_cur = kill ? 0.0f : ch.a_cur;
+        ch.t_cur = kill ? 0.0f : ch.t_cur;
+    } else if (kill) {
         ch.a_done += (double)ch.a_cur;
         ch.t_done += (double)ch.t_cur;
         ch.n_done += 1u;
@@ -345,16 +376,30 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     const float h = 0.5f * a.step * a.step;
     float rho[D];          // HMC: momentum before the closing half step
     bool inside = true;    // HMC: every leapfrog point has p > 0
-    if (kill || large) {
-        sample_mu<D, MU, 4 * NB>(a, head[3], cand, y);
-        if constexpr (TILED) tile_sample(a, ch.tpx0, ch.tpy0, ch.tw, ch.th, cand, y);
+    if constexpr (FLAT) {
+        // regeneration: the candidate uniforms; local move: x + step z
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[i] = kill ? pr->cand[i] : fmaf(a.step, pr->z[i], ch.x[i]);
+    } else if (kill || large) {
+        if constexpr (PRE) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) y[i] = pr->cand[i];
+        } else {
+            sample_mu<D, MU, 4 * NB>(a, head[3], cand, y);
+            if constexpr (TILED) tile_sample(a, ch.tpx0, ch.tpy0, ch.tw, ch.th, cand, y);
+        }
     } else {
         if (uses_grad(LOC) && !(ch.status & ST_GRAD_VALID)) {
             (void)log_target<D, TGT, true>(P, a.n_comp, ch.x, ch.g);
             ch.status |= ST_GRAD_VALID;
         }
         float z[D];
-        box_muller<D, 4 * NB>(cand, z);
+        if constexpr (PRE) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) z[i] = pr->z[i];
+        } else {
+            box_muller<D, 4 * NB>(cand, z);
+        }
         if constexpr (LOC == LOC_HMC) {
             // leapfrog with unit mass from (x, rho_0 = z): half a momentum
             // step, n position steps separated by full momentum steps; the
@@ -380,12 +425,13 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         } else {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                float delta = a.step * z[i];
                 if (LOC == LOC_MALA) {
-                    delta = fmaf(h, ch.g[i], delta);
+                    const float delta = fmaf(h, ch.g[i], a.step * z[i]);
                     zz = fmaf(z[i], z[i], zz);
+                    y[i] = ch.x[i] + delta;
+                } else {
+                    y[i] = fmaf(a.step, z[i], ch.x[i]);
                 }
-                y[i] = ch.x[i] + delta;
             }
         }
     }
@@ -428,10 +474,20 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                 }
                 lr = inside ? lr + 0.5f * (zz - kk) : -INFINITY;
             }
-            accept = logf(head[2]) < lr;
+            if constexpr (PRE) {
+                accept = pr->lacc < lr;
+            } else {
+                accept = logf(head[2]) < lr;
+            }
         }
     }
-    if (kill || accept) {
+    if constexpr (FLAT) {
+        const bool take = kill || accept;
+#pragma unroll
+        for (int i = 0; i < D; ++i) ch.x[i] = take ? y[i] : ch.x[i];
+        ch.lp = take ? lpy : ch.lp;
+        ch.lu = take ? luy : ch.lu;
+    } else if (kill || accept) {
 #pragma unroll
         for (int i = 0; i < D; ++i) ch.x[i] = y[i];
         if (uses_grad(LOC)) {

@@ -76,8 +76,10 @@ __device__ __forceinline__ void box_muller(const float cand[NC], float z[D]) {
     }
 }
 
-// e^x through the hardware base-2 exponential; used for mixture weights
-// relative to a running maximum, where the argument is <= 0.
+// e^x through the hardware base-2 exponential (relative error about
+// |x| 2^-24 from the rounding of x log2 e, plus the instruction's own);
+// used for mixture weights relative to a running maximum, the killing rate
+// and the integrand p = e^{log p}.
 __device__ __forceinline__ float exp_rel(float x) {
     return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
 }

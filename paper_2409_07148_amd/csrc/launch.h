@@ -23,6 +23,11 @@ struct KernelSet {
     const void *step_mh = nullptr;           // the MH reference chain M^l (c_tilde = 0)
     const void *step_tiled = nullptr;        // image integrand, tile-stratified
     const void *drain_tiled = nullptr;
+    // small populations with the uniform mu: a chip-wide pre-pass of every
+    // step's state-independent random inputs, and the step kernel that
+    // reads them instead of drawing them on its own serial path
+    const void *rand_prepass = nullptr;
+    const void *step_pre = nullptr;
 };
 
 // Binned splats of one step launch into the image: per-band LDS

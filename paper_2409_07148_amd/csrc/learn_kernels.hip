@@ -148,10 +148,30 @@ __device__ __forceinline__ float row16_sum(float v) {
 // LDS in wave order and the block writes one partial row set:
 // partials[block][row][64], rows: 0 S0, 1 + i P1_i, 1 + d + i P2_i,
 // 1 + 2d [LW, W].  Samples: the block's contiguous range in passes of 4,
-// wave v taking passes v, v + NLL_WAVES, ...
+// two passes per iteration, wave v taking pass pairs v, v + NLL_WAVES, ...
+// Exponentials and logarithms go through the base-2 hardware instructions
+// (e^y = 2^{y log2 e}; the rounding of y log2 e adds |y| 2^-24 relative).
 __host__ __device__ constexpr int nll_feature_tiles(int D) { return (2 * D + 15) / 16; }
 
-template <int D>
+// x[0..D) of one sample row (16-byte loads where the rows are 16-byte aligned)
+template <int D, bool VEC>
+__device__ __forceinline__ void load_row(const float *p, float (&x)[D]) {
+    if constexpr (VEC && D % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < D; i += 4) {
+            const float4 v = *reinterpret_cast<const float4 *>(p + i);
+            x[i] = v.x;
+            x[i + 1] = v.y;
+            x[i + 2] = v.z;
+            x[i + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < D; ++i) x[i] = p[i];
+    }
+}
+
+template <int D, bool VEC>
 __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
     typedef double double4_t __attribute__((ext_vector_type(4)));
     constexpr int NF = nll_feature_tiles(D);
@@ -160,7 +180,6 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
     __shared__ float lse_part[64];
     const int l = threadIdx.x % 64, wv = threadIdx.x / 64;
     const int K = a.n_comp;
-    const int n_ct = (K + 15) / 16;  // component tiles in use
 
     // the mixture weights ln pi = logits - LSE(logits) (one wave-wide pass)
     {
@@ -202,61 +221,99 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
 #pragma unroll
         for (int u = 0; u < NF; ++u) acc[t][u] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
+    constexpr float LOG2E = 1.4426950408889634f, LN2 = 0.6931471805599453f;
+    const bool defensive = l % 16 == 0 && a.beta > 0.0f;  // the uniform share, once per sample row
     const int64_t lo = (int64_t)blockIdx.x * a.per_block;
     const int64_t hi = lo + a.per_block < a.n ? lo + a.per_block : a.n;
-    const int sl = l / 16;  // this lane's sample within the pass
-    // this lane's column of B: feature f = 16 u + l % 16
-    for (int64_t p = lo + 4 * (int64_t)wv; p < hi; p += 4 * NLL_WAVES) {
-        const int64_t n = p + sl;
-        const bool valid = n < hi;
-        const float w = valid ? a.w[n] : 0.0f;
-        float x[D];
-        bool in = true;
+    const int sl = l / 16;  // this lane's sample within a pass
+    // NP passes per iteration, so that the lane exchanges of one pass overlap
+    // the arithmetic of the other; a sample past the range is replaced by
+    // the range's last one with weight 0 (loads stay unconditional)
+    constexpr int NP = D <= 10 ? 2 : 1;
+    // feature 16 u + l % 16 of this lane: coordinate fx[u], squared or not,
+    // or zero past 2d
+    int fx[NF];
+    bool fsq[NF];
+    double fone[NF];
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            x[i] = valid ? a.x[n * D + i] : 0.5f;
-            in = in && x[i] >= 0.0f && x[i] <= 1.0f;
-        }
-        float at[4];
-        float mx = in ? lbeta : -INFINITY;
+    for (int u = 0; u < NF; ++u) {
+        const int f = 16 * u + l % 16;
+        fx[u] = f < D ? f : (f < 2 * D ? f - D : 0);
+        fsq[u] = f >= D && f < 2 * D;
+        fone[u] = f < 2 * D ? 1.0 : 0.0;
+    }
+    for (int64_t p = lo + 4 * NP * (int64_t)wv; p < hi; p += 4 * NP * NLL_WAVES) {
+        float x[NP][D], w[NP], at[NP][4], mx[NP], xf[NP][NF];
+        bool in[NP];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            float q = 0.0f;
+        for (int j = 0; j < NP; ++j) {
+            const int64_t n = p + 4 * j + sl;
+            const bool valid = n < hi;
+            const int64_t nl = valid ? n : hi - 1;
+            load_row<D, VEC>(a.x + nl * D, x[j]);
+            // this lane's B column: feature 16 u + l % 16 is x or x^2 of
+            // coordinate fx[u] (a second load of the same row, in cache)
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                const float z = (x[i] - m[t][i]) * is[t][i];
-                q = fmaf(z, z, q);
+            for (int u = 0; u < NF; ++u) xf[j][u] = a.x[nl * D + fx[u]];
+            const float wl = a.w[nl];
+            w[j] = valid ? wl : 0.0f;
+            float xlo = x[j][0], xhi = x[j][0];
+#pragma unroll
+            for (int i = 1; i < D; ++i) {
+                xlo = fminf(xlo, x[j][i]);
+                xhi = fmaxf(xhi, x[j][i]);
             }
-            at[t] = t < n_ct ? fmaf(-0.5f, q, c[t]) : -INFINITY;
-            mx = fmaxf(mx, at[t]);
-        }
-        const float M = row16_max(mx);
-        float e[4], se = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            e[t] = at[t] > -INFINITY ? expf(at[t] - M) : 0.0f;
-            se += e[t];
-        }
-        // the defensive uniform share counts once per sample (lane 0 of the row)
-        const float eb = (l % 16 == 0 && in && a.beta > 0.0f) ? expf(lbeta - M) : 0.0f;
-        const float S = row16_sum(se + eb);
-        const float inv_s = S > 0.0f ? 1.0f / S : 0.0f;
-        const double wd = (double)w;
-        if (l % 16 == 0) {
-            lw += wd * (double)(M + logf(S));
-            wsum += wd;
-        }
-        double bf[NF];
-#pragma unroll
-        for (int u = 0; u < NF; ++u) {
-            const int f = 16 * u + l % 16;
-            const double xv = f < 2 * D ? (double)x[f < D ? f : f - D] : 0.0;
-            bf[u] = f < D ? xv : (f < 2 * D ? xv * xv : 0.0);
+            in[j] = xlo >= 0.0f && xhi <= 1.0f;
+            mx[j] = in[j] ? lbeta : -INFINITY;
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            if (t < n_ct) {
-                const double wr = wd * (double)(e[t] * inv_s);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                float q = 0.0f;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const float z = (x[j][i] - m[t][i]) * is[t][i];
+                    q = fmaf(z, z, q);
+                }
+                at[j][t] = fmaf(-0.5f, q, c[t]);   // -inf for components past K
+                mx[j] = fmaxf(mx[j], at[j][t]);
+            }
+        }
+        float M[NP], S[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            M[j] = row16_max(mx[j]);
+            M[j] = M[j] > -INFINITY ? M[j] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            float se = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                at[j][t] = __builtin_amdgcn_exp2f((at[j][t] - M[j]) * LOG2E);   // e^{a - M}
+                se += at[j][t];
+            }
+            if (defensive && in[j]) se += __builtin_amdgcn_exp2f((lbeta - M[j]) * LOG2E);
+            S[j] = row16_sum(se);
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const float inv_s = S[j] > 0.0f ? __builtin_amdgcn_rcpf(S[j]) : 0.0f;
+            const double wd = (double)w[j];
+            if (l % 16 == 0) {
+                lw += wd * (double)(M[j] + __builtin_amdgcn_logf(S[j]) * LN2);
+                wsum += wd;
+            }
+            double bf[NF];
+#pragma unroll
+            for (int u = 0; u < NF; ++u) {
+                const double xv = (double)xf[j][u];
+                bf[u] = fsq[u] ? xv * xv : xv * fone[u];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double wr = wd * (double)(at[j][t] * inv_s);
                 s0[t] += wr;
 #pragma unroll
                 for (int u = 0; u < NF; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(wr, bf[u], acc[t][u], 0, 0, 0);
@@ -395,7 +452,11 @@ hipError_t launch_colsum(const float *d, float *db, int G, int n, hipStream_t s)
 template <int D>
 static void launch_nll_d(const NllArgs &a, hipStream_t s) {
     const int entries = nll_rows(D) * 64;
-    hipLaunchKernelGGL(gmm_nll_kernel<D>, dim3(a.n_blocks), dim3(64 * NLL_WAVES), 0, s, a);
+    // rows of D % 4 == 0 floats are 16-byte aligned when x is
+    if (D % 4 == 0 && reinterpret_cast<uintptr_t>(a.x) % 16 == 0)
+        hipLaunchKernelGGL((gmm_nll_kernel<D, true>), dim3(a.n_blocks), dim3(64 * NLL_WAVES), 0, s, a);
+    else
+        hipLaunchKernelGGL((gmm_nll_kernel<D, false>), dim3(a.n_blocks), dim3(64 * NLL_WAVES), 0, s, a);
     hipLaunchKernelGGL(gmm_nll_sum_kernel, dim3((entries + 255) / 256), dim3(256), 0, s, (const double *)a.partials,
                        entries, a.n_blocks, a.totals);
     hipLaunchKernelGGL(gmm_nll_grad_kernel<D>, dim3(1), dim3(64), 0, s, a, (const double *)a.totals);

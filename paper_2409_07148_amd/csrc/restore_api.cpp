@@ -44,7 +44,19 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     size_t x, logp, logu, grad, a_cur, t_cur, last_dt, a_done, t_done, n_done, status;
     size_t list0, list1, counts, counters, params, mu, partials, results;
-    size_t bin_pix, bin_val, bin_count, bin_partial, img_tours, tile_results, total;
+    size_t bin_pix, bin_val, bin_count, bin_partial, img_tours, tile_results, rand, total;
+};
+
+// Small populations (fewer than 2^16 chains: a few waves, each step a long
+// serial instruction stream) with the uniform mu: the state-independent
+// random inputs of every step -- Philox blocks, the clocks' logarithms,
+// Box-Muller -- come from a chip-wide pre-pass, `chunk` steps at a time, into
+// a buffer of rand_fields(d) x chunk x C floats (at most 32 MiB); the chains
+// are the same either way.  Off for the MH chain, the image integrand, the
+// learned mu, LDS-staged parameters and RESTORE_FLAG_INLINE_RNG.
+struct RandPlan {
+    int chunk = 0;   // steps per pre-pass (0: off)
+    int fields = 0;
 };
 
 // Binned splats (image integrand): bands of 2^SPLAT_BAND_SHIFT pixels, each
@@ -93,12 +105,28 @@ SplatPlan splat_plan(const restore_config *cfg, int tgt) {
     return sp;
 }
 
+constexpr int64_t RAND_BUFFER_BYTES = 32LL << 20;
+
+RandPlan rand_plan(const restore_config *cfg, int tgt, int d, int mu) {
+    RandPlan rp;
+    if (cfg->n_chains >= (1LL << 16) || mu != MU_UNIFORM || tgt == TGT_PSS || cfg->c_tilde == 0.0 ||
+        (cfg->flags & (RESTORE_FLAG_INLINE_RNG | RESTORE_FLAG_PARAMS_LDS)))
+        return rp;
+    const int64_t per_step = cfg->n_chains * (int64_t)rand_fields(d) * (int64_t)sizeof(float);
+    const int64_t chunk = std::min<int64_t>(256, RAND_BUFFER_BYTES / per_step);
+    if (chunk < 16) return rp;
+    rp.chunk = (int)chunk;
+    rp.fields = rand_fields(d);
+    return rp;
+}
+
 int n_param_floats(int tgt, int loc, int d, int K) {
     if (tgt == TGT_PSS) return PSS_SLAB;
     return comp_stride(tgt, d) * K + (loc == LOC_RWU ? INFLOW_STRIDE * K : 0);
 }
 
-Layout make_layout(int64_t C, int d, bool grad, int n_params, int n_mu_floats, const SplatPlan &sp) {
+Layout make_layout(int64_t C, int d, bool grad, int n_params, int n_mu_floats, const SplatPlan &sp,
+                   const RandPlan &rp) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
@@ -129,6 +157,7 @@ Layout make_layout(int64_t C, int d, bool grad, int n_params, int n_mu_floats, c
     L.bin_partial = nb ? take(4 * (size_t)sp.n_slices * (nb << SPLAT_BAND_SHIFT)) : (size_t)-1;
     L.img_tours = sp.batches ? take(8 * (size_t)sp.batches * std::max(1, sp.n_tiles)) : (size_t)-1;
     L.tile_results = sp.n_tiles ? take(8 * (size_t)sp.n_tiles * TR_SLOTS) : (size_t)-1;
+    L.rand = rp.chunk ? take(4 * (size_t)rp.fields * (size_t)rp.chunk * c) : (size_t)-1;
     L.total = o;
     return L;
 }
@@ -422,6 +451,7 @@ struct restore_ctx {
     float *image = nullptr;
     restore_mu mu{};
     SplatPlan splat{};
+    RandPlan rand{};
     StepArgs args{};
 };
 
@@ -528,7 +558,8 @@ restore_status restore_state_bytes(const restore_target *target, const restore_m
     restore_status st = validate(target, mu, local, cfg, &v);
     if (st != RESTORE_OK) return st;
     *bytes_out = make_layout(cfg->n_chains, v.d, uses_grad(v.loc), n_param_floats(v.tgt, v.loc, v.d, v.K),
-                             v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0, splat_plan(cfg, v.tgt)).total;
+                             v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0, splat_plan(cfg, v.tgt),
+                             rand_plan(cfg, v.tgt, v.d, v.mu)).total;
     return RESTORE_OK;
 }
 
@@ -548,7 +579,8 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     const int n_params = n_param_floats(v.tgt, v.loc, v.d, v.K);
     const int n_mu = v.mu == MU_GMM ? mu_slab_floats(v.d, mu->n_comp) : 0;
     const SplatPlan sp = splat_plan(cfg, v.tgt);
-    const Layout lay = make_layout(cfg->n_chains, v.d, uses_grad(v.loc), n_params, n_mu, sp);
+    const RandPlan rp = rand_plan(cfg, v.tgt, v.d, v.mu);
+    const Layout lay = make_layout(cfg->n_chains, v.d, uses_grad(v.loc), n_params, n_mu, sp, rp);
     if (state_bytes < lay.total)
         return fail(RESTORE_E_BUFFER_TOO_SMALL, "state buffer holds %zu bytes, %zu needed", state_bytes, lay.total);
     KernelSet ks = find_kernels(v.tgt, v.d, v.loc, v.mu);
@@ -578,6 +610,7 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     c->image = (cfg->integrands & RESTORE_INTEGRAND_PIXEL) ? image_dev : nullptr;
     c->mu = *mu;
     c->splat = sp;
+    c->rand = ks.step_pre ? rp : RandPlan{};
     fill_args(c);
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -644,6 +677,23 @@ static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_recor
         hipError_t e = hipLaunchKernel(c->ks.step_tiled, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs,
                                        tile_shm, s);
         if (e != hipSuccess) return hip_fail(e, "tiled step launch");
+    } else if (c->rand.chunk && !x_out) {
+        // small population: per chunk, a chip-wide pre-pass of the steps'
+        // random inputs, then the steps reading them
+        float *buf = at<float>(c, c->lay.rand);
+        const float *cbuf = buf;
+        int chunk = c->rand.chunk;
+        void *pargs[] = {&a, &buf, &chunk};
+        void *sargs[] = {&a, &cbuf, &chunk};
+        for (int32_t done = 0; done < n_steps; done += chunk) {
+            a.s0 = (uint32_t)(c->steps_taken + done);
+            a.n_steps = std::min<int32_t>(chunk, n_steps - done);
+            hipError_t e = hipLaunchKernel(c->ks.rand_prepass, dim3((unsigned)((c->cfg.n_chains + 255) / 256),
+                                                                    (unsigned)a.n_steps), dim3(256), pargs, 0, s);
+            if (e != hipSuccess) return hip_fail(e, "random pre-pass launch");
+            e = hipLaunchKernel(c->ks.step_pre, grid_for(c->cfg.n_chains, c->block), dim3(c->block), sargs, 0, s);
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+        }
     } else if (!c->splat.n_bins) {
         const void *fn = c->lds ? c->ks.step_lds : c->ks.step;
         hipError_t e = hipLaunchKernel(fn, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, shm, s);

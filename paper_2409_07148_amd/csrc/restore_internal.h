@@ -65,6 +65,10 @@ constexpr int PSS_SLAB = 112;
 __host__ __device__ constexpr int mu_stride(int d) { return ((1 + 2 * d + 3) / 4) * 4; }
 __host__ __device__ constexpr int mu_slab_floats(int d, int K) { return 4 + K * mu_stride(d) + K + K * 2 * d; }
 
+// Fields of the precomputed random inputs of one step (StepRand: t1, e2,
+// ln u_acc, d candidate uniforms, d Box-Muller normals).
+__host__ __device__ constexpr int rand_fields(int D) { return 3 + 2 * D; }
+
 // Per-launch arguments of the step kernels.
 struct StepArgs {
     // chain state (structure of arrays, C chains)

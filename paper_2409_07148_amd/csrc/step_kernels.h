@@ -63,6 +63,97 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_float
     add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill, n_large, n_large_acc);
 }
 
+// Pre-pass of a chunk of steps for a small population (uniform mu): thread
+// (chain c, step j of the chunk) draws step a.s0 + j of chain c and writes
+// its StepRand fields to out[f][j][c] (field f of rand_fields(D); a field
+// is chunk x C floats).  Chip-wide, so the Philox blocks and the
+// transcendental mappings of every step run on all compute units instead of
+// on the few waves of the population's serial step loop.
+template <int D>
+__global__ __launch_bounds__(256) void rand_prepass_kernel(StepArgs a, float *out, int chunk) {
+    constexpr int NB = NBlocks<D>::value;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (c >= a.n_chains || j >= a.n_steps) return;
+    float head[4], cand[4 * NB];
+    draw_step<NB>(a.s0 + (uint32_t)j, a.chain0 + (uint32_t)c, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
+    const int64_t C = a.n_chains, fs = (int64_t)chunk * C;
+    float *o = out + (int64_t)j * C + c;
+    o[0] = -logf(head[0]);
+    o[fs] = -logf(head[1]);
+    o[2 * fs] = logf(head[2]);
+    float z[D];
+    box_muller<D, 4 * NB>(cand, z);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        o[(3 + i) * fs] = cand[i];
+        o[(3 + D + i) * fs] = z[i];
+    }
+}
+
+// Steps with regeneration whose random inputs come from the pre-pass (a
+// chunk of at most `chunk` steps; step it of the launch reads field f at
+// pre[(f chunk + it) C + c]).  Two register buffers of PF steps alternate:
+// one is loaded while the other's steps run.  The same chains as
+// step_kernel, bit for bit.
+template <int D, int TGT, int LOC>
+__global__ __launch_bounds__(256) void step_pre_kernel(StepArgs a, const float *pre, int chunk) {
+    constexpr int F = rand_fields(D);
+    constexpr int PF = F <= 8 ? 4 : (F <= 16 ? 2 : 1);
+    const const_fptr P = (const_fptr)a.params;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_chains) return;
+    Chain<D, LOC> ch;
+    load_chain(a, (uint32_t)c, ch);
+    // the buffer base is wave-uniform and every byte offset fits in 32 bits
+    // (at most 32 MiB), so the loads take the scalar-base addressing mode
+    const char *pb = reinterpret_cast<const char *>(pre);
+    const uint32_t C4 = 4u * (uint32_t)a.n_chains, fs4 = (uint32_t)chunk * C4;
+    auto ld = [&](uint32_t off) { return *reinterpret_cast<const float *>(pb + off); };
+    auto fetch = [&](StepRand<D> &r, int it) {
+        const uint32_t o = (uint32_t)it * C4 + 4u * (uint32_t)c;
+        r.t1 = ld(o);
+        r.e2 = ld(o + fs4);
+        r.lacc = ld(o + 2 * fs4);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            r.cand[i] = ld(o + (3 + i) * fs4);
+            r.z[i] = ld(o + (3 + D + i) * fs4);
+        }
+    };
+    unsigned long long n_acc = 0, n_kill = 0;
+    bool kill = false, accept = false;
+    auto run = [&](const StepRand<D> (&r)[PF], int it0) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            if (it0 + j < a.n_steps) {
+                step_once<D, TGT, LOC, MU_UNIFORM, false, const_fptr, false, false, false, true>(
+                    a, P, a.s0 + (uint32_t)(it0 + j), (uint32_t)c, ch, kill, accept, &r[j]);
+                n_acc += __popcll(__ballot(accept));
+                n_kill += __popcll(__ballot(kill));
+            }
+        }
+    };
+    auto load = [&](StepRand<D> (&r)[PF], int it0) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
+            if (it0 + j < a.n_steps) fetch(r[j], it0 + j);
+    };
+    StepRand<D> A[PF], B[PF];
+    load(A, 0);
+    for (int it0 = 0; it0 < a.n_steps; it0 += 2 * PF) {
+        load(B, it0 + PF);
+        run(A, it0);
+        load(A, it0 + 2 * PF);
+        run(B, it0 + PF);
+    }
+    ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT)) | (kill ? ST_LAST_KILL : 0u) |
+                (accept ? ST_LAST_ACCEPT : 0u);
+    store_chain(a, (uint32_t)c, ch);
+    const unsigned long long lanes = __popcll(__ballot(1));
+    add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill);
+}
+
 // Binning of the records staged in LDS: rows [0, rows) of this thread's
 // column.  Counts per band (LDS atomics), one global reservation per band
 // and workgroup, then each record goes to its band's bucket at the reserved
@@ -347,6 +438,10 @@ static KernelSet make_set() {
     k.step_mh = (const void *)step_kernel<D, TGT, LOC, MU, false, true>;
     k.drain = (const void *)drain_kernel<D, TGT, LOC, MU, false>;
     k.drain_lds = (const void *)drain_kernel<D, TGT, LOC, MU, true>;
+    if constexpr (TGT != TGT_PSS && MU == MU_UNIFORM) {
+        k.rand_prepass = (const void *)rand_prepass_kernel<D>;
+        k.step_pre = (const void *)step_pre_kernel<D, TGT, LOC>;
+    }
     if constexpr (TGT == TGT_PSS) {
         k.step_binned = (const void *)step_binned_kernel<D, TGT, LOC, MU, false>;
         k.step_binned_lds = (const void *)step_binned_kernel<D, TGT, LOC, MU, true>;

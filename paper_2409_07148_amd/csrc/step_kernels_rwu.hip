@@ -1,7 +1,7 @@
 // Kernel table of the chain kernels (templates in step_kernels.h) with local
 // dynamics that are not pi-invariant: the unadjusted random-walk jump
 // process, whose killing rate carries the adjoint generator term of Sec.
-// 6.1, eq. (killing-rate).  Built for the isotropic mixtures (Q^T p in
+// 6.2, eq. (killing-rate).  Built for the isotropic mixtures (Q^T p in
 // closed form) with the uniform regeneration distribution.  A translation
 // unit of its own, so the library's kernels compile in parallel.
 #include "step_kernels.h"

@@ -657,6 +657,38 @@ def test_split_steps_block_size_and_lds_are_bit_identical(R):
     ref.close()
 
 
+@pytest.mark.parametrize("which", ["iso2d_rw", "full8d_mala", "iso2d_hmc", "iso2d_unadjusted", "full16d_rw"])
+def test_random_prepass_gives_the_inline_chains(R, which):
+    """Populations below 2^16 chains take every step's random inputs from a
+    chip-wide pre-pass (chunks of steps); with RESTORE_FLAG_INLINE_RNG the
+    step kernel draws them itself.  Both give the same chains bit for bit,
+    also across chunk boundaries and with the drain."""
+    from workloads import gmm_full, gmm_iso_2d, gmm_iso_2d_unadjusted
+    wl = {"iso2d_rw": lambda: gmm_iso_2d(n_chains=4096, n_steps=700),
+          "full8d_mala": lambda: gmm_full(n_chains=3001, n_steps=300, c_tilde=1e3),
+          "iso2d_hmc": lambda: gmm_iso_2d(n_chains=1000, n_steps=300).with_(local="hmc", n_leapfrog=5),
+          "iso2d_unadjusted": lambda: gmm_iso_2d_unadjusted(n_chains=4096, n_steps=600),
+          "full16d_rw": lambda: gmm_full(d=16, K=8, n_chains=777, n_steps=400, local="rwmh", step=0.01,
+                                         problem_seed=4222, c_tilde=10.0)}[which]()
+    out = []
+    for flags in (0, R.FLAG_INLINE_RNG):
+        run = R.Run(R.problem_from_workload(wl, flags=flags))
+        run.step(wl.n_steps // 3)
+        run.step(wl.n_steps - wl.n_steps // 3)
+        mid = _state_snapshot(run)
+        run.drain()
+        est = run.estimate()
+        out.append((mid, _state_snapshot(run), est))
+        run.close()
+    (m0, f0, e0), (m1, f1, e1) = out
+    for key in m0:
+        assert np.array_equal(m0[key], m1[key]), ("after the steps", key)
+        assert np.array_equal(f0[key], f1[key]), ("after the drain", key)
+    assert e0["transitions"] == e1["transitions"] and e0["p_lambda"] == e1["p_lambda"]
+    _say(f"[prepass {which}] {wl.n_chains} chains x {wl.n_steps} steps: pre-pass and inline chains identical "
+         f"({e0['transitions']} transitions, accept rate {e0['accept_rate']:.3f})")
+
+
 def test_drain_lds_matches_scalar_params(R):
     from workloads import gmm_iso_2d
     wl = gmm_iso_2d(n_chains=2000, n_steps=50)

@@ -109,11 +109,13 @@ EXPORTS = ["restore_state_bytes", "restore_init", "restore_step", "restore_drain
            "restore_gmm_nll_noalloc", "restore_adam_step", "restore_image_estimate", "restore_reset_sums", "restore_last_error"]
 
 
-def _load() -> C.CDLL:
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+def _load(path: str = LIB_PATH) -> C.CDLL:
+    """The C ABI library at `path` (the in-tree build by default) with its
+    prototypes declared."""
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() "
                           "(there is no fallback implementation)")
-    lib = C.CDLL(LIB_PATH)
+    lib = C.CDLL(path)
     P = C.POINTER
     lib.restore_state_bytes.argtypes = [P(restore_target), P(restore_mu), P(restore_local_kernel),
                                         P(restore_config), P(C.c_size_t)]

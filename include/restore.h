@@ -186,6 +186,20 @@ typedef struct {
                                         2^16 chains, which by default take
                                         them from a chip-wide pre-pass (the
                                         chains are the same either way)      */
+#define RESTORE_FLAG_IMAGE_FIXED 32  /* PIXEL, untiled runs only (else
+                                        UNSUPPORTED): every splat adds its
+                                        dt rounded to a multiple of 2^-32
+                                        to a 64-bit integer per pixel in the
+                                        state buffer (exact integer sums, so
+                                        the image is the same bit for bit
+                                        whatever the order of the atomics,
+                                        the block size or the launch
+                                        split); after each restore_step and
+                                        restore_drain the caller's float
+                                        image receives the sums rounded to
+                                        float32, and restore_image_estimate
+                                        reads the integers.  A pixel holds
+                                        up to 2^32 units of time            */
 #define RESTORE_FLAG_RB_DT       8   /* accumulate the conditional mean
                                         E[dt | x] = 1 / (1 + k(x)) of the
                                         holding time in place of the sampled
@@ -269,7 +283,8 @@ typedef struct restore_ctx restore_ctx;
  * the per-chain state of Alg. 2 (x, the cached log p, log u and grad log p,
  * the running and completed tour sums of Sec. 6.3) in structure-of-arrays
  * layout, the packed parameters, reduction and drain scratch, the splat
- * buckets of the image integrand, and for populations below 2^16 chains
+ * buckets of the image integrand (or its 64-bit fixed-point sums with
+ * RESTORE_FLAG_IMAGE_FIXED), and for populations below 2^16 chains
  * with the uniform mu the buffer (at most 32 MiB) of the random-input
  * pre-pass of restore_step.  Pure host computation; the same
  * validation as restore_init (INVALID_ARG, UNSUPPORTED, NONFINITE). */
@@ -296,7 +311,8 @@ restore_status restore_init(restore_ctx **out, const restore_target *target,
  * f(x_{i-1}) to the chain's float64 sums (dt = 1 with RESTORE_FLAG_RB_DT,
  * the discrete-time average; else the Exp(1) holding time of the
  * continuous-time chain with generator K_l - id).
- * With the PIXEL integrand (unless RESTORE_FLAG_SPLAT_DIRECT) the steps run
+ * With the PIXEL integrand (unless RESTORE_FLAG_SPLAT_DIRECT or
+ * RESTORE_FLAG_IMAGE_FIXED) the steps run
  * as launches of at most 64 steps whose splat records are binned by image
  * band in the state buffer and summed into the image after each launch.
  * Populations below 2^16 chains with the uniform mu (restore, no image, no

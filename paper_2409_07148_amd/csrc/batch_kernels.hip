@@ -57,6 +57,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
         ch.last_dt = 0.0f;
         ch.splat_pix = -1;
         ch.splat_acc = 0.0f;
+        ch.splat_fx = 0ull;
     }
     unsigned long long n_t = 0, n_acc = 0, n_kill = 0;
     bool kill = false, accept = false;

@@ -96,6 +96,7 @@ struct Chain {
     // steps in the same pixel (rejected moves) are combined in registers
     int32_t splat_pix;
     float splat_acc;
+    unsigned long long splat_fx;   // the same in fixed point (image_fx runs)
     // binned splats: the record this step closed (pixel -1: none)
     int32_t out_pix;
     float out_acc;
@@ -106,8 +107,16 @@ struct Chain {
     int32_t tpx0, tpy0, tw, th;
 };
 
-__device__ __forceinline__ void flush_splat(const StepArgs &a, int32_t pix, float acc) {
-    if (pix >= 0) atomicAdd(a.image + pix, acc);
+__device__ __forceinline__ void flush_splat(const StepArgs &a, int32_t pix, float acc, unsigned long long fx) {
+    if (pix < 0) return;
+    if (a.image_fx) atomicAdd(a.image_fx + pix, fx);
+    else atomicAdd(a.image + pix, acc);
+}
+
+// A holding time in units of 2^-32 (dt < 2^5, so below 2^37): integer sums
+// of these are exact, hence independent of the order of the atomics.
+__device__ __forceinline__ unsigned long long dt_fixed(float dt) {
+    return (unsigned long long)__float2ull_rn(dt * 0x1p32f);
 }
 
 // image index of a tile-local splat index (row stride tile_px); -1 stays -1
@@ -198,6 +207,7 @@ __device__ __forceinline__ void load_chain(const StepArgs &a, uint32_t c, Chain<
     ch.last_dt = a.last_dt[c];
     ch.splat_pix = -1;
     ch.splat_acc = 0.0f;
+    ch.splat_fx = 0ull;
     ch.out_pix = -1;
     ch.out_acc = 0.0f;
     ch.tpx0 = ch.tpy0 = ch.tw = ch.th = 0;
@@ -339,12 +349,14 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                 ch.out_acc = ch.splat_acc;
             } else {
                 flush_splat(a, TILED ? tile_to_image(a, ch.tpx0, ch.tpy0, ch.img_base, ch.splat_pix) : ch.splat_pix,
-                            ch.splat_acc);
+                            ch.splat_acc, ch.splat_fx);
             }
             ch.splat_pix = pix;
             ch.splat_acc = 0.0f;
+            ch.splat_fx = 0ull;
         }
-        ch.splat_acc += dt;
+        if (a.image_fx) ch.splat_fx += dt_fixed(dt);
+        else ch.splat_acc += dt;
     }
     ch.last_dt = dt;
     // random-walk kinds with precomputed inputs run branch-free (selects):

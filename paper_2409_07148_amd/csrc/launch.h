@@ -48,6 +48,7 @@ hipError_t launch_splat_accumulate(const SplatArgs &s, hipStream_t stream);
 // (restore_image_estimate).
 struct ImageEstimateArgs {
     const float *image;      // [batches][n_pix]
+    const unsigned long long *image_fx;  // the same in units of 2^-32, or nullptr
     const uint32_t *n_done;  // per chain
     const double *t_done, *a_done;
     int64_t n_chains;
@@ -60,6 +61,8 @@ struct ImageEstimateArgs {
     int32_t tile_px, tiles_x, n_tiles, image_w, image_h;
 };
 hipError_t launch_image_estimate(const ImageEstimateArgs &a, hipStream_t stream);
+// image[i] = fx[i] 2^-32 rounded to float32, i < n (fixed-point image runs).
+hipError_t launch_image_from_fixed(const unsigned long long *fx, float *image, int64_t n, hipStream_t stream);
 
 KernelSet find_kernels(int tgt, int d, int loc, int mu);
 KernelSet find_kernels_hmc(int tgt, int d, int mu);   // loc = LOC_HMC

@@ -44,7 +44,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     size_t x, logp, logu, grad, a_cur, t_cur, last_dt, a_done, t_done, n_done, status;
     size_t list0, list1, counts, counters, params, mu, partials, results;
-    size_t bin_pix, bin_val, bin_count, bin_partial, img_tours, tile_results, rand, total;
+    size_t bin_pix, bin_val, bin_count, bin_partial, img_tours, tile_results, rand, img_fx, total;
 };
 
 // Small populations (fewer than 2^16 chains: a few waves, each step a long
@@ -68,8 +68,9 @@ struct SplatPlan {
     int n_bins = 0;
     int n_slices = 0;
     int64_t cap = 0;
-    int64_t n_pix = 0;   // pixels of all batch images
+    int64_t n_pix = 0;   // pixels of all batch images (binned or fixed-point runs)
     int batches = 0;     // image batches (0: no image)
+    bool fixed = false;  // RESTORE_FLAG_IMAGE_FIXED: direct splats into u64 sums
     // tile-stratified runs: tiles of tile_px x tile_px pixels, tiles_x per
     // row, n_tiles in all (0: off)
     int tile_px = 0, tiles_x = 0, n_tiles = 0;
@@ -88,9 +89,15 @@ SplatPlan splat_plan(const restore_config *cfg, int tgt) {
         sp.n_tiles = sp.tiles_x * ((cfg->image_h + cfg->tile_px - 1) / cfg->tile_px);
         return sp;
     }
+    const int64_t n_pix = (int64_t)cfg->image_w * cfg->image_h * sp.batches;
+    if (cfg->flags & RESTORE_FLAG_IMAGE_FIXED) {
+        // fixed-point sums: every splat goes straight to its u64 pixel
+        sp.fixed = true;
+        sp.n_pix = n_pix;
+        return sp;
+    }
     // the MH chain's kernel splats directly
     if ((cfg->flags & RESTORE_FLAG_SPLAT_DIRECT) || cfg->c_tilde == 0.0) return sp;
-    const int64_t n_pix = (int64_t)cfg->image_w * cfg->image_h * sp.batches;
     const int64_t band = 1LL << SPLAT_BAND_SHIFT;
     const int64_t n_bins = (n_pix + band - 1) / band;
     const int64_t records = cfg->n_chains * (int64_t)(SPLAT_LAUNCH_STEPS + 1);
@@ -158,6 +165,7 @@ Layout make_layout(int64_t C, int d, bool grad, int n_params, int n_mu_floats, c
     L.img_tours = sp.batches ? take(8 * (size_t)sp.batches * std::max(1, sp.n_tiles)) : (size_t)-1;
     L.tile_results = sp.n_tiles ? take(8 * (size_t)sp.n_tiles * TR_SLOTS) : (size_t)-1;
     L.rand = rp.chunk ? take(4 * (size_t)rp.fields * (size_t)rp.chunk * c) : (size_t)-1;
+    L.img_fx = sp.fixed ? take(8 * (size_t)sp.n_pix) : (size_t)-1;
     L.total = o;
     return L;
 }
@@ -247,6 +255,12 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
             return fail(RESTORE_E_INVALID_ARG, "more image batches than chains");
     } else if (cfg->image_batches > 1) {
         return fail(RESTORE_E_INVALID_ARG, "image_batches needs the PIXEL integrand");
+    }
+    if (cfg->flags & RESTORE_FLAG_IMAGE_FIXED) {
+        if (!(cfg->integrands & RESTORE_INTEGRAND_PIXEL))
+            return fail(RESTORE_E_INVALID_ARG, "RESTORE_FLAG_IMAGE_FIXED needs the PIXEL integrand");
+        if (cfg->tile_px != 0)
+            return fail(RESTORE_E_UNSUPPORTED, "RESTORE_FLAG_IMAGE_FIXED is built for untiled runs");
     }
     if (cfg->tile_px != 0) {
         if (cfg->tile_px < 1 || cfg->tile_px > 64) return fail(RESTORE_E_INVALID_ARG, "tile_px must be in 0..64");
@@ -513,6 +527,13 @@ void fill_args(restore_ctx *c) {
     a.bin_count = at<uint32_t>(c, c->lay.bin_count);
     a.bin_cap = (int32_t)c->splat.cap;
     a.n_bins = c->splat.n_bins;
+    a.image_fx = c->splat.fixed ? at<unsigned long long>(c, c->lay.img_fx) : nullptr;
+}
+
+// Fixed-point image runs: the caller's float image from the u64 sums.
+hipError_t publish_fixed_image(restore_ctx *c, hipStream_t s) {
+    if (!c->splat.fixed) return hipSuccess;
+    return launch_image_from_fixed(c->args.image_fx, c->image, c->splat.n_pix, s);
 }
 
 dim3 grid_for(int64_t n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
@@ -641,6 +662,9 @@ restore_status restore_init(restore_ctx **out, const restore_target *target, con
     if (sp.n_bins)
         hipLaunchKernelGGL(zero_u32_kernel, dim3(SPLAT_MAX_BANDS * SPLAT_COUNTER_STRIDE / 256), dim3(256), 0, s,
                            c->args.bin_count, SPLAT_MAX_BANDS * SPLAT_COUNTER_STRIDE);
+    if (sp.fixed)
+        hipLaunchKernelGGL(zero_u64_kernel, grid_for(sp.n_pix, 256), dim3(256), 0, s, c->args.image_fx,
+                           (int)sp.n_pix);
     StepArgs a = c->args;
     void *kargs[] = {&a};
     e = hipLaunchKernel(ks.init, grid_for(cfg->n_chains, 256), dim3(256), kargs, 0, s);
@@ -724,6 +748,8 @@ static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_recor
         }
     }
     c->steps_taken += n_steps;
+    hipError_t e = publish_fixed_image(c, s);
+    if (e != hipSuccess) return hip_fail(e, "fixed-point image launch");
     return RESTORE_OK;
 }
 
@@ -784,6 +810,8 @@ restore_status restore_drain(restore_ctx *c, void *stream) {
         if (last) break;
         chunk *= 2;
     }
+    hipError_t e = publish_fixed_image(c, s);
+    if (e != hipSuccess) return hip_fail(e, "fixed-point image launch");
     c->drained = true;
     return RESTORE_OK;
 }
@@ -948,6 +976,8 @@ restore_status restore_reset_sums(restore_ctx *c, void *stream) {
     if (c->image) {
         const int64_t n = (int64_t)c->cfg.image_w * c->cfg.image_h * image_batches_of(&c->cfg);
         hipLaunchKernelGGL(zero_f32_kernel, grid_for(n, 256), dim3(256), 0, s, c->image, n);
+        if (c->splat.fixed)
+            hipLaunchKernelGGL(zero_u64_kernel, grid_for(n, 256), dim3(256), 0, s, c->args.image_fx, (int)n);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reset launch");
@@ -959,6 +989,7 @@ restore_status restore_image_estimate(restore_ctx *c, float *mean_dev, float *se
     if (!c->image) return fail(RESTORE_E_BAD_STATE, "the run has no PIXEL integrand");
     ImageEstimateArgs a{};
     a.image = c->image;
+    a.image_fx = c->args.image_fx;
     a.n_done = c->args.n_done;
     a.t_done = c->args.t_done;
     a.a_done = c->args.a_done;

@@ -87,6 +87,7 @@ struct StepArgs {
     const float *params;           // packed target slab
     const float *mu_params;        // learned mu slab (inside the state buffer)
     float *image;                  // pixel splats or nullptr
+    unsigned long long *image_fx;  // fixed-point pixel sums (dt 2^32 each) or nullptr
     const uint32_t *list;          // drain: chains to run, or nullptr (all)
     const uint32_t *list_count;    // drain: number of entries in list
     int64_t n_chains;

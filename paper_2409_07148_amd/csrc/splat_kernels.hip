@@ -115,15 +115,20 @@ __global__ __launch_bounds__(256) void image_estimate_kernel(ImageEstimateArgs a
         const int w = min(a.tile_px, a.image_w - tx * a.tile_px), h = min(a.tile_px, a.image_h - ty * a.tile_px);
         scale *= (double)w * h / ((double)a.image_w * a.image_h);
     }
+    // batch image b at this pixel (exact from the fixed-point sums if any)
+    auto S_b = [&](int b) {
+        const int64_t i = (int64_t)b * a.n_pix + px;
+        return a.image_fx ? (double)a.image_fx[i] * 0x1p-32 : (double)a.image[i];
+    };
     double sS = 0.0, sN = 0.0;
     for (int b = 0; b < B; ++b) {
-        sS += (double)a.image[(int64_t)b * a.n_pix + px];
+        sS += S_b(b);
         sN += tours[b];
     }
     const double R = sN > 0.0 ? sS / sN : 0.0;
     double ss = 0.0;
     for (int b = 0; b < B; ++b) {
-        const double e = (double)a.image[(int64_t)b * a.n_pix + px] - R * tours[b];
+        const double e = S_b(b) - R * tours[b];
         ss += e * e;
     }
     a.mean[px] = (float)(scale * R);
@@ -136,6 +141,17 @@ hipError_t launch_image_estimate(const ImageEstimateArgs &a, hipStream_t stream)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(image_estimate_kernel, dim3((unsigned)((a.n_pix + 255) / 256)), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+__global__ void image_from_fixed_kernel(const unsigned long long *fx, float *image, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) image[i] = (float)((double)fx[i] * 0x1p-32);
+}
+
+hipError_t launch_image_from_fixed(const unsigned long long *fx, float *image, int64_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(image_from_fixed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, fx, image,
+                       n);
     return hipGetLastError();
 }
 

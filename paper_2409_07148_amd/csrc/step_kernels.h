@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_float
     }
     ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT)) | (kill ? ST_LAST_KILL : 0u) |
                 (accept ? ST_LAST_ACCEPT : 0u);
-    if (TGT == TGT_PSS && a.image) flush_splat(a, ch.splat_pix, ch.splat_acc);
+    if (TGT == TGT_PSS && a.image) flush_splat(a, ch.splat_pix, ch.splat_acc, ch.splat_fx);
     store_chain(a, (uint32_t)c, ch);
     const unsigned long long lanes = __popcll(__ballot(1));
     add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill, n_large, n_large_acc);
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void drain_kernel(StepArgs a, int n_param_floa
     if (alive && last_chunk) ch.status |= ST_CENSORED;
     if (TGT == TGT_PSS && a.image)
         flush_splat(a, TILED ? tile_to_image(a, ch.tpx0, ch.tpy0, ch.img_base, ch.splat_pix) : ch.splat_pix,
-                    ch.splat_acc);
+                    ch.splat_acc, ch.splat_fx);
     store_chain(a, c, ch);
     add_counters(a.counters, n_t, n_acc, n_kill);
     if (!last_chunk) {

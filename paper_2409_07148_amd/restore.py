@@ -24,7 +24,7 @@ TARGET_GMM_ISO, TARGET_GMM_FULL, TARGET_PSS = 0, 1, 2
 MU_UNIFORM_BOX, MU_GMM_DIAG = 0, 1
 LOCAL_RWMH, LOCAL_MALA, LOCAL_HMC, LOCAL_RW_UNADJUSTED = 0, 1, 2, 3
 INTEGRAND_ONE, INTEGRAND_P, INTEGRAND_PIXEL = 1, 2, 4
-FLAG_PARAMS_LDS, FLAG_SPLAT_DIRECT, FLAG_SPLAT_TIGHT, FLAG_RB_DT, FLAG_INLINE_RNG = 1, 2, 4, 8, 16
+FLAG_PARAMS_LDS, FLAG_SPLAT_DIRECT, FLAG_SPLAT_TIGHT, FLAG_RB_DT, FLAG_INLINE_RNG, FLAG_IMAGE_FIXED = 1, 2, 4, 8, 16, 32
 ST_ALIVE, ST_CENSORED, ST_LAST_KILL, ST_LAST_ACCEPT, ST_GRAD_VALID, ST_LAST_LARGE = 1, 2, 4, 8, 16, 32
 
 

@@ -312,3 +312,23 @@ def test_binding_refuses_to_load_without_the_library(tmp_path):
                        text=True, timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "no fallback" in r.stderr
+
+
+def test_fixed_point_image_flag(R):
+    """RESTORE_FLAG_IMAGE_FIXED: a 64-bit sum per pixel of every batch image
+    in place of the splat buckets (the same size as the direct path plus
+    8 bytes per pixel); it needs the PIXEL integrand and untiled runs."""
+    direct = _pss_problem(R, n_chains=8192, flags=R.FLAG_SPLAT_DIRECT)
+    fixed = _pss_problem(R, n_chains=8192, flags=R.FLAG_IMAGE_FIXED)
+    nd = R.restore_state_bytes(direct.target, direct.mu, direct.local, direct.cfg)
+    nf = R.restore_state_bytes(fixed.target, fixed.mu, fixed.local, fixed.cfg)
+    n_pix = 64 * 64 * max(1, fixed.cfg.image_batches)
+    assert 8 * n_pix <= nf - nd <= 8 * n_pix + 256
+    p = _problem(R, flags=R.FLAG_IMAGE_FIXED)
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+    assert e.value.status == R.E_INVALID_ARG
+    t = _pss_problem(R, n_chains=8192, flags=R.FLAG_IMAGE_FIXED, tile_px=16)
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_state_bytes(t.target, t.mu, t.local, t.cfg)
+    assert e.value.status == R.E_UNSUPPORTED

@@ -285,8 +285,8 @@ typedef struct restore_ctx restore_ctx;
  * layout, the packed parameters, reduction and drain scratch, the splat
  * buckets of the image integrand (or its 64-bit fixed-point sums with
  * RESTORE_FLAG_IMAGE_FIXED), and for populations below 2^16 chains
- * with the uniform mu the buffer (at most 32 MiB) of the random-input
- * pre-pass of restore_step.  Pure host computation; the same
+ * with the uniform mu the two halves (at most 32 MiB each) of the
+ * random-input pre-pass buffer of restore_step and restore_drain.  Pure host computation; the same
  * validation as restore_init (INVALID_ARG, UNSUPPORTED, NONFINITE). */
 restore_status restore_state_bytes(const restore_target *target, const restore_mu *mu,
                                    const restore_local_kernel *local,
@@ -316,11 +316,14 @@ restore_status restore_init(restore_ctx **out, const restore_target *target,
  * as launches of at most 64 steps whose splat records are binned by image
  * band in the state buffer and summed into the image after each launch.
  * Populations below 2^16 chains with the uniform mu (restore, no image, no
- * LDS staging, no RESTORE_FLAG_INLINE_RNG) run chunks of steps, each a
- * chip-wide pre-pass of the steps' state-independent random inputs (the
- * Philox blocks, the clocks' exponentials, ln u_acc, the candidate
- * uniforms and their Box-Muller normals) followed by the step launch that
- * reads them.  The chains are the same either way. */
+ * LDS staging, no RESTORE_FLAG_INLINE_RNG) run chunks of steps whose
+ * state-independent random inputs (the Philox blocks, the clocks'
+ * exponentials, ln u_acc, the candidate uniforms and their Box-Muller
+ * normals) come from a chip-wide pre-pass: each step launch reads one half
+ * of the buffer while extra workgroups of the same launch draw the next
+ * chunk into the other half (only the first chunk of a context, or of a
+ * call that follows restore_step_record, takes a pre-pass launch of its
+ * own).  The chains are the same either way. */
 restore_status restore_step(restore_ctx *ctx, int32_t n_steps, void *stream);
 
 /* End of the budget (the estimators of Sec. 7.4 assume a run that ends at
@@ -329,7 +332,9 @@ restore_status restore_step(restore_ctx *ctx, int32_t n_steps, void *stream);
  * have passed (the tour is censored: excluded from the estimates, counted
  * and reported).  Retired chains are compacted out of the launches with
  * wavefront ballots (launches of 1, 2, 4, ... steps; below 2^16 chains one
- * launch over the whole cap); the chains are the same either way.  After
+ * launch over the whole cap, whose first steps take their random inputs
+ * from the pre-pass buffer when restore_step uses it); the chains are the
+ * same either way.  After
  * restore_drain no further restore_step.  For the MH chain (c_tilde = 0)
  * there is nothing to finish: no launch. */
 restore_status restore_drain(restore_ctx *ctx, void *stream);

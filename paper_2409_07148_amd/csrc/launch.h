@@ -27,7 +27,8 @@ struct KernelSet {
     // step's state-independent random inputs, and the step kernel that
     // reads them instead of drawing them on its own serial path
     const void *rand_prepass = nullptr;
-    const void *step_pre = nullptr;
+    const void *step_pre = nullptr;    // also runs the next chunk's pre-pass
+    const void *drain_pre = nullptr;
 };
 
 // Binned splats of one step launch into the image: per-band LDS

@@ -51,9 +51,12 @@ struct Layout {
 // serial instruction stream) with the uniform mu: the state-independent
 // random inputs of every step -- Philox blocks, the clocks' logarithms,
 // Box-Muller -- come from a chip-wide pre-pass, `chunk` steps at a time, into
-// a buffer of rand_fields(d) x chunk x C floats (at most 32 MiB); the chains
-// are the same either way.  Off for the MH chain, the image integrand, the
-// learned mu, LDS-staged parameters and RESTORE_FLAG_INLINE_RNG.
+// one half of a buffer of 2 x rand_fields(d) x chunk x C floats (at most
+// 32 MiB per half).  Each step launch reads one half while its extra
+// workgroups fill the other with the next chunk (which the next step
+// launch or the drain then finds ready).  The chains are the same either
+// way.  Off for the MH chain, the image integrand, the learned mu,
+// LDS-staged parameters and RESTORE_FLAG_INLINE_RNG.
 struct RandPlan {
     int chunk = 0;   // steps per pre-pass (0: off)
     int fields = 0;
@@ -112,7 +115,7 @@ SplatPlan splat_plan(const restore_config *cfg, int tgt) {
     return sp;
 }
 
-constexpr int64_t RAND_BUFFER_BYTES = 32LL << 20;
+constexpr int64_t RAND_HALF_BYTES = 32LL << 20;
 
 RandPlan rand_plan(const restore_config *cfg, int tgt, int d, int mu) {
     RandPlan rp;
@@ -120,7 +123,7 @@ RandPlan rand_plan(const restore_config *cfg, int tgt, int d, int mu) {
         (cfg->flags & (RESTORE_FLAG_INLINE_RNG | RESTORE_FLAG_PARAMS_LDS)))
         return rp;
     const int64_t per_step = cfg->n_chains * (int64_t)rand_fields(d) * (int64_t)sizeof(float);
-    const int64_t chunk = std::min<int64_t>(256, RAND_BUFFER_BYTES / per_step);
+    const int64_t chunk = std::min<int64_t>(256, RAND_HALF_BYTES / per_step);
     if (chunk < 16) return rp;
     rp.chunk = (int)chunk;
     rp.fields = rand_fields(d);
@@ -164,7 +167,7 @@ Layout make_layout(int64_t C, int d, bool grad, int n_params, int n_mu_floats, c
     L.bin_partial = nb ? take(4 * (size_t)sp.n_slices * (nb << SPLAT_BAND_SHIFT)) : (size_t)-1;
     L.img_tours = sp.batches ? take(8 * (size_t)sp.batches * std::max(1, sp.n_tiles)) : (size_t)-1;
     L.tile_results = sp.n_tiles ? take(8 * (size_t)sp.n_tiles * TR_SLOTS) : (size_t)-1;
-    L.rand = rp.chunk ? take(4 * (size_t)rp.fields * (size_t)rp.chunk * c) : (size_t)-1;
+    L.rand = rp.chunk ? take(2 * 4 * (size_t)rp.fields * (size_t)rp.chunk * c) : (size_t)-1;
     L.img_fx = sp.fixed ? take(8 * (size_t)sp.n_pix) : (size_t)-1;
     L.total = o;
     return L;
@@ -466,6 +469,11 @@ struct restore_ctx {
     restore_mu mu{};
     SplatPlan splat{};
     RandPlan rand{};
+    // pre-pass buffer: half pre_half holds the inputs of steps
+    // [pre_s0, pre_s0 + pre_n) (pre_n = 0: nothing yet)
+    int pre_half = 0;
+    int64_t pre_s0 = 0;
+    int32_t pre_n = 0;
     StepArgs args{};
 };
 
@@ -528,6 +536,30 @@ void fill_args(restore_ctx *c) {
     a.bin_cap = (int32_t)c->splat.cap;
     a.n_bins = c->splat.n_bins;
     a.image_fx = c->splat.fixed ? at<unsigned long long>(c, c->lay.img_fx) : nullptr;
+}
+
+// Half h of the pre-pass buffer.
+float *rand_half(restore_ctx *c, int h) {
+    return at<float>(c, c->lay.rand) + (size_t)h * c->rand.fields * (size_t)c->rand.chunk * c->cfg.n_chains;
+}
+
+// Make the current half of the pre-pass buffer hold steps [s, s + n)
+// (n <= chunk): kept from the previous step launch if it drew them, else
+// drawn by a pre-pass launch.
+restore_status ensure_pre(restore_ctx *c, int64_t s, int32_t n, hipStream_t stream) {
+    if (n <= 0 || (c->pre_n > 0 && c->pre_s0 == s && c->pre_n >= n)) return RESTORE_OK;
+    StepArgs a = c->args;
+    a.s0 = (uint32_t)s;
+    a.n_steps = n;
+    float *buf = rand_half(c, c->pre_half);
+    int chunk = c->rand.chunk;
+    void *pargs[] = {&a, &buf, &chunk};
+    hipError_t e = hipLaunchKernel(c->ks.rand_prepass, dim3((unsigned)((c->cfg.n_chains + 255) / 256), (unsigned)n),
+                                   dim3(256), pargs, 0, stream);
+    if (e != hipSuccess) return hip_fail(e, "random pre-pass launch");
+    c->pre_s0 = s;
+    c->pre_n = n;
+    return RESTORE_OK;
 }
 
 // Fixed-point image runs: the caller's float image from the u64 sums.
@@ -702,21 +734,27 @@ static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_recor
                                        tile_shm, s);
         if (e != hipSuccess) return hip_fail(e, "tiled step launch");
     } else if (c->rand.chunk && !x_out) {
-        // small population: per chunk, a chip-wide pre-pass of the steps'
-        // random inputs, then the steps reading them
-        float *buf = at<float>(c, c->lay.rand);
-        const float *cbuf = buf;
+        // small population: per chunk, the steps reading their random inputs
+        // from one half of the pre-pass buffer while extra workgroups of the
+        // same launch fill the other half with the next chunk
         int chunk = c->rand.chunk;
-        void *pargs[] = {&a, &buf, &chunk};
-        void *sargs[] = {&a, &cbuf, &chunk};
+        const int64_t step_blocks = (c->cfg.n_chains + c->block - 1) / c->block;
+        const int64_t gen_blocks = step_blocks * ((chunk + PRE_GEN_STEPS - 1) / PRE_GEN_STEPS);
         for (int32_t done = 0; done < n_steps; done += chunk) {
-            a.s0 = (uint32_t)(c->steps_taken + done);
+            const int64_t s_first = c->steps_taken + done;
+            a.s0 = (uint32_t)s_first;
             a.n_steps = std::min<int32_t>(chunk, n_steps - done);
-            hipError_t e = hipLaunchKernel(c->ks.rand_prepass, dim3((unsigned)((c->cfg.n_chains + 255) / 256),
-                                                                    (unsigned)a.n_steps), dim3(256), pargs, 0, s);
-            if (e != hipSuccess) return hip_fail(e, "random pre-pass launch");
-            e = hipLaunchKernel(c->ks.step_pre, grid_for(c->cfg.n_chains, c->block), dim3(c->block), sargs, 0, s);
+            restore_status st = ensure_pre(c, s_first, a.n_steps, s);
+            if (st != RESTORE_OK) return st;
+            const float *cur = rand_half(c, c->pre_half);
+            PreGen g{rand_half(c, 1 - c->pre_half), (uint32_t)(s_first + a.n_steps), chunk, (int32_t)step_blocks};
+            void *sargs[] = {&a, &cur, &chunk, &g};
+            hipError_t e = hipLaunchKernel(c->ks.step_pre, dim3((unsigned)(step_blocks + gen_blocks)),
+                                           dim3(c->block), sargs, 0, s);
             if (e != hipSuccess) return hip_fail(e, "step launch");
+            c->pre_half = 1 - c->pre_half;
+            c->pre_s0 = s_first + a.n_steps;
+            c->pre_n = chunk;
         }
     } else if (!c->splat.n_bins) {
         const void *fn = c->lds ? c->ks.step_lds : c->ks.step;
@@ -775,6 +813,25 @@ restore_status restore_drain(restore_ctx *c, void *stream) {
         return RESTORE_OK;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (c->rand.chunk) {
+        // small population: one launch over the whole cap, its first steps'
+        // random inputs from the pre-pass buffer (usually drawn already by
+        // the last step launch)
+        const int32_t n_pre = std::min<int32_t>(c->rand.chunk, c->cfg.drain_cap);
+        restore_status st = ensure_pre(c, c->steps_taken, n_pre, s);
+        if (st != RESTORE_OK) return st;
+        StepArgs a = c->args;
+        a.s0 = (uint32_t)c->steps_taken;
+        a.n_steps = c->cfg.drain_cap;
+        const float *cur = rand_half(c, c->pre_half);
+        int chunk = c->rand.chunk, np = n_pre;
+        void *kargs[] = {&a, &cur, &chunk, &np};
+        hipError_t e = hipLaunchKernel(c->ks.drain_pre, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs,
+                                       0, s);
+        if (e != hipSuccess) return hip_fail(e, "drain launch");
+        c->drained = true;
+        return RESTORE_OK;
+    }
     uint32_t *counts = at<uint32_t>(c, c->lay.counts);
     uint32_t *lists[2] = {at<uint32_t>(c, c->lay.list0), at<uint32_t>(c, c->lay.list1)};
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, counts, 4);

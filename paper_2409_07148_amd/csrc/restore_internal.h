@@ -69,6 +69,17 @@ __host__ __device__ constexpr int mu_slab_floats(int d, int K) { return 4 + K * 
 // ln u_acc, d candidate uniforms, d Box-Muller normals).
 __host__ __device__ constexpr int rand_fields(int D) { return 3 + 2 * D; }
 
+// The pre-pass of the following chunk, run by extra workgroups of a step
+// launch: workgroup step_blocks + g covers its threads' chains for
+// PRE_GEN_STEPS steps of that chunk.
+constexpr int PRE_GEN_STEPS = 8;
+struct PreGen {
+    float *out;           // the buffer half it fills
+    uint32_t s0;          // first step it draws
+    int32_t n_steps;      // steps it draws (<= chunk; 0: none)
+    int32_t step_blocks;  // workgroups of the step launch proper
+};
+
 // Per-launch arguments of the step kernels.
 struct StepArgs {
     // chain state (structure of arrays, C chains)

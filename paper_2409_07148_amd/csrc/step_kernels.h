@@ -64,19 +64,17 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_float
 }
 
 // Pre-pass of a chunk of steps for a small population (uniform mu): thread
-// (chain c, step j of the chunk) draws step a.s0 + j of chain c and writes
-// its StepRand fields to out[f][j][c] (field f of rand_fields(D); a field
-// is chunk x C floats).  Chip-wide, so the Philox blocks and the
+// (chain c, step j of the chunk) draws step s0 + j of chain c and writes its
+// StepRand fields to out[f][j][c] (field f of rand_fields(D); a field is
+// chunk x C floats).  Chip-wide, so the Philox blocks and the
 // transcendental mappings of every step run on all compute units instead of
 // on the few waves of the population's serial step loop.
 template <int D>
-__global__ __launch_bounds__(256) void rand_prepass_kernel(StepArgs a, float *out, int chunk) {
+__device__ __forceinline__ void prepass_one(const StepArgs &a, uint32_t s0, int64_t c, int j, float *out,
+                                            int chunk) {
     constexpr int NB = NBlocks<D>::value;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (c >= a.n_chains || j >= a.n_steps) return;
     float head[4], cand[4 * NB];
-    draw_step<NB>(a.s0 + (uint32_t)j, a.chain0 + (uint32_t)c, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
+    draw_step<NB>(s0 + (uint32_t)j, a.chain0 + (uint32_t)c, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
     const int64_t C = a.n_chains, fs = (int64_t)chunk * C;
     float *o = out + (int64_t)j * C + c;
     o[0] = -logf(head[0]);
@@ -91,27 +89,47 @@ __global__ __launch_bounds__(256) void rand_prepass_kernel(StepArgs a, float *ou
     }
 }
 
-// Steps with regeneration whose random inputs come from the pre-pass (a
-// chunk of at most `chunk` steps; step it of the launch reads field f at
-// pre[(f chunk + it) C + c]).  Two register buffers of PF steps alternate:
-// one is loaded while the other's steps run.  The same chains as
-// step_kernel, bit for bit.
-template <int D, int TGT, int LOC>
-__global__ __launch_bounds__(256) void step_pre_kernel(StepArgs a, const float *pre, int chunk) {
-    constexpr int F = rand_fields(D);
-    constexpr int PF = F <= 8 ? 4 : (F <= 16 ? 2 : 1);
-    const const_fptr P = (const_fptr)a.params;
+template <int D>
+__global__ __launch_bounds__(256) void rand_prepass_kernel(StepArgs a, float *out, int chunk) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (c >= a.n_chains || j >= a.n_steps) return;
+    prepass_one<D>(a, a.s0, c, j, out, chunk);
+}
+
+// The pre-pass of the following chunk, run by extra workgroups of a step
+// launch (on the compute units its few step waves leave idle): workgroup
+// step_blocks + g covers the threads' chains for PRE_GEN_STEPS steps.
+template <int D>
+__device__ __forceinline__ void pregen_block(const StepArgs &a, const PreGen &g, int chunk) {
+    const int64_t cb = ((int64_t)a.n_chains + blockDim.x - 1) / blockDim.x;
+    const int64_t gb = (int64_t)blockIdx.x - g.step_blocks;
+    const int64_t c = (gb % cb) * blockDim.x + threadIdx.x;
+    const int j0 = (int)(gb / cb) * PRE_GEN_STEPS;
     if (c >= a.n_chains) return;
-    Chain<D, LOC> ch;
-    load_chain(a, (uint32_t)c, ch);
-    // the buffer base is wave-uniform and every byte offset fits in 32 bits
-    // (at most 32 MiB), so the loads take the scalar-base addressing mode
-    const char *pb = reinterpret_cast<const char *>(pre);
-    const uint32_t C4 = 4u * (uint32_t)a.n_chains, fs4 = (uint32_t)chunk * C4;
-    auto ld = [&](uint32_t off) { return *reinterpret_cast<const float *>(pb + off); };
-    auto fetch = [&](StepRand<D> &r, int it) {
-        const uint32_t o = (uint32_t)it * C4 + 4u * (uint32_t)c;
+    const int j1 = min(j0 + PRE_GEN_STEPS, g.n_steps);
+    for (int j = j0; j < j1; ++j) prepass_one<D>(a, g.s0, c, j, g.out, chunk);
+}
+
+// Register double buffer of precomputed step inputs: PF steps per buffer,
+// loaded from pre (chunk stride) one buffer ahead of the steps that use it.
+// The loads are unconditional (a step past `last` re-reads step `last`,
+// which the buffer holds): straight-line code, so the compiler waits for
+// the older buffer only (a count of outstanding loads) instead of for
+// every load in flight.
+template <int D>
+struct PreFetch {
+    static constexpr int F = rand_fields(D);
+    static constexpr int PF = F <= 8 ? 4 : (F <= 16 ? 2 : 1);
+    const char *pb;
+    uint32_t C4, fs4, lane4;
+    int last;
+    __device__ __forceinline__ PreFetch(const float *pre, int64_t n_chains, int chunk, int64_t c, int last_)
+        : pb(reinterpret_cast<const char *>(pre)), C4(4u * (uint32_t)n_chains),
+          fs4((uint32_t)chunk * 4u * (uint32_t)n_chains), lane4(4u * (uint32_t)c), last(last_) {}
+    __device__ __forceinline__ float ld(uint32_t off) const { return *reinterpret_cast<const float *>(pb + off); }
+    __device__ __forceinline__ void fetch(StepRand<D> &r, int it) const {
+        const uint32_t o = (uint32_t)it * C4 + lane4;
         r.t1 = ld(o);
         r.e2 = ld(o + fs4);
         r.lacc = ld(o + 2 * fs4);
@@ -120,7 +138,34 @@ __global__ __launch_bounds__(256) void step_pre_kernel(StepArgs a, const float *
             r.cand[i] = ld(o + (3 + i) * fs4);
             r.z[i] = ld(o + (3 + D + i) * fs4);
         }
-    };
+    }
+    __device__ __forceinline__ void load(StepRand<D> (&r)[PF], int it0) const {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) fetch(r[j], min(it0 + j, last));
+    }
+};
+
+// Steps with regeneration whose random inputs come from the pre-pass (a
+// chunk of at most `chunk` steps; step it of the launch reads field f at
+// pre[(f chunk + it) C + c]).  Two register buffers of PF steps alternate:
+// one is loaded while the other's steps run.  The same chains as
+// step_kernel, bit for bit.
+template <int D, int TGT, int LOC>
+__global__ __launch_bounds__(256) void step_pre_kernel(StepArgs a, const float *pre, int chunk, PreGen g) {
+    if ((int64_t)blockIdx.x >= g.step_blocks) {
+        pregen_block<D>(a, g, chunk);
+        return;
+    }
+    using PFT = PreFetch<D>;
+    constexpr int PF = PFT::PF;
+    const const_fptr P = (const_fptr)a.params;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_chains) return;
+    Chain<D, LOC> ch;
+    load_chain(a, (uint32_t)c, ch);
+    // the buffer base is wave-uniform and every byte offset fits in 32 bits
+    // (at most 32 MiB per half), so the loads take the scalar-base mode
+    const PFT pf(pre, a.n_chains, chunk, c, a.n_steps - 1);
     unsigned long long n_acc = 0, n_kill = 0;
     bool kill = false, accept = false;
     auto run = [&](const StepRand<D> (&r)[PF], int it0) {
@@ -134,17 +179,12 @@ __global__ __launch_bounds__(256) void step_pre_kernel(StepArgs a, const float *
             }
         }
     };
-    auto load = [&](StepRand<D> (&r)[PF], int it0) {
-#pragma unroll
-        for (int j = 0; j < PF; ++j)
-            if (it0 + j < a.n_steps) fetch(r[j], it0 + j);
-    };
     StepRand<D> A[PF], B[PF];
-    load(A, 0);
+    pf.load(A, 0);
     for (int it0 = 0; it0 < a.n_steps; it0 += 2 * PF) {
-        load(B, it0 + PF);
+        pf.load(B, it0 + PF);
         run(A, it0);
-        load(A, it0 + 2 * PF);
+        pf.load(A, it0 + 2 * PF);
         run(B, it0 + PF);
     }
     ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT)) | (kill ? ST_LAST_KILL : 0u) |
@@ -152,6 +192,74 @@ __global__ __launch_bounds__(256) void step_pre_kernel(StepArgs a, const float *
     store_chain(a, (uint32_t)c, ch);
     const unsigned long long lanes = __popcll(__ballot(1));
     add_counters(a.counters, lanes * (unsigned long long)a.n_steps, n_acc, n_kill);
+}
+
+// The drain of a small population in one launch (no chain list): the first
+// n_pre steps take their random inputs from the pre-pass, later ones draw
+// them inline.  A wave ends when its last lane's tour is killed; survivors
+// of all a.n_steps steps are censored.  The same chains as drain_kernel.
+template <int D, int TGT, int LOC>
+__global__ __launch_bounds__(256) void drain_pre_kernel(StepArgs a, const float *pre, int chunk, int n_pre) {
+    using PFT = PreFetch<D>;
+    constexpr int PF = PFT::PF;
+    const const_fptr P = (const_fptr)a.params;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_chains) return;
+    Chain<D, LOC> ch;
+    load_chain(a, (uint32_t)c, ch);
+    bool alive = (ch.status & ST_ALIVE) != 0u;
+    unsigned long long n_t = 0, n_acc = 0, n_kill = 0;
+    bool stepped = false, kill_last = false, acc_last = false;
+    // one drain step; false once no lane of the wave is alive
+    auto step = [&](int it, const StepRand<D> *r) {
+        const unsigned long long live = __ballot(alive);
+        if (live == 0ull) return false;
+        n_t += __popcll(live);
+        bool kill = false, accept = false;
+        if (alive) {
+            if (r)
+                step_once<D, TGT, LOC, MU_UNIFORM, true, const_fptr, false, false, false, true>(
+                    a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch, kill, accept, r);
+            else
+                step_once<D, TGT, LOC, MU_UNIFORM, true, const_fptr>(a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch,
+                                                                     kill, accept);
+            stepped = true;
+            kill_last = kill;
+            acc_last = accept;
+            alive = !kill;
+        }
+        n_acc += __popcll(__ballot(accept));
+        n_kill += __popcll(__ballot(kill));
+        return true;
+    };
+    n_pre = min(n_pre, a.n_steps);
+    bool more = true;
+    int it = 0;
+    if (n_pre > 0) {
+        const PFT pf(pre, a.n_chains, chunk, c, n_pre - 1);
+        auto run = [&](const StepRand<D> (&r)[PF], int it0) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j)
+                if (more && it0 + j < n_pre) more = step(it0 + j, &r[j]);
+        };
+        StepRand<D> A[PF], B[PF];
+        pf.load(A, 0);
+        for (int it0 = 0; more && it0 < n_pre; it0 += 2 * PF) {
+            pf.load(B, it0 + PF);
+            run(A, it0);
+            pf.load(A, it0 + 2 * PF);
+            run(B, it0 + PF);
+        }
+        it = n_pre;
+    }
+    for (; more && it < a.n_steps; ++it) more = step(it, nullptr);
+    if (stepped) {
+        ch.status = (ch.status & ~(ST_LAST_KILL | ST_LAST_ACCEPT | ST_ALIVE)) | (alive ? ST_ALIVE : 0u) |
+                    (kill_last ? ST_LAST_KILL : 0u) | (acc_last ? ST_LAST_ACCEPT : 0u);
+    }
+    if (alive) ch.status |= ST_CENSORED;
+    store_chain(a, (uint32_t)c, ch);
+    add_counters(a.counters, n_t, n_acc, n_kill);
 }
 
 // Binning of the records staged in LDS: rows [0, rows) of this thread's
@@ -441,6 +549,7 @@ static KernelSet make_set() {
     if constexpr (TGT != TGT_PSS && MU == MU_UNIFORM) {
         k.rand_prepass = (const void *)rand_prepass_kernel<D>;
         k.step_pre = (const void *)step_pre_kernel<D, TGT, LOC>;
+        k.drain_pre = (const void *)drain_pre_kernel<D, TGT, LOC>;
     }
     if constexpr (TGT == TGT_PSS) {
         k.step_binned = (const void *)step_binned_kernel<D, TGT, LOC, MU, false>;

@@ -689,6 +689,34 @@ def test_random_prepass_gives_the_inline_chains(R, which):
          f"({e0['transitions']} transitions, accept rate {e0['accept_rate']:.3f})")
 
 
+@pytest.mark.parametrize("drain_cap", [0, 37, 300])
+def test_prepass_buffer_reuse_after_recorded_steps_and_short_drains(R, drain_cap):
+    """The pre-pass buffer across calls: steps whose inputs the previous
+    launch drew, a recorded stretch (inline draws, after which the buffer no
+    longer holds the next step), odd step counts, then drains of 0 steps,
+    fewer steps than a chunk and more: the same chains bit for bit as the
+    inline draws."""
+    from workloads import gmm_iso_2d
+    wl = gmm_iso_2d(n_chains=3000, n_steps=0)
+    out = []
+    for flags in (0, R.FLAG_INLINE_RNG):
+        run = R.Run(R.problem_from_workload(wl, flags=flags, drain_cap=drain_cap))
+        run.step(301)
+        run.step(5)
+        run.step_record(11, 64)
+        run.step(257)
+        run.drain()
+        est = run.estimate()
+        out.append((_state_snapshot(run), est))
+        run.close()
+    (f0, e0), (f1, e1) = out
+    for key in f0:
+        assert np.array_equal(f0[key], f1[key]), key
+    assert e0["transitions"] == e1["transitions"] and e0["tours_censored"] == e1["tours_censored"]
+    _say(f"[prepass reuse drain_cap {drain_cap}] identical ({e0['transitions']} transitions, "
+         f"{e0['tours_censored']} censored)")
+
+
 def test_drain_lds_matches_scalar_params(R):
     from workloads import gmm_iso_2d
     wl = gmm_iso_2d(n_chains=2000, n_steps=50)

@@ -499,13 +499,22 @@ restore_status restore_step_record(restore_ctx *ctx, int32_t n_steps, int64_t n_
  * be state-independent for k = c_tilde u / p, Sec. 6.2).
  * Parameters theta (float32, row-major, out x in):
  *   [ W1 (H x in) | b1 (H) | W2 (H x H) | b2 (H) | W3 (O x H) | b3 (O) ],
- *   O = K (1 + 2 d).  The layers run on the matrix cores
- *   (v_mfma_f32_32x32x16_bf16: bf16 operands, float32 accumulation). */
+ *   O = K (1 + 2 d).  Two arithmetic paths (the precision field):
+ *   RESTORE_MLP_FP32: float32 FMAs in a fixed order, one fused launch per
+ *   pass (each layer a matrix-vector product per context row; in_dim and
+ *   hidden at most 256, else UNSUPPORTED); RESTORE_MLP_BF16: the layers
+ *   as GEMMs on the matrix cores (v_mfma_f32_32x32x16_bf16: bf16 operands,
+ *   float32 accumulation); RESTORE_MLP_AUTO: FP32 for G <= 16 context
+ *   rows within those widths, else BF16. */
+#define RESTORE_MLP_AUTO 0
+#define RESTORE_MLP_FP32 1
+#define RESTORE_MLP_BF16 2
 typedef struct {
     int32_t in_dim;   /* context length (12 for the learned-mu workload) */
     int32_t hidden;   /* H                                               */
     int32_t n_comp;   /* K <= 64                                         */
     int32_t dim;      /* d <= 16                                         */
+    int32_t precision;/* RESTORE_MLP_AUTO, _FP32 or _BF16               */
 } restore_mlp_shape;
 
 /* Number of float32 parameters, and activations saved per context row. */

@@ -34,7 +34,19 @@ restore_status shape_ok(const restore_mlp_shape *s) {
         return fail(RESTORE_E_INVALID_ARG, "in_dim and hidden must be in 1..4096");
     if (s->n_comp < 1 || s->n_comp > 64) return fail(RESTORE_E_INVALID_ARG, "n_comp must be in 1..64");
     if (s->dim < 1 || s->dim > LEARN_MAX_DIM) return fail(RESTORE_E_INVALID_ARG, "dim must be in 1..16");
+    if (s->precision < RESTORE_MLP_AUTO || s->precision > RESTORE_MLP_BF16)
+        return fail(RESTORE_E_INVALID_ARG, "precision must be RESTORE_MLP_AUTO, _FP32 or _BF16");
+    if (s->precision == RESTORE_MLP_FP32 && (s->in_dim > MLP_F32_MAX_WIDTH || s->hidden > MLP_F32_MAX_WIDTH))
+        return fail(RESTORE_E_UNSUPPORTED, "the float32 MLP takes in_dim and hidden up to " + std::to_string(MLP_F32_MAX_WIDTH));
     return RESTORE_OK;
+}
+
+// The float32 path for explicit FP32, and for AUTO with few context rows
+// (matrix-vector products, where bf16 GEMM tiles would be mostly padding).
+bool use_f32(const restore_mlp_shape *s, int G) {
+    if (s->precision == RESTORE_MLP_FP32) return true;
+    return s->precision == RESTORE_MLP_AUTO && G <= 16 && s->in_dim <= MLP_F32_MAX_WIDTH &&
+           s->hidden <= MLP_F32_MAX_WIDTH;
 }
 
 Offsets offsets(const restore_mlp_shape *s) {
@@ -50,6 +62,20 @@ Offsets offsets(const restore_mlp_shape *s) {
     o.b3 = o.W3 + (int64_t)o.O * o.H;
     o.total = o.b3 + o.O;
     return o;
+}
+
+MlpDims dims(const Offsets &o) {
+    MlpDims m{};
+    m.in = (int)o.in;
+    m.H = (int)o.H;
+    m.O = (int)o.O;
+    m.W1 = o.W1;
+    m.b1 = o.b1;
+    m.W2 = o.W2;
+    m.b2 = o.b2;
+    m.W3 = o.W3;
+    m.b3 = o.b3;
+    return m;
 }
 
 }  // namespace
@@ -72,6 +98,11 @@ restore_status restore_mlp_forward(const restore_mlp_shape *shape, const float *
     if (!theta || !ctx || !act || !out || G < 1) return fail(RESTORE_E_INVALID_ARG, "null buffer or G < 1");
     const Offsets o = offsets(shape);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (use_f32(shape, G)) {
+        hipError_t e = launch_mlp_forward_f32(dims(o), theta, ctx, G, act, out, s);
+        if (e != hipSuccess) return hip_fail(e, "mlp forward");
+        return RESTORE_OK;
+    }
     float *z1 = act, *h1 = act + (int64_t)G * o.H, *z2 = act + 2LL * G * o.H, *h2 = act + 3LL * G * o.H;
     // z1 = ctx W1^T + b1, h1 = gelu(z1); z2 = h1 W2^T + b2, h2 = gelu(z2); out = h2 W3^T + b3
     hipError_t e = launch_gemm_bf16(G, o.H, o.in, ctx, o.in, false, theta + o.W1, o.in, true, z1, o.H, false, s);
@@ -91,6 +122,11 @@ restore_status restore_mlp_backward(const restore_mlp_shape *shape, const float 
     if (!theta || !ctx || !act || !dout || !work || !grad || G < 1) return fail(RESTORE_E_INVALID_ARG, "null buffer");
     const Offsets o = offsets(shape);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (use_f32(shape, G)) {
+        hipError_t e = launch_mlp_backward_f32(dims(o), theta, ctx, G, act, dout, work, grad, s);
+        if (e != hipSuccess) return hip_fail(e, "mlp backward");
+        return RESTORE_OK;
+    }
     const float *z1 = act, *h1 = act + (int64_t)G * o.H, *z2 = act + 2LL * G * o.H, *h2 = act + 3LL * G * o.H;
     float *dh = work, *dz = work + (int64_t)G * o.H;
     // out layer: dW3 = dout^T h2, db3 = colsum(dout), dh2 = dout W3
@@ -141,6 +177,7 @@ restore_status restore_gmm_nll(int32_t n_comp, int32_t dim, float beta, const fl
     a.per_block = ((n + a.n_blocks - 1) / a.n_blocks + quantum - 1) / quantum * quantum;
     a.partials = static_cast<double *>(workspace);
     a.totals = a.partials + (size_t)NLL_MAX_BLOCKS * 64 * nll_rows(dim);
+    a.done = reinterpret_cast<unsigned int *>(a.partials + NLL_WORKSPACE_DOUBLES - 64);
     a.dout = dout;
     a.loss = loss_dev;
     hipError_t e = launch_gmm_nll(a, static_cast<hipStream_t>(stream));

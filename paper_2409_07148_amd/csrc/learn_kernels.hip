@@ -14,10 +14,15 @@
 //    pass, log-sum-exp over 16-lane rows), the responsibility-weighted
 //    moments on the FP64 matrix cores (v_mfma_f64_16x16x4f64); fixed-order
 //    block and grid reductions, so the result is bit-reproducible.
+//  * mlp_forward_f32_kernel / mlp_backward_f32_kernel: the same MLP in
+//    float32 for a few context rows, where each layer is a matrix-vector
+//    product: one launch per pass, plain FMAs in a fixed order.
 //  * adam_kernel: Adam on float32 master weights.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "learn.h"
@@ -95,12 +100,161 @@ __global__ void colsum_kernel(const float *d, float *db, int G, int n) {
     db[j] = s;
 }
 
+// ---- float32 MLP for a few context rows ---------------------------------
+
+// z[j] = b[j] + sum_i W[j][i] src[i] (row-major W, n_out x n_in), summed in
+// order of i; h[j] = gelu(z[j]).  src, z and h in LDS.
+__device__ __forceinline__ void dense_f32(const float *W, const float *b, const float *src, int n_in, int n_out,
+                                          float *z, float *h) {
+    for (int j = threadIdx.x; j < n_out; j += blockDim.x) {
+        const float *w = W + (int64_t)j * n_in;
+        float acc = 0.0f;
+        for (int i = 0; i < n_in; ++i) acc = fmaf(w[i], src[i], acc);
+        acc += b[j];
+        z[j] = acc;
+        h[j] = gelu(acc);
+    }
+}
+
+// Workgroup (x, g): the hidden layers of context row g, then outputs
+// [256 x, 256 x + 256) of that row; workgroup (0, g) also stores the row's
+// activations z1, h1, z2, h2 (four [G][H] blocks).
+__global__ __launch_bounds__(256) void mlp_forward_f32_kernel(MlpDims m, const float *theta, const float *ctx,
+                                                              int G, float *act, float *out) {
+    __shared__ float c[MLP_F32_MAX_WIDTH], z1[MLP_F32_MAX_WIDTH], h1[MLP_F32_MAX_WIDTH];
+    __shared__ float z2[MLP_F32_MAX_WIDTH], h2[MLP_F32_MAX_WIDTH];
+    const int g = blockIdx.y, t = threadIdx.x;
+    for (int i = t; i < m.in; i += blockDim.x) c[i] = ctx[(int64_t)g * m.in + i];
+    __syncthreads();
+    dense_f32(theta + m.W1, theta + m.b1, c, m.in, m.H, z1, h1);
+    __syncthreads();
+    dense_f32(theta + m.W2, theta + m.b2, h1, m.H, m.H, z2, h2);
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        const int64_t GH = (int64_t)G * m.H, row = (int64_t)g * m.H;
+        for (int j = t; j < m.H; j += blockDim.x) {
+            act[row + j] = z1[j];
+            act[GH + row + j] = h1[j];
+            act[2 * GH + row + j] = z2[j];
+            act[3 * GH + row + j] = h2[j];
+        }
+    }
+    const int o = blockIdx.x * blockDim.x + t;
+    if (o < m.O) {
+        const float *w = theta + m.W3 + (int64_t)o * m.H;
+        float acc = 0.0f;
+        for (int i = 0; i < m.H; ++i) acc = fmaf(w[i], h2[i], acc);
+        out[(int64_t)g * m.O + o] = acc + theta[m.b3 + o];
+    }
+}
+
+// sum over rows r = p, p + groups, ... < n_rows of v[r] W[r][col] (row-major
+// W with n_cols columns): eight running sums (eight loads in flight), added
+// pairwise at the end -- a fixed order.
+__device__ __forceinline__ float strided_dot(const float *v, const float *W, int n_rows, int n_cols, int col, int p,
+                                             int groups) {
+    const float *w = W + col;
+    float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    int r = p;
+    for (; r + 7 * groups < n_rows; r += 8 * groups) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int ru = r + u * groups;
+            acc[u] = fmaf(v[ru], w[(int64_t)ru * n_cols], acc[u]);
+        }
+    }
+    for (; r < n_rows; r += groups) acc[0] = fmaf(v[r], w[(int64_t)r * n_cols], acc[0]);
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+// grad = d(sum_g dout[g] . out[g]) / d theta.  Workgroups 1.. take dW3 and
+// db3 (sums over the rows g, in order); workgroup 0 takes the chain through
+// the hidden layers row by row (dh2 = dout W3 and dh1 = dz2 W2 each split
+// over 256 / H thread groups and combined in group order; dz2 and dz1 into
+// work),
+// then dW2, db2, dW1, db1 (sums over g in order).
+__global__ __launch_bounds__(256) void mlp_backward_f32_kernel(MlpDims m, const float *theta, const float *ctx,
+                                                               int G, const float *act, const float *dout,
+                                                               float *work, float *grad) {
+    const int t = threadIdx.x;
+    const int64_t GH = (int64_t)G * m.H;
+    const float *z1 = act, *h1 = act + GH, *z2 = act + 2 * GH, *h2 = act + 3 * GH;
+    if (blockIdx.x > 0) {
+        const int64_t n3 = (int64_t)m.O * m.H;
+        for (int64_t e = (int64_t)(blockIdx.x - 1) * blockDim.x + t; e < n3 + m.O;
+             e += (int64_t)(gridDim.x - 1) * blockDim.x) {
+            float acc = 0.0f;
+            if (e < n3) {
+                const int64_t o = e / m.H, h = e - o * m.H;
+                for (int g = 0; g < G; ++g) acc = fmaf(dout[(int64_t)g * m.O + o], h2[(int64_t)g * m.H + h], acc);
+                grad[m.W3 + e] = acc;
+            } else {
+                const int64_t o = e - n3;
+                for (int g = 0; g < G; ++g) acc += dout[(int64_t)g * m.O + o];
+                grad[m.b3 + o] = acc;
+            }
+        }
+        return;
+    }
+    __shared__ float part[256], dz2s[MLP_F32_MAX_WIDTH];
+    float *dz2w = work, *dz1w = work + GH;
+    const int groups = max(1, (int)blockDim.x / m.H);
+    for (int g = 0; g < G; ++g) {
+        const float *dg = dout + (int64_t)g * m.O;
+        if (t < groups * m.H) part[t] = strided_dot(dg, theta + m.W3, m.O, m.H, t % m.H, t / m.H, groups);
+        __syncthreads();
+        for (int h = t; h < m.H; h += blockDim.x) {
+            float dh = 0.0f;
+            for (int p = 0; p < groups; ++p) dh += part[p * m.H + h];
+            const float dz = dh * gelu_grad(z2[(int64_t)g * m.H + h]);
+            dz2s[h] = dz;
+            dz2w[(int64_t)g * m.H + h] = dz;
+        }
+        __syncthreads();
+        if (t < groups * m.H) part[t] = strided_dot(dz2s, theta + m.W2, m.H, m.H, t % m.H, t / m.H, groups);
+        __syncthreads();
+        for (int i = t; i < m.H; i += blockDim.x) {
+            float dh = 0.0f;
+            for (int p = 0; p < groups; ++p) dh += part[p * m.H + i];
+            dz1w[(int64_t)g * m.H + i] = dh * gelu_grad(z1[(int64_t)g * m.H + i]);
+        }
+        __syncthreads();
+    }
+    for (int64_t e = t; e < (int64_t)m.H * m.H; e += blockDim.x) {
+        const int64_t j = e / m.H, i = e - j * m.H;
+        float acc = 0.0f;
+        for (int g = 0; g < G; ++g) acc = fmaf(dz2w[(int64_t)g * m.H + j], h1[(int64_t)g * m.H + i], acc);
+        grad[m.W2 + e] = acc;
+    }
+    for (int64_t e = t; e < (int64_t)m.H * m.in; e += blockDim.x) {
+        const int64_t j = e / m.in, i = e - j * m.in;
+        float acc = 0.0f;
+        for (int g = 0; g < G; ++g) acc = fmaf(dz1w[(int64_t)g * m.H + j], ctx[(int64_t)g * m.in + i], acc);
+        grad[m.W1 + e] = acc;
+    }
+    for (int j = t; j < m.H; j += blockDim.x) {
+        float a2 = 0.0f, a1 = 0.0f;
+        for (int g = 0; g < G; ++g) {
+            a2 += dz2w[(int64_t)g * m.H + j];
+            a1 += dz1w[(int64_t)g * m.H + j];
+        }
+        grad[m.b2 + j] = a2;
+        grad[m.b1 + j] = a1;
+    }
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
     return v;
 }
 __device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
@@ -180,6 +334,8 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
     __shared__ float lse_part[64];
     const int l = threadIdx.x % 64, wv = threadIdx.x / 64;
     const int K = a.n_comp;
+    // the completion counter of the sum launch that follows on the stream
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.done = 0u;
 
     // the mixture weights ln pi = logits - LSE(logits) (one wave-wide pass)
     {
@@ -193,8 +349,10 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
     const float lbeta = a.beta > 0.0f ? logf(a.beta) : -INFINITY;
     const float l1mb = a.beta < 1.0f ? log1pf(-a.beta) : -INFINITY;
 
-    // this lane's four components
-    float m[4][D], is[4][D], c[4];
+    // this lane's four components: the score of coordinate i is
+    // z_i = (x_i - m_i) / s_i = fma(x_i, is_i, nm_i) with is_i = 1 / s_i and
+    // nm_i = -m_i is_i (one instruction per coordinate)
+    float nm[4][D], is[4][D], c[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int k = l % 16 + 16 * t;
@@ -202,12 +360,12 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
         c[t] = act ? l1mb + a.gmm[k] - logit_lse - 0.5f * D * 1.8378770664093453f : -INFINITY;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            m[t][i] = 0.0f;
+            nm[t][i] = 0.0f;
             is[t][i] = 0.0f;
             if (act) {
                 const float ls = a.gmm[K + K * D + k * D + i];
-                m[t][i] = a.gmm[K + k * D + i];
                 is[t][i] = expf(-ls);
+                nm[t][i] = -a.gmm[K + k * D + i] * is[t][i];
                 c[t] -= ls;
             }
         }
@@ -221,7 +379,12 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
 #pragma unroll
         for (int u = 0; u < NF; ++u) acc[t][u] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
-    constexpr float LOG2E = 1.4426950408889634f, LN2 = 0.6931471805599453f;
+    // scores in base 2 from here on: a_k log2 e = c_k log2 e - (log2 e / 2) q,
+    // so that the exponentials take the hardware 2^x directly
+    constexpr float LOG2E = 1.4426950408889634f, LN2 = 0.6931471805599453f, HALF_LOG2E = 0.7213475204444817f;
+    const float lbeta2 = lbeta * LOG2E;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) c[t] *= LOG2E;
     const bool defensive = l % 16 == 0 && a.beta > 0.0f;  // the uniform share, once per sample row
     const int64_t lo = (int64_t)blockIdx.x * a.per_block;
     const int64_t hi = lo + a.per_block < a.n ? lo + a.per_block : a.n;
@@ -242,29 +405,50 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
         fsq[u] = f >= D && f < 2 * D;
         fone[u] = f < 2 * D ? 1.0 : 0.0;
     }
-    for (int64_t p = lo + 4 * NP * (int64_t)wv; p < hi; p += 4 * NP * NLL_WAVES) {
-        float x[NP][D], w[NP], at[NP][4], mx[NP], xf[NP][NF];
-        bool in[NP];
+    // the rows of the next iteration are loaded while this one computes
+    // (two waves per SIMD hide little latency on their own); above d = 12
+    // the second set of registers would spill, and the rows are loaded at
+    // the top of their own iteration
+    constexpr int64_t STRIDE = 4 * NP * NLL_WAVES;
+    constexpr bool PREFETCH = D <= 12;
+    float xn[NP][D], xfn[NP][NF], wn[NP];
+    auto fetch = [&](int64_t p) {
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             const int64_t n = p + 4 * j + sl;
-            const bool valid = n < hi;
-            const int64_t nl = valid ? n : hi - 1;
-            load_row<D, VEC>(a.x + nl * D, x[j]);
+            const int64_t nl = n < hi ? n : hi - 1;
+            load_row<D, VEC>(a.x + nl * D, xn[j]);
             // this lane's B column: feature 16 u + l % 16 is x or x^2 of
             // coordinate fx[u] (a second load of the same row, in cache)
 #pragma unroll
-            for (int u = 0; u < NF; ++u) xf[j][u] = a.x[nl * D + fx[u]];
-            const float wl = a.w[nl];
-            w[j] = valid ? wl : 0.0f;
-            float xlo = x[j][0], xhi = x[j][0];
+            for (int u = 0; u < NF; ++u) xfn[j][u] = a.x[nl * D + fx[u]];
+            wn[j] = a.w[nl];
+        }
+    };
+    const int64_t p0 = lo + 4 * NP * (int64_t)wv;
+    if (PREFETCH && p0 < hi) fetch(p0);
+    for (int64_t p = p0; p < hi; p += STRIDE) {
+        float x[NP][D], w[NP], at[NP][4], mx[NP], xf[NP][NF];
+        bool in[NP];
+        if (!PREFETCH) fetch(p);
 #pragma unroll
-            for (int i = 1; i < D; ++i) {
-                xlo = fminf(xlo, x[j][i]);
-                xhi = fmaxf(xhi, x[j][i]);
-            }
-            in[j] = xlo >= 0.0f && xhi <= 1.0f;
-            mx[j] = in[j] ? lbeta : -INFINITY;
+        for (int j = 0; j < NP; ++j) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) x[j][i] = xn[j][i];
+#pragma unroll
+            for (int u = 0; u < NF; ++u) xf[j][u] = xfn[j][u];
+            w[j] = p + 4 * j + sl < hi ? wn[j] : 0.0f;
+        }
+        if (PREFETCH && p + STRIDE < hi) fetch(p + STRIDE);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            // the sample lies in the box when none of its coordinates lies
+            // outside: the 16 lanes of its row hold every coordinate in
+            // xf[j][0] (coordinate l % 16, or l % 16 - d), one ballot
+            const float xc = xf[j][0];
+            const unsigned long long out = __ballot(!(xc >= 0.0f && xc <= 1.0f));
+            in[j] = ((out >> (l & 48)) & 0xFFFFull) == 0ull;
+            mx[j] = in[j] ? lbeta2 : -INFINITY;
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -273,10 +457,10 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
                 float q = 0.0f;
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
-                    const float z = (x[j][i] - m[t][i]) * is[t][i];
+                    const float z = fmaf(x[j][i], is[t][i], nm[t][i]);
                     q = fmaf(z, z, q);
                 }
-                at[j][t] = fmaf(-0.5f, q, c[t]);   // -inf for components past K
+                at[j][t] = fmaf(-HALF_LOG2E, q, c[t]);   // -inf for components past K
                 mx[j] = fmaxf(mx[j], at[j][t]);
             }
         }
@@ -291,18 +475,19 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
             float se = 0.0f;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                at[j][t] = __builtin_amdgcn_exp2f((at[j][t] - M[j]) * LOG2E);   // e^{a - M}
+                at[j][t] = __builtin_amdgcn_exp2f(at[j][t] - M[j]);   // e^{a - M ln 2}
                 se += at[j][t];
             }
-            if (defensive && in[j]) se += __builtin_amdgcn_exp2f((lbeta - M[j]) * LOG2E);
+            if (defensive && in[j]) se += __builtin_amdgcn_exp2f(lbeta2 - M[j]);
             S[j] = row16_sum(se);
         }
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             const float inv_s = S[j] > 0.0f ? __builtin_amdgcn_rcpf(S[j]) : 0.0f;
+            const float w_inv_s = w[j] * inv_s;   // w r = e^{a - M} w / S
             const double wd = (double)w[j];
             if (l % 16 == 0) {
-                lw += wd * (double)(M[j] + __builtin_amdgcn_logf(S[j]) * LN2);
+                lw += wd * (double)((M[j] + __builtin_amdgcn_logf(S[j])) * LN2);
                 wsum += wd;
             }
             double bf[NF];
@@ -313,7 +498,7 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const double wr = wd * (double)(at[j][t] * inv_s);
+                const double wr = (double)(at[j][t] * w_inv_s);
                 s0[t] += wr;
 #pragma unroll
                 for (int u = 0; u < NF; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(wr, bf[u], acc[t][u], 0, 0, 0);
@@ -368,15 +553,6 @@ __global__ __launch_bounds__(64 * NLL_WAVES) void gmm_nll_kernel(NllArgs a) {
 }
 
 // totals[j] = sum over blocks b (fixed order) of partials[b][j].
-__global__ __launch_bounds__(256) void gmm_nll_sum_kernel(const double *partials, int entries, int n_blocks,
-                                                           double *totals) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= entries) return;
-    double v = 0.0;
-    for (int b = 0; b < n_blocks; ++b) v += partials[(int64_t)b * entries + j];
-    totals[j] = v;
-}
-
 // Gradient of L = -sum w log u / sum w with respect to the mixture outputs,
 // from the uncentred moments (float64): with S1 = sum w r (x - m) / s and
 // S2 = sum w r ((x - m) / s)^2,
@@ -385,8 +561,9 @@ __global__ __launch_bounds__(256) void gmm_nll_sum_kernel(const double *partials
 //   dL/dlogit_k = -(S0_k - pi_k sum_j S0_j) / W
 //   dL/dm_ki    = -S1_ki / (W s_ki)
 //   dL/dlog s_ki = -(S2_ki - S0_k) / W
+// (one wave: lane k takes component k)
 template <int D>
-__global__ __launch_bounds__(64) void gmm_nll_grad_kernel(NllArgs a, const double *totals) {
+__device__ __forceinline__ void nll_grad_wave(const NllArgs &a, const double *totals) {
     const int k = threadIdx.x;
     const int K = a.n_comp;
     const double *S = totals;
@@ -396,8 +573,8 @@ __global__ __launch_bounds__(64) void gmm_nll_grad_kernel(NllArgs a, const doubl
     const float lmax = wave_max(logit);
     const float pk = act ? expf(logit - lmax) : 0.0f;
     const float pi = pk / wave_sum(pk);
-    double s0tot = 0.0;
-    for (int j = 0; j < K; ++j) s0tot += S[j];
+    // sum_j S0_j by a butterfly over the wave (a fixed order)
+    const double s0tot = wave_sum(act ? s0 : 0.0);
     if (act) {
         a.dout[k] = (float)(-(s0 - (double)pi * s0tot) / W);
 #pragma unroll
@@ -412,6 +589,39 @@ __global__ __launch_bounds__(64) void gmm_nll_grad_kernel(NllArgs a, const doubl
         }
     }
     if (k == 0) a.loss[0] = -lw / W;
+}
+
+// totals[j] = sum over blocks b of partials[b][j]: a workgroup takes 16
+// entries; its thread (part q, entry e) sums blocks q, q + 16, ... in order,
+// and the 16 parts are then added in order of q (a fixed order, so the
+// totals are bit-reproducible).  The workgroup that finishes last (a
+// device-scope counter, zeroed by the NLL launch) then turns the totals
+// into the loss and the gradient.
+template <int D>
+__global__ __launch_bounds__(256) void gmm_nll_sum_kernel(NllArgs a) {
+    constexpr int entries = nll_rows(D) * 64;
+    __shared__ double part[256];
+    __shared__ bool last;
+    const int e = threadIdx.x % 16, q = threadIdx.x / 16;
+    const int j = blockIdx.x * 16 + e;
+    const double *partials = a.partials;
+    double v = 0.0;
+    if (j < entries)
+        for (int b = q; b < a.n_blocks; b += 16) v += partials[(int64_t)b * entries + j];
+    part[threadIdx.x] = v;
+    __syncthreads();
+    if (q == 0 && j < entries) {
+        double t = part[e];
+        for (int r = 1; r < 16; ++r) t += part[16 * r + e];
+        a.totals[j] = t;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(a.done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x < 64) nll_grad_wave<D>(a, a.totals);
 }
 
 __global__ void adam_kernel(float *theta, const float *grad, float *m, float *v, int64_t n, float lr, float b1,
@@ -431,6 +641,22 @@ hipError_t launch_gemm_bf16(int M, int N, int K, const float *A, int64_t lda, bo
     const dim3 grid((M + 31) / 32, (N + 31) / 32);
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(64), 0, s, M, N, K, A, lda, (int)transA, B, ldb, (int)transB, C,
                        ldc, (int)accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward_f32(const MlpDims &m, const float *theta, const float *ctx, int G, float *act,
+                                  float *out, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_forward_f32_kernel, dim3((m.O + 255) / 256, G), dim3(256), 0, s, m, theta, ctx, G, act,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward_f32(const MlpDims &m, const float *theta, const float *ctx, int G, const float *act,
+                                   const float *dout, float *work, float *grad, hipStream_t s) {
+    const int64_t n3 = (int64_t)m.O * m.H + m.O;
+    const int64_t blocks = 1 + std::min<int64_t>((n3 + 255) / 256, 4096);
+    hipLaunchKernelGGL(mlp_backward_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, theta, ctx, G, act, dout,
+                       work, grad);
     return hipGetLastError();
 }
 
@@ -457,9 +683,7 @@ static void launch_nll_d(const NllArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((gmm_nll_kernel<D, true>), dim3(a.n_blocks), dim3(64 * NLL_WAVES), 0, s, a);
     else
         hipLaunchKernelGGL((gmm_nll_kernel<D, false>), dim3(a.n_blocks), dim3(64 * NLL_WAVES), 0, s, a);
-    hipLaunchKernelGGL(gmm_nll_sum_kernel, dim3((entries + 255) / 256), dim3(256), 0, s, (const double *)a.partials,
-                       entries, a.n_blocks, a.totals);
-    hipLaunchKernelGGL(gmm_nll_grad_kernel<D>, dim3(1), dim3(64), 0, s, a, (const double *)a.totals);
+    hipLaunchKernelGGL(gmm_nll_sum_kernel<D>, dim3((entries + 15) / 16), dim3(256), 0, s, a);
 }
 
 hipError_t launch_gmm_nll(const NllArgs &a, hipStream_t s) {

@@ -25,6 +25,7 @@ MU_UNIFORM_BOX, MU_GMM_DIAG = 0, 1
 LOCAL_RWMH, LOCAL_MALA, LOCAL_HMC, LOCAL_RW_UNADJUSTED = 0, 1, 2, 3
 INTEGRAND_ONE, INTEGRAND_P, INTEGRAND_PIXEL = 1, 2, 4
 FLAG_PARAMS_LDS, FLAG_SPLAT_DIRECT, FLAG_SPLAT_TIGHT, FLAG_RB_DT, FLAG_INLINE_RNG, FLAG_IMAGE_FIXED = 1, 2, 4, 8, 16, 32
+MLP_AUTO, MLP_FP32, MLP_BF16 = 0, 1, 2
 ST_ALIVE, ST_CENSORED, ST_LAST_KILL, ST_LAST_ACCEPT, ST_GRAD_VALID, ST_LAST_LARGE = 1, 2, 4, 8, 16, 32
 
 
@@ -92,7 +93,8 @@ class restore_batch_tiling(C.Structure):
 
 
 class restore_mlp_shape(C.Structure):
-    _fields_ = [("in_dim", C.c_int32), ("hidden", C.c_int32), ("n_comp", C.c_int32), ("dim", C.c_int32)]
+    _fields_ = [("in_dim", C.c_int32), ("hidden", C.c_int32), ("n_comp", C.c_int32), ("dim", C.c_int32),
+                ("precision", C.c_int32)]
 
 
 class restore_chain_sums(C.Structure):

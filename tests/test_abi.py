@@ -211,8 +211,19 @@ def test_nll_and_mlp_argument_validation(R):
     assert e.value.status == R.E_INVALID_ARG
     n, a = R.restore_mlp_param_count(R.restore_mlp_shape(12, 64, 64, 8))
     assert n == 64 * 12 + 64 + 64 * 64 + 64 + 1088 * 64 + 1088 and a == 4 * 64
-    # partial sums of up to 256 workgroups and the totals, 34 rows of 64 (d = 16)
-    assert R.restore_gmm_nll_workspace_bytes() == 257 * 34 * 64 * 8
+    # precision: AUTO, FP32 (widths up to 256) or BF16
+    for p, status in ((3, R.E_INVALID_ARG), (-1, R.E_INVALID_ARG)):
+        with pytest.raises(R.RestoreError) as e:
+            R.restore_mlp_param_count(R.restore_mlp_shape(12, 64, 64, 8, p))
+        assert e.value.status == status
+    with pytest.raises(R.RestoreError) as e:
+        R.restore_mlp_param_count(R.restore_mlp_shape(12, 257, 64, 8, R.MLP_FP32))
+    assert e.value.status == R.E_UNSUPPORTED
+    assert R.restore_mlp_param_count(R.restore_mlp_shape(12, 257, 64, 8, R.MLP_BF16))[0] > 0
+    assert R.restore_mlp_param_count(R.restore_mlp_shape(12, 257, 64, 8, R.MLP_AUTO))[0] > 0
+    # partial sums of up to 256 workgroups and the totals, 34 rows of 64 (d = 16),
+    # and one line for the completion counter of the sum launch
+    assert R.restore_gmm_nll_workspace_bytes() == 257 * 34 * 64 * 8 + 64 * 8
     with pytest.raises(R.RestoreError) as e:
         R.restore_adam_step(0, 0, 0, 0, 10, 1, 1e-3, stream=0)
     assert e.value.status == R.E_INVALID_ARG

@@ -5,12 +5,19 @@ Tolerances come from the arithmetic, computed per element in float64:
   * a matrix-core GEMM C = A B rounds A and B to bf16 (round to nearest,
     relative error <= 2^-8 each) and accumulates the exact products in
     float32:  |dC| <= (2^-7 + 2^-16 + (k + 2) 2^-24) (|A||B|)  plus the
-    propagated error of inexact inputs, |dA||B| + |A||dB|;
+    propagated error of inexact inputs, |dA||B| + |A||dB|; the float32 path
+    sums float32 products:  |dC| <= (k + 2) 2^-24 (|A||B|)  plus the same
+    propagated error;
   * GELU in float32 (erff, expf): |dh| <= 2^-21 max(1, |z|) + |gelu'(z)||dz|;
-  * the NLL kernel evaluates a_k = c_k - |z|^2/2 in float32 (|da| <=
-    2^-24 (2|c| + (d + 6) q + 4), q = |z|^2) and log u by log-sum-exp; a
-    responsibility r = exp(a - log u) then carries the relative error
-    rho = da_k + sum_j r_j da_j + 2^-24 (8 + 2|log u|); the sums over
+  * the NLL kernel evaluates a_k log2 e = c_k log2 e - (log2 e / 2) |z|^2 in
+    float32 (the base-2 scaling adds the roundings of c_k log2 e and of the
+    constant), each score z_i = fma(x_i, 1/s_i, -m_i/s_i) off by
+    2^-24 (|z_i| + |m_i/s_i|) from the rounding of the fma and of the
+    precomputed m_i/s_i (|da| <= 2^-24 (3|c| + (d + 7) q + 4 +
+    2 sum_i |z_i m_i/s_i|), q = |z|^2), and
+    log u by log-sum-exp; a weighted responsibility w r = e^{a - M} (w / S)
+    (two float32 products) then carries the relative error
+    rho = da_k + sum_j r_j da_j + 2^-24 (9 + 2|log u|); the sums over
     samples are taken in float64 and cast to float32 once.
 Each bound is doubled as a margin for the transcendental functions (<= 1 ulp
 each on this target).
@@ -39,9 +46,9 @@ def R():
     return restore
 
 
-def _gemm_bound(A, B, dA=None, dB=None):
+def _gemm_bound(A, B, dA=None, dB=None, bf16=True):
     k = A.shape[1]
-    b = (2 * U8 + U8 * U8 + (k + 2) * U24) * (np.abs(A) @ np.abs(B))
+    b = ((2 * U8 + U8 * U8 if bf16 else 0.0) + (k + 2) * U24) * (np.abs(A) @ np.abs(B))
     if dA is not None:
         b += dA @ np.abs(B)
     if dB is not None:
@@ -54,11 +61,11 @@ def _gelu_bound(z, dz):
     return 2.0 ** -21 * np.maximum(1.0, np.abs(z)) + np.abs(L.gelu_grad(z)) * dz
 
 
-def _mlp_case(R, in_dim, H, K, d, G, seed):
+def _mlp_case(R, in_dim, H, K, d, G, seed, precision):
     import torch
     from oracle import learned_mu as L
     rng = np.random.default_rng(seed)
-    shape = R.restore_mlp_shape(in_dim, H, K, d)
+    shape = R.restore_mlp_shape(in_dim, H, K, d, precision)
     n, n_act = R.restore_mlp_param_count(shape)
     _, n_o = L.param_layout(in_dim, H, K, d)
     assert n == n_o and n_act == 4 * H
@@ -81,67 +88,84 @@ def _mlp_case(R, in_dim, H, K, d, G, seed):
             grad.cpu().numpy().astype(np.float64))
 
 
-MLP_CASES = [(12, 64, 64, 8, 1), (12, 40, 5, 3, 37), (7, 33, 3, 2, 70), (12, 64, 64, 8, 96)]
+MLP_CASES = [(12, 64, 64, 8, 1), (12, 40, 5, 3, 37), (7, 33, 3, 2, 70), (12, 64, 64, 8, 96), (12, 256, 64, 16, 3),
+             (5, 200, 7, 16, 16)]
+PRECISIONS = ["bf16", "fp32"]
 
 
+def _prec(R, name):
+    return {"bf16": R.MLP_BF16, "fp32": R.MLP_FP32}[name]
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
 @pytest.mark.parametrize("in_dim,H,K,d,G", MLP_CASES)
-def test_mlp_forward_layers_match_oracle(R, in_dim, H, K, d, G):
+def test_mlp_forward_layers_match_oracle(R, in_dim, H, K, d, G, prec):
     """Each layer of restore_mlp_forward against its float64 definition,
-    evaluated on the kernel's own input to that layer, within the bf16
-    GEMM bound; the whole forward against the oracle within the propagated
-    bound."""
+    evaluated on the kernel's own input to that layer, within the GEMM
+    bound of the path (bf16 matrix cores or float32 FMAs); the whole
+    forward against the oracle within the propagated bound."""
     from oracle import learned_mu as L
-    theta, ctx, _, z1, h1, z2, h2, out, _ = _mlp_case(R, in_dim, H, K, d, G, seed=in_dim * 1000 + G)
+    bf = prec == "bf16"
+    theta, ctx, _, z1, h1, z2, h2, out, _ = _mlp_case(R, in_dim, H, K, d, G, seed=in_dim * 1000 + G,
+                                                      precision=_prec(R, prec))
     layout, _ = L.param_layout(in_dim, H, K, d)
     P = L.unpack(theta, layout)
-    _say(f"[mlp fwd] in {in_dim} H {H} K {K} d {d} G {G}")
+    _say(f"[mlp fwd {prec}] in {in_dim} H {H} K {K} d {d} G {G}")
     # per layer, from the kernel's own input
     for name, x, W, b, z in (("z1", ctx, P["W1"], P["b1"], z1), ("z2", h1, P["W2"], P["b2"], z2),
                              ("out", h2, P["W3"], P["b3"], out)):
         exact = x @ W.T + b
-        bound = 2 * (_gemm_bound(x, W.T) + U24 * np.abs(exact)) + 1e-30
+        bound = 2 * (_gemm_bound(x, W.T, bf16=bf) + U24 * np.abs(exact)) + 1e-30
         err = np.abs(z - exact)
         assert np.all(err <= bound), (name, float((err / bound).max()))
     for name, z, h in (("h1", z1, h1), ("h2", z2, h2)):
         assert np.all(np.abs(h - L.gelu(z)) <= 2 * _gelu_bound(z, 0.0)), name
     # end to end, bound propagated through the layers
     ref, cache = L.mlp_forward(theta, ctx, in_dim, H, K, d)
-    e1 = _gemm_bound(ctx, P["W1"].T) + U24 * np.abs(cache["z1"])
+    e1 = _gemm_bound(ctx, P["W1"].T, bf16=bf) + U24 * np.abs(cache["z1"])
     eh1 = _gelu_bound(cache["z1"], e1)
-    e2 = _gemm_bound(cache["h1"], P["W2"].T, dA=eh1) + U24 * np.abs(cache["z2"])
+    e2 = _gemm_bound(cache["h1"], P["W2"].T, dA=eh1, bf16=bf) + U24 * np.abs(cache["z2"])
     eh2 = _gelu_bound(cache["z2"], e2)
-    e3 = _gemm_bound(cache["h2"], P["W3"].T, dA=eh2) + U24 * np.abs(ref)
+    e3 = _gemm_bound(cache["h2"], P["W3"].T, dA=eh2, bf16=bf) + U24 * np.abs(ref)
     err = np.abs(out - ref)
     assert np.all(err <= 2 * e3 + 1e-30), float((err / (2 * e3)).max())
-    _say(f"[mlp fwd] max err/bound {float((err / (2 * e3)).max()):.3f}")
+    # normwise relative error (elements of the output summed with
+    # cancellation have no meaningful elementwise relative error)
+    rel = float(err.max() / np.abs(ref).max())
+    _say(f"[mlp fwd {prec}] max err/bound {float((err / (2 * e3)).max()):.3f}, normwise rel err {rel:.2e}")
+    if not bf:
+        assert rel < 1e-5
 
 
+@pytest.mark.parametrize("prec", PRECISIONS)
 @pytest.mark.parametrize("in_dim,H,K,d,G", MLP_CASES)
-def test_mlp_backward_matches_oracle(R, in_dim, H, K, d, G):
+def test_mlp_backward_matches_oracle(R, in_dim, H, K, d, G, prec):
     """restore_mlp_backward against the oracle's hand-written backward pass
     evaluated on the kernel's saved activations, within the bound of the
-    bf16 GEMMs propagated through the layers."""
+    path's GEMMs propagated through the layers."""
     from oracle import learned_mu as L
-    theta, ctx, dout, z1, h1, z2, h2, _, grad = _mlp_case(R, in_dim, H, K, d, G, seed=in_dim * 1000 + G + 1)
+    bf = prec == "bf16"
+    theta, ctx, dout, z1, h1, z2, h2, _, grad = _mlp_case(R, in_dim, H, K, d, G, seed=in_dim * 1000 + G + 1,
+                                                          precision=_prec(R, prec))
     layout, n = L.param_layout(in_dim, H, K, d)
     P = L.unpack(theta, layout)
     cache = {"c": ctx, "z1": z1, "h1": h1, "z2": z2, "h2": h2, "P": P, "layout": layout}
     ref = L.mlp_backward(cache, dout)
     # bounds, layer by layer
     gp = L.gelu_grad
-    bW3 = _gemm_bound(dout.T, h2)
+    bW3 = _gemm_bound(dout.T, h2, bf16=bf)
     bb3 = (G + 1) * U24 * np.abs(dout).sum(0)
-    edh2 = _gemm_bound(dout, P["W3"])
+    edh2 = _gemm_bound(dout, P["W3"], bf16=bf)
     dh2 = dout @ P["W3"]
     edz2 = edh2 * np.abs(gp(z2)) + 2.0 ** -21 * np.abs(dh2)
     dz2 = dh2 * gp(z2)
-    bW2 = _gemm_bound(dz2.T, h1, dA=edz2.T)
+    bW2 = _gemm_bound(dz2.T, h1, dA=edz2.T, bf16=bf)
     bb2 = edz2.sum(0) + (G + 1) * U24 * np.abs(dz2).sum(0)
-    edh1 = _gemm_bound(dz2, P["W2"], dA=edz2)
+    edh1 = _gemm_bound(dz2, P["W2"], dA=edz2, bf16=bf)
     dh1 = dz2 @ P["W2"]
     edz1 = edh1 * np.abs(gp(z1)) + 2.0 ** -21 * np.abs(dh1)
     dz1 = dh1 * gp(z1)
-    bW1 = _gemm_bound(dz1.T, ctx, dA=edz1.T)
+    bW1 = _gemm_bound(dz1.T, ctx, dA=edz1.T, bf16=bf)
     bb1 = edz1.sum(0) + (G + 1) * U24 * np.abs(dz1).sum(0)
     bound = np.zeros(n)
     for k, b in (("W1", bW1), ("b1", bb1), ("W2", bW2), ("b2", bb2), ("W3", bW3), ("b3", bb3)):
@@ -150,9 +174,32 @@ def test_mlp_backward_matches_oracle(R, in_dim, H, K, d, G):
     bound = 2 * (bound + U24 * np.abs(ref)) + 1e-30
     err = np.abs(grad - ref)
     worst = int(np.argmax(err / bound))
-    _say(f"[mlp bwd] in {in_dim} H {H} K {K} d {d} G {G}: max err/bound {err[worst] / bound[worst]:.3f}")
+    # normwise relative error of each parameter block
+    rel = max(float(err[o:o + int(np.prod(sh))].max() / max(np.abs(ref[o:o + int(np.prod(sh))]).max(), 1e-300))
+              for o, sh in layout.values())
+    _say(f"[mlp bwd {prec}] in {in_dim} H {H} K {K} d {d} G {G}: max err/bound {err[worst] / bound[worst]:.3f}, "
+         f"normwise rel err per block {rel:.2e}")
     assert np.all(np.isfinite(grad))
     assert np.all(err <= bound), (worst, grad[worst], ref[worst], bound[worst])
+    if not bf:
+        assert rel < 1e-5
+
+
+@pytest.mark.parametrize("G", [1, 16, 17])
+def test_mlp_auto_precision_picks_the_path(R, G):
+    """RESTORE_MLP_AUTO runs the float32 path for up to 16 context rows
+    and the bf16 matrix-core path above: bit for bit the explicit path's
+    forward output and gradient."""
+    import torch
+    res = {}
+    for name, p in (("auto", R.MLP_AUTO), ("fp32", R.MLP_FP32), ("bf16", R.MLP_BF16)):
+        *_, out, grad = _mlp_case(R, 12, 64, 16, 4, G, seed=77 + G, precision=p)
+        res[name] = (out, grad)
+    want = "fp32" if G <= 16 else "bf16"
+    other = "bf16" if want == "fp32" else "fp32"
+    assert np.array_equal(res["auto"][0], res[want][0]) and np.array_equal(res["auto"][1], res[want][1])
+    assert not np.array_equal(res["auto"][0], res[other][0])
+    _say(f"[mlp auto] G {G}: the {want} path")
 
 
 def _nll_inputs(K, d, n, seed):
@@ -179,8 +226,9 @@ def _nll_bound(row, x, w, beta, K, d):
     z = (x[:, None, :] - m[None]) / s[None]
     q = (z * z).sum(-1)
     c = comp + 0.5 * q
-    da = U24 * (2 * np.abs(c) + (d + 6) * q + 4)
-    rho = da + (r * da).sum(1, keepdims=True) + U24 * (8 + 2 * np.abs(lu))[:, None]
+    zm = (np.abs(z) * np.abs(m / s)[None]).sum(-1)
+    da = U24 * (3 * np.abs(c) + (d + 7) * q + 4 + 2 * zm)
+    rho = da + (r * da).sum(1, keepdims=True) + U24 * (9 + 2 * np.abs(lu))[:, None]
     W = w.sum()
     wr = w[:, None] * r
     e0 = (wr * (rho + 4 * U24)).sum(0) / W

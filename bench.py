@@ -225,6 +225,24 @@ def bench_batched(args):
                      "pass_ms_events": ev_g, "traffic": None},
     }
     b.close()
+    # the drain's share of the pass: the same batch with drain_cap = 0 (every
+    # tour in flight censored at the budget) under the same tiling
+    b0 = R.Batch([w.with_(drain_cap=0) for w in wls], n_steps=B)
+    b0.set_tiling(tiling.block_size, tiling.order, tiling.buckets)
+    for _ in range(args.warmup):
+        b0.run(R.BATCH_MODE_GRAPH)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        b0.run(R.BATCH_MODE_GRAPH)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ev_0 = e0.elapsed_time(e1) / args.steps
+    trans0 = sum(e["transitions"] for e in b0.estimates())
+    b0.close()
+    line["drain_share"] = {"pass_ms_without_drain": ev_0, "time": (ev_g - ev_0) / ev_g,
+                           "transitions": (trans - trans0) / trans}
     truths = json.load(open(os.path.join(ROOT, "tests", "golden", "truths.json")))
     if "batched_uneven" in truths:
         import numpy as np

@@ -40,6 +40,11 @@
  *     is a function of (seed, chain, target_id) only, so it does not depend
  *     on how steps are split across calls or how chains are mapped to lanes.
  *   - The support of every target is the unit box [0,1]^d; p = 0 outside.
+ *   - Tracing: with RESTORE_TRACE=1 in the environment at the first call,
+ *     the compute entry points (init, step, step_record, drain, the
+ *     estimates, the batch calls, the MLP, NLL and Adam calls) each open a
+ *     roctx range named after the function (rocprofv3 --marker-trace); the
+ *     range covers the host call, i.e. the enqueueing of its launches.
  */
 #ifndef RESTORE_H
 #define RESTORE_H

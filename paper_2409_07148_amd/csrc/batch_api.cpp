@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "trace.h"
 #include "../../include/restore.h"
 #include "batch.h"
 #include "restore_internal.h"
@@ -261,6 +262,7 @@ restore_status restore_batch_init(restore_batch **out, int32_t n_targets, const 
                                   const restore_local_kernel *locals, const restore_config *cfgs,
                                   const restore_mu *mus, int32_t n_steps, void *state_dev, size_t state_bytes,
                                   void *stream) {
+    restore::TraceRange trace_range("restore_batch_init");
     if (!out) return fail(RESTORE_E_INVALID_ARG, "null out");
     *out = nullptr;
     restore_status st = validate(n_targets, targets, locals, cfgs, mus);
@@ -368,6 +370,7 @@ restore_status restore_batch_get_tiling(const restore_batch *b, restore_batch_ti
 }
 
 restore_status restore_batch_run(restore_batch *b, int32_t mode, void *stream) {
+    restore::TraceRange trace_range("restore_batch_run");
     if (!b) return fail(RESTORE_E_INVALID_ARG, "null batch");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
@@ -419,6 +422,7 @@ restore_status restore_batch_run(restore_batch *b, int32_t mode, void *stream) {
 }
 
 restore_status restore_batch_estimates(restore_batch *b, restore_estimate_out *out, void *stream) {
+    restore::TraceRange trace_range("restore_batch_estimates");
     if (!b || !out) return fail(RESTORE_E_INVALID_ARG, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<double> res((size_t)b->n * BS_SLOTS);
@@ -494,6 +498,7 @@ static uint64_t batch_key(const restore_batch *b) {
 
 restore_status restore_batch_autotune(restore_batch *b, const char *cache_path, restore_batch_tiling *chosen,
                                       double *best_ms, void *stream) {
+    restore::TraceRange trace_range("restore_batch_autotune");
     if (!b) return fail(RESTORE_E_INVALID_ARG, "null batch");
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0;

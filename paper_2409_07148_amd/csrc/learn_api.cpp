@@ -8,6 +8,7 @@
 #include <mutex>
 #include <string>
 
+#include "trace.h"
 #include "../../include/restore.h"
 #include "learn.h"
 
@@ -93,6 +94,7 @@ restore_status restore_mlp_param_count(const restore_mlp_shape *shape, int64_t *
 
 restore_status restore_mlp_forward(const restore_mlp_shape *shape, const float *theta, const float *ctx, int32_t G,
                                    float *act, float *out, void *stream) {
+    restore::TraceRange trace_range("restore_mlp_forward");
     restore_status st = shape_ok(shape);
     if (st != RESTORE_OK) return st;
     if (!theta || !ctx || !act || !out || G < 1) return fail(RESTORE_E_INVALID_ARG, "null buffer or G < 1");
@@ -117,6 +119,7 @@ restore_status restore_mlp_forward(const restore_mlp_shape *shape, const float *
 
 restore_status restore_mlp_backward(const restore_mlp_shape *shape, const float *theta, const float *ctx, int32_t G,
                                     const float *act, const float *dout, float *work, float *grad, void *stream) {
+    restore::TraceRange trace_range("restore_mlp_backward");
     restore_status st = shape_ok(shape);
     if (st != RESTORE_OK) return st;
     if (!theta || !ctx || !act || !dout || !work || !grad || G < 1) return fail(RESTORE_E_INVALID_ARG, "null buffer");
@@ -155,6 +158,7 @@ restore_status restore_gmm_nll_workspace_bytes(size_t *bytes) {
 restore_status restore_gmm_nll(int32_t n_comp, int32_t dim, float beta, const float *gmm, const float *x,
                                const float *w, int64_t n, float *dout, double *loss_dev, void *workspace,
                                size_t workspace_bytes, void *stream) {
+    restore::TraceRange trace_range("restore_gmm_nll");
     if (n_comp < 1 || n_comp > 64 || dim < 1 || dim > LEARN_MAX_DIM) return fail(RESTORE_E_INVALID_ARG, "bad mixture shape");
     if (!(beta >= 0.0f && beta < 1.0f)) return fail(RESTORE_E_INVALID_ARG, "beta must be in [0, 1)");
     if (!gmm || !x || !w || !dout || !loss_dev || !workspace || n < 1) return fail(RESTORE_E_INVALID_ARG, "null buffer");
@@ -217,6 +221,7 @@ restore_status scratch_address(void **out) {
 
 restore_status restore_gmm_nll_noalloc(int32_t n_comp, int32_t dim, float beta, const float *gmm, const float *x,
                                        const float *w, int64_t n, float *dout, double *loss_dev, void *stream) {
+    restore::TraceRange trace_range("restore_gmm_nll_noalloc");
     void *ws = nullptr;
     restore_status st = scratch_address(&ws);
     if (st != RESTORE_OK) return st;
@@ -228,6 +233,7 @@ restore_status restore_gmm_nll_noalloc(int32_t n_comp, int32_t dim, float beta, 
 
 restore_status restore_adam_step(float *theta, const float *grad, float *m, float *v, int64_t n, int32_t t, float lr,
                                  float beta1, float beta2, float eps, void *stream) {
+    restore::TraceRange trace_range("restore_adam_step");
     if (!theta || !grad || !m || !v || n < 1 || t < 1) return fail(RESTORE_E_INVALID_ARG, "bad Adam arguments");
     hipError_t e = launch_adam(theta, grad, m, v, n, lr, beta1, beta2, eps, t, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "adam");

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "trace.h"
 #include "../../include/restore.h"
 #include "launch.h"
 #include "restore_internal.h"
@@ -619,6 +620,7 @@ restore_status restore_state_bytes(const restore_target *target, const restore_m
 restore_status restore_init(restore_ctx **out, const restore_target *target, const restore_mu *mu,
                             const restore_local_kernel *local, const restore_config *cfg, void *state_dev,
                             size_t state_bytes, float *image_dev, void *stream) {
+    restore::TraceRange trace_range("restore_init");
     if (!out) return fail(RESTORE_E_INVALID_ARG, "null out");
     *out = nullptr;
     Validated v;
@@ -792,11 +794,13 @@ static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_recor
 }
 
 restore_status restore_step(restore_ctx *c, int32_t n_steps, void *stream) {
+    restore::TraceRange trace_range("restore_step");
     return step_impl(c, n_steps, 0, nullptr, nullptr, stream);
 }
 
 restore_status restore_step_record(restore_ctx *c, int32_t n_steps, int64_t n_record, float *x_out, float *w_out,
                                    void *stream) {
+    restore::TraceRange trace_range("restore_step_record");
     if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
     if (n_record < 1 || n_record > c->cfg.n_chains || !x_out || !w_out)
         return fail(RESTORE_E_INVALID_ARG, "n_record must be in 1..n_chains with non-null buffers");
@@ -805,6 +809,7 @@ restore_status restore_step_record(restore_ctx *c, int32_t n_steps, int64_t n_re
 }
 
 restore_status restore_drain(restore_ctx *c, void *stream) {
+    restore::TraceRange trace_range("restore_drain");
     if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
     if (c->drained) return fail(RESTORE_E_BAD_STATE, "restore_drain called twice");
     if (c->mh) {
@@ -959,6 +964,7 @@ static restore_status estimate_tiles(restore_ctx *c, restore_estimate_out *out, 
 }
 
 restore_status restore_estimate(restore_ctx *c, restore_estimate_out *out, void *stream) {
+    restore::TraceRange trace_range("restore_estimate");
     if (!c || !out) return fail(RESTORE_E_INVALID_ARG, "null argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (c->splat.n_tiles) return estimate_tiles(c, out, s);
@@ -1019,6 +1025,7 @@ restore_status restore_estimate(restore_ctx *c, restore_estimate_out *out, void 
 }
 
 restore_status restore_reset_sums(restore_ctx *c, void *stream) {
+    restore::TraceRange trace_range("restore_reset_sums");
     if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
     if (!c->mh)
         return fail(RESTORE_E_BAD_STATE, "sums are reset only for the MH chain (c_tilde = 0): a restore tour in "
@@ -1042,6 +1049,7 @@ restore_status restore_reset_sums(restore_ctx *c, void *stream) {
 }
 
 restore_status restore_image_estimate(restore_ctx *c, float *mean_dev, float *se_dev, void *stream) {
+    restore::TraceRange trace_range("restore_image_estimate");
     if (!c || !mean_dev || !se_dev) return fail(RESTORE_E_INVALID_ARG, "null argument");
     if (!c->image) return fail(RESTORE_E_BAD_STATE, "the run has no PIXEL integrand");
     ImageEstimateArgs a{};
@@ -1080,6 +1088,7 @@ restore_status restore_get_state_view(const restore_ctx *c, restore_state_view *
 }
 
 restore_status restore_refresh_cache(restore_ctx *c, void *stream) {
+    restore::TraceRange trace_range("restore_refresh_cache");
     if (!c) return fail(RESTORE_E_INVALID_ARG, "null ctx");
     StepArgs a = c->args;
     void *kargs[] = {&a};

@@ -343,3 +343,38 @@ def test_fixed_point_image_flag(R):
     with pytest.raises(R.RestoreError) as e:
         R.restore_state_bytes(t.target, t.mu, t.local, t.cfg)
     assert e.value.status == R.E_UNSUPPORTED
+
+
+_TRACE_PROBE = """
+import sys
+sys.path.insert(0, {root!r})
+from paper_2409_07148_amd import restore as R
+from workloads import gmm_full
+p = R.problem_from_workload(gmm_full(n_chains=1000))
+n = R.restore_state_bytes(p.target, p.mu, p.local, p.cfg)
+try:
+    R.restore_init(p.target, p.mu, p.local, p.cfg, 256 + 4, n, stream=0)
+except R.RestoreError as e:
+    assert e.status == R.E_INVALID_ARG
+print("roctx mapped:", "librocprofiler-sdk-roctx" in open("/proc/self/maps").read())
+"""
+
+
+@pytest.mark.parametrize("env,mapped", [("1", True), ("0", False), (None, False)])
+def test_trace_ranges_open_roctx_only_when_asked(env, mapped):
+    """RESTORE_TRACE=1 makes the first traced entry point (here restore_init
+    with a misaligned state buffer, rejected before any device call) open
+    the profiler SDK's roctx library; unset or 0 leaves it unloaded."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if not os.path.exists("/opt/rocm/lib/librocprofiler-sdk-roctx.so.1") and mapped:
+        pytest.skip("no roctx library in this image")
+    e = {k: v for k, v in os.environ.items() if k != "RESTORE_TRACE"}
+    if env is not None:
+        e["RESTORE_TRACE"] = env
+    out = subprocess.run([sys.executable, "-c", _TRACE_PROBE.format(root=root)], capture_output=True, text=True,
+                         env=e, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert f"roctx mapped: {mapped}" in out.stdout, out.stdout

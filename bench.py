@@ -728,6 +728,8 @@ def main():
                     help="image workload: tile-stratified restore with P x P-pixel tiles")
     ap.add_argument("--no-mh", action="store_true",
                     help="skip the comparison with the MH chain M^l (mixture proposal, burn-in)")
+    ap.add_argument("--image-fixed", action="store_true",
+                    help="image workload: fixed-point (u64) image sums, bit-reproducible")
     ap.add_argument("--no-image", action="store_true",
                     help="diagnostic: run the rendering-shaped workload without its pixel integrand")
     ap.add_argument("--learned-pass", action="store_true",
@@ -765,7 +767,9 @@ def main():
         wl = wl.with_(tile_px=args.tiles)
     if args.no_image:
         wl = wl.with_(image=None)
-    prob = R.problem_from_workload(wl, lds=args.lds)
+    if args.image_fixed and (wl.target != "pss" or args.tiles):
+        sys.exit("--image-fixed needs the untiled image workload")
+    prob = R.problem_from_workload(wl, lds=args.lds, flags=R.FLAG_IMAGE_FIXED if args.image_fixed else 0)
     stream = torch.cuda.current_stream()
     nbytes = R.restore_state_bytes(prob.target, prob.mu, prob.local, prob.cfg)
     state = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
@@ -871,6 +875,7 @@ def main():
         line["image"] = {"width": prob.cfg.image_w, "height": prob.cfg.image_h,
                          "batches": max(1, prob.cfg.image_batches),
                          "splats": ("tile-stratified, LDS tile per workgroup" if prob.cfg.tile_px else
+                                    "fixed-point u64 sums" if prob.cfg.flags & R.FLAG_IMAGE_FIXED else
                                     "direct" if prob.cfg.flags & R.FLAG_SPLAT_DIRECT else "binned"),
                          "median_rel_se": float(rel.median().item()) if prob.cfg.image_batches > 1 else None,
                          "estimate_total": float(img_mean.double().sum().item())}

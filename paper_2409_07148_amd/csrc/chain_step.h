@@ -294,8 +294,8 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     } else {
         draw_step<NB>(s, a.chain0 + chain, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
         // the two exponential clocks
-        t1 = -logf(head[0]);
-        e2 = -logf(head[1]);
+        t1 = -ln_u01(head[0]);
+        e2 = -ln_u01(head[1]);
     }
     float t2 = INFINITY;
     float inv_k = INFINITY;
@@ -489,7 +489,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
             if constexpr (PRE) {
                 accept = pr->lacc < lr;
             } else {
-                accept = logf(head[2]) < lr;
+                accept = ln_u01(head[2]) < lr;
             }
         }
     }

@@ -12,7 +12,15 @@ namespace restore {
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies with a Weyl-sequence key schedule.  The key and all
 // counter words except the chain id are wave-uniform, so the first rounds
-// run largely on the scalar unit.
+// run largely on the scalar unit.  From the fourth round on every word
+// differs between lanes, and each of the round's two three-way xors is one
+// gfx950 three-input bit operation (truth table 0x96 = a ^ b ^ c) instead
+// of two xors; the first three rounds keep plain xors, whose wave-uniform
+// parts the compiler moves to the scalar unit.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 struct Philox {
     static constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
     static constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
@@ -23,8 +31,9 @@ struct Philox {
         for (int r = 0; r < 10; ++r) {
             const uint64_t p0 = (uint64_t)M0 * c0;
             const uint64_t p1 = (uint64_t)M1 * c2;
-            const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-            const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+            const uint32_t h1 = (uint32_t)(p1 >> 32), h0 = (uint32_t)(p0 >> 32);
+            const uint32_t n0 = r < 3 ? h1 ^ c1 ^ k0 : xor3(h1, c1, k0);
+            const uint32_t n2 = r < 3 ? h0 ^ c3 ^ k1 : xor3(h0, c3, k1);
             c1 = (uint32_t)p1;
             c3 = (uint32_t)p0;
             c0 = n0;
@@ -39,9 +48,16 @@ struct Philox {
 // Odd 23-bit uniform in (0,1): (2 (r >> 9) + 1) 2^-24 == ((r >> 8) | 1) 2^-24,
 // exact in float32.  Built from the exponent bits: f = 1 + (r >> 9) 2^-23
 // lies in [1, 2), and f - (1 - 2^-24) is exact (Sterbenz) and equals
-// (r >> 9) 2^-23 + 2^-24.
+// (r >> 9) 2^-23 + 2^-24.  The bits of f, (r >> 9) | 0x3F800000, are one
+// funnel shift of the 64-bit pair (0x7F, r).
 __device__ __forceinline__ float u01(uint32_t r) {
-    return __uint_as_float((r >> 9) | 0x3F800000u) - 0x1.fffffep-1f;
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, r, 9)) - 0x1.fffffep-1f;
+}
+
+// ln u of a uniform from u01 (u >= 2^-24, so no denormal-range handling):
+// the hardware base-2 logarithm times ln 2, a few ulps of ln u.
+__device__ __forceinline__ float ln_u01(float u) {
+    return __builtin_amdgcn_logf(u) * 0.6931471805599453f;
 }
 
 // Uniforms of one step: head = (u_E1, u_E2, u_acc, u_cat) from block 0;
@@ -69,7 +85,7 @@ template <int D, int NC>
 __device__ __forceinline__ void box_muller(const float cand[NC], float z[D]) {
 #pragma unroll
     for (int m = 0; 2 * m < D; ++m) {
-        const float rho = sqrtf(-2.0f * logf(cand[2 * m]));
+        const float rho = sqrtf(-2.0f * ln_u01(cand[2 * m]));
         const float ang = cand[2 * m + 1];
         z[2 * m] = rho * __builtin_amdgcn_cosf(ang);
         if (2 * m + 1 < D) z[2 * m + 1] = rho * __builtin_amdgcn_sinf(ang);
@@ -97,6 +113,49 @@ __device__ __forceinline__ void lse_push(float &M, float &S, float a, float &sc,
     w = up ? 1.0f : e;
     S = up ? fmaf(S, e, 1.0f) : S + e;
     M = up ? a : M;
+}
+
+// Mixture log-densities in base 2.  The host folds log2 e into the packed
+// component parameters, so a component's term a_k = log2(w_k N_k(y)) comes
+// straight out of its quadratic form and its weight is exp2 of a difference
+// of terms: no scaling per component.  log2 of a sum is converted back to a
+// natural logarithm once, at the end.
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr float LN2 = 0.6931471805599453f;
+
+// B terms of a blocked online log-sum-exp in base 2:
+//   m = max(M, a_0, .., a_{B-1}),  S <- S 2^{M - m} + sum_b 2^{a_b - m},  M <- m.
+// sc = 2^{M - m} and w_b = 2^{a_b - m} are returned for running gradient
+// sums.  One max per term and one exponential per term plus one per block
+// (the per-term update of lse_push costs a compare, two selects and a
+// choice of sums instead).  S >= 1 once a term has been pushed (the largest
+// term contributes 2^0).  M = -inf (empty sum) gives sc = 0; every a_b must
+// be > -inf, which the packed parameters guarantee by flooring each
+// component's log-weight at -2^100 instead of -inf.
+template <int B>
+__device__ __forceinline__ void lse2_block(float &M, float &S, const float (&a)[B], float &sc, float (&w)[B]) {
+    float m = M;
+#pragma unroll
+    for (int b = 0; b < B; ++b) m = fmaxf(m, a[b]);
+    sc = __builtin_amdgcn_exp2f(M - m);
+#pragma unroll
+    for (int b = 0; b < B; ++b) w[b] = __builtin_amdgcn_exp2f(a[b] - m);
+    float t;
+    if constexpr (B == 4) {
+        t = (w[0] + w[1]) + (w[2] + w[3]);
+    } else {
+        t = w[0];
+#pragma unroll
+        for (int b = 1; b < B; ++b) t += w[b];
+    }
+    S = fmaf(S, sc, t);
+    M = m;
+}
+
+// ln of the base-2 log-sum-exp (M, S): (M + log2 S) ln 2, with S >= 1 (no
+// denormal range for the hardware logarithm).
+__device__ __forceinline__ float lse2_ln(float M, float S) {
+    return fmaf(M, LN2, __builtin_amdgcn_logf(S) * LN2);
 }
 
 template <int D>

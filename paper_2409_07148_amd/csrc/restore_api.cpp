@@ -289,6 +289,14 @@ restore_status validate(const restore_target *t, const restore_mu *mu, const res
     return RESTORE_OK;
 }
 
+// A natural log-weight as the slab's base-2 term (the mixture densities'
+// layout in restore_internal.h): scaled by log2 e, -inf floored at -2^100 so
+// that the kernels' log-sum-exp never subtracts two infinities.
+float log_weight2(double ln_w) {
+    const double v = ln_w * M_LOG2E;
+    return v > -0x1p100 ? (float)v : -0x1p100f;
+}
+
 // Float64 factorisation of the canonical parameters into the float32 slab.
 restore_status pack_params(const restore_target *t, const Validated &v, std::vector<float> *out) {
     const int d = v.d, K = v.K;
@@ -302,9 +310,9 @@ restore_status pack_params(const restore_target *t, const Validated &v, std::vec
         for (int k = 0; k < K; ++k) {
             if (!(w[k] >= 0.0) || !(s[k] > 0.0)) return fail(RESTORE_E_INVALID_ARG, "weights >= 0, sigmas > 0");
             float *o = out->data() + (size_t)k * S;
-            o[0] = (float)(std::log(w[k]) - 0.5 * d * (LN2PI + 2.0 * std::log(s[k])));
+            o[0] = log_weight2(std::log(w[k]) - 0.5 * d * (LN2PI + 2.0 * std::log(s[k])));
             for (int i = 0; i < d; ++i) o[1 + i] = (float)m[(size_t)k * d + i];
-            o[1 + d] = (float)(1.0 / (s[k] * s[k]));
+            o[1 + d] = (float)(0.5 * M_LOG2E / (s[k] * s[k]));
             if (v.loc == LOC_RWU) {
                 // Q^T p terms (layout in restore_internal.h)
                 const double s2 = s[k] * s[k], tot = s2 + j2, alpha = s2 / tot;
@@ -350,11 +358,12 @@ restore_status pack_params(const restore_target *t, const Validated &v, std::vec
                 }
             }
             float *o = out->data() + (size_t)k * S;
-            o[0] = (float)(std::log(w[k]) - 0.5 * d * LN2PI - logdiag);
+            o[0] = log_weight2(std::log(w[k]) - 0.5 * d * LN2PI - logdiag);
             for (int i = 0; i < d; ++i) o[1 + i] = (float)m[(size_t)k * d + i];
+            const double scale = std::sqrt(0.5 * M_LOG2E);
             int at = 1 + d;
             for (int i = 0; i < d; ++i)
-                for (int j = 0; j <= i; ++j) o[at++] = (float)W[i * d + j];
+                for (int j = 0; j <= i; ++j) o[at++] = (float)(scale * W[i * d + j]);
         }
         return RESTORE_OK;
     }
@@ -409,7 +418,8 @@ restore_status pack_mu(const std::vector<float> &raw, int K, int d, float beta, 
     const int S = mu_stride(d);
     out->assign((size_t)mu_slab_floats(d, K), 0.0f);
     float *o = out->data();
-    o[0] = b > 0.0 ? (float)std::log(b) : -INFINITY;
+    o[0] = b > 0.0 ? (float)std::log2(b) : -INFINITY;
+    const double scale = std::sqrt(0.5 * M_LOG2E);
     double cum = b;
     for (int k = 0; k < K; ++k) {
         const double pk = std::exp((double)logit[k] - mx) / den;
@@ -420,11 +430,11 @@ restore_status pack_mu(const std::vector<float> &raw, int K, int d, float beta, 
             const double ls = lstd[(size_t)k * d + i];
             c -= ls;
             ck[1 + i] = mean[(size_t)k * d + i];
-            ck[1 + d + i] = (float)std::exp(-ls);
+            ck[1 + d + i] = (float)(scale * std::exp(-ls));
             ms[i] = mean[(size_t)k * d + i];
             ms[d + i] = (float)std::exp(ls);
         }
-        ck[0] = (float)c;
+        ck[0] = log_weight2(c);
         o[4 + (size_t)K * S + k] = (float)cum;
         cum += (1.0 - b) * pk;
     }

@@ -33,10 +33,14 @@ enum CounterSlot : int {
 constexpr int CNT_SPREAD = 64;
 constexpr int CNT_LINE = 32;
 
-// Number of float32 values per mixture component in the packed slab.
-//   ISO : [ c_k | m_k (d) | 1/s_k^2 ]                    c_k = ln w_k - d/2 ln(2 pi s_k^2)
-//   FULL: [ c_k | m_k (d) | W_k lower-tri rows (d(d+1)/2) ] W_k = L_k^-1, S_k = L_k L_k^T,
-//                                                         c_k = ln w_k - d/2 ln 2pi - sum ln L_k,ii
+// Number of float32 values per mixture component in the packed slab.  The
+// log-weights and quadratic forms are in base 2 (scaled by log2 e), and a
+// log-weight of -inf (w_k = 0) is stored as -2^100:
+//   ISO : [ c_k | m_k (d) | h_k ]       c_k = log2 e (ln w_k - d/2 ln(2 pi s_k^2)),
+//                                       h_k = log2 e / (2 s_k^2)
+//   FULL: [ c_k | m_k (d) | W_k lower-tri rows (d(d+1)/2) ]
+//         W_k = sqrt(log2 e / 2) L_k^-1 (S_k = L_k L_k^T),
+//         c_k = log2 e (ln w_k - d/2 ln 2pi - sum ln L_k,ii)
 // rounded up to a multiple of 4 floats.
 __host__ __device__ constexpr int comp_stride(int kind, int d) {
     return kind == TGT_ISO ? ((2 + d + 3) / 4) * 4 : ((1 + d + d * (d + 1) / 2 + 3) / 4) * 4;
@@ -57,9 +61,11 @@ constexpr int PSS_SLAB = 112;
 
 // Learned regeneration distribution slab (float32, factorised on the host
 // in float64 from the caller's logits / means / log standard deviations):
-//   [0]                 ln beta (-inf when beta = 0)
-//   [4 + k * S, ...)    component k: [ c_k | m_k (d) | 1/s_k (d) ],
-//                       c_k = ln(1 - beta) + ln pi_k - d/2 ln 2 pi - sum_i ln s_ki
+//   [0]                 log2 beta (-inf when beta = 0)
+//   [4 + k * S, ...)    component k: [ c_k | m_k (d) | r_k (d) ], in base 2 as the
+//                       mixture targets: r_ki = sqrt(log2 e / 2) / s_ki,
+//                       c_k = log2 e (ln(1 - beta) + ln pi_k - d/2 ln 2 pi - sum_i ln s_ki),
+//                       floored at -2^100
 //   [4 + K * S, ...)    cumulative weights q_0 = beta, q_j = beta + (1 - beta) sum_{k<j} pi_k
 //   [4 + K * S + K, ...) per component [ m_k (d) | s_k (d) ] for the sampler
 __host__ __device__ constexpr int mu_stride(int d) { return ((1 + 2 * d + 3) / 4) * 4; }

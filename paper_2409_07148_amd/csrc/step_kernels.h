@@ -77,9 +77,9 @@ __device__ __forceinline__ void prepass_one(const StepArgs &a, uint32_t s0, int6
     draw_step<NB>(s0 + (uint32_t)j, a.chain0 + (uint32_t)c, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
     const int64_t C = a.n_chains, fs = (int64_t)chunk * C;
     float *o = out + (int64_t)j * C + c;
-    o[0] = -logf(head[0]);
-    o[fs] = -logf(head[1]);
-    o[2 * fs] = logf(head[2]);
+    o[0] = -ln_u01(head[0]);
+    o[fs] = -ln_u01(head[1]);
+    o[2 * fs] = ln_u01(head[2]);
     float z[D];
     box_muller<D, 4 * NB>(cand, z);
 #pragma unroll

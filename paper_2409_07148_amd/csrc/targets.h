@@ -1,11 +1,13 @@
 // Target densities p and regeneration densities u evaluated per lane.
 //
-// All mixtures are evaluated in log space with a running maximum (online
-// log-sum-exp, one exponential per component) so that neither the far tails
-// nor the sharp peaks of the components leave the float32 range.  Parameters are read from a packed
-// slab whose addresses are wave-uniform: from global memory they become
-// scalar loads (SGPR operands of the FMAs); with LDS staging they are
-// broadcast reads.
+// The Gaussian mixtures are evaluated in log space, in base 2 (log2 e is
+// folded into the packed parameters on the host), with a blocked online
+// log-sum-exp: a block of components' terms, one maximum over them and the
+// running maximum, one exponential per term and one per block.  Neither far
+// tails nor sharp peaks leave the float32 range.  Parameters are read from
+// a packed slab whose addresses are wave-uniform: from global memory they
+// become scalar loads (SGPR operands of the FMAs); with LDS staging they
+// are broadcast reads.
 #pragma once
 
 #include "device_common.h"
@@ -18,48 +20,64 @@ namespace restore {
 // compiler cannot prove disjoint from the slab.
 typedef const __attribute__((address_space(4))) float *const_fptr;
 
-// Isotropic Gaussian mixture: a_k = c_k - (1/(2 s_k^2)) |y - m_k|^2,
-// grad log p = sum_k r_k (-(y - m_k) / s_k^2), r = softmax(a).
+// Components per log-sum-exp block: four for values alone; two when the
+// gradient needs each component's vector until the block's weights are
+// known (fewer live registers).
+template <bool GRAD>
+struct LseBlock { static constexpr int value = GRAD ? 2 : 4; };
+
+// Isotropic Gaussian mixture, slab terms in base 2 (h_k = log2 e / (2 s_k^2)):
+//   a_k = c_k - h_k |y - m_k|^2 = log2(w_k N(y; m_k, s_k^2 I)),
+//   grad log p = -2 ln 2 sum_k r_k h_k (y - m_k),  r = softmax of the a_k in base 2.
 template <int D>
 struct GmmIso {
     static constexpr int STRIDE = comp_stride(TGT_ISO, D);
 
+    template <int B, bool GRAD, class PT>
+    __device__ __forceinline__ static void push(PT P, int k0, const float y[D], float &M, float &S, float G[D],
+                                                bool want) {
+        float a[B], dx[B][D];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const auto pk = P + (k0 + b) * STRIDE;
+            float q = 0.0f;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                dx[b][i] = y[i] - pk[1 + i];
+                q = fmaf(dx[b][i], dx[b][i], q);
+            }
+            a[b] = pk[0] - pk[1 + D] * q;
+        }
+        float sc, w[B];
+        lse2_block<B>(M, S, a, sc, w);
+        if (GRAD && want) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) G[i] *= sc;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const float wh = w[b] * P[(k0 + b) * STRIDE + 1 + D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) G[i] = fmaf(wh, dx[b][i], G[i]);
+            }
+        }
+    }
+
     template <bool GRAD, class PT>
     __device__ __forceinline__ static float eval(PT P, int K, const float y[D], float g[D], bool want) {
+        constexpr int B = LseBlock<GRAD>::value;
         float M = -INFINITY, S = 0.0f;
         float G[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) G[i] = 0.0f;
-        // unrolled by four: the parameters of four neighbouring components
-        // are then fetched with wide scalar loads and one wait, instead of a
-        // wait per component (a small launch has no other wave on the SIMD
-        // to hide the scalar-load latency)
-#pragma unroll 4
-        for (int k = 0; k < K; ++k) {
-            const auto pk = P + k * STRIDE;
-            const float ivar = pk[1 + D];
-            float dx[D], q = 0.0f;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                dx[i] = y[i] - pk[1 + i];
-                q = fmaf(dx[i], dx[i], q);
-            }
-            const float ak = fmaf(-0.5f * ivar, q, pk[0]);
-            float sc, w;
-            lse_push(M, S, ak, sc, w);
-            if (GRAD && want) {
-                const float wi = -w * ivar;
-#pragma unroll
-                for (int i = 0; i < D; ++i) G[i] = fmaf(G[i], sc, wi * dx[i]);
-            }
-        }
-        const float lp = M + logf(S);
+        int k = 0;
+        for (; k + B <= K; k += B) push<B, GRAD>(P, k, y, M, S, G, want);
+        for (; k < K; ++k) push<1, GRAD>(P, k, y, M, S, G, want);
         if (GRAD && want) {
-            const float inv = 1.0f / S;
+            const float f = (-2.0f * LN2) / S;
 #pragma unroll
-            for (int i = 0; i < D; ++i) g[i] = G[i] * inv;
+            for (int i = 0; i < D; ++i) g[i] = G[i] * f;
         }
-        return lp;
+        return lse2_ln(M, S);
     }
 };
 
@@ -99,55 +117,74 @@ struct GmmIsoInflow {
     }
 };
 
-// Full-covariance Gaussian mixture with whitening factors W_k = L_k^-1
-// (S_k = L_k L_k^T, W_k lower triangular):
-//   v_k = W_k (y - m_k),  a_k = c_k - |v_k|^2 / 2,
-//   grad log p = sum_k r_k (-W_k^T v_k)  (= -S_k^-1 (y - m_k)).
+// Full-covariance Gaussian mixture with scaled whitening factors
+// W_k = sqrt(log2 e / 2) L_k^-1 (S_k = L_k L_k^T, W_k lower triangular),
+// terms in base 2:
+//   v_k = W_k (y - m_k),  a_k = c_k - |v_k|^2 = log2(w_k N(y; m_k, S_k)),
+//   grad log p = -2 ln 2 sum_k r_k W_k^T v_k  (= -sum_k r_k S_k^-1 (y - m_k)).
 template <int D>
 struct GmmFull {
     static constexpr int STRIDE = comp_stride(TGT_FULL, D);
 
-    template <bool GRAD, class PT>
-    __device__ __forceinline__ static float eval(PT P, int K, const float y[D], float g[D], bool want) {
-        float M = -INFINITY, S = 0.0f;
-        float G[D];
+    template <int B, bool GRAD, class PT>
+    __device__ __forceinline__ static void push(PT P, int k0, const float y[D], float &M, float &S, float G[D],
+                                                bool want) {
+        float a[B], v[B][D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) G[i] = 0.0f;
-        for (int k = 0; k < K; ++k) {
-            const auto pk = P + k * STRIDE;
+        for (int b = 0; b < B; ++b) {
+            const auto pk = P + (k0 + b) * STRIDE;
             const auto W = pk + 1 + D;
-            float dx[D], v[D];
+            float dx[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) dx[i] = y[i] - pk[1 + i];
-            float q = 0.0f;
+            // -a_k accumulated from -c_k: the sign folds into the maximum
+            // and the differences of lse2_block
+            float t = -pk[0];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 float acc = W[i * (i + 1) / 2] * dx[0];
 #pragma unroll
                 for (int j = 1; j <= i; ++j) acc = fmaf(W[i * (i + 1) / 2 + j], dx[j], acc);
-                v[i] = acc;
-                q = fmaf(acc, acc, q);
+                v[b][i] = acc;
+                t = fmaf(acc, acc, t);
             }
-            const float ak = fmaf(-0.5f, q, pk[0]);
-            float sc, w;
-            lse_push(M, S, ak, sc, w);
-            if (GRAD && want) {
+            a[b] = -t;
+        }
+        float sc, w[B];
+        lse2_block<B>(M, S, a, sc, w);
+        if (GRAD && want) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) G[j] *= sc;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const auto W = P + (k0 + b) * STRIDE + 1 + D;
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     float u = 0.0f;
 #pragma unroll
-                    for (int i = j; i < D; ++i) u = fmaf(W[i * (i + 1) / 2 + j], v[i], u);
-                    G[j] = fmaf(G[j], sc, -w * u);
+                    for (int i = j; i < D; ++i) u = fmaf(W[i * (i + 1) / 2 + j], v[b][i], u);
+                    G[j] = fmaf(w[b], u, G[j]);
                 }
             }
         }
-        const float lp = M + logf(S);
-        if (GRAD && want) {
-            const float inv = 1.0f / S;
+    }
+
+    template <bool GRAD, class PT>
+    __device__ __forceinline__ static float eval(PT P, int K, const float y[D], float g[D], bool want) {
+        constexpr int B = LseBlock<GRAD>::value;
+        float M = -INFINITY, S = 0.0f;
+        float G[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) g[i] = G[i] * inv;
+        for (int i = 0; i < D; ++i) G[i] = 0.0f;
+        int k = 0;
+        for (; k + B <= K; k += B) push<B, GRAD>(P, k, y, M, S, G, want);
+        for (; k < K; ++k) push<1, GRAD>(P, k, y, M, S, G, want);
+        if (GRAD && want) {
+            const float f = (-2.0f * LN2) / S;
+#pragma unroll
+            for (int i = 0; i < D; ++i) g[i] = G[i] * f;
         }
-        return lp;
+        return lse2_ln(M, S);
     }
 };
 
@@ -205,33 +242,44 @@ struct Pss {
 
 // Learned regeneration distribution: defensive mixture
 //   u(y) = beta 1_box(y) + (1 - beta) sum_k pi_k N(y; m_k, diag(s_k^2))
-// (slab layout in restore_internal.h).  log u by an online log-sum-exp with
-// scalar-loaded parameters; sampling picks the share by the cumulative
-// weights and gathers the chosen component per lane.
+// (slab layout in restore_internal.h).  log u by the blocked base-2
+// log-sum-exp with scalar-loaded parameters; sampling picks the share by
+// the cumulative weights and gathers the chosen component per lane.
 template <int D>
 struct MuGmm {
     static constexpr int STRIDE = mu_stride(D);
 
     template <class PT>
     __device__ __forceinline__ static float log_u(PT P, int K, const float y[D]) {
-        float M = in_unit_box<D>(y) ? P[0] : -INFINITY, S = 1.0f;
+        // the defensive share as the first term of the sum: log2 beta on the
+        // box (S = 1), nothing outside it (S = 0)
+        const bool in = in_unit_box<D>(y);
+        float M = in ? P[0] : -INFINITY, S = 1.0f;
         if (M == -INFINITY) S = 0.0f;
-        // unrolled by two: two components' parameters per scalar-load wait
-        // (2.7% faster at 64 components than one; four is slower again)
-#pragma unroll 2
-        for (int k = 0; k < K; ++k) {
-            const auto pk = P + 4 + k * STRIDE;
-            float q = 0.0f;
+        int k = 0;
+        for (; k + 4 <= K; k += 4) push<4>(P, k, y, M, S);
+        for (; k < K; ++k) push<1>(P, k, y, M, S);
+        return lse2_ln(M, S);
+    }
+
+    // B components' terms a_k = c_k - |(y - m_k) r_k|^2 (r_k the scaled
+    // inverse standard deviations), accumulated from -c_k as in GmmFull
+    template <int B, class PT>
+    __device__ __forceinline__ static void push(PT P, int k0, const float y[D], float &M, float &S) {
+        float a[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const auto pk = P + 4 + (k0 + b) * STRIDE;
+            float t = -pk[0];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const float z = (y[i] - pk[1 + i]) * pk[1 + D + i];
-                q = fmaf(z, z, q);
+                t = fmaf(z, z, t);
             }
-            const float ak = fmaf(-0.5f, q, pk[0]);
-            float sc, w;
-            lse_push(M, S, ak, sc, w);
+            a[b] = -t;
         }
-        return M + logf(S);
+        float sc, w[B];
+        lse2_block<B>(M, S, a, sc, w);
     }
 
     // y ~ mu from the category uniform, the candidate uniforms (uniform

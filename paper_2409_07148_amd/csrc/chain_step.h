@@ -15,6 +15,13 @@ namespace restore {
 template <int D>
 struct NBlocks { static constexpr int value = (D + 3) / 4; };
 
+// Most components per log-sum-exp block of the target density: the HMC
+// kernels keep the leapfrog state besides the chain's, and blocks of one
+// component keep their scalar registers from spilling (measured faster
+// there; the other kernels gain from blocks).
+template <int LOC>
+struct DensityBlock { static constexpr int value = LOC == LOC_HMC ? 1 : 4; };
+
 // Parameters of the target in LDS (broadcast reads) or read through the
 // constant address space (wave-uniform addresses -> scalar loads).
 template <bool LDS>
@@ -402,7 +409,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         }
     } else {
         if (uses_grad(LOC) && !(ch.status & ST_GRAD_VALID)) {
-            (void)log_target<D, TGT, true>(P, a.n_comp, ch.x, ch.g);
+            (void)log_target<D, TGT, true, DensityBlock<LOC>::value>(P, a.n_comp, ch.x, ch.g);
             ch.status |= ST_GRAD_VALID;
         }
         float z[D];
@@ -427,7 +434,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                 float gq[D];
 #pragma unroll
                 for (int i = 0; i < D; ++i) y[i] = fmaf(e, rho[i], y[i]);
-                const float lq = log_target<D, TGT, true>(P, a.n_comp, y, gq);
+                const float lq = log_target<D, TGT, true, DensityBlock<LOC>::value>(P, a.n_comp, y, gq);
                 inside = inside && lq > -INFINITY;
 #pragma unroll
                 for (int i = 0; i < D; ++i) rho[i] = fmaf(e, gq[i], rho[i]);
@@ -449,7 +456,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     }
 
     float gy[D];
-    float lpy = log_target<D, TGT, uses_grad(LOC)>(P, a.n_comp, y, gy, !kill);
+    float lpy = log_target<D, TGT, uses_grad(LOC), DensityBlock<LOC>::value>(P, a.n_comp, y, gy, !kill);
     if constexpr (TILED) {
         // the chain's target is p restricted to its tile
         if (!in_tile(a, y, ch.tpx0, ch.tpy0, ch.tw, ch.th)) lpy = -INFINITY;

@@ -131,9 +131,20 @@ constexpr float LN2 = 0.6931471805599453f;
 // choice of sums instead).  S >= 1 once a term has been pushed (the largest
 // term contributes 2^0).  M = -inf (empty sum) gives sc = 0; every a_b must
 // be > -inf, which the packed parameters guarantee by flooring each
-// component's log-weight at -2^100 instead of -inf.
+// component's log-weight at -2^100 instead of -inf.  A block of one term
+// takes lse_push's form in base 2 (one exponential instead of two).
 template <int B>
 __device__ __forceinline__ void lse2_block(float &M, float &S, const float (&a)[B], float &sc, float (&w)[B]) {
+    if constexpr (B == 1) {
+        const float d = a[0] - M;
+        const float e = __builtin_amdgcn_exp2f(-fabsf(d));
+        const bool up = d > 0.0f;
+        sc = up ? e : 1.0f;
+        w[0] = up ? 1.0f : e;
+        S = up ? fmaf(S, e, 1.0f) : S + e;
+        M = up ? a[0] : M;
+        return;
+    }
     float m = M;
 #pragma unroll
     for (int b = 0; b < B; ++b) m = fmaxf(m, a[b]);

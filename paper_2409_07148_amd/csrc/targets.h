@@ -20,11 +20,21 @@ namespace restore {
 // compiler cannot prove disjoint from the slab.
 typedef const __attribute__((address_space(4))) float *const_fptr;
 
-// Components per log-sum-exp block: four for values alone; two when the
+// Components per log-sum-exp block: four for values alone, two when the
 // gradient needs each component's vector until the block's weights are
-// known (fewer live registers).
-template <bool GRAD>
-struct LseBlock { static constexpr int value = GRAD ? 2 : 4; };
+// known (fewer live registers), and fewer while the block's parameters
+// (STRIDE floats per component, scalar operands of the FMAs) would take
+// more than LSE_SGPR_BUDGET scalar registers at once: past that the
+// compiler reloads and spills them, which costs more than the shared
+// maximum saves.
+// BMAX caps the block for kernels whose own state already crowds the
+// scalar registers.
+constexpr int LSE_SGPR_BUDGET = 96;
+template <int STRIDE, bool GRAD, int BMAX = 4>
+struct LseBlock {
+    static constexpr int cap(int b) { return (b > 1 && b * STRIDE > LSE_SGPR_BUDGET) ? cap(b / 2) : b; }
+    static constexpr int value = cap((GRAD ? 2 : 4) < BMAX ? (GRAD ? 2 : 4) : BMAX);
+};
 
 // Isotropic Gaussian mixture, slab terms in base 2 (h_k = log2 e / (2 s_k^2)):
 //   a_k = c_k - h_k |y - m_k|^2 = log2(w_k N(y; m_k, s_k^2 I)),
@@ -62,9 +72,9 @@ struct GmmIso {
         }
     }
 
-    template <bool GRAD, class PT>
+    template <bool GRAD, int BMAX = 4, class PT>
     __device__ __forceinline__ static float eval(PT P, int K, const float y[D], float g[D], bool want) {
-        constexpr int B = LseBlock<GRAD>::value;
+        constexpr int B = LseBlock<STRIDE, GRAD, BMAX>::value;
         float M = -INFINITY, S = 0.0f;
         float G[D];
 #pragma unroll
@@ -169,9 +179,9 @@ struct GmmFull {
         }
     }
 
-    template <bool GRAD, class PT>
+    template <bool GRAD, int BMAX = 4, class PT>
     __device__ __forceinline__ static float eval(PT P, int K, const float y[D], float g[D], bool want) {
-        constexpr int B = LseBlock<GRAD>::value;
+        constexpr int B = LseBlock<STRIDE, GRAD, BMAX>::value;
         float M = -INFINITY, S = 0.0f;
         float G[D];
 #pragma unroll
@@ -213,7 +223,7 @@ struct Pss {
         return t;
     }
 
-    template <bool GRAD, class PT>
+    template <bool GRAD, int BMAX = 4, class PT>
     __device__ __forceinline__ static float eval(PT P, int K, const float y[D], float g[D], bool want) {
         static_assert(D == 12, "the rendering-shaped integrand lives on [0,1]^12");
         (void)K; (void)g; (void)want;
@@ -256,8 +266,9 @@ struct MuGmm {
         const bool in = in_unit_box<D>(y);
         float M = in ? P[0] : -INFINITY, S = 1.0f;
         if (M == -INFINITY) S = 0.0f;
+        constexpr int B = LseBlock<STRIDE, false>::value;
         int k = 0;
-        for (; k + 4 <= K; k += 4) push<4>(P, k, y, M, S);
+        for (; k + B <= K; k += B) push<B>(P, k, y, M, S);
         for (; k < K; ++k) push<1>(P, k, y, M, S);
         return lse2_ln(M, S);
     }
@@ -315,9 +326,9 @@ struct TargetOf<D, TGT_PSS> { using type = Pss<D>; };
 // log p(y) with p = 0 outside the unit box; with GRAD, lanes that `want` it
 // also get grad log p(y) (the gradient work is skipped by waves where no
 // lane wants it).
-template <int D, int TGT, bool GRAD, class PT>
+template <int D, int TGT, bool GRAD, int BMAX = 4, class PT>
 __device__ __forceinline__ float log_target(PT P, int K, const float y[D], float g[D], bool want = true) {
-    const float lp = TargetOf<D, TGT>::type::template eval<GRAD>(P, K, y, g, want);
+    const float lp = TargetOf<D, TGT>::type::template eval<GRAD, BMAX>(P, K, y, g, want);
     const bool in = in_unit_box<D>(y);
     if (GRAD && want) {
 #pragma unroll

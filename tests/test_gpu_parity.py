@@ -251,6 +251,36 @@ def test_single_transitions_pss_12d(R):
     assert k > 100 and a > 100
 
 
+def test_zero_weight_components_match_oracle(R):
+    """Components of weight zero (log-weight -inf, which the packed slab
+    floors at -2^100 so that no log-sum-exp block subtracts two
+    infinities): an isotropic 2-D mixture with one, the 8-D full-covariance
+    mixture with two of its 16 (one of them in each of two blocks), and a
+    learned-form mu whose first logit underflows its softmax weight to 0.
+    Single transitions against the oracle, and no NaN in the cached
+    densities."""
+    from workloads import gmm_full, gmm_iso_2d
+    from tests import helpers as H
+    wl = gmm_iso_2d(n_chains=8192)
+    p = dict(wl.params)
+    p["weights"] = np.array([0.5, 0.0, 0.3, 0.2])
+    wl = wl.with_(params=p)
+    _single_step_check(R, wl, warm=5, label="iso2d zero weight")
+    _single_step_check(R, wl, x_init=_pi_draws(wl, wl.n_chains, 11), label="iso2d zero weight pi")
+    wl = gmm_full(n_chains=8192)
+    p = dict(wl.params)
+    w = np.array(p["weights"], dtype=np.float64)
+    w[[3, 9]] = 0.0
+    p["weights"] = w / w.sum()
+    wl = wl.with_(params=p)
+    _single_step_check(R, wl, x_init=_pi_draws(wl, wl.n_chains, 12), c_tilde=1e5, label="8d zero weights pi")
+    _single_step_check(R, wl, warm=3, label="8d zero weights warm")
+    mu = H.mixture_mu_from_target(gmm_full(n_chains=8192))
+    mu["logits"] = np.array(mu["logits"], dtype=np.float64)
+    mu["logits"][0] = -1.0e4
+    _single_step_check(R, gmm_full(n_chains=8192), warm=3, c_tilde=3.34e8, mu=mu, label="8d dead mu component")
+
+
 def test_init_with_learned_mu_matches_oracle(R):
     from workloads import gmm_full
     from oracle import oracle as O

@@ -42,11 +42,37 @@ __device__ __forceinline__ typename ParamPtr<LDS>::type stage_params(const float
     }
 }
 
+// The learned mu's component blocks in LDS, for kernels that evaluate log u
+// at every step (see MuGmm::log_u); the other kernels read them through the
+// scalar cache, with the same arithmetic and so the same results.
+typedef const __attribute__((address_space(3))) float *lds_fptr;
+
 template <int D, int MU>
-__device__ __forceinline__ float log_mu(const StepArgs &a, const float y[D]) {
+__device__ __forceinline__ auto stage_mu(const StepArgs &a, float *smem) {
     if constexpr (MU == MU_GMM) {
-        return MuGmm<D>::log_u((const_fptr)a.mu_params, a.mu_comp, y);
+        const int n = a.mu_comp * MuGmm<D>::STRIDE;
+        const float *src = a.mu_params + 4;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) smem[i] = src[i];
+        __syncthreads();
+        return (lds_fptr)smem;
     } else {
+        (void)a; (void)smem;
+        return (const_fptr) nullptr;
+    }
+}
+
+template <int D, int MU, class RT = const_fptr>
+__device__ __forceinline__ float log_mu(const StepArgs &a, const float y[D], RT R = RT()) {
+    if constexpr (MU == MU_GMM) {
+        const auto P = (const_fptr)a.mu_params;
+        if constexpr (std::is_same<RT, lds_fptr>::value) {
+            return MuGmm<D>::log_u(P, R, a.mu_comp, y);
+        } else {
+            (void)R;
+            return MuGmm<D>::log_u(P, P + 4, a.mu_comp, y);
+        }
+    } else {
+        (void)R;
         // uniform mu on the box: u = 1 there
         (void)a;
         return in_unit_box<D>(y) ? 0.0f : -INFINITY;
@@ -62,9 +88,9 @@ __device__ __forceinline__ float log_mu(const StepArgs &a, const float y[D]) {
 // sup (p - Q^T p) / u) the value is NaN: the step's holding time is then
 // NaN and the chain's sums are reported as non-finite.  Off the box (p = 0,
 // k = inf) it is not used and set to 0.
-template <int D, int TGT, int LOC, int MU, class PT>
-__device__ __forceinline__ float log_u_state(const StepArgs &a, PT P, const float y[D], float lp) {
-    const float lu = log_mu<D, MU>(a, y);
+template <int D, int TGT, int LOC, int MU, class PT, class RT = const_fptr>
+__device__ __forceinline__ float log_u_state(const StepArgs &a, PT P, const float y[D], float lp, RT R = RT()) {
+    const float lu = log_mu<D, MU>(a, y, R);
     if constexpr (LOC == LOC_RWU && TGT == TGT_ISO) {
         if (lp == -INFINITY) return 0.0f;
         const float lq = GmmIsoInflow<D>::log_inflow(P, a.n_comp, y) - a.log_c;
@@ -280,10 +306,10 @@ struct StepRand {
 // small-step update; dt f(x_{i-1}) goes straight to the float64 chain sums,
 // as the chain has no tours.  ST_LAST_LARGE reports the large-step choice.
 template <int D, int TGT, int LOC, int MU, bool RETIRE, class PT, bool BIN = false, bool MH = false,
-          bool TILED = false, bool PRE = false>
+          bool TILED = false, bool PRE = false, class RT = const_fptr>
 __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
                                           uint32_t chain, Chain<D, LOC> &ch, bool &kill, bool &accept,
-                                          const StepRand<D> *pr = nullptr) {
+                                          const StepRand<D> *pr = nullptr, RT mu_r = RT()) {
     static_assert(!PRE || (MU == MU_UNIFORM && !MH && !TILED), "precomputed inputs: uniform mu, restore only");
     constexpr int NB = NBlocks<D>::value;
     if constexpr (std::is_same<PT, const_fptr>::value) {
@@ -461,7 +487,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         // the chain's target is p restricted to its tile
         if (!in_tile(a, y, ch.tpx0, ch.tpy0, ch.tw, ch.th)) lpy = -INFINITY;
     }
-    const float luy = (MH && large) ? log_mu<D, MU>(a, y) : log_u_state<D, TGT, LOC, MU>(a, P, y, lpy);
+    const float luy = (MH && large) ? log_mu<D, MU>(a, y, mu_r) : log_u_state<D, TGT, LOC, MU>(a, P, y, lpy, mu_r);
 
     accept = false;
     if (!kill) {

@@ -428,13 +428,16 @@ restore_status pack_mu(const std::vector<float> &raw, int K, int d, float beta, 
         float *ms = o + 4 + (size_t)K * S + K + (size_t)k * 2 * d;
         for (int i = 0; i < d; ++i) {
             const double ls = lstd[(size_t)k * d + i];
+            // n from the float32 r: fma(y, r, n) is then (y - m) r up to
+            // the one rounding of n
+            const float r = (float)(scale * std::exp(-ls));
             c -= ls;
-            ck[1 + i] = mean[(size_t)k * d + i];
-            ck[1 + d + i] = (float)(scale * std::exp(-ls));
+            ck[i] = r;
+            ck[d + i] = (float)(-(double)mean[(size_t)k * d + i] * (double)r);
             ms[i] = mean[(size_t)k * d + i];
             ms[d + i] = (float)std::exp(ls);
         }
-        ck[0] = log_weight2(c);
+        ck[2 * d] = log_weight2(c);
         o[4 + (size_t)K * S + k] = (float)cum;
         cum += (1.0 - b) * pk;
     }
@@ -547,6 +550,15 @@ void fill_args(restore_ctx *c) {
     a.bin_cap = (int32_t)c->splat.cap;
     a.n_bins = c->splat.n_bins;
     a.image_fx = c->splat.fixed ? at<unsigned long long>(c, c->lay.img_fx) : nullptr;
+}
+
+// Dynamic LDS bytes of a step or drain launch (mu_lds_offset in
+// restore_internal.h): staged target parameters, then the learned mu's
+// component blocks.
+size_t kernel_lds_bytes(const restore_ctx *c, bool params_lds) {
+    size_t floats = (size_t)mu_lds_offset(params_lds, c->n_params);
+    if (c->v.mu == MU_GMM) floats += (size_t)c->mu.n_comp * (size_t)mu_stride(c->v.d);
+    return floats * sizeof(float);
 }
 
 // Half h of the pre-pass buffer.
@@ -733,11 +745,12 @@ static restore_status step_impl(restore_ctx *c, int32_t n_steps, int64_t n_recor
     a.rec_chains = n_record;
     int np = c->n_params;
     void *kargs[] = {&a, &np};
-    const size_t shm = c->lds ? (size_t)c->n_params * sizeof(float) : 0;
+    const size_t shm = kernel_lds_bytes(c, c->lds);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (c->mh) {
         // the MH chain: parameters through the scalar cache, direct splats
-        hipError_t e = hipLaunchKernel(c->ks.step_mh, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs, 0, s);
+        hipError_t e = hipLaunchKernel(c->ks.step_mh, grid_for(c->cfg.n_chains, c->block), dim3(c->block), kargs,
+                                       kernel_lds_bytes(c, false), s);
         if (e != hipSuccess) return hip_fail(e, "MH step launch");
     } else if (c->splat.n_tiles) {
         // tile-stratified: an LDS copy of the workgroup's tile takes the splats
@@ -852,7 +865,7 @@ restore_status restore_drain(restore_ctx *c, void *stream) {
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, counts, 4);
     const bool tiled = c->splat.n_tiles > 0;
     const void *fn = tiled ? c->ks.drain_tiled : c->lds ? c->ks.drain_lds : c->ks.drain;
-    const size_t shm = (c->lds && !tiled) ? (size_t)c->n_params * sizeof(float) : 0;
+    const size_t shm = tiled ? 0 : kernel_lds_bytes(c, c->lds);
     // chunks of 1, 2, 4, ... steps: survivors are compacted between chunks
     // while many chains retire, and the long tail takes few launches.  A
     // population below 2^16 chains has too few waves to fill the chip, so

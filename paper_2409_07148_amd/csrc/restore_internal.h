@@ -62,14 +62,21 @@ constexpr int PSS_SLAB = 112;
 // Learned regeneration distribution slab (float32, factorised on the host
 // in float64 from the caller's logits / means / log standard deviations):
 //   [0]                 log2 beta (-inf when beta = 0)
-//   [4 + k * S, ...)    component k: [ c_k | m_k (d) | r_k (d) ], in base 2 as the
-//                       mixture targets: r_ki = sqrt(log2 e / 2) / s_ki,
+//   [4 + k * S, ...)    component k: [ r_k (d) | n_k (d) | c_k ], in base 2 as the
+//                       mixture targets: r_ki = sqrt(log2 e / 2) / s_ki, n_ki = -m_ki r_ki
+//                       (the scaled score is fma(y_i, r_ki, n_ki)),
 //                       c_k = log2 e (ln(1 - beta) + ln pi_k - d/2 ln 2 pi - sum_i ln s_ki),
 //                       floored at -2^100
 //   [4 + K * S, ...)    cumulative weights q_0 = beta, q_j = beta + (1 - beta) sum_{k<j} pi_k
 //   [4 + K * S + K, ...) per component [ m_k (d) | s_k (d) ] for the sampler
 __host__ __device__ constexpr int mu_stride(int d) { return ((1 + 2 * d + 3) / 4) * 4; }
 __host__ __device__ constexpr int mu_slab_floats(int d, int K) { return 4 + K * mu_stride(d) + K + K * 2 * d; }
+// Dynamic LDS of the step and drain kernels: the target parameters when
+// they are staged (RESTORE_FLAG_PARAMS_LDS), rounded up to 4 floats, then
+// the learned mu's K * mu_stride(d) component floats.
+__host__ __device__ constexpr int mu_lds_offset(bool params_lds, int n_param_floats) {
+    return params_lds ? (n_param_floats + 3) / 4 * 4 : 0;
+}
 
 // Fields of the precomputed random inputs of one step (StepRand: t1, e2,
 // ln u_acc, d candidate uniforms, d Box-Muller normals).

@@ -31,6 +31,7 @@ template <int D, int TGT, int LOC, int MU, bool LDS, bool MH = false>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_floats) {
     extern __shared__ float smem[];
     const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
+    const auto MR = stage_mu<D, MU>(a, smem + mu_lds_offset(LDS, n_param_floats));
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n_chains) return;
     Chain<D, LOC> ch;
@@ -44,8 +45,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a, int n_param_float
 #pragma unroll
             for (int i = 0; i < D; ++i) xo[i] = ch.x[i];
         }
-        step_once<D, TGT, LOC, MU, false, decltype(P), false, MH>(a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch,
-                                                                 kill, accept);
+        step_once<D, TGT, LOC, MU, false, decltype(P), false, MH, false, false, decltype(MR)>(
+            a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch, kill, accept, nullptr, MR);
         if (rec) a.rec_w[(int64_t)it * a.rec_chains + c] = ch.last_dt;
         n_acc += __popcll(__ballot(accept));
         n_kill += __popcll(__ballot(kill));
@@ -313,6 +314,7 @@ __global__ __launch_bounds__(256) void step_binned_kernel(StepArgs a, int n_para
     __shared__ float rec_val[SPLAT_ROWS + 1][256];
     __shared__ uint32_t cnt[SPLAT_MAX_BANDS], base[SPLAT_MAX_BANDS];
     const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
+    const auto MR = stage_mu<D, MU>(a, smem + mu_lds_offset(LDS, n_param_floats));
     const int t = threadIdx.x;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + t;
     const bool active = c < a.n_chains;
@@ -332,8 +334,8 @@ __global__ __launch_bounds__(256) void step_binned_kernel(StepArgs a, int n_para
 #pragma unroll
                 for (int i = 0; i < D; ++i) xo[i] = ch.x[i];
             }
-            step_once<D, TGT, LOC, MU, false, decltype(P), true>(a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch,
-                                                                 kill, accept);
+            step_once<D, TGT, LOC, MU, false, decltype(P), true, false, false, false, decltype(MR)>(
+                a, P, a.s0 + (uint32_t)it, (uint32_t)c, ch, kill, accept, nullptr, MR);
             if (rec) a.rec_w[(int64_t)it * a.rec_chains + c] = ch.last_dt;
             if (ch.out_pix >= 0) {
                 rp = (uint32_t)ch.out_pix;
@@ -430,6 +432,8 @@ __global__ __launch_bounds__(256) void drain_kernel(StepArgs a, int n_param_floa
                                                      int last_chunk) {
     extern __shared__ float smem[];
     const auto P = stage_params<LDS>(a.params, n_param_floats, smem);
+    // (tile-stratified runs have the uniform mu)
+    const auto MR = stage_mu<D, TILED ? MU_UNIFORM : MU>(a, smem + mu_lds_offset(LDS, n_param_floats));
     if (blockIdx.x == 0 && threadIdx.x == 0) *count_zero = 0u;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n_in = a.list ? (int64_t)*a.list_count : a.n_chains;
@@ -446,8 +450,8 @@ __global__ __launch_bounds__(256) void drain_kernel(StepArgs a, int n_param_floa
         n_t += __popcll(live);
         bool kill = false, accept = false;
         if (alive) {
-            step_once<D, TGT, LOC, MU, true, decltype(P), false, false, TILED>(a, P, a.s0 + (uint32_t)it, c, ch,
-                                                                               kill, accept);
+            step_once<D, TGT, LOC, MU, true, decltype(P), false, false, TILED, false, decltype(MR)>(
+                a, P, a.s0 + (uint32_t)it, c, ch, kill, accept, nullptr, MR);
             stepped = true;
             kill_last = kill;
             acc_last = accept;

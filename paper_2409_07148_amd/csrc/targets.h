@@ -259,8 +259,12 @@ template <int D>
 struct MuGmm {
     static constexpr int STRIDE = mu_stride(D);
 
-    template <class PT>
-    __device__ __forceinline__ static float log_u(PT P, int K, const float y[D]) {
+    // log u(y).  P: the slab (scalar loads); R: its component blocks, either
+    // P + 4 or an LDS copy (the scales r_k then come from LDS reads instead of
+    // one VALU move each: a VALU operand takes one scalar register at most,
+    // and the score fma(y_i, r_ki, n_ki) has two per-component factors).
+    template <class PT, class RT>
+    __device__ __forceinline__ static float log_u(PT P, RT R, int K, const float y[D]) {
         // the defensive share as the first term of the sum: log2 beta on the
         // box (S = 1), nothing outside it (S = 0)
         const bool in = in_unit_box<D>(y);
@@ -268,23 +272,24 @@ struct MuGmm {
         if (M == -INFINITY) S = 0.0f;
         constexpr int B = LseBlock<STRIDE, false>::value;
         int k = 0;
-        for (; k + B <= K; k += B) push<B>(P, k, y, M, S);
-        for (; k < K; ++k) push<1>(P, k, y, M, S);
+        for (; k + B <= K; k += B) push<B>(P, R, k, y, M, S);
+        for (; k < K; ++k) push<1>(P, R, k, y, M, S);
         return lse2_ln(M, S);
     }
 
-    // B components' terms a_k = c_k - |(y - m_k) r_k|^2 (r_k the scaled
-    // inverse standard deviations), accumulated from -c_k as in GmmFull
-    template <int B, class PT>
-    __device__ __forceinline__ static void push(PT P, int k0, const float y[D], float &M, float &S) {
+    // B components' terms a_k = c_k - |(y - m_k) r_k|^2 with the scaled
+    // score fma(y_i, r_ki, -m_ki r_ki), accumulated from -c_k as in GmmFull
+    template <int B, class PT, class RT>
+    __device__ __forceinline__ static void push(PT P, RT R, int k0, const float y[D], float &M, float &S) {
         float a[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const auto pk = P + 4 + (k0 + b) * STRIDE;
-            float t = -pk[0];
+            const auto rk = R + (k0 + b) * STRIDE;
+            float t = -pk[2 * D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                const float z = (y[i] - pk[1 + i]) * pk[1 + D + i];
+                const float z = fmaf(y[i], rk[i], pk[D + i]);
                 t = fmaf(z, z, t);
             }
             a[b] = -t;

@@ -42,15 +42,14 @@ __device__ __forceinline__ typename ParamPtr<LDS>::type stage_params(const float
     }
 }
 
-// The learned mu's component blocks in LDS, for kernels that evaluate log u
-// at every step (see MuGmm::log_u); the other kernels read them through the
-// scalar cache, with the same arithmetic and so the same results.
-typedef const __attribute__((address_space(3))) float *lds_fptr;
-
+// The learned mu's component blocks and cumulative weights in LDS, for
+// kernels that evaluate log u and sample mu at every step (see MuGmm); the
+// other kernels read them through the scalar cache, with the same
+// arithmetic and so the same results.
 template <int D, int MU>
 __device__ __forceinline__ auto stage_mu(const StepArgs &a, float *smem) {
     if constexpr (MU == MU_GMM) {
-        const int n = a.mu_comp * MuGmm<D>::STRIDE;
+        const int n = a.mu_comp * (MuGmm<D>::STRIDE + 1);
         const float *src = a.mu_params + 4;
         for (int i = threadIdx.x; i < n; i += blockDim.x) smem[i] = src[i];
         __syncthreads();
@@ -65,7 +64,7 @@ template <int D, int MU, class RT = const_fptr>
 __device__ __forceinline__ float log_mu(const StepArgs &a, const float y[D], RT R = RT()) {
     if constexpr (MU == MU_GMM) {
         const auto P = (const_fptr)a.mu_params;
-        if constexpr (std::is_same<RT, lds_fptr>::value) {
+        if constexpr (std::is_same<typename std::remove_cv<RT>::type, lds_fptr>::value) {
             return MuGmm<D>::log_u(P, R, a.mu_comp, y);
         } else {
             (void)R;
@@ -103,12 +102,14 @@ __device__ __forceinline__ float log_u_state(const StepArgs &a, PT P, const floa
     }
 }
 
-template <int D, int MU, int NC>
-__device__ __forceinline__ void sample_mu(const StepArgs &a, float u_cat, const float cand[NC], float y[D]) {
+template <int D, int MU, int NC, class RT = const_fptr>
+__device__ __forceinline__ void sample_mu(const StepArgs &a, float u_cat, const float cand[NC], float y[D],
+                                          RT R = RT()) {
     if constexpr (MU == MU_GMM) {
-        MuGmm<D>::template sample<const_fptr, NC>((const_fptr)a.mu_params, a.mu_params, a.mu_comp, u_cat, cand, y);
+        MuGmm<D>::template sample<const_fptr, NC, RT>((const_fptr)a.mu_params, a.mu_params, a.mu_comp, u_cat, cand,
+                                                      y, R);
     } else {
-        (void)a; (void)u_cat;
+        (void)a; (void)u_cat; (void)R;
 #pragma unroll
         for (int i = 0; i < D; ++i) y[i] = cand[i];
     }
@@ -430,7 +431,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
 #pragma unroll
             for (int i = 0; i < D; ++i) y[i] = pr->cand[i];
         } else {
-            sample_mu<D, MU, 4 * NB>(a, head[3], cand, y);
+            sample_mu<D, MU, 4 * NB, RT>(a, head[3], cand, y, mu_r);
             if constexpr (TILED) tile_sample(a, ch.tpx0, ch.tpy0, ch.tw, ch.th, cand, y);
         }
     } else {

@@ -554,10 +554,10 @@ void fill_args(restore_ctx *c) {
 
 // Dynamic LDS bytes of a step or drain launch (mu_lds_offset in
 // restore_internal.h): staged target parameters, then the learned mu's
-// component blocks.
+// component blocks and cumulative weights.
 size_t kernel_lds_bytes(const restore_ctx *c, bool params_lds) {
     size_t floats = (size_t)mu_lds_offset(params_lds, c->n_params);
-    if (c->v.mu == MU_GMM) floats += (size_t)c->mu.n_comp * (size_t)mu_stride(c->v.d);
+    if (c->v.mu == MU_GMM) floats += (size_t)c->mu.n_comp * (size_t)(mu_stride(c->v.d) + 1);
     return floats * sizeof(float);
 }
 

@@ -73,7 +73,8 @@ __host__ __device__ constexpr int mu_stride(int d) { return ((1 + 2 * d + 3) / 4
 __host__ __device__ constexpr int mu_slab_floats(int d, int K) { return 4 + K * mu_stride(d) + K + K * 2 * d; }
 // Dynamic LDS of the step and drain kernels: the target parameters when
 // they are staged (RESTORE_FLAG_PARAMS_LDS), rounded up to 4 floats, then
-// the learned mu's K * mu_stride(d) component floats.
+// the learned mu's K * mu_stride(d) component floats and K cumulative
+// weights (slab floats [4, 4 + K (mu_stride(d) + 1))).
 __host__ __device__ constexpr int mu_lds_offset(bool params_lds, int n_param_floats) {
     return params_lds ? (n_param_floats + 3) / 4 * 4 : 0;
 }

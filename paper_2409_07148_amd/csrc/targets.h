@@ -10,6 +10,9 @@
 // are broadcast reads.
 #pragma once
 
+#include <type_traits>
+
+#include "../../include/restore.h"
 #include "device_common.h"
 
 namespace restore {
@@ -19,6 +22,8 @@ namespace restore {
 // when the kernel also writes global memory (image splats) that the
 // compiler cannot prove disjoint from the slab.
 typedef const __attribute__((address_space(4))) float *const_fptr;
+// An LDS copy of read-only parameters (per-lane indexed reads are ds_reads).
+typedef const __attribute__((address_space(3))) float *lds_fptr;
 
 // Components per log-sum-exp block: four for values alone, two when the
 // gradient needs each component's vector until the block's weights are
@@ -300,9 +305,13 @@ struct MuGmm {
 
     // y ~ mu from the category uniform, the candidate uniforms (uniform
     // share) and their Box-Muller normals (Gaussian components)
-    template <class PT, int NC>
+    // (R as in log_u: with the LDS copy, which also holds the cumulative
+    // weights, the component is found by a binary search with per-lane LDS
+    // reads instead of K - 1 compares; both give the largest j with
+    // cum[j] <= u_cat, the cumulative weights being non-decreasing)
+    template <class PT, int NC, class RT = PT>
     __device__ __forceinline__ static void sample(PT P, const float *G, int K, float u_cat, const float cand[NC],
-                                                  float y[D]) {
+                                                  float y[D], RT R = RT()) {
         const auto cum = P + 4 + K * STRIDE;
         if (u_cat < cum[0]) {
 #pragma unroll
@@ -310,7 +319,18 @@ struct MuGmm {
             return;
         }
         int pick = 0;
-        for (int j = 1; j < K; ++j) pick += (cum[j] <= u_cat) ? 1 : 0;
+        if constexpr (std::is_same<typename std::remove_cv<RT>::type, lds_fptr>::value) {
+            static_assert(RESTORE_MAX_COMP <= 64, "six halvings cover the components");
+            const auto lcum = R + K * STRIDE;
+#pragma unroll
+            for (int h = 32; h > 0; h >>= 1) {
+                const int j = pick + h;
+                if (j < K && lcum[j] <= u_cat) pick = j;
+            }
+        } else {
+            (void)R;
+            for (int j = 1; j < K; ++j) pick += (cum[j] <= u_cat) ? 1 : 0;
+        }
         float z[D];
         box_muller<D, NC>(cand, z);
         const float *ms = G + 4 + K * STRIDE + K + pick * 2 * D;

@@ -80,13 +80,17 @@ __device__ __forceinline__ void draw_step(uint32_t step, uint32_t chain, uint32_
 
 // Box-Muller on consecutive candidate pairs: z_{2m} = rho cos(2 pi u_{2m+1}),
 // z_{2m+1} = rho sin(2 pi u_{2m+1}), rho = sqrt(-2 ln u_{2m}).  The hardware
-// sine/cosine take their argument in revolutions; -2 ln u >= 1.1e-7 for the
-// odd 23-bit uniforms, so the hardware square root needs no denormal path.
-template <int D, int NC>
+// sine/cosine take their argument in revolutions.  -2 ln u >= 1.1e-7 for
+// the odd 23-bit uniforms, so HW_SQRT may take the hardware square root
+// without the library's denormal and rounding fix-ups (about 1 ulp): the
+// learned mu's sampler does; the local proposals keep sqrtf, with which the
+// uniform-mu step kernel schedules 1% faster.
+template <int D, int NC, bool HW_SQRT = false>
 __device__ __forceinline__ void box_muller(const float cand[NC], float z[D]) {
 #pragma unroll
     for (int m = 0; 2 * m < D; ++m) {
-        const float rho = __builtin_amdgcn_sqrtf(-2.0f * ln_u01(cand[2 * m]));
+        const float r2 = -2.0f * ln_u01(cand[2 * m]);
+        const float rho = HW_SQRT ? __builtin_amdgcn_sqrtf(r2) : sqrtf(r2);
         const float ang = cand[2 * m + 1];
         z[2 * m] = rho * __builtin_amdgcn_cosf(ang);
         if (2 * m + 1 < D) z[2 * m + 1] = rho * __builtin_amdgcn_sinf(ang);

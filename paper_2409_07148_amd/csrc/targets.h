@@ -329,10 +329,12 @@ struct MuGmm {
             }
         } else {
             (void)R;
+            // eight weights per scalar-load wait
+#pragma unroll 8
             for (int j = 1; j < K; ++j) pick += (cum[j] <= u_cat) ? 1 : 0;
         }
         float z[D];
-        box_muller<D, NC>(cand, z);
+        box_muller<D, NC, true>(cand, z);
         const float *ms = G + 4 + K * STRIDE + K + pick * 2 * D;
 #pragma unroll
         for (int i = 0; i < D; ++i) y[i] = fmaf(ms[D + i], z[i], ms[i]);

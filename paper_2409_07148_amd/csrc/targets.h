@@ -265,9 +265,10 @@ struct MuGmm {
     static constexpr int STRIDE = mu_stride(D);
 
     // log u(y).  P: the slab (scalar loads); R: its component blocks, either
-    // P + 4 or an LDS copy (the scales r_k then come from LDS reads instead of
-    // one VALU move each: a VALU operand takes one scalar register at most,
-    // and the score fma(y_i, r_ki, n_ki) has two per-component factors).
+    // P + 4 or an LDS copy.  The score fma(y_i, r_ki, n_ki) has two
+    // per-component operands and a VALU instruction reads at most one
+    // scalar register, so from P alone one of them costs a VALU move; from
+    // the LDS copy r_ki arrives in a vector register by a ds_read.
     template <class PT, class RT>
     __device__ __forceinline__ static float log_u(PT P, RT R, int K, const float y[D]) {
         // the defensive share as the first term of the sum: log2 beta on the

@@ -99,17 +99,19 @@ __device__ __forceinline__ void box_muller(const float cand[NC], float z[D]) {
 
 // e^x through the hardware base-2 exponential (relative error about
 // |x| 2^-24 from the rounding of x log2 e, plus the instruction's own);
-// used for mixture weights relative to a running maximum, the killing rate
-// and the integrand p = e^{log p}.
+// used for the killing rate, the integrand p = e^{log p} and the natural-
+// log sums of lse_push.
 __device__ __forceinline__ float exp_rel(float x) {
     return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
 }
 
-// One term of the online log-sum-exp, (M, S) <- (max(M, a),
-// S e^{M - max} + e^{a - max}), with a single exponential: of the two
-// factors one is exactly 1 and the other is e^{-|a - M|}.  sc and w return
-// the factors applied to the old sum and to the new term (for running
-// gradient sums).  Same values, bit for bit, as evaluating both factors.
+// One term of an online log-sum-exp in natural logs (the inflow density of
+// the unadjusted jump process; the mixture densities use lse2_block below),
+// (M, S) <- (max(M, a), S e^{M - max} + e^{a - max}), with a single
+// exponential: of the two factors one is exactly 1 and the other is
+// e^{-|a - M|}.  sc and w return the factors applied to the old sum and to
+// the new term (for running gradient sums).  Same values, bit for bit, as
+// evaluating both factors.
 __device__ __forceinline__ void lse_push(float &M, float &S, float a, float &sc, float &w) {
     const float d = a - M;
     const float e = exp_rel(-fabsf(d));

@@ -687,6 +687,44 @@ def test_split_steps_block_size_and_lds_are_bit_identical(R):
     ref.close()
 
 
+def test_learned_mu_lds_copy_is_bit_identical(R):
+    """A learned-form mu: the step and drain kernels read its scales and
+    cumulative weights from an LDS copy placed after the staged target
+    parameters (or at the start of LDS), the init and refresh kernels from
+    the scalar cache.  Block sizes, LDS-staged target parameters, step
+    splits and the drain give the same chains bit for bit; at c~ = 3.34
+    both regenerations (component pick, log u) and MALA moves occur."""
+    from workloads import gmm_full
+    from tests import helpers as H
+    wl = gmm_full(n_chains=5000, n_steps=0, c_tilde=3.34)
+    mu = H.mixture_mu_from_target(wl)
+    out = []
+    for kw, split in [({}, (40,)), ({"block_size": 64}, (13, 27)), ({"lds": True}, (40,)),
+                      ({"block_size": 128, "lds": True}, (1, 39))]:
+        run = R.Run(R.problem_from_workload(wl, mu=mu, **kw))
+        for n in split:
+            run.step(n)
+        mid = _state_snapshot(run)
+        run.refresh_cache()
+        _sync()
+        ref = _state_snapshot(run)
+        run.drain()
+        est = run.estimate()
+        out.append((kw, mid, ref, _state_snapshot(run), est))
+        run.close()
+    kw0, m0, r0, f0, e0 = out[0]
+    for key in ("logp", "logu"):
+        # the refresh kernel recomputes the cached densities on the scalar path
+        assert np.array_equal(m0[key], r0[key]), key
+    for kw, m, r, f, e in out[1:]:
+        for key in m0:
+            assert np.array_equal(m0[key], m[key]), (kw, "after the steps", key)
+            assert np.array_equal(f0[key], f[key]), (kw, "after the drain", key)
+        assert e["transitions"] == e0["transitions"] and e["p_lambda"] == e0["p_lambda"]
+    _say(f"[learned mu lds] identical over {len(out)} launch shapes ({e0['transitions']} transitions, "
+         f"kill rate {e0['kill_rate']:.3f}, accept rate {e0['accept_rate']:.3f})")
+
+
 @pytest.mark.parametrize("which", ["iso2d_rw", "full8d_mala", "iso2d_hmc", "iso2d_unadjusted", "full16d_rw"])
 def test_random_prepass_gives_the_inline_chains(R, which):
     """Populations below 2^16 chains take every step's random inputs from a

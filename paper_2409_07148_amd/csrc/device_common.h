@@ -176,12 +176,19 @@ __device__ __forceinline__ float lse2_ln(float M, float S) {
     return fmaf(M, LN2, __builtin_amdgcn_logf(S) * LN2);
 }
 
+// y in [0,1]^d.  A float in [+0, 1] has bits 0 .. 0x3F800000 as an unsigned
+// integer, while negative values and NaNs lie above that, so the test is one
+// unsigned maximum over the coordinates (three-input maxima) and one compare
+// instead of two float compares per coordinate.  -0 counts as outside; no
+// state holds it: uniforms are >= 2^-24, and a move adds a nonzero Gaussian
+// step (the Box-Muller cosine and sine of an odd multiple of 2^-24
+// revolutions are never zero), whose exact cancellation gives +0.
 template <int D>
 __device__ __forceinline__ bool in_unit_box(const float y[D]) {
-    bool in = true;
+    uint32_t m = __float_as_uint(y[0]);
 #pragma unroll
-    for (int i = 0; i < D; ++i) in = in && (y[i] >= 0.0f) && (y[i] <= 1.0f);
-    return in;
+    for (int i = 1; i < D; ++i) m = max(m, __float_as_uint(y[i]));
+    return m <= 0x3F800000u;
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

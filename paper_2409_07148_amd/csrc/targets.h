@@ -251,7 +251,9 @@ struct Pss {
             const float q = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
             light += expf(fmaf(-0.5f * P[105 + l], q, P[108 + l]));
         }
-        return logf(ta) + logf(tb) + logf(light);
+        // one logarithm of the product (ta, tb in (0, 2], light >= b: no
+        // overflow; the product's two roundings add 2^-23 relative)
+        return logf(ta * tb * light);
     }
 };
 

@@ -294,10 +294,26 @@ struct MuGmm {
         for (int b = 0; b < B; ++b) {
             const auto pk = P + 4 + (k0 + b) * STRIDE;
             const auto rk = R + (k0 + b) * STRIDE;
+            // from the LDS copy in 16-byte reads (component blocks are a
+            // multiple of 4 floats from a 16-byte aligned start)
+            float r[D];
+            if constexpr (std::is_same<typename std::remove_cv<RT>::type, lds_fptr>::value && D % 4 == 0) {
+                typedef float v4f __attribute__((ext_vector_type(4)));
+                typedef const __attribute__((address_space(3))) v4f *lds_v4ptr;
+                const auto r4 = (lds_v4ptr)rk;
+#pragma unroll
+                for (int i = 0; i < D / 4; ++i) {
+                    const v4f v = r4[i];
+                    r[4 * i] = v.x; r[4 * i + 1] = v.y; r[4 * i + 2] = v.z; r[4 * i + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < D; ++i) r[i] = rk[i];
+            }
             float t = -pk[2 * D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                const float z = fmaf(y[i], rk[i], pk[D + i]);
+                const float z = fmaf(y[i], r[i], pk[D + i]);
                 t = fmaf(z, z, t);
             }
             a[b] = -t;

@@ -17,12 +17,14 @@
 
 namespace restore {
 
-template <int D, int MU>
-__device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &t, const WorkItem &w) {
-    constexpr int NB = NBlocks<D>::value;
-    if ((int)threadIdx.x >= w.count) return;
-    const uint32_t chain = (uint32_t)(w.first + (int)threadIdx.x);
+// LDS floats of the largest learned-mu copy: component blocks and
+// cumulative weights of RESTORE_MAX_COMP components at RESTORE_MAX_DIM.
+constexpr int MU_LDS_FLOATS = RESTORE_MAX_COMP * (MuGmm<RESTORE_MAX_DIM>::STRIDE + 1);
 
+template <int D, int MU>
+__device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &t, const WorkItem &w,
+                                         float *mu_sh) {
+    constexpr int NB = NBlocks<D>::value;
     StepArgs a{};
     a.n_chains = t.n_chains;
     a.n_comp = t.K;
@@ -41,15 +43,22 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
         a.mu_beta = t.mu_beta;
     }
     const const_fptr P = (const_fptr)(b.params + t.param_offset);
+    // a learned mu is read from the workgroup's LDS copy for this item, as
+    // in the single-target kernels (the same arithmetic, the same chains);
+    // every thread of the workgroup copies and meets the barrier
+    const auto MR = stage_mu<D, MU>(a, mu_sh);
+    using RT = decltype(MR);
+    if ((int)threadIdx.x >= w.count) return;
+    const uint32_t chain = (uint32_t)(w.first + (int)threadIdx.x);
 
     // x_0 ~ mu, cached log p and log u; zero sums
     Chain<D, LOC_RWMH> ch;
     {
         float head[4], cand[4 * NB];
         draw_step<NB>(0u, t.chain0 + chain, t.target_id, PURPOSE_INIT, t.key0, t.key1, head, cand);
-        sample_mu<D, MU, 4 * NB>(a, head[3], cand, ch.x);
+        sample_mu<D, MU, 4 * NB, RT>(a, head[3], cand, ch.x, MR);
         ch.lp = log_target<D, TGT_FULL, false>(P, t.K, ch.x, ch.g);
-        ch.lu = log_mu<D, MU>(a, ch.x);
+        ch.lu = log_mu<D, MU, RT>(a, ch.x, MR);
         ch.a_cur = ch.t_cur = 0.0f;
         ch.a_done = ch.t_done = 0.0;
         ch.n_done = 0u;
@@ -62,7 +71,8 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
     unsigned long long n_t = 0, n_acc = 0, n_kill = 0;
     bool kill = false, accept = false;
     for (int s = 0; s < t.n_steps; ++s) {
-        step_once<D, TGT_FULL, LOC_RWMH, MU, false>(a, P, (uint32_t)s, chain, ch, kill, accept);
+        step_once<D, TGT_FULL, LOC_RWMH, MU, false, const_fptr, false, false, false, false, RT>(
+            a, P, (uint32_t)s, chain, ch, kill, accept, nullptr, MR);
         n_acc += __popcll(__ballot(accept));
         n_kill += __popcll(__ballot(kill));
     }
@@ -75,7 +85,8 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
         n_t += __popcll(live);
         bool k = false, ac = false;
         if (alive) {
-            step_once<D, TGT_FULL, LOC_RWMH, MU, true>(a, P, (uint32_t)s, chain, ch, k, ac);
+            step_once<D, TGT_FULL, LOC_RWMH, MU, true, const_fptr, false, false, false, false, RT>(
+                a, P, (uint32_t)s, chain, ch, k, ac, nullptr, MR);
             alive = !k;
         }
         n_acc += __popcll(__ballot(ac));
@@ -97,9 +108,10 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
 }
 
 template <int DLO, int DHI, int MU>
-__device__ __forceinline__ void run_item_dispatch(const BatchArgs &b, const BatchTarget &t, const WorkItem &w) {
+__device__ __forceinline__ void run_item_dispatch(const BatchArgs &b, const BatchTarget &t, const WorkItem &w,
+                                                  float *mu_sh) {
 #define RESTORE_BATCH_CASE(D) \
-    case D: if constexpr (D >= DLO && D <= DHI) run_item<D, MU>(b, t, w); break;
+    case D: if constexpr (D >= DLO && D <= DHI) run_item<D, MU>(b, t, w, mu_sh); break;
     switch (t.d) {
         RESTORE_BATCH_CASE(1) RESTORE_BATCH_CASE(2) RESTORE_BATCH_CASE(3) RESTORE_BATCH_CASE(4)
         RESTORE_BATCH_CASE(5) RESTORE_BATCH_CASE(6) RESTORE_BATCH_CASE(7) RESTORE_BATCH_CASE(8)
@@ -115,6 +127,7 @@ __device__ __forceinline__ void run_item_dispatch(const BatchArgs &b, const Batc
 template <int DLO, int DHI, int MU>
 __global__ __launch_bounds__(256) void batch_persistent_kernel(BatchArgs b) {
     __shared__ int32_t item_sh;
+    __shared__ float mu_sh[MU == MU_GMM ? MU_LDS_FLOATS : 1];
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) item_sh = atomicAdd(b.queue_head, 1);
@@ -123,13 +136,14 @@ __global__ __launch_bounds__(256) void batch_persistent_kernel(BatchArgs b) {
         if (item >= b.n_items) break;
         const WorkItem w = b.items[item];
         const BatchTarget t = b.targets[w.target];
-        run_item_dispatch<DLO, DHI, MU>(b, t, w);
+        run_item_dispatch<DLO, DHI, MU>(b, t, w, mu_sh);
     }
 }
 
 // One launch per target (the comparison mode): block i takes the i-th tile.
 template <int DLO, int DHI, int MU>
 __global__ __launch_bounds__(256) void batch_target_kernel(BatchArgs b, int32_t target) {
+    __shared__ float mu_sh[MU == MU_GMM ? MU_LDS_FLOATS : 1];
     const BatchTarget t = b.targets[target];
     WorkItem w;
     w.target = target;
@@ -137,7 +151,7 @@ __global__ __launch_bounds__(256) void batch_target_kernel(BatchArgs b, int32_t 
     w.count = min((int32_t)blockDim.x, t.n_chains - w.first);
     w.pad = 0;
     if (w.count <= 0) return;
-    run_item_dispatch<DLO, DHI, MU>(b, t, w);
+    run_item_dispatch<DLO, DHI, MU>(b, t, w, mu_sh);
 }
 
 __global__ void batch_zero_kernel(BatchArgs b) {

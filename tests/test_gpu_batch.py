@@ -92,6 +92,50 @@ def test_batch_with_learned_form_mu_reproduces_single_target_runs(R, buckets):
     b.close()
 
 
+def test_batch_largest_learned_form_mu(R):
+    """The largest learned-form mu a batched workgroup copies to LDS: 64
+    components at d = 16 (and at d = 8), each target's own mixture with a
+    defensive share.  The 8-D target equals its single-target run bit for
+    bit; the 16-D target, which has no single-target kernel with a learned
+    mu, is compared with the oracle chain by chain on sampled chains.  Both
+    the persistent (graph) and the one-launch-per-target kernels."""
+    from tests import helpers as H
+    from tests import chain_parity as CP
+    from workloads import gmm_full
+    from oracle import oracle as O
+    # c~ = 1: about half the transitions kill, the rest are local moves
+    wls = [gmm_full(d=16, K=64, n_chains=900, n_steps=40, local="rwmh", step=0.01, problem_seed=1080,
+                    c_tilde=1.0),
+           gmm_full(d=8, K=64, n_chains=1300, n_steps=40, local="rwmh", step=0.02, problem_seed=1072,
+                    c_tilde=1.0)]
+    mus = [H.mixture_mu_from_target(w) for w in wls]
+    b = R.Batch(wls, n_steps=40, mus=mus)
+    ids = np.unique(np.concatenate([np.random.default_rng(8).integers(0, wls[0].n_chains, 30), [0, 899]]))
+    oprob = O.Problem(wls[0], mu=mus[0], target_id=0)
+    rs = [O.run(oprob, int(c), int(c) + 1, threads=1) for c in ids]
+    cat = lambda f: np.concatenate([getattr(r, f) for r in rs])
+    ores = O.RunResult(cat("n_done"), cat("t_done"), cat("a_done"), cat("censored"), cat("t_censored"),
+                       cat("transitions"), cat("accepts"), cat("kills"), None, oprob.c_tilde,
+                       min_margin=np.concatenate([r.min_margin for r in rs]))
+    run = R.Run(R.problem_from_workload(wls[1], target_id=1, mu=mus[1]))
+    run.step(wls[1].n_steps)
+    run.drain()
+    arr = {k: v.cpu().numpy() for k, v in run.arrays().items()}
+    run.close()
+    for mode in (R.BATCH_MODE_GRAPH, R.BATCH_MODE_SEPARATE):
+        b.run(mode)
+        got = _sums(b, 0)
+        CP.check_chain_sums({k: got[k][ids] for k in ("n_done", "t_done", "a_done")}, ores, wls[0], mu=mus[0],
+                            say=_say, label=f"batch d=16 64-component mu, mode {mode}")
+        got = _sums(b, 1)
+        for k in ("n_done", "t_done", "a_done"):
+            assert np.array_equal(got[k], arr[k]), (mode, k)
+        est = b.estimates()
+        _say(f"[batch largest mu] mode {mode}: d=16 kill rate {est[0]['kill_rate']:.3f}, "
+             f"tours {est[0]['tours_done']}; d=8 identical to its single-target run")
+    b.close()
+
+
 def test_batch_results_do_not_depend_on_tiling_or_mode(R):
     wls = _small_batch(n_targets=10)
     b = R.Batch(wls, n_steps=wls[0].n_steps)

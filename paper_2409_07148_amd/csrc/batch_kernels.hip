@@ -29,13 +29,15 @@ __device__ __forceinline__ void run_item(const BatchArgs &b, const BatchTarget &
     a.n_chains = t.n_chains;
     a.n_comp = t.K;
     a.log_c = t.log_c;
-    a.no_kill = t.no_kill;
+    // the step keeps these in scalar registers: the item (and so its target)
+    // is the same for every lane of the workgroup
+    a.no_kill = __builtin_amdgcn_readfirstlane(t.no_kill);
     a.step = t.step;
-    a.key0 = t.key0;
-    a.key1 = t.key1;
-    a.target_id = t.target_id;
+    a.key0 = __builtin_amdgcn_readfirstlane(t.key0);
+    a.key1 = __builtin_amdgcn_readfirstlane(t.key1);
+    a.target_id = __builtin_amdgcn_readfirstlane(t.target_id);
     a.chain0 = t.chain0;
-    a.integrand_p = t.integrand_p;
+    a.integrand_p = __builtin_amdgcn_readfirstlane(t.integrand_p);
     a.image = nullptr;
     if (MU == MU_GMM) {
         a.mu_params = b.params + t.mu_offset;

@@ -320,13 +320,23 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
         asm volatile("" : "+s"(pv));
         P = (PT)pv;
     }
+    // per-step copies of the launch's scalars: the Philox key schedule, the
+    // target's counter word and the flags are then recomputed every step on
+    // the scalar unit; hoisted out of the step loop they outlive the
+    // density's parameter loads, spill to VGPR lanes and every step reads
+    // them back with VALU instructions.  (The Metropolis-Hastings chain's
+    // kernels and the image integrand's schedule better with the hoisted
+    // values: measured.)
+    uint32_t k0 = a.key0, k1 = a.key1, tid = a.target_id;
+    int32_t no_kill = a.no_kill, rb_dt = a.rb_dt, f_p = a.integrand_p;
+    if constexpr (!MH && TGT != TGT_PSS) asm volatile("" : "+s"(k0), "+s"(k1), "+s"(tid), "+s"(no_kill), "+s"(rb_dt), "+s"(f_p));
     float head[4], cand[4 * NB];
     float t1, e2;
     if constexpr (PRE) {
         t1 = pr->t1;
         e2 = pr->e2;
     } else {
-        draw_step<NB>(s, a.chain0 + chain, a.target_id, PURPOSE_STEP, a.key0, a.key1, head, cand);
+        draw_step<NB>(s, a.chain0 + chain, tid, PURPOSE_STEP, k0, k1, head, cand);
         // the two exponential clocks
         t1 = -ln_u01(head[0]);
         e2 = -ln_u01(head[1]);
@@ -334,7 +344,7 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     float t2 = INFINITY;
     float inv_k = INFINITY;
     kill = false;
-    if (!MH && !a.no_kill) {
+    if (!MH && !no_kill) {
         // t2 = E2 / k = E2 exp(log p - log u - ln c_tilde); p = 0 gives t2 = 0
         // (hardware 2^x: |x| 2^-24 relative, far inside the decision margins)
         inv_k = exp_rel(ch.lp - ch.lu - a.log_c);
@@ -344,23 +354,23 @@ __device__ __forceinline__ void step_once(const StepArgs &a, PT P, uint32_t s,
     // the holding time dt = min(t1, t2) ~ Exp(1 + k) whichever clock fires;
     // with rb_dt its conditional mean 1 / (1 + k) is accumulated instead
     float dt = kill ? t2 : t1;
-    if (a.rb_dt) dt = inv_k > 1e30f ? 1.0f : inv_k / (1.0f + inv_k);
+    if (rb_dt) dt = inv_k > 1e30f ? 1.0f : inv_k / (1.0f + inv_k);
 
     bool large = false;
     if constexpr (MH) {
         if (a.large_prob > 0.0f) {
             uint32_t r[4];
-            Philox::block(s, a.chain0 + chain, a.target_id, PURPOSE_LARGE << 16, a.key0, a.key1, r);
+            Philox::block(s, a.chain0 + chain, tid, PURPOSE_LARGE << 16, k0, k1, r);
             large = u01(r[0]) < a.large_prob;
         }
         ch.status = large ? (ch.status | ST_LAST_LARGE) : (ch.status & ~ST_LAST_LARGE);
         // no tours: dt f(x_{i-1}) goes to the chain sums
         ch.t_done += (double)dt;
-        if (a.integrand_p) ch.a_done = fma((double)dt, (double)exp_rel(ch.lp), ch.a_done);
+        if (f_p) ch.a_done = fma((double)dt, (double)exp_rel(ch.lp), ch.a_done);
     } else {
         // accumulate dt f(x_{i-1}) into the tour in flight
         ch.t_cur += dt;
-        if (a.integrand_p) ch.a_cur = fmaf(dt, exp_rel(ch.lp), ch.a_cur);
+        if (f_p) ch.a_cur = fmaf(dt, exp_rel(ch.lp), ch.a_cur);
     }
     if (TGT == TGT_PSS && a.image) {
         // f = 1_pixel(x0, x1) at the pre-transition state (p = 0 off the box)

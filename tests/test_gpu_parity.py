@@ -830,6 +830,32 @@ def test_ragged_chain_counts(R, n_chains):
     _check_estimate_is_the_oracle_formula(R, est, arr, wl.c_tilde, f"ragged {n_chains}")
 
 
+@pytest.mark.parametrize("inline", [True, False])
+def test_integrand_one_alone_leaves_the_chains_unchanged(R, inline):
+    """With f = 1 as the only integrand the f = p sums are skipped and
+    nothing else changes: every chain's tour count, tour time, state and
+    status equal those of the run with both integrands bit for bit, and its
+    f = p sums stay zero.  8-D MALA at c~ = 3.34 (local moves and
+    regenerations), with the step kernel's own Philox draws (inline) and
+    with the pre-pass inputs."""
+    from workloads import gmm_full
+    wl = gmm_full(n_chains=3000, n_steps=64, c_tilde=3.34)
+    got = []
+    for fp in (True, False):
+        run = R.Run(R.problem_from_workload(wl, integrand_p=fp, flags=R.FLAG_INLINE_RNG if inline else 0))
+        run.step(wl.n_steps)
+        run.drain()
+        got.append({k: v.cpu().numpy().copy() for k, v in run.arrays().items()})
+        est = run.estimate()
+        run.close()
+    both, one = got
+    for k in ("n_done", "t_done", "x", "status", "t_cur"):
+        assert np.array_equal(both[k], one[k]), k
+    assert not np.any(one["a_done"]) and np.any(both["a_done"])
+    _say(f"[f = 1 alone, inline={inline}] {int(one['n_done'].sum())} tours, kill rate {est['kill_rate']:.3f}: "
+         f"identical chains, f = p sums zero")
+
+
 def test_zero_drain_cap_censors_every_tour_in_flight(R):
     from workloads import gmm_iso_2d
     wl = gmm_iso_2d(n_chains=512, n_steps=30)
